@@ -1,0 +1,15 @@
+"""FP64 CPU oracle for the Gaussian-primitive slice acquisition model.
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline leg use it to judge the HIP path.  The product path never imports it.
+
+* ``core``  -- ctypes wrapper of the C oracle (world frame, FP64, OpenMP).
+* ``brute`` -- NumPy brute force over every (slice, pixel, Gaussian) triple.
+* ``optim`` -- masked-MSE loss and AdamW written from their definitions.
+"""
+from .core import (build, load, forward, forward_pixels, backward, backward_subset,
+                   num_threads, problem_arrays)
+from .optim import masked_mse, adamw_step, StepLR
+
+__all__ = ["build", "load", "forward", "forward_pixels", "backward", "backward_subset",
+           "num_threads", "problem_arrays", "masked_mse", "adamw_step", "StepLR"]

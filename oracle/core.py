@@ -1,0 +1,150 @@
+"""ctypes wrapper of the C oracle (``svr_oracle.c``).  Test infrastructure only.
+
+Inputs are the float32 arrays of a :class:`paper_2512_11624_amd.synth.Problem`
+(or any object with the same attributes); they are widened to float64 here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, FP64)."""
+    src = os.path.join(_HERE, "svr_oracle.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_gauss", C.c_int64),
+        ("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p), ("amp", C.c_void_p),
+        ("n_subjects", C.c_int32), ("gauss_offsets", C.c_void_p),
+        ("n_slices", C.c_int32), ("slice_subject", C.c_void_p), ("height", C.c_void_p),
+        ("width", C.c_void_p), ("pix_offset", C.c_void_p),
+        ("rot0", C.c_void_p), ("trans0", C.c_void_p), ("pose", C.c_void_p),
+        ("spacing", C.c_void_p), ("psf_fwhm", C.c_void_p),
+    ]
+
+
+def load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                build(force=False)
+            lib = C.CDLL(_LIB_PATH)
+            P = C.POINTER(_Problem)
+            vp = C.c_void_p
+            lib.ora_forward.argtypes = [P, C.c_double, vp, vp, vp]
+            lib.ora_forward_pixels.argtypes = [P, C.c_double, C.c_int64, vp, vp]
+            lib.ora_backward.argtypes = [P, C.c_double, vp, vp, vp, vp, vp, vp]
+            lib.ora_backward_subset.argtypes = [P, C.c_double, vp, C.c_int64, vp, vp, vp, vp, vp]
+            for f in ("ora_forward", "ora_forward_pixels", "ora_backward", "ora_backward_subset",
+                      "ora_num_threads"):
+                getattr(lib, f).restype = C.c_int
+            _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(load().ora_num_threads())
+
+
+def problem_arrays(prob, params=None, pose=None):
+    """Float64 / int copies of everything the oracle reads."""
+    mean, log_scale, quat, amp = params if params is not None else prob.params()
+    pose = prob.pose if pose is None else pose
+    d = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    height = np.ascontiguousarray(prob.height, np.int32)
+    width = np.ascontiguousarray(prob.width, np.int32)
+    npx = height.astype(np.int64) * width.astype(np.int64)
+    return dict(
+        mean=d(mean), log_scale=d(log_scale), quat=d(quat), amp=d(amp),
+        gauss_offsets=np.ascontiguousarray(prob.gauss_offsets, np.int64),
+        slice_subject=np.ascontiguousarray(prob.slice_subject, np.int32),
+        height=height, width=width,
+        pix_offset=np.concatenate([[0], np.cumsum(npx)]).astype(np.int64),
+        rot0=d(prob.rot0), trans0=d(prob.trans0), pose=d(pose), spacing=d(prob.spacing),
+        psf_fwhm=d(prob.psf_fwhm))
+
+
+def _struct(a):
+    ptr = lambda k: a[k].ctypes.data
+    return _Problem(a["mean"].shape[0], ptr("mean"), ptr("log_scale"), ptr("quat"), ptr("amp"),
+                    a["gauss_offsets"].shape[0] - 1, ptr("gauss_offsets"),
+                    a["height"].shape[0], ptr("slice_subject"), ptr("height"), ptr("width"),
+                    ptr("pix_offset"), ptr("rot0"), ptr("trans0"), ptr("pose"), ptr("spacing"),
+                    ptr("psf_fwhm"))
+
+
+def forward(prob, tau=3.0, params=None, pose=None, counts=False):
+    """Predicted pixels [P] (float64).  tau = inf gives the exact model."""
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    out = np.zeros(int(a["pix_offset"][-1]), np.float64)
+    n_in, n_pairs = C.c_int64(0), C.c_int64(0)
+    rc = load().ora_forward(C.byref(s), float(tau), out.ctypes.data, C.addressof(n_in),
+                            C.addressof(n_pairs))
+    if rc != 0:
+        raise RuntimeError("ora_forward failed")
+    if counts:
+        return out, int(n_in.value), int(n_pairs.value)
+    return out
+
+
+def forward_pixels(prob, pix, tau=3.0, params=None, pose=None):
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    pix = np.ascontiguousarray(pix, np.int64)
+    out = np.zeros(len(pix), np.float64)
+    rc = load().ora_forward_pixels(C.byref(s), float(tau), len(pix), pix.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("ora_forward_pixels failed")
+    return out
+
+
+def backward(prob, grad_pred, tau=3.0, params=None, pose=None):
+    """Gradient of sum(grad_pred * y): dict of mean, log_scale, quat, amp, pose."""
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    n, m = a["mean"].shape[0], a["height"].shape[0]
+    g = np.ascontiguousarray(grad_pred, np.float64)
+    out = dict(mean=np.zeros((n, 3)), log_scale=np.zeros((n, 3)), quat=np.zeros((n, 4)),
+               amp=np.zeros(n), pose=np.zeros((m, 6)))
+    rc = load().ora_backward(C.byref(s), float(tau), g.ctypes.data, out["mean"].ctypes.data,
+                             out["log_scale"].ctypes.data, out["quat"].ctypes.data,
+                             out["amp"].ctypes.data, out["pose"].ctypes.data)
+    if rc != 0:
+        raise RuntimeError("ora_backward failed")
+    return out
+
+
+def backward_subset(prob, grad_pred, gauss_idx, tau=3.0, params=None, pose=None):
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    idx = np.ascontiguousarray(gauss_idx, np.int64)
+    k = len(idx)
+    g = np.ascontiguousarray(grad_pred, np.float64)
+    out = dict(mean=np.zeros((k, 3)), log_scale=np.zeros((k, 3)), quat=np.zeros((k, 4)),
+               amp=np.zeros(k))
+    rc = load().ora_backward_subset(C.byref(s), float(tau), g.ctypes.data, k, idx.ctypes.data,
+                                    out["mean"].ctypes.data, out["log_scale"].ctypes.data,
+                                    out["quat"].ctypes.data, out["amp"].ctypes.data)
+    if rc != 0:
+        raise RuntimeError("ora_backward_subset failed")
+    return out
