@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the hot path on one MI355X.
+
+Workload (default): the fetal-scale head phantom -- 500,000 Gaussians, four
+stacks (axial, coronal, sagittal, oblique) of 32 slices of 256x256 pixels at
+0.8 x 0.8 x 3.5 mm, PSF FWHM (0.8, 0.8, 3.5) mm, per-slice motion ~N(0, 4 deg),
+~N(0, 2 mm).  Observations are the library's own forward of the ground-truth
+Gaussians at the true poses plus Rician noise at SNR 20 (synthetic data; no
+dataset).  One step = svr_project_bin + svr_forward (masked MSE) +
+svr_backward + svr_step (AdamW) from identity pose initialisation, i.e. one
+full fitting iteration; inputs are resident in HBM before timing starts.
+
+value = Gaussian-pixel pairs inside the 3-sigma footprint per step (counted
+by the forward kernel) / seconds per step.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gaussian-pixel pair evals/s fwd+bwd; s to PSNR target learned vs plain"
+PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
+LR = [2.5e-2, 2.5e-2, 1e-2, 1e-2, 2.5e-3, 1e-1]   # mean, scale, quat, amp, rotation, translation
+
+# Algorithmic work per unit ("Roofline accounting").
+FLOP_FWD_PAIR = 13.0      # 12 FLOP + 1 exp per in-cut pixel-Gaussian pair
+FLOP_BWD_PAIR = 32.0      # 31 FLOP + 1 exp per in-cut pair (recomputation included)
+FLOP_CULL_CAND = 25.0     # plane test per (slice, Gaussian) candidate
+FLOP_CULL_REC = 150.0     # projection per kept record
+FLOP_PROJ_BWD_REC = 400.0
+BYTES_SORT_INST_PASS = 20.0   # upsweep key read 4 + downsweep key/value read 8 + write 8
+BYTES_EMIT = (32.0, 8.0)      # per record, per instance
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name, seed=0):
+    from paper_2512_11624_amd import synth
+    if name == "head":
+        prob = synth.config2(seed)
+        desc = ("head phantom, 500k Gaussians, 4 stacks x 32 slices of 256x256 px at 0.8x0.8x3.5 mm, "
+                "motion N(0,4deg)/N(0,2mm), Rician SNR 20")
+    elif name == "head-stress":
+        prob = synth.config3(seed)
+        desc = "head phantom, 1.2M Gaussians, 6 stacks x 40 slices of 320x320 px at 0.7x0.7x3 mm"
+    elif name == "cube":
+        prob = synth.config1(seed)
+        desc = "cube phantom, 2,000 Gaussians, 3 stacks x 16 slices of 32x32 px at 1x1x3 mm"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return prob, desc
+
+
+def stage_roofline(stage, ms, st, n_incut):
+    """(bound, achieved, peak, unit, algorithmic amount per launch) of one stage."""
+    sec = ms / 1e3
+    if stage == "forward_tile":
+        w = FLOP_FWD_PAIR * n_incut
+        return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
+    if stage == "backward_tile":
+        w = FLOP_BWD_PAIR * n_incut
+        return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
+    if stage == "cull_count":
+        w = FLOP_CULL_CAND * st["n_candidates"] + FLOP_CULL_REC * st["n_records"]
+        return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
+    if stage == "project_backward":
+        w = FLOP_PROJ_BWD_REC * st["n_records"]
+        return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
+    if stage == "sort":
+        w = BYTES_SORT_INST_PASS * st["n_instances"] * st["sort_passes"]
+        return "hbm", w / sec / 1e9, PEAK_HBM / 1e9, "GB/s", w
+    if stage == "emit":
+        w = BYTES_EMIT[0] * st["n_records"] + BYTES_EMIT[1] * st["n_instances"]
+        return "hbm", w / sec / 1e9, PEAK_HBM / 1e9, "GB/s", w
+    return None
+
+
+def cpu_baseline(prob, params, pose, target, budget_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    every Gaussian against a subset of slices spread over the stacks."""
+    import oracle
+    from paper_2512_11624_amd import synth
+    oracle.build(force=False)
+
+    def run(sel):
+        po = prob.pix_offset
+        pix = np.concatenate([np.arange(po[i], po[i + 1]) for i in sel])
+        sub = synth.Problem(prob.mean, prob.log_scale, prob.quat, prob.amp, prob.gauss_offsets,
+                            prob.slice_subject[sel], prob.height[sel], prob.width[sel], prob.spacing[sel],
+                            prob.psf_fwhm[sel], prob.rot0[sel], prob.trans0[sel], prob.pose[sel], prob.mask[pix])
+        t0 = time.perf_counter()
+        y, n_in, _ = oracle.forward(sub, 3.0, params=params, pose=pose[sel], counts=True)
+        _, g, _ = oracle.masked_mse(y, target[pix], sub.mask, sub.pix_offset)
+        oracle.backward(sub, g, 3.0, params=params, pose=pose[sel])
+        return time.perf_counter() - t0, n_in
+
+    M = prob.n_slices
+    k = min(4, M)
+    sel = np.linspace(0, M - 1, k).round().astype(int)
+    dt, n_in = run(sel)
+    if dt < budget_s / 3 and k < M:
+        k = int(min(M, max(k + 1, k * budget_s / max(dt, 1e-3))))
+        sel = np.unique(np.linspace(0, M - 1, k).round().astype(int))
+        dt, n_in = run(sel)
+    return dict(value=n_in / dt, unit="pair-evals/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"FP64 oracle fwd+masked-MSE+bwd, all {prob.n_gauss} Gaussians x {len(sel)} of {M} "
+                       f"slices ({n_in} in-cut pairs, {dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="head", choices=["head", "head-stress", "cube"])
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true", help="pick tile/batch/persistent with svr_autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
+              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_11624_amd import svr, synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    prob, desc = make_workload(args.workload)
+    log(f"workload: {desc}; N={prob.n_gauss} M={prob.n_slices} P={prob.n_pixels}")
+
+    ctx = svr.Context(0)
+    ctx.svr_set_config(tile=args.tile, batch=args.batch, persistent=args.persistent, cutoff=3.0)
+    ctx.svr_set_geometry(prob)
+    N, M, P = prob.n_gauss, prob.n_slices, prob.n_pixels
+
+    # observations: forward of the ground truth at the true poses + Rician noise (SNR 20)
+    gt = svr.Params.from_arrays(*prob.params(), prob.pose)
+    ctx.svr_project_bin(*gt.views())
+    clean = torch.empty(P, device=dev)
+    ctx.svr_forward(clean)
+    clean_np = clean.cpu().numpy()
+    mask_np = prob.mask
+    sigma = float(clean_np[mask_np > 0].mean()) / 20.0 if (mask_np > 0).any() else 0.05
+    target_np = synth.rician(clean_np, 1234, sigma)
+    target = torch.as_tensor(target_np, device=dev)
+    mask = torch.as_tensor(mask_np, device=dev)
+    del gt
+
+    # initial iterate: perturbed Gaussians, identity (zero) pose deltas
+    init = synth.perturb_params(prob, 7, d_mu=0.2, d_ls=0.05, d_q=0.05, d_c=0.02)
+    par = svr.Params.from_arrays(*init, np.zeros((M, 6), np.float32))
+    grad = svr.Params(N, M)
+    m_state = torch.zeros_like(par.flat)
+    v_state = torch.zeros_like(par.flat)
+    pred = torch.empty(P, device=dev)
+    gpred = torch.empty(P, device=dev)
+    loss = torch.empty(1, device=dev)
+    sse = torch.empty(M, device=dev)
+    it = [0]
+
+    def step():
+        it[0] += 1
+        ctx.svr_project_bin(*par.views())
+        ctx.svr_forward(pred, target, mask, loss=loss, slice_sse=sse, grad_pred=gpred)
+        ctx.svr_backward(gpred, *grad.views())
+        ctx.svr_step(par.views(), grad.views(), m_state, v_state, LR, it[0])
+
+    tuned = None
+    if args.autotune:
+        ctx.svr_project_bin(*par.views())
+        ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
+        tuned, times = ctx.svr_autotune(*par.views(), gpred, cache_path=os.path.join(ROOT, "gpurun_out", "autotune.txt")
+                                        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+        log(f"autotune: {tuned} ({len(times)} trials, best {min(times):.3f} ms)")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # in-cut pair count at the current iterate (the algorithmic work of a step)
+    ctx.svr_project_bin(*par.views())
+    ctx.svr_set_count_pairs(True)
+    ctx.svr_forward(pred)
+    st = ctx.svr_get_stats(sync=True)
+    ctx.svr_set_count_pairs(False)
+    n_incut = int(st["n_incut"])
+    log(f"stats: {st}")
+
+    ctx.svr_set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = ctx.svr_get_timing()
+    ctx.svr_set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n_incut / (ms_per_step / 1e3)
+    final_loss = float(loss.item())
+    log(f"{ms_per_step:.3f} ms/step, {value:.4g} pair-evals/s, loss {final_loss:.5g}")
+
+    stages = {k: dict(calls=c, avg_ms=(t / c if c else 0.0)) for k, (c, t) in timing.items() if c}
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"]):
+        log(f"  {k:18s} {v['calls']:5d} calls  {v['avg_ms']:.4f} ms avg")
+    per_step = {k: v["avg_ms"] * v["calls"] / args.steps for k, v in stages.items()}
+    dominant = max(per_step, key=per_step.get)
+    rl = stage_roofline(dominant, stages[dominant]["avg_ms"], st, n_incut)
+    roofline = None
+    if rl:
+        bound, achieved, peak, unit, work = rl
+        roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
+                        frac=round(achieved / peak, 6), traffic=None, kernel=dominant,
+                        avg_ms=round(stages[dominant]["avg_ms"], 5), work_per_launch=work)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(prob, init, np.zeros((M, 6), np.float32), target_np)
+            log(f"cpu baseline: {cpu}")
+        except Exception as e:  # reported, never silently replaced
+            cpu = dict(error=str(e))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "gaussians": N, "slices": M, "pixels": P,
+                   "tile": ctx.svr_get_config()["tile"], "batch": ctx.svr_get_config()["batch"],
+                   "persistent": ctx.svr_get_config()["persistent"], "cutoff_sigma": 3.0,
+                   "step": "project_bin+forward(masked MSE)+backward+AdamW", "autotuned": tuned is not None},
+        "pairs": {"in_cut_per_step": n_incut, "records": st["n_records"], "instances": st["n_instances"],
+                  "candidates": st["n_candidates"], "evaluated_upper_bound": st["n_evaluated"]},
+        "stages_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
+        "final_loss": final_loss,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

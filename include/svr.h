@@ -1,0 +1,271 @@
+/* svr.h -- C ABI of libsvr, the MI355X (gfx950) hot path of Gaussian-primitive
+ * slice-to-volume reconstruction.
+ *
+ * The model (paper Sec. 2.1 Eq. 1, Sec. 2.3 Eqs. 3-5).  The high-resolution
+ * volume is a field of N anisotropic Gaussians (Sec. 2.2): mean mu_j, scale
+ * s_j = exp(log_scale_j), rotation from the quaternion q_j = (w,x,y,z)
+ * (normalised on use), Sigma_j = R_j diag(s_j^2) R_j^T, amplitude c_j.  Slice i
+ * has a nominal rotation R0_i (columns: slice x axis, slice y axis, normal) and
+ * centre t0_i, a rigid 6-DoF pose delta (omega_i [rad], tau_i [mm]) with
+ * R_i = Exp(omega_i) R0_i and t_i = t0_i + tau_i, pixel spacing (dx, dy), and a
+ * Gaussian PSF with per-axis FWHM f (sigma = f / 2.355) in the slice frame.
+ * Pixel (row r, column k) sits at u = ((k-(W-1)/2) dx, (r-(H-1)/2) dy, 0) in the
+ * slice frame and at x = R_i u + t_i in the world.  The predicted pixel is
+ *
+ *   y = sum_j c_j sqrt(det Sigma_j / det Sigma_obs) max(exp(-q/2) - exp(-T^2/2), 0),
+ *   Sigma_obs = Sigma_j + R_i Sigma_PSF R_i^T  (Eq. 4),  q = d^T Sigma_obs^-1 d,
+ *   d = x - mu_j,
+ *
+ * over the Gaussians of the slice's subject, where T is the footprint cutoff
+ * in standard deviations (3 by default): pairs beyond the T-sigma footprint
+ * contribute nothing and the window is continuous at the cut.  The fitting
+ * loss is the masked mean squared error L = sum m (y - I)^2 / sum m.
+ *
+ * Conventions for every call:
+ *   - Every call returns an svr_status; nothing throws across the ABI.  On an
+ *     error svr_last_error(ctx) describes it; outputs are then unspecified.
+ *   - Pointers documented as DEVICE are device memory on the context's GPU,
+ *     float32 (or the stated integer type), contiguous, 4-byte aligned, owned
+ *     by the caller and never freed by the library.  HOST pointers are read
+ *     during the call only.
+ *   - All device work is enqueued asynchronously on the context's stream.
+ *     svr_project_bin is the one call that synchronises that stream (it reads
+ *     the record and instance counts back); svr_get_stats with
+ *     SVR_STATS_SYNC also does.
+ *   - Argument checks run on the host before any launch.
+ *   - A context is not thread safe; use one context per host thread.
+ */
+#ifndef SVR_H
+#define SVR_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SVR_ABI_VERSION 1
+
+typedef enum {
+    SVR_OK = 0,
+    SVR_ERR_ARG = -1,       /* invalid argument (null, size, range) */
+    SVR_ERR_HIP = -2,       /* HIP runtime error or no usable GPU */
+    SVR_ERR_CAPACITY = -3,  /* a count exceeds a representable or configured limit */
+    SVR_ERR_STATE = -4,     /* calls out of order (e.g. forward before project_bin) */
+    SVR_ERR_NODEVICE = -5   /* compute call on a host-only context */
+} svr_status;
+
+typedef struct svr_ctx svr_ctx;
+
+/* Library ABI version (SVR_ABI_VERSION). */
+int svr_abi_version(void);
+
+/* Human-readable name of a status code; never NULL. */
+const char* svr_status_string(int status);
+
+/* Create a context on GPU `device` that enqueues work on `hip_stream` (a
+ * hipStream_t; NULL = the legacy default stream).  device = -1 creates a
+ * host-only context that validates arguments and geometry but makes no HIP
+ * call (compute calls then return SVR_ERR_NODEVICE).  Returns SVR_ERR_HIP if
+ * the device cannot be used.  *out is NULL on failure. */
+int svr_ctx_create(svr_ctx** out, int device, void* hip_stream);
+
+/* Free the context and all device scratch it owns.  NULL is accepted. */
+int svr_ctx_destroy(svr_ctx* ctx);
+
+/* Change the stream subsequent calls enqueue on. */
+int svr_set_stream(svr_ctx* ctx, void* hip_stream);
+
+/* Message of the last failing call on this context ("" if none). */
+const char* svr_last_error(const svr_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Acquisition geometry (Sec. 2.1, 2.3).  HOST arrays, copied into the
+ * context; fixed until the next svr_set_geometry.  Subjects are independent
+ * reconstructions batched together: subject s owns Gaussians
+ * [gauss_offsets[s], gauss_offsets[s+1]) and the slices with slice_subject
+ * == s, which must be contiguous and in nondecreasing subject order.  Pixels
+ * of slice i are row-major and follow slice i-1 directly; the pixel offset of
+ * slice i is sum_{k<i} height[k]*width[k].
+ * Errors: SVR_ERR_ARG for null arrays, nonpositive sizes, unsorted subjects,
+ * negative spacing/FWHM, non-monotone Gaussian offsets; SVR_ERR_CAPACITY when
+ * the total pixel or tile count exceeds 2^31-1 or a subject has more than
+ * 4096 slices. */
+typedef struct {
+    int32_t n_subjects;
+    const int64_t* gauss_offsets;  /* [n_subjects+1], gauss_offsets[0] = 0 */
+    int32_t n_slices;
+    const int32_t* slice_subject;  /* [M] */
+    const int32_t* height;         /* [M] rows, >= 1 */
+    const int32_t* width;          /* [M] columns, >= 1 */
+    const float* spacing;          /* [M,2] dx (between columns), dy (between rows), mm, > 0 */
+    const float* psf_fwhm;         /* [M,3] slice-frame FWHM, mm, >= 0 */
+    const float* rot0;             /* [M,9] row-major nominal rotation */
+    const float* trans0;           /* [M,3] nominal slice centre, mm */
+} svr_geometry;
+
+int svr_set_geometry(svr_ctx* ctx, const svr_geometry* geom);
+
+/* Total pixel count P of the current geometry (0 if none). */
+int64_t svr_num_pixels(const svr_ctx* ctx);
+
+/* Kernel configuration of the tile stages.  tile: 8, 16 or 32 (pixels per
+ * tile side); batch: Gaussian records staged in LDS per step, 32..256 and a
+ * multiple of 32; persistent: 0 = one workgroup per tile, 1 = a persistent
+ * grid that pulls tiles from a work queue ordered by decreasing instance
+ * count; cutoff: footprint radius T in standard deviations, (0, 8].
+ * Changing tile or cutoff invalidates the last svr_project_bin. */
+typedef struct {
+    int32_t tile;
+    int32_t batch;
+    int32_t persistent;
+    float cutoff;
+} svr_config;
+
+int svr_set_config(svr_ctx* ctx, const svr_config* cfg);
+int svr_get_config(const svr_ctx* ctx, svr_config* cfg);
+
+/* ------------------------------------------------------------------------ */
+/* Parameters: DEVICE pointers, float32.
+ *   mean [N,3], log_scale [N,3], quat [N,4] (w,x,y,z, nonzero), amp [N],
+ *   pose [M,6] = (omega_x, omega_y, omega_z [rad], tau_x, tau_y, tau_z [mm]). */
+typedef struct {
+    const float* mean;
+    const float* log_scale;
+    const float* quat;
+    const float* amp;
+    const float* pose;
+} svr_params;
+
+/* Gradients: DEVICE pointers with the shapes of svr_params, overwritten. */
+typedef struct {
+    float* mean;
+    float* log_scale;
+    float* quat;
+    float* amp;
+    float* pose;
+} svr_grads;
+
+/* Cull, project and bin (Sec. 2.3 Eq. 4 evaluated per slice and Gaussian;
+ * replaces the paper's Top-K neighbour search of Sec. 2.5).
+ * For every slice i and Gaussian j of the same subject, keeps the pair when
+ * the slice plane crosses j's T-sigma footprint (minimum of q over the plane
+ * <= T^2), writes one record (in-plane centre, in-plane conic, amplitude,
+ * through-plane term) and one instance per overlapped pixel tile, then sorts
+ * the instances by (slice, tile) with a stable LDS radix sort and builds
+ * per-tile ranges.  The records stay valid until the next call; svr_forward
+ * and svr_backward use them and assume the parameters have not changed.
+ * Synchronises the stream once to read the counts.  Errors: SVR_ERR_STATE
+ * without geometry, SVR_ERR_ARG for null pointers or N different from the
+ * geometry's Gaussian count, SVR_ERR_CAPACITY above 2^31-1 records or
+ * instances. */
+int svr_project_bin(svr_ctx* ctx, const svr_params* params);
+
+/* Forward model and masked-MSE loss (Eq. 5 with the exact amplitude; the
+ * masked MSE replaces Eq. 7's L1 term).  pred [P] DEVICE is overwritten with
+ * the predicted pixels.  When target [P] and mask [P] (DEVICE, mask in {0,1})
+ * are given, the optional outputs are written: loss [1] = sum m (y-I)^2 /
+ * sum m, slice_sse [M] = per-slice sum m (y-I)^2, grad_pred [P] = dL/dy =
+ * 2 m (y - I) / sum m.  Any of them may be NULL.  A mask summing to zero
+ * gives loss 0 and grad 0.  Errors: SVR_ERR_STATE before svr_project_bin,
+ * SVR_ERR_ARG for a requested output without target and mask. */
+int svr_forward(svr_ctx* ctx, const float* target, const float* mask, float* pred,
+                float* loss, float* slice_sse, float* grad_pred);
+
+/* Adjoint of svr_forward: with g = grad_pred [P] (DEVICE) scaled by
+ * *grad_scale (DEVICE float [1], NULL = 1), writes the gradient of
+ * sum_p g_p y_p with respect to every parameter of the last svr_project_bin
+ * (Gaussian mean, log_scale, quaternion, amplitude and slice poses; the pose
+ * gradient is with respect to (omega, tau) through the left Jacobian of
+ * SO(3)).  Pixel-Gaussian terms are recomputed per tile, no per-pair state is
+ * kept.  Errors: SVR_ERR_STATE before svr_project_bin, SVR_ERR_ARG for null
+ * pointers. */
+int svr_backward(svr_ctx* ctx, const float* grad_pred, const float* grad_scale,
+                 const svr_grads* out);
+
+/* AdamW (App. A.1).  lr[6] = learning rates of the groups mean, log_scale,
+ * quat, amp, pose rotation omega, pose translation tau.  Updates params,
+ * exp_avg and exp_avg_sq in place; step counts from 1 (bias correction).
+ * exp_avg / exp_avg_sq are DEVICE float32 [N*11 + M*6], laid out as
+ * mean (3N), log_scale (3N), quat (4N), amp (N), pose (6M).  Follows
+ * torch.optim.AdamW: p *= 1 - lr*wd; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr/(1-b1^t) * m / (sqrt(v)/sqrt(1-b2^t) + eps).
+ * Errors: SVR_ERR_ARG for null pointers, step < 1, betas outside [0,1). */
+typedef struct {
+    float lr[6];
+    double beta1, beta2, eps, weight_decay;  /* double so that 1 - beta is exact on the host */
+} svr_adam;
+
+int svr_step(svr_ctx* ctx, const svr_grads* params_inout, const svr_grads* grads,
+             float* exp_avg, float* exp_avg_sq, const svr_adam* hp, int64_t step);
+
+/* Counters of the last svr_project_bin / svr_forward.  Record and instance
+ * counts are exact after svr_project_bin.  n_incut (pairs inside the cutoff,
+ * i.e. Gaussian-pixel terms that contribute) is counted by svr_forward only
+ * when flags has SVR_STATS_SYNC set at the *next* svr_get_stats call after a
+ * forward run with counting enabled via svr_set_count_pairs(ctx, 1); the
+ * call then synchronises the stream. */
+typedef struct {
+    int64_t n_gauss;
+    int64_t n_slices;
+    int64_t n_pixels;
+    int64_t n_tiles;
+    int64_t n_candidates;   /* (slice, Gaussian) pairs tested */
+    int64_t n_records;      /* pairs kept (plane crosses the footprint, bbox non-empty) */
+    int64_t n_instances;    /* (tile, record) pairs */
+    int64_t n_incut;        /* (pixel, Gaussian) pairs with q < T^2; -1 if not counted */
+    int64_t n_evaluated;    /* pixel-record evaluations the forward tile kernel performs */
+    int32_t key_bits;       /* bits of the sort key */
+    int32_t sort_passes;
+} svr_stats;
+
+#define SVR_STATS_SYNC 1
+int svr_set_count_pairs(svr_ctx* ctx, int enable);
+int svr_get_stats(svr_ctx* ctx, int flags, svr_stats* out);
+
+/* Stable radix sort used by tile binning, exposed for verification: sorts the
+ * n (key, value) pairs in place by the low key_bits bits of the key (1..32),
+ * keeping the input order of equal keys.  keys/vals are DEVICE uint32 [n];
+ * scratch is owned by the context.  Keys with bits set above key_bits give
+ * an unspecified order.  Errors: SVR_ERR_ARG for null pointers with n > 0,
+ * n < 0 or key_bits outside 1..32. */
+int svr_sort_pairs(svr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits);
+
+/* Per-stage GPU timing.  When enabled, every stage the library launches is
+ * bracketed by HIP events on the context stream; svr_get_timing synchronises
+ * the stream, folds the completed intervals into per-stage totals and copies
+ * up to max_out entries (HOST array) in a fixed stage order, setting *n_out.
+ * Stage names: slice_pose, cull_count, scan, emit, sort, tile_ranges,
+ * tile_order, mask_sum, forward_tile, loss_reduce, zero_fill, backward_tile,
+ * project_backward, pose_chain, adam.  Enabling or disabling clears the
+ * totals. */
+typedef struct {
+    char name[32];
+    int64_t calls;
+    double total_ms;
+} svr_timer;
+
+int svr_set_timing(svr_ctx* ctx, int enable);
+int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuner (batched launch).  Times the forward and backward tile kernels
+ * on the current bins for every tile size in {8,16,32}, LDS batch in
+ * {32,64,128,256} and persistent in {0,1} (those allowed by flags), picks the
+ * fastest and makes it the context's configuration (re-binning when the tile
+ * size changes).  params/grad_pred as in svr_project_bin / svr_backward
+ * (grad_pred may be any DEVICE buffer of P floats).  Results are cached in the
+ * context per shape bucket (pixels, records, instances rounded to powers of
+ * two) and, when cache_path is non-NULL, in a small text file there.
+ * out receives the chosen configuration; times_ms (HOST, may be NULL)
+ * receives up to max_times measured (forward + backward) times in trial
+ * order.  Synchronises the stream. */
+#define SVR_TUNE_TILE 1
+#define SVR_TUNE_BATCH 2
+#define SVR_TUNE_PERSISTENT 4
+#define SVR_TUNE_ALL 7
+int svr_autotune(svr_ctx* ctx, const svr_params* params, const float* grad_pred, int flags,
+                 const char* cache_path, svr_config* out, float* times_ms, int max_times);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

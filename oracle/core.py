@@ -54,8 +54,10 @@ def load():
             lib.ora_forward_pixels.argtypes = [P, C.c_double, C.c_int64, vp, vp]
             lib.ora_backward.argtypes = [P, C.c_double, vp, vp, vp, vp, vp, vp]
             lib.ora_backward_subset.argtypes = [P, C.c_double, vp, C.c_int64, vp, vp, vp, vp, vp]
+            lib.ora_backward_band.argtypes = [P, C.c_double, C.c_double, vp] + [vp] * 10
+            lib.ora_forward_band.argtypes = [P, C.c_double, C.c_double, vp, vp]
             for f in ("ora_forward", "ora_forward_pixels", "ora_backward", "ora_backward_subset",
-                      "ora_num_threads"):
+                      "ora_backward_band", "ora_forward_band", "ora_num_threads"):
                 getattr(lib, f).restype = C.c_int
             _lib = lib
     return _lib
@@ -148,3 +150,32 @@ def backward_subset(prob, grad_pred, gauss_idx, tau=3.0, params=None, pose=None)
     if rc != 0:
         raise RuntimeError("ora_backward_subset failed")
     return out
+
+
+def backward_band(prob, grad_pred, tau=3.0, band=1e-3, params=None, pose=None):
+    """(gradient without the pairs within band*tau^2 of the cut, bound of their
+    absolute contributions), as two dicts keyed like :func:`backward`."""
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    n, m = a["mean"].shape[0], a["height"].shape[0]
+    g = np.ascontiguousarray(grad_pred, np.float64)
+    mk = lambda: dict(mean=np.zeros((n, 3)), log_scale=np.zeros((n, 3)), quat=np.zeros((n, 4)),
+                      amp=np.zeros(n), pose=np.zeros((m, 6)))
+    out, bnd = mk(), mk()
+    keys = ("mean", "log_scale", "quat", "amp", "pose")
+    rc = load().ora_backward_band(C.byref(s), float(tau), float(band), g.ctypes.data,
+                                  *[out[k].ctypes.data for k in keys], *[bnd[k].ctypes.data for k in keys])
+    if rc != 0:
+        raise RuntimeError("ora_backward_band failed")
+    return out, bnd
+
+
+def forward_band(prob, tau=3.0, band=1e-3, params=None, pose=None):
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    P = int(a["pix_offset"][-1])
+    core, bnd = np.zeros(P), np.zeros(P)
+    rc = load().ora_forward_band(C.byref(s), float(tau), float(band), core.ctypes.data, bnd.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("ora_forward_band failed")
+    return core, bnd

@@ -359,11 +359,72 @@ int ora_forward_pixels(const ora_problem* p, double tau, int64_t n_sel, const in
     return 0;
 }
 
+/* Chain dLoss/dSigma_j (G, full symmetric matrix) and the direct sqrt(det)
+ * term (wv) to the log-scales and the stored quaternion. */
+static void chain_gauss(const ora_gauss* g, const double* Gsum, double wv_sum, double* gls_out,
+                        double* gq_out) {
+    /* Sigma_j = R diag(s^2) R^T */
+    double Rt[9], RtG[9], RtGR[9];
+    mat3_transpose(g->R, Rt);
+    mat3_mul(Rt, Gsum, RtG);
+    mat3_mul(RtG, g->R, RtGR);
+    for (int k = 0; k < 3; ++k) gls_out[k] = wv_sum + 2.0 * g->s2[k] * RtGR[4 * k];
+    double GR[9], dR[9];
+    mat3_mul(Gsum, g->R, GR);
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dR[3 * a + b] = 2.0 * GR[3 * a + b] * g->s2[b];
+    double w = g->qn[0], x = g->qn[1], y = g->qn[2], z = g->qn[3];
+    const double dRw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
+    const double dRx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+    const double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
+    const double dRz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
+    double gqn[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 9; ++k) {
+        gqn[0] += dR[k] * dRw[k];
+        gqn[1] += dR[k] * dRx[k];
+        gqn[2] += dR[k] * dRy[k];
+        gqn[3] += dR[k] * dRz[k];
+    }
+    double dotp = gqn[0] * g->qn[0] + gqn[1] * g->qn[1] + gqn[2] * g->qn[2] + gqn[3] * g->qn[3];
+    for (int k = 0; k < 4; ++k) gq_out[k] = (gqn[k] - g->qn[k] * dotp) / g->qlen;
+}
+
+/* Absolute contributions of one (pixel, Gaussian) pair to every gradient
+ * component, added to bnd = [mean 3 | log_scale 3 | quat 4 | amp 1 | per-slice
+ * pose 6*M] (pose rows start at offset 11).  Used for pairs whose inside/outside
+ * decision lies within rounding of the cut. */
+static void band_pair(const ora_gauss* g, const ora_slice* s, double gp, double c, double rho,
+                      const double* L, const double* Ld, const double* Ru, double q, double etau,
+                      double* bnd, int32_t slice) {
+    double e = exp(-0.5 * q);
+    double we = gp * c * rho * e;
+    double wv = gp * c * rho * (e - etau);
+    double Gp[9], gls[3], gq[4], A[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Gp[3 * a + b] = 0.5 * we * Ld[a] * Ld[b] - 0.5 * wv * L[3 * a + b];
+    chain_gauss(g, Gp, wv, gls, gq);
+    double dx[3] = {-we * Ld[0], -we * Ld[1], -we * Ld[2]};
+    mat3_mul(s->P, Gp, A);
+    double pd[3] = {Ru[1] * dx[2] - Ru[2] * dx[1] + 2.0 * (A[5] - A[7]),
+                    Ru[2] * dx[0] - Ru[0] * dx[2] + 2.0 * (A[6] - A[2]),
+                    Ru[0] * dx[1] - Ru[1] * dx[0] + 2.0 * (A[1] - A[3])};
+    for (int a = 0; a < 3; ++a) bnd[a] += fabs(we * Ld[a]);
+    for (int a = 0; a < 3; ++a) bnd[3 + a] += fabs(gls[a]);
+    for (int a = 0; a < 4; ++a) bnd[6 + a] += fabs(gq[a]);
+    bnd[10] += fabs(gp * rho * (e - etau));
+    /* pose: |d delta| in the left-perturbation frame and |d tau| */
+    for (int a = 0; a < 3; ++a) {
+        bnd[11 + 6 * slice + a] += fabs(pd[a]);
+        bnd[11 + 6 * slice + 3 + a] += fabs(dx[a]);
+    }
+}
+
 /* Per-Gaussian gradient over all its slices; pose contributions are added to
  * gpose_delta/gpose_tau ([M,3] each) when non-NULL. */
 static void gauss_backward(const ora_problem* p, const ora_gauss* G, const ora_slice* S, int64_t j,
                            double tau, const double* grad_pred, double* gmu_out, double* gls_out,
-                           double* gq_out, double* gc_out, double* gdelta, double* gtau) {
+                           double* gq_out, double* gc_out, double* gdelta, double* gtau,
+                           double band, double* bnd) {
     const int fin = is_finite_tau(tau);
     const double etau = fin ? exp(-0.5 * tau * tau) : 0.0;
     const double tau2 = fin ? tau * tau : INFINITY;
@@ -378,7 +439,7 @@ static void gauss_backward(const ora_problem* p, const ora_gauss* G, const ora_s
         if (p->slice_subject[i] != sub) continue;
         const ora_slice* s = &S[i];
         ora_pair pr;
-        setup_pair(g, mu, s, tau, &pr);
+        setup_pair(g, mu, s, bnd ? tau * sqrt(1.0 + band) : tau, &pr);
         if (!pr.keep) continue;
         double Gij[9] = {0}, ptau[3] = {0}, pdel[3] = {0};
         for (int r = pr.r0; r <= pr.r1; ++r)
@@ -389,6 +450,10 @@ static void gauss_backward(const ora_problem* p, const ora_gauss* G, const ora_s
                 pixel_world(s, r, k, x, Ru);
                 for (int a = 0; a < 3; ++a) d[a] = x[a] - mu[a];
                 double q = quad(pr.L, d, Ld);
+                if (bnd && fabs(q - tau2) <= band * tau2) {
+                    band_pair(g, s, gp, c, pr.rho, pr.L, Ld, Ru, q, etau, bnd, i);
+                    continue;
+                }
                 if (q > tau2) continue;
                 double e = exp(-0.5 * q);
                 double we = gp * c * pr.rho * e;
@@ -421,30 +486,7 @@ static void gauss_backward(const ora_problem* p, const ora_gauss* G, const ora_s
             }
         }
     }
-    /* Sigma_j = R diag(s^2) R^T */
-    double Rt[9], RtG[9], RtGR[9];
-    mat3_transpose(g->R, Rt);
-    mat3_mul(Rt, Gsum, RtG);
-    mat3_mul(RtG, g->R, RtGR);
-    for (int k = 0; k < 3; ++k) gls_out[k] = wv_sum + 2.0 * g->s2[k] * RtGR[4 * k];
-    double GR[9], dR[9];
-    mat3_mul(Gsum, g->R, GR);
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) dR[3 * a + b] = 2.0 * GR[3 * a + b] * g->s2[b];
-    double w = g->qn[0], x = g->qn[1], y = g->qn[2], z = g->qn[3];
-    const double dRw[9] = {0, -2 * z, 2 * y, 2 * z, 0, -2 * x, -2 * y, 2 * x, 0};
-    const double dRx[9] = {0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
-    const double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0, 2 * z, -2 * w, 2 * z, -4 * y};
-    const double dRz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0};
-    double gqn[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 9; ++k) {
-        gqn[0] += dR[k] * dRw[k];
-        gqn[1] += dR[k] * dRx[k];
-        gqn[2] += dR[k] * dRy[k];
-        gqn[3] += dR[k] * dRz[k];
-    }
-    double dotp = gqn[0] * g->qn[0] + gqn[1] * g->qn[1] + gqn[2] * g->qn[2] + gqn[3] * g->qn[3];
-    for (int k = 0; k < 4; ++k) gq_out[k] = (gqn[k] - g->qn[k] * dotp) / g->qlen;
+    chain_gauss(g, Gsum, wv_sum, gls_out, gq_out);
     for (int a = 0; a < 3; ++a) gmu_out[a] = gmu[a];
     *gc_out = gc;
 }
@@ -464,7 +506,7 @@ int ora_backward(const ora_problem* p, double tau, const double* grad_pred, doub
 #pragma omp for schedule(dynamic, 16)
         for (int64_t j = 0; j < p->n_gauss; ++j)
             gauss_backward(p, G, S, j, tau, grad_pred, g_mean + 3 * j, g_log_scale + 3 * j,
-                           g_quat + 4 * j, g_amp + j, gdel, gtau);
+                           g_quat + 4 * j, g_amp + j, gdel, gtau, 0.0, NULL);
 #pragma omp critical
         for (size_t k = 0; k < (size_t)M * 6; ++k) dsum[k] += dloc[k];
         free(dloc);
@@ -492,7 +534,102 @@ int ora_backward_subset(const ora_problem* p, double tau, const double* grad_pre
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t e = 0; e < n_sel; ++e)
         gauss_backward(p, G, S, gauss_idx[e], tau, grad_pred, g_mean + 3 * e, g_log_scale + 3 * e,
-                       g_quat + 4 * e, g_amp + e, NULL, NULL);
+                       g_quat + 4 * e, g_amp + e, NULL, NULL, 0.0, NULL);
+    free(G);
+    free(S);
+    return 0;
+}
+
+/* Band-split gradient: pairs with |q - tau^2| <= band * tau^2 are left out of
+ * the gradient and their absolute contributions are summed into b_* instead
+ * (b_pose in the (omega, tau) parameterisation, bounded through |J_l^T|).  Any
+ * gradient that decides those pairs either way lies within g +- b. */
+int ora_backward_band(const ora_problem* p, double tau, double band, const double* grad_pred,
+                      double* g_mean, double* g_log_scale, double* g_quat, double* g_amp,
+                      double* g_pose, double* b_mean, double* b_log_scale, double* b_quat,
+                      double* b_amp, double* b_pose) {
+    ora_gauss* G = make_gauss(p);
+    ora_slice* S = make_slices(p);
+    int32_t M = p->n_slices;
+    size_t nb = 11 + 6 * (size_t)M;
+    double* dsum = (double*)calloc((size_t)M * 6 + 6, sizeof(double));
+    double* bpose = (double*)calloc((size_t)M * 6 + 6, sizeof(double));
+    if (!G || !S || !dsum || !bpose) { free(G); free(S); free(dsum); free(bpose); return -1; }
+#pragma omp parallel
+    {
+        double* dloc = (double*)calloc((size_t)M * 6 + 6, sizeof(double));
+        double* bloc = (double*)calloc(nb, sizeof(double));
+        double* bpl = (double*)calloc((size_t)M * 6 + 6, sizeof(double));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t j = 0; j < p->n_gauss; ++j) {
+            memset(bloc, 0, 11 * sizeof(double));
+            gauss_backward(p, G, S, j, tau, grad_pred, g_mean + 3 * j, g_log_scale + 3 * j,
+                           g_quat + 4 * j, g_amp + j, dloc, dloc + 3 * (size_t)M, band, bloc);
+            for (int a = 0; a < 3; ++a) { b_mean[3 * j + a] = bloc[a]; b_log_scale[3 * j + a] = bloc[3 + a]; }
+            for (int a = 0; a < 4; ++a) b_quat[4 * j + a] = bloc[6 + a];
+            b_amp[j] = bloc[10];
+            for (size_t k = 0; k < (size_t)M * 6; ++k) { bpl[k] += bloc[11 + k]; bloc[11 + k] = 0.0; }
+        }
+#pragma omp critical
+        {
+            for (size_t k = 0; k < (size_t)M * 6; ++k) { dsum[k] += dloc[k]; bpose[k] += bpl[k]; }
+        }
+        free(dloc);
+        free(bloc);
+        free(bpl);
+    }
+    for (int32_t i = 0; i < M; ++i) {
+        double J[9];
+        so3_left_jacobian(p->pose + 6 * i, J);
+        const double* dd = dsum + 3 * i;
+        for (int a = 0; a < 3; ++a)
+            g_pose[6 * i + a] = J[a] * dd[0] + J[3 + a] * dd[1] + J[6 + a] * dd[2];
+        for (int a = 0; a < 3; ++a) g_pose[6 * i + 3 + a] = dsum[3 * (size_t)M + 3 * i + a];
+        const double* bd = bpose + 6 * (size_t)i;
+        for (int a = 0; a < 3; ++a)
+            b_pose[6 * i + a] = fabs(J[a]) * bd[0] + fabs(J[3 + a]) * bd[1] + fabs(J[6 + a]) * bd[2];
+        for (int a = 0; a < 3; ++a) b_pose[6 * i + 3 + a] = bd[3 + a];
+    }
+    free(dsum);
+    free(bpose);
+    free(G);
+    free(S);
+    return 0;
+}
+
+/* Band-split forward: pred_core excludes pairs with |q - tau^2| <= band * tau^2,
+ * b_pred sums their |value|. */
+int ora_forward_band(const ora_problem* p, double tau, double band, double* pred_core, double* b_pred) {
+    ora_gauss* G = make_gauss(p);
+    ora_slice* S = make_slices(p);
+    if (!G || !S) { free(G); free(S); return -1; }
+    const double etau = exp(-0.5 * tau * tau);
+    const double tau2 = tau * tau;
+    memset(pred_core, 0, sizeof(double) * (size_t)p->pix_offset[p->n_slices]);
+    memset(b_pred, 0, sizeof(double) * (size_t)p->pix_offset[p->n_slices]);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t i = 0; i < p->n_slices; ++i) {
+        const ora_slice* s = &S[i];
+        int32_t sub = p->slice_subject[i];
+        for (int64_t j = p->gauss_offsets[sub]; j < p->gauss_offsets[sub + 1]; ++j) {
+            const double* mu = p->mean + 3 * j;
+            ora_pair pr;
+            setup_pair(&G[j], mu, s, tau * sqrt(1.0 + band), &pr);
+            if (!pr.keep) continue;
+            double cr = p->amp[j] * pr.rho;
+            for (int r = pr.r0; r <= pr.r1; ++r)
+                for (int k = pr.k0; k <= pr.k1; ++k) {
+                    double x[3], Ru[3], d[3], Ld[3];
+                    pixel_world(s, r, k, x, Ru);
+                    for (int a = 0; a < 3; ++a) d[a] = x[a] - mu[a];
+                    double q = quad(pr.L, d, Ld);
+                    int64_t pix = s->off + (int64_t)r * s->W + k;
+                    double v = cr * (exp(-0.5 * q) - etau);
+                    if (fabs(q - tau2) <= band * tau2) b_pred[pix] += fabs(v);
+                    else if (q < tau2) pred_core[pix] += v;
+                }
+        }
+    }
     free(G);
     free(S);
     return 0;

@@ -69,6 +69,17 @@ int ora_backward_subset(const ora_problem* p, double tau, const double* grad_pre
                         double* g_mean, double* g_log_scale, double* g_quat,
                         double* g_amp);
 
+/* Band-split variants: pairs whose q lies within band * tau^2 of the cut are
+ * excluded from the result and their absolute contributions are reported
+ * separately, component by component.  Any evaluation that decides those
+ * pairs either way (e.g. in lower precision) lies within result +- bound. */
+int ora_backward_band(const ora_problem* p, double tau, double band, const double* grad_pred,
+                      double* g_mean, double* g_log_scale, double* g_quat, double* g_amp,
+                      double* g_pose, double* b_mean, double* b_log_scale, double* b_quat,
+                      double* b_amp, double* b_pose);
+int ora_forward_band(const ora_problem* p, double tau, double band, double* pred_core,
+                     double* b_pred);
+
 int ora_num_threads(void);
 
 #ifdef __cplusplus

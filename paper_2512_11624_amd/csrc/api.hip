@@ -1,0 +1,981 @@
+// C ABI of libsvr: context, geometry, and the project_bin / forward /
+// backward / step pipeline.  See include/svr.h for the contract.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "svr.h"
+#include "svr_internal.h"
+
+namespace svr {
+hipError_t launch_scan_int(const int* in, int* out, int64_t n, long long* totals, void* tmp,
+                           hipStream_t st);
+hipError_t launch_tile_cost_keys(const int2* ranges, int32_t n_tiles, uint32_t* keys, uint32_t* vals,
+                                 hipStream_t st);
+}  // namespace svr
+
+using namespace svr;
+
+namespace {
+enum Stage {
+    ST_SLICE_POSE, ST_CULL_COUNT, ST_SCAN, ST_EMIT, ST_SORT, ST_TILE_RANGES, ST_TILE_ORDER, ST_MASK_SUM,
+    ST_FORWARD, ST_LOSS, ST_ZERO, ST_BACKWARD, ST_PROJECT_BACKWARD, ST_POSE_CHAIN, ST_ADAM, ST_COUNT
+};
+const char* const kStageNames[ST_COUNT] = {
+    "slice_pose", "cull_count", "scan", "emit", "sort", "tile_ranges", "tile_order", "mask_sum",
+    "forward_tile", "loss_reduce", "zero_fill", "backward_tile", "project_backward", "pose_chain", "adam"};
+
+constexpr int kGaussBlock = 256;
+constexpr int kMaxSubjectSlices = 4096;
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t cap = 0;  // elements
+};
+}  // namespace
+
+struct svr_ctx {
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int n_cu = 256;
+
+    // geometry (host)
+    bool has_geom = false;
+    int32_t n_subjects = 0, M = 0;
+    int64_t N = 0, P = 0;
+    std::vector<int64_t> gauss_off;
+    std::vector<int32_t> slice_subject, H, W;
+    std::vector<float> spacing, fwhm, rot0, trans0;
+    std::vector<int64_t> pix_off;
+    int32_t max_subject_slices = 0;
+
+    svr_config cfg{16, 128, 0, 3.0f};
+
+    // tile tables (host)
+    int32_t n_tiles = 0, key_bits = 1;
+    int32_t n_blocks = 0;
+
+    // device tables
+    DevBuf<SliceGeo> d_geo;
+    DevBuf<SlicePose> d_pose;
+    DevBuf<SubjectInfo> d_subj;
+    DevBuf<GaussBlock> d_blocks;
+    DevBuf<int32_t> d_tile_slice;
+    DevBuf<int2> d_counts, d_offsets;
+    DevBuf<char> d_scan_tmp;
+    DevBuf<long long> d_totals;
+    long long* h_totals = nullptr;
+    DevBuf<Record> d_rec;
+    DevBuf<RecGrad> d_rgrad;
+    DevBuf<uint32_t> d_keys, d_vals, d_keys2, d_vals2;
+    DevBuf<char> d_sort_tmp;
+    DevBuf<int2> d_ranges;
+    DevBuf<float> d_tile_sse, d_partial, d_msum, d_slice_sse, d_pose_acc;
+    DevBuf<int> d_work;
+    DevBuf<unsigned long long> d_incut;
+    DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
+    DevBuf<char> d_tsort_tmp;
+    const int32_t* tile_order = nullptr;
+
+    // binning state
+    bool binned = false;
+    int64_t n_rec = 0, n_inst = 0, n_cand = 0;
+    const uint32_t* sorted_vals = nullptr;
+    svr_params params{};
+    bool count_pairs = false;
+    bool incut_pending = false;
+    int64_t n_incut = -1;
+
+    std::map<std::string, svr_config> tune_cache;
+
+    // stage timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Pending { int stage; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    int64_t t_calls[ST_COUNT] = {0};
+    double t_ms[ST_COUNT] = {0.0};
+};
+
+namespace {
+
+int fail(svr_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return fail((ctx), SVR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e));        \
+    } while (0)
+
+template <class T>
+hipError_t ensure(DevBuf<T>& b, size_t need, bool exact = false) {
+    if (need == 0) need = 1;
+    if (b.cap >= need) return hipSuccess;
+    size_t n = exact ? need : std::max(need, b.cap + b.cap / 2);
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void**)&b.p, n * sizeof(T));
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return e;
+    }
+    b.cap = n;
+    return hipSuccess;
+}
+
+template <class T>
+void release(DevBuf<T>& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+int enter(svr_ctx* c) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (c->host_only) return fail(c, SVR_ERR_NODEVICE, "host-only context has no GPU");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return fail(c, SVR_ERR_HIP, "hipSetDevice(%d): %s", c->device, hipGetErrorString(e));
+    return SVR_OK;
+}
+
+bool valid_config(const svr_config& g) {
+    return (g.tile == 8 || g.tile == 16 || g.tile == 32) && g.batch >= 32 && g.batch <= 256 &&
+           (g.batch % 32) == 0 && (g.persistent == 0 || g.persistent == 1) && g.cutoff > 0.f &&
+           g.cutoff <= 8.f && isfinite(g.cutoff);
+}
+
+// Builds host tile tables and (if a device is present) uploads every table.
+int build_tables(svr_ctx* c) {
+    const int T = c->cfg.tile;
+    std::vector<SliceGeo> geo(c->M);
+    int64_t tiles = 0;
+    for (int i = 0; i < c->M; ++i) {
+        SliceGeo& g = geo[i];
+        for (int k = 0; k < 9; ++k) g.R0[k] = c->rot0[9 * i + k];
+        for (int k = 0; k < 3; ++k) g.t0[k] = c->trans0[3 * i + k];
+        for (int k = 0; k < 3; ++k) {
+            const float sg = c->fwhm[3 * i + k] / 2.355f;
+            g.sig2[k] = sg * sg;
+        }
+        g.dx = c->spacing[2 * i];
+        g.dy = c->spacing[2 * i + 1];
+        g.H = c->H[i];
+        g.W = c->W[i];
+        g.ntx = (g.W + T - 1) / T;
+        g.nty = (g.H + T - 1) / T;
+        g.tile_base = (int32_t)tiles;
+        g.subject = c->slice_subject[i];
+        g.pix_off = c->pix_off[i];
+        tiles += (int64_t)g.ntx * g.nty;
+    }
+    if (tiles > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "tile count %lld exceeds 2^31-1", (long long)tiles);
+    c->n_tiles = (int32_t)tiles;
+    // 2^key_bits > n_tiles, so the all-ones padding key sorts after every tile
+    int kb = 1;
+    while (kb < 32 && (1LL << kb) <= tiles) ++kb;
+    c->key_bits = kb;
+    std::vector<int32_t> tile_slice((size_t)tiles);
+    for (int i = 0; i < c->M; ++i)
+        for (int t = 0; t < geo[i].ntx * geo[i].nty; ++t) tile_slice[geo[i].tile_base + t] = i;
+    std::vector<SubjectInfo> subj(c->n_subjects);
+    std::vector<GaussBlock> blocks;
+    for (int s = 0; s < c->n_subjects; ++s) {
+        subj[s].g_begin = c->gauss_off[s];
+        subj[s].g_end = c->gauss_off[s + 1];
+        subj[s].s_begin = 0;
+        subj[s].s_end = 0;
+        for (int64_t g0 = subj[s].g_begin; g0 < subj[s].g_end; g0 += kGaussBlock) {
+            GaussBlock b;
+            b.g_begin = g0;
+            b.g_end = std::min(g0 + kGaussBlock, subj[s].g_end);
+            b.subject = s;
+            b.pad = 0;
+            blocks.push_back(b);
+        }
+    }
+    {
+        int i = 0;
+        for (int s = 0; s < c->n_subjects; ++s) {
+            subj[s].s_begin = i;
+            while (i < c->M && c->slice_subject[i] == s) ++i;
+            subj[s].s_end = i;
+        }
+    }
+    c->n_blocks = (int32_t)blocks.size();
+    if (c->host_only) return SVR_OK;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, ensure(c->d_geo, geo.size()));
+    HIPCHK(c, ensure(c->d_pose, geo.size()));
+    HIPCHK(c, ensure(c->d_subj, subj.size()));
+    HIPCHK(c, ensure(c->d_blocks, blocks.size()));
+    HIPCHK(c, ensure(c->d_tile_slice, tile_slice.size()));
+    HIPCHK(c, ensure(c->d_ranges, tile_slice.size()));
+    HIPCHK(c, ensure(c->d_tile_sse, tile_slice.size()));
+    HIPCHK(c, ensure(c->d_slice_sse, (size_t)c->M));
+    HIPCHK(c, ensure(c->d_pose_acc, (size_t)c->M * 6));
+    HIPCHK(c, ensure(c->d_counts, (size_t)c->N));
+    HIPCHK(c, ensure(c->d_offsets, (size_t)c->N));
+    if (!geo.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_geo.p, geo.data(), geo.size() * sizeof(SliceGeo), hipMemcpyHostToDevice, st));
+    if (!subj.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_subj.p, subj.data(), subj.size() * sizeof(SubjectInfo), hipMemcpyHostToDevice, st));
+    if (!blocks.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_blocks.p, blocks.data(), blocks.size() * sizeof(GaussBlock), hipMemcpyHostToDevice, st));
+    if (!tile_slice.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_tile_slice.p, tile_slice.data(), tile_slice.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->binned = false;
+    return SVR_OK;
+}
+
+hipEvent_t take_event(svr_ctx* c) {
+    if (!c->ev_free.empty()) {
+        hipEvent_t e = c->ev_free.back();
+        c->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one stage with events on the context stream when timing is on.
+struct StageScope {
+    svr_ctx* c;
+    int stage;
+    hipEvent_t a = nullptr;
+    StageScope(svr_ctx* ctx, int s) : c(ctx), stage(s) {
+        if (c->timing) {
+            a = take_event(c);
+            if (a && hipEventRecord(a, c->stream) != hipSuccess) a = nullptr;
+        }
+    }
+    ~StageScope() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (b && hipEventRecord(b, c->stream) == hipSuccess) c->pending.push_back({stage, a, b});
+        else c->ev_free.push_back(a);
+    }
+};
+
+int fold_timing(svr_ctx* c) {
+    if (c->pending.empty()) return SVR_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->t_ms[p.stage] += ms;
+            c->t_calls[p.stage] += 1;
+        }
+        c->ev_free.push_back(p.a);
+        c->ev_free.push_back(p.b);
+    }
+    c->pending.clear();
+    return SVR_OK;
+}
+
+ProjectArgs project_args(svr_ctx* c) {
+    ProjectArgs a;
+    a.mean = c->params.mean;
+    a.log_scale = c->params.log_scale;
+    a.quat = c->params.quat;
+    a.amp = c->params.amp;
+    a.geo = c->d_geo.p;
+    a.pose = c->d_pose.p;
+    a.subj = c->d_subj.p;
+    a.blocks = c->d_blocks.p;
+    a.n_blocks = c->n_blocks;
+    a.tile = c->cfg.tile;
+    a.tau = c->cfg.cutoff;
+    return a;
+}
+
+RenderArgs render_args(svr_ctx* c) {
+    RenderArgs a;
+    a.geo = c->d_geo.p;
+    a.tile_slice = c->d_tile_slice.p;
+    a.ranges = c->d_ranges.p;
+    a.inst_rec = c->sorted_vals;
+    a.rec = c->d_rec.p;
+    a.tile_order = c->cfg.persistent ? c->tile_order : nullptr;
+    a.n_tiles = c->n_tiles;
+    a.tile = c->cfg.tile;
+    a.batch = c->cfg.batch;
+    a.persistent = c->cfg.persistent;
+    a.tau2 = c->cfg.cutoff * c->cfg.cutoff;
+    a.etau = expf(-0.5f * a.tau2);
+    a.n_cu = c->n_cu;
+    return a;
+}
+
+// Persistent-mode work order: tiles by decreasing instance count.
+int build_tile_order(svr_ctx* c) {
+    hipStream_t st = c->stream;
+    const size_t nt = (size_t)c->n_tiles;
+    HIPCHK(c, ensure(c->d_tkeys, nt));
+    HIPCHK(c, ensure(c->d_tvals, nt));
+    HIPCHK(c, ensure(c->d_tkeys2, nt));
+    HIPCHK(c, ensure(c->d_tvals2, nt));
+    HIPCHK(c, ensure(c->d_tsort_tmp, sort_tmp_bytes((int64_t)nt)));
+    bool alt = false;
+    {
+        StageScope sc(c, ST_TILE_ORDER);
+        HIPCHK(c, launch_tile_cost_keys(c->d_ranges.p, c->n_tiles, c->d_tkeys.p, c->d_tvals.p, st));
+        HIPCHK(c, launch_radix_sort(c->d_tkeys.p, c->d_tvals.p, c->d_tkeys2.p, c->d_tvals2.p, (int64_t)nt, 16,
+                                    c->d_tsort_tmp.p, &alt, st));
+    }
+    c->tile_order = (const int32_t*)(alt ? c->d_tvals2.p : c->d_tvals.p);
+    return SVR_OK;
+}
+
+int project_bin_impl(svr_ctx* c, const svr_params* p) {
+    hipStream_t st = c->stream;
+    c->params = *p;
+    c->binned = false;
+    c->incut_pending = false;
+    c->n_incut = -1;
+    {
+        StageScope sc(c, ST_SLICE_POSE);
+        HIPCHK(c, launch_slice_pose(c->d_geo.p, p->pose, c->d_pose.p, c->M, st));
+    }
+    ProjectArgs pa = project_args(c);
+    {
+        StageScope sc(c, ST_CULL_COUNT);
+        HIPCHK(c, launch_cull_count(pa, c->d_counts.p, st));
+    }
+    HIPCHK(c, ensure(c->d_scan_tmp, scan_tmp_bytes(c->N) + 64));
+    HIPCHK(c, ensure(c->d_totals, 2));
+    {
+        StageScope sc(c, ST_SCAN);
+        HIPCHK(c, launch_scan_int2(c->d_counts.p, c->d_offsets.p, c->N, c->d_totals.p, c->d_scan_tmp.p, st));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_totals, c->d_totals.p, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const long long nrec = c->h_totals[0], ninst = c->h_totals[1];
+    if (nrec > 0x7fffffffLL || ninst > 0x7fffffffLL)
+        return fail(c, SVR_ERR_CAPACITY, "records (%lld) or instances (%lld) exceed 2^31-1", nrec, ninst);
+    c->n_rec = nrec;
+    c->n_inst = ninst;
+    int64_t cand = 0;
+    for (int s = 0; s < c->n_subjects; ++s) {
+        int ns = 0;
+        for (int i = 0; i < c->M; ++i) ns += (c->slice_subject[i] == s);
+        cand += (c->gauss_off[s + 1] - c->gauss_off[s]) * (int64_t)ns;
+    }
+    c->n_cand = cand;
+    HIPCHK(c, ensure(c->d_rec, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_rgrad, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_keys, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_vals, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_keys2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_vals2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_sort_tmp, sort_tmp_bytes(ninst)));
+    {
+        StageScope sc(c, ST_EMIT);
+        HIPCHK(c, launch_emit(pa, c->d_counts.p, c->d_offsets.p, c->d_rec.p, c->d_keys.p, c->d_vals.p, st));
+    }
+    bool alt = false;
+    {
+        StageScope sc(c, ST_SORT);
+        HIPCHK(c, launch_radix_sort(c->d_keys.p, c->d_vals.p, c->d_keys2.p, c->d_vals2.p, ninst, c->key_bits,
+                                    c->d_sort_tmp.p, &alt, st));
+    }
+    const uint32_t* sk = alt ? c->d_keys2.p : c->d_keys.p;
+    c->sorted_vals = alt ? c->d_vals2.p : c->d_vals.p;
+    {
+        StageScope sc(c, ST_TILE_RANGES);
+        HIPCHK(c, launch_tile_ranges(sk, ninst, c->d_ranges.p, c->n_tiles, st));
+    }
+    if (c->cfg.persistent) {
+        int rc = build_tile_order(c);
+        if (rc != SVR_OK) return rc;
+    }
+    c->binned = true;
+    return SVR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int svr_abi_version(void) { return SVR_ABI_VERSION; }
+
+const char* svr_status_string(int s) {
+    switch (s) {
+        case SVR_OK: return "SVR_OK";
+        case SVR_ERR_ARG: return "SVR_ERR_ARG";
+        case SVR_ERR_HIP: return "SVR_ERR_HIP";
+        case SVR_ERR_CAPACITY: return "SVR_ERR_CAPACITY";
+        case SVR_ERR_STATE: return "SVR_ERR_STATE";
+        case SVR_ERR_NODEVICE: return "SVR_ERR_NODEVICE";
+        default: return "SVR_ERR_UNKNOWN";
+    }
+}
+
+int svr_ctx_create(svr_ctx** out, int device, void* hip_stream) {
+    if (!out) return SVR_ERR_ARG;
+    *out = nullptr;
+    if (device < -1) return SVR_ERR_ARG;
+    svr_ctx* c = new (std::nothrow) svr_ctx();
+    if (!c) return SVR_ERR_CAPACITY;
+    if (device == -1) {
+        c->host_only = true;
+        *out = c;
+        return SVR_OK;
+    }
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+        delete c;
+        return SVR_ERR_HIP;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SVR_ERR_HIP;
+    }
+    c->device = device;
+    c->host_only = false;
+    c->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->n_cu = cus;
+    if (hipHostMalloc((void**)&c->h_totals, 4 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SVR_ERR_HIP;
+    }
+    *out = c;
+    return SVR_OK;
+}
+
+int svr_ctx_destroy(svr_ctx* c) {
+    if (!c) return SVR_OK;
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        release(c->d_geo); release(c->d_pose); release(c->d_subj); release(c->d_blocks);
+        release(c->d_tile_slice); release(c->d_counts); release(c->d_offsets); release(c->d_scan_tmp);
+        release(c->d_totals); release(c->d_rec); release(c->d_rgrad); release(c->d_keys);
+        release(c->d_vals); release(c->d_keys2); release(c->d_vals2); release(c->d_sort_tmp);
+        release(c->d_ranges); release(c->d_tile_sse); release(c->d_partial); release(c->d_msum);
+        release(c->d_slice_sse); release(c->d_pose_acc); release(c->d_work); release(c->d_incut);
+        release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
+        release(c->d_tsort_tmp);
+        if (c->h_totals) (void)hipHostFree(c->h_totals);
+        for (auto& p : c->pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    }
+    delete c;
+    return SVR_OK;
+}
+
+int svr_set_stream(svr_ctx* c, void* s) {
+    if (!c) return SVR_ERR_ARG;
+    c->stream = (hipStream_t)s;
+    return SVR_OK;
+}
+
+const char* svr_last_error(const svr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int svr_set_geometry(svr_ctx* c, const svr_geometry* g) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!g) return fail(c, SVR_ERR_ARG, "geometry is NULL");
+    if (g->n_subjects < 1) return fail(c, SVR_ERR_ARG, "n_subjects must be >= 1");
+    if (g->n_slices < 0) return fail(c, SVR_ERR_ARG, "n_slices must be >= 0");
+    if (!g->gauss_offsets) return fail(c, SVR_ERR_ARG, "gauss_offsets is NULL");
+    if (g->n_slices > 0 && (!g->slice_subject || !g->height || !g->width || !g->spacing || !g->psf_fwhm ||
+                            !g->rot0 || !g->trans0))
+        return fail(c, SVR_ERR_ARG, "a per-slice array is NULL");
+    if (g->gauss_offsets[0] != 0) return fail(c, SVR_ERR_ARG, "gauss_offsets[0] must be 0");
+    for (int s = 0; s < g->n_subjects; ++s)
+        if (g->gauss_offsets[s + 1] < g->gauss_offsets[s])
+            return fail(c, SVR_ERR_ARG, "gauss_offsets must be nondecreasing (subject %d)", s);
+    const int M = g->n_slices;
+    int64_t P = 0;
+    std::vector<int> per_subject(g->n_subjects, 0);
+    for (int i = 0; i < M; ++i) {
+        if (g->slice_subject[i] < 0 || g->slice_subject[i] >= g->n_subjects)
+            return fail(c, SVR_ERR_ARG, "slice %d: subject %d out of range", i, g->slice_subject[i]);
+        if (i > 0 && g->slice_subject[i] < g->slice_subject[i - 1])
+            return fail(c, SVR_ERR_ARG, "slices must be grouped by nondecreasing subject (slice %d)", i);
+        if (g->height[i] < 1 || g->width[i] < 1)
+            return fail(c, SVR_ERR_ARG, "slice %d: size %dx%d must be positive", i, g->height[i], g->width[i]);
+        if (!(g->spacing[2 * i] > 0.f) || !(g->spacing[2 * i + 1] > 0.f) || !isfinite(g->spacing[2 * i]) ||
+            !isfinite(g->spacing[2 * i + 1]))
+            return fail(c, SVR_ERR_ARG, "slice %d: spacing must be positive and finite", i);
+        for (int k = 0; k < 3; ++k)
+            if (!(g->psf_fwhm[3 * i + k] >= 0.f) || !isfinite(g->psf_fwhm[3 * i + k]))
+                return fail(c, SVR_ERR_ARG, "slice %d: PSF FWHM must be >= 0 and finite", i);
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(g->rot0[9 * i + k])) return fail(c, SVR_ERR_ARG, "slice %d: rot0 not finite", i);
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(g->trans0[3 * i + k])) return fail(c, SVR_ERR_ARG, "slice %d: trans0 not finite", i);
+        P += (int64_t)g->height[i] * g->width[i];
+        per_subject[g->slice_subject[i]]++;
+    }
+    if (P > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "pixel count %lld exceeds 2^31-1", (long long)P);
+    int maxs = 0;
+    for (int s = 0; s < g->n_subjects; ++s) maxs = std::max(maxs, per_subject[s]);
+    if (maxs > kMaxSubjectSlices)
+        return fail(c, SVR_ERR_CAPACITY, "a subject has %d slices (limit %d)", maxs, kMaxSubjectSlices);
+    c->n_subjects = g->n_subjects;
+    c->M = M;
+    c->N = g->gauss_offsets[g->n_subjects];
+    c->P = P;
+    c->gauss_off.assign(g->gauss_offsets, g->gauss_offsets + g->n_subjects + 1);
+    c->slice_subject.assign(g->slice_subject, g->slice_subject + M);
+    c->H.assign(g->height, g->height + M);
+    c->W.assign(g->width, g->width + M);
+    c->spacing.assign(g->spacing, g->spacing + 2 * M);
+    c->fwhm.assign(g->psf_fwhm, g->psf_fwhm + 3 * M);
+    c->rot0.assign(g->rot0, g->rot0 + 9 * M);
+    c->trans0.assign(g->trans0, g->trans0 + 3 * M);
+    c->pix_off.assign(M + 1, 0);
+    for (int i = 0; i < M; ++i) c->pix_off[i + 1] = c->pix_off[i] + (int64_t)g->height[i] * g->width[i];
+    c->max_subject_slices = maxs;
+    c->has_geom = true;
+    c->binned = false;
+    if (!c->host_only && hipSetDevice(c->device) != hipSuccess)
+        return fail(c, SVR_ERR_HIP, "hipSetDevice(%d) failed", c->device);
+    return build_tables(c);
+}
+
+int64_t svr_num_pixels(const svr_ctx* c) { return (c && c->has_geom) ? c->P : 0; }
+
+int svr_set_config(svr_ctx* c, const svr_config* cfg) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!cfg) return fail(c, SVR_ERR_ARG, "config is NULL");
+    if (!valid_config(*cfg))
+        return fail(c, SVR_ERR_ARG, "invalid config (tile %d, batch %d, persistent %d, cutoff %g)", cfg->tile,
+                    cfg->batch, cfg->persistent, (double)cfg->cutoff);
+    const bool retile = cfg->tile != c->cfg.tile;
+    const bool recut = cfg->cutoff != c->cfg.cutoff;
+    const bool repersist = cfg->persistent != c->cfg.persistent;
+    c->cfg = *cfg;
+    if (retile || recut) c->binned = false;
+    if (retile && c->has_geom) {
+        if (!c->host_only) (void)hipSetDevice(c->device);
+        int rc = build_tables(c);
+        if (rc != SVR_OK) return rc;
+    }
+    if (repersist && c->binned && c->cfg.persistent && !c->host_only) {
+        (void)hipSetDevice(c->device);
+        int rc = build_tile_order(c);
+        if (rc != SVR_OK) return rc;
+    }
+    return SVR_OK;
+}
+
+int svr_get_config(const svr_ctx* c, svr_config* cfg) {
+    if (!c || !cfg) return SVR_ERR_ARG;
+    *cfg = c->cfg;
+    return SVR_OK;
+}
+
+int svr_project_bin(svr_ctx* c, const svr_params* p) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!p) return fail(c, SVR_ERR_ARG, "params is NULL");
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "svr_set_geometry has not been called");
+    if (c->N > 0 && (!p->mean || !p->log_scale || !p->quat || !p->amp))
+        return fail(c, SVR_ERR_ARG, "a Gaussian parameter pointer is NULL");
+    if (c->M > 0 && !p->pose) return fail(c, SVR_ERR_ARG, "pose is NULL");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    return project_bin_impl(c, p);
+}
+
+int svr_forward(svr_ctx* c, const float* target, const float* mask, float* pred, float* loss,
+                float* slice_sse, float* grad_pred) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!pred) return fail(c, SVR_ERR_ARG, "pred is NULL");
+    const bool want_loss = loss || slice_sse || grad_pred;
+    if (want_loss && (!target || !mask))
+        return fail(c, SVR_ERR_ARG, "loss outputs requested without target and mask");
+    if (!c->binned) return fail(c, SVR_ERR_STATE, "svr_project_bin has not been called");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    hipStream_t st = c->stream;
+    RenderArgs ra = render_args(c);
+    HIPCHK(c, ensure(c->d_msum, 4));
+    HIPCHK(c, ensure(c->d_partial, 1024));
+    HIPCHK(c, ensure(c->d_work, 4));
+    HIPCHK(c, ensure(c->d_incut, 1));
+    if (want_loss) {
+        StageScope sc(c, ST_MASK_SUM);
+        HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_msum.p, st));
+    }
+    unsigned long long* incut = nullptr;
+    if (c->count_pairs) {
+        HIPCHK(c, launch_fill_zero(c->d_incut.p, sizeof(unsigned long long), st));
+        incut = c->d_incut.p;
+    }
+    {
+        StageScope sc(c, ST_FORWARD);
+        HIPCHK(c, launch_forward(ra, want_loss ? target : nullptr, mask, c->d_msum.p, pred, grad_pred,
+                                 c->d_tile_sse.p, incut, c->d_work.p, st));
+    }
+    if (want_loss) {
+        StageScope sc(c, ST_LOSS);
+        float* sse = slice_sse ? slice_sse : c->d_slice_sse.p;
+        HIPCHK(c, launch_loss_finalize(c->d_tile_sse.p, c->d_geo.p, c->M, c->d_msum.p, sse, loss, st));
+    }
+    c->incut_pending = c->count_pairs;
+    return SVR_OK;
+}
+
+int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, const svr_grads* out) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!grad_pred) return fail(c, SVR_ERR_ARG, "grad_pred is NULL");
+    if (!out || (c->N > 0 && (!out->mean || !out->log_scale || !out->quat || !out->amp)) ||
+        (c->M > 0 && !out->pose))
+        return fail(c, SVR_ERR_ARG, "a gradient output pointer is NULL");
+    if (!c->binned) return fail(c, SVR_ERR_STATE, "svr_project_bin has not been called");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    hipStream_t st = c->stream;
+    HIPCHK(c, ensure(c->d_work, 4));
+    {
+        StageScope sc(c, ST_ZERO);
+        HIPCHK(c, launch_fill_zero(c->d_rgrad.p, sizeof(RecGrad) * (size_t)c->n_rec, st));
+        HIPCHK(c, launch_fill_zero(c->d_pose_acc.p, sizeof(float) * 6 * (size_t)c->M, st));
+    }
+    RenderArgs ra = render_args(c);
+    {
+        StageScope sc(c, ST_BACKWARD);
+        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_rgrad.p, c->d_work.p, st));
+    }
+    ProjectArgs pa = project_args(c);
+    {
+        StageScope sc(c, ST_PROJECT_BACKWARD);
+        HIPCHK(c, launch_project_backward(pa, c->d_offsets.p, c->d_counts.p, c->d_rec.p, c->d_rgrad.p,
+                                          out->mean, out->log_scale, out->quat, out->amp, c->d_pose_acc.p,
+                                          c->max_subject_slices, st));
+    }
+    {
+        StageScope sc(c, ST_POSE_CHAIN);
+        HIPCHK(c, launch_pose_chain(c->params.pose, c->d_pose_acc.p, out->pose, c->M, st));
+    }
+    return SVR_OK;
+}
+
+int svr_step(svr_ctx* c, const svr_grads* p, const svr_grads* g, float* m, float* v, const svr_adam* hp,
+             int64_t step) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!p || !g || !hp || !m || !v) return fail(c, SVR_ERR_ARG, "NULL argument");
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "svr_set_geometry has not been called");
+    if (step < 1) return fail(c, SVR_ERR_ARG, "step must be >= 1");
+    if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0 && hp->beta2 >= 0.0 && hp->beta2 < 1.0 && hp->eps >= 0.0))
+        return fail(c, SVR_ERR_ARG, "invalid Adam hyper-parameters");
+    if (c->N > 0 && (!p->mean || !p->log_scale || !p->quat || !p->amp || !g->mean || !g->log_scale ||
+                     !g->quat || !g->amp))
+        return fail(c, SVR_ERR_ARG, "a parameter or gradient pointer is NULL");
+    if (c->M > 0 && (!p->pose || !g->pose)) return fail(c, SVR_ERR_ARG, "pose pointer is NULL");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    const int64_t N = c->N, M = c->M;
+    AdamSeg s[5];
+    int ns = 0;
+    int64_t off = 0;
+    auto add = [&](float* pp, const float* gg, int64_t n, float la, float lb, int pose) {
+        if (n <= 0) return;
+        s[ns].p = pp;
+        s[ns].g = gg;
+        s[ns].n = n;
+        s[ns].state_off = off;
+        s[ns].lr_a = la;
+        s[ns].lr_b = lb;
+        s[ns].pose_layout = pose;
+        ++ns;
+    };
+    add(p->mean, g->mean, 3 * N, hp->lr[0], hp->lr[0], 0); off += 3 * N;
+    add(p->log_scale, g->log_scale, 3 * N, hp->lr[1], hp->lr[1], 0); off += 3 * N;
+    add(p->quat, g->quat, 4 * N, hp->lr[2], hp->lr[2], 0); off += 4 * N;
+    add(p->amp, g->amp, N, hp->lr[3], hp->lr[3], 0); off += N;
+    add(p->pose, g->pose, 6 * M, hp->lr[4], hp->lr[5], 1);
+    StageScope sc(c, ST_ADAM);
+    HIPCHK(c, launch_adam(s, ns, m, v, hp->beta1, hp->beta2, hp->eps, hp->weight_decay, step, c->stream));
+    return SVR_OK;
+}
+
+int svr_set_count_pairs(svr_ctx* c, int enable) {
+    if (!c) return SVR_ERR_ARG;
+    c->count_pairs = enable != 0;
+    return SVR_OK;
+}
+
+int svr_get_stats(svr_ctx* c, int flags, svr_stats* out) {
+    if (!c || !out) return SVR_ERR_ARG;
+    c->err.clear();
+    memset(out, 0, sizeof(*out));
+    out->n_gauss = c->N;
+    out->n_slices = c->M;
+    out->n_pixels = c->P;
+    out->n_tiles = c->n_tiles;
+    out->key_bits = c->key_bits;
+    out->sort_passes = (c->key_bits + 7) / 8;
+    out->n_candidates = c->binned ? c->n_cand : 0;
+    out->n_records = c->binned ? c->n_rec : 0;
+    out->n_instances = c->binned ? c->n_inst : 0;
+    out->n_incut = -1;
+    out->n_evaluated = -1;
+    if (c->binned) {
+        // evaluated pixel-record terms of the forward: every instance costs a
+        // full tile of pixels (before per-wave row culling)
+        out->n_evaluated = c->n_inst * (int64_t)c->cfg.tile * c->cfg.tile;
+    }
+    if ((flags & SVR_STATS_SYNC) && c->incut_pending && !c->host_only) {
+        int rc = enter(c);
+        if (rc != SVR_OK) return rc;
+        unsigned long long h = 0;
+        HIPCHK(c, hipMemcpyAsync(&h, c->d_incut.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->n_incut = (int64_t)h;
+        c->incut_pending = false;
+    }
+    out->n_incut = c->n_incut;
+    return SVR_OK;
+}
+
+int svr_set_timing(svr_ctx* c, int enable) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        int rc = fold_timing(c);
+        if (rc != SVR_OK) return rc;
+    }
+    c->timing = enable != 0;
+    for (int s = 0; s < ST_COUNT; ++s) {
+        c->t_ms[s] = 0.0;
+        c->t_calls[s] = 0;
+    }
+    return SVR_OK;
+}
+
+int svr_get_timing(svr_ctx* c, svr_timer* out, int max_out, int* n_out) {
+    if (!c || (max_out > 0 && !out)) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        int rc = fold_timing(c);
+        if (rc != SVR_OK) return rc;
+    }
+    int n = 0;
+    for (int s = 0; s < ST_COUNT && n < max_out; ++s, ++n) {
+        memset(out[n].name, 0, sizeof out[n].name);
+        strncpy(out[n].name, kStageNames[s], sizeof out[n].name - 1);
+        out[n].calls = c->t_calls[s];
+        out[n].total_ms = c->t_ms[s];
+    }
+    if (n_out) *n_out = n;
+    return SVR_OK;
+}
+
+int svr_sort_pairs(svr_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (n < 0 || key_bits < 1 || key_bits > 32) return fail(c, SVR_ERR_ARG, "n < 0 or key_bits out of range");
+    if (n > 0 && (!keys || !vals)) return fail(c, SVR_ERR_ARG, "keys/vals NULL");
+    if (n > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "n exceeds 2^31-1");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (n <= 1) return SVR_OK;
+    hipStream_t st = c->stream;
+    DevBuf<uint32_t> k2, v2;
+    DevBuf<char> tmp;
+    HIPCHK(c, ensure(k2, (size_t)n, true));
+    HIPCHK(c, ensure(v2, (size_t)n, true));
+    HIPCHK(c, ensure(tmp, sort_tmp_bytes(n), true));
+    bool alt = false;
+    hipError_t e = launch_radix_sort(keys, vals, k2.p, v2.p, n, key_bits, tmp.p, &alt, st);
+    if (e == hipSuccess && alt) {
+        e = hipMemcpyAsync(keys, k2.p, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(vals, v2.p, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    }
+    hipError_t e2 = hipStreamSynchronize(st);
+    release(k2);
+    release(v2);
+    release(tmp);
+    if (e != hipSuccess) return fail(c, SVR_ERR_HIP, "radix sort: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(c, SVR_ERR_HIP, "radix sort sync: %s", hipGetErrorString(e2));
+    return SVR_OK;
+}
+
+static std::string tune_key(const svr_ctx* c) {
+    auto lg = [](int64_t v) {
+        int k = 0;
+        while (v > 1) { v >>= 1; ++k; }
+        return k;
+    };
+    char buf[128];
+    snprintf(buf, sizeof buf, "gfx950:P%d:R%d:I%d:S%d", lg(c->P), lg(c->n_rec), lg(c->n_inst), c->n_subjects);
+    return buf;
+}
+
+static void tune_cache_load(svr_ctx* c, const char* path) {
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    svr_config g;
+    while (fscanf(f, "%127s %d %d %d %f", key, &g.tile, &g.batch, &g.persistent, &g.cutoff) == 5)
+        if (valid_config(g)) c->tune_cache[key] = g;
+    fclose(f);
+}
+
+static void tune_cache_save(svr_ctx* c, const char* path) {
+    if (!path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto& kv : c->tune_cache)
+        fprintf(f, "%s %d %d %d %.6g\n", kv.first.c_str(), kv.second.tile, kv.second.batch, kv.second.persistent,
+                (double)kv.second.cutoff);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+int svr_autotune(svr_ctx* c, const svr_params* params, const float* grad_pred, int flags, const char* cache_path,
+                 svr_config* out, float* times_ms, int max_times) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (!params || !grad_pred || !out) return fail(c, SVR_ERR_ARG, "NULL argument");
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "svr_set_geometry has not been called");
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    hipStream_t st = c->stream;
+    const svr_config base = c->cfg;
+    if (!c->binned || c->params.mean != params->mean) {
+        rc = project_bin_impl(c, params);
+        if (rc != SVR_OK) return rc;
+    }
+    tune_cache_load(c, cache_path);
+    const std::string key = tune_key(c);
+    auto hit = c->tune_cache.find(key);
+    if (hit != c->tune_cache.end()) {
+        svr_config g = hit->second;
+        g.cutoff = base.cutoff;
+        rc = svr_set_config(c, &g);
+        if (rc != SVR_OK) return rc;
+        if (!c->binned) {
+            rc = project_bin_impl(c, params);
+            if (rc != SVR_OK) return rc;
+        }
+        *out = c->cfg;
+        return SVR_OK;
+    }
+    DevBuf<float> pred, grads;
+    HIPCHK(c, ensure(pred, (size_t)c->P, true));
+    const size_t ng = (size_t)c->N * 11 + (size_t)c->M * 6;
+    HIPCHK(c, ensure(grads, ng, true));
+    svr_grads gout;
+    gout.mean = grads.p;
+    gout.log_scale = grads.p + 3 * c->N;
+    gout.quat = grads.p + 6 * c->N;
+    gout.amp = grads.p + 10 * c->N;
+    gout.pose = grads.p + 11 * c->N;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    std::vector<int> tiles = (flags & SVR_TUNE_TILE) ? std::vector<int>{8, 16, 32} : std::vector<int>{base.tile};
+    std::vector<int> batches =
+        (flags & SVR_TUNE_BATCH) ? std::vector<int>{32, 64, 128, 256} : std::vector<int>{base.batch};
+    std::vector<int> pers = (flags & SVR_TUNE_PERSISTENT) ? std::vector<int>{0, 1} : std::vector<int>{base.persistent};
+    float best = 1e30f;
+    svr_config best_cfg = base;
+    int nt = 0;
+    int status = SVR_OK;
+    for (int T : tiles) {
+        for (int P : pers) {
+            svr_config g = base;
+            g.tile = T;
+            g.persistent = P;
+            status = svr_set_config(c, &g);
+            if (status != SVR_OK) break;
+            if (!c->binned) {
+                status = project_bin_impl(c, params);
+                if (status != SVR_OK) break;
+            }
+            for (int B : batches) {
+                c->cfg.batch = B;
+                float tbest = 1e30f;
+                for (int rep = 0; rep < 4; ++rep) {
+                    if (hipEventRecord(e0, st) != hipSuccess) { status = SVR_ERR_HIP; break; }
+                    status = svr_forward(c, nullptr, nullptr, pred.p, nullptr, nullptr, nullptr);
+                    if (status != SVR_OK) break;
+                    status = svr_backward(c, grad_pred, nullptr, &gout);
+                    if (status != SVR_OK) break;
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        status = SVR_ERR_HIP;
+                        break;
+                    }
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (rep > 0) tbest = std::min(tbest, ms);
+                }
+                if (status != SVR_OK) break;
+                if (times_ms && nt < max_times) times_ms[nt] = tbest;
+                ++nt;
+                if (tbest < best) {
+                    best = tbest;
+                    best_cfg = c->cfg;
+                }
+            }
+            if (status != SVR_OK) break;
+        }
+        if (status != SVR_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    release(pred);
+    release(grads);
+    if (status != SVR_OK) return status;
+    rc = svr_set_config(c, &best_cfg);
+    if (rc != SVR_OK) return rc;
+    if (!c->binned) {
+        rc = project_bin_impl(c, params);
+        if (rc != SVR_OK) return rc;
+    }
+    c->tune_cache[key] = best_cfg;
+    tune_cache_save(c, cache_path);
+    *out = c->cfg;
+    return SVR_OK;
+}
+
+}  // extern "C"

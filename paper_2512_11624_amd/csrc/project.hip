@@ -1,0 +1,520 @@
+// Slice pose, Gaussian activation, culling + projection + emission, and the
+// projection adjoint.  gfx950, FP32.
+//
+// Geometry of one (slice i, Gaussian j) pair in the slice frame (paper Sec. 2.3,
+// Eq. 4 rotated into slice coordinates):
+//   m  = R_i^T (mu_j - t_i)                      Gaussian centre in the slice frame
+//   S' = R_i^T Sigma_j R_i + diag(sigma_PSF^2)   observed covariance in the slice frame
+// With S' = [[C0, b], [b^T, s]] (C0 the in-plane 2x2 block, s the normal entry),
+// the quadratic form at the in-plane point u (third coordinate 0) splits into
+//   q(u) = beta + (u - u*)^T A (u - u*),   beta = m_z^2 / s,
+//   u* = m_xy - b m_z / s,  A = C^-1,  C = C0 - b b^T / s   (Schur complement),
+// and det S' = det C * s.  The pair contributes inside the T-sigma footprint only
+// if beta <= T^2 (plane test), then on the ellipse (u-u*)^T A (u-u*) <= T^2 - beta,
+// whose bounding box has half-widths sqrt((T^2-beta) C_xx), sqrt((T^2-beta) C_yy).
+// The amplitude is c_j sqrt(det Sigma_j / det S') = c_j exp(sum log s_j) / sqrt(det C s).
+#include "svr_internal.h"
+
+namespace svr {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kList = 32;
+
+struct GAct {
+    float mu[3];
+    float R[9];
+    float s2[3];
+    float S[6];  // xx, xy, xz, yy, yz, zz
+    float lsum;
+    float qn[4];
+    float qinv;
+    float c;
+};
+
+__device__ inline float sym(const float* S, int a, int b) {
+    // index into (xx, xy, xz, yy, yz, zz)
+    const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+    return S[idx[3 * a + b]];
+}
+
+__device__ inline void activate(const ProjectArgs& a, int64_t j, GAct& g) {
+    for (int k = 0; k < 3; ++k) g.mu[k] = a.mean[3 * j + k];
+    float w = a.quat[4 * j], x = a.quat[4 * j + 1], y = a.quat[4 * j + 2], z = a.quat[4 * j + 3];
+    float qinv = rsqrtf(w * w + x * x + y * y + z * z);
+    w *= qinv; x *= qinv; y *= qinv; z *= qinv;
+    g.qn[0] = w; g.qn[1] = x; g.qn[2] = y; g.qn[3] = z;
+    g.qinv = qinv;
+    // R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]_x
+    const float d = w * w - x * x - y * y - z * z;
+    g.R[0] = d + 2 * x * x; g.R[1] = 2 * (x * y - w * z); g.R[2] = 2 * (x * z + w * y);
+    g.R[3] = 2 * (x * y + w * z); g.R[4] = d + 2 * y * y; g.R[5] = 2 * (y * z - w * x);
+    g.R[6] = 2 * (x * z - w * y); g.R[7] = 2 * (y * z + w * x); g.R[8] = d + 2 * z * z;
+    float ls0 = a.log_scale[3 * j], ls1 = a.log_scale[3 * j + 1], ls2 = a.log_scale[3 * j + 2];
+    g.s2[0] = expf(2.f * ls0); g.s2[1] = expf(2.f * ls1); g.s2[2] = expf(2.f * ls2);
+    g.lsum = ls0 + ls1 + ls2;
+    // Sigma = R diag(s2) R^T
+    int o = 0;
+    for (int p = 0; p < 3; ++p)
+        for (int q = p; q < 3; ++q) {
+            g.S[o++] = g.R[3 * p] * g.s2[0] * g.R[3 * q] + g.R[3 * p + 1] * g.s2[1] * g.R[3 * q + 1] +
+                       g.R[3 * p + 2] * g.s2[2] * g.R[3 * q + 2];
+        }
+    g.c = a.amp[j];
+}
+
+__device__ inline void activate_dummy(GAct& g) {
+    for (int k = 0; k < 3; ++k) { g.mu[k] = 0.f; g.s2[k] = 1.f; }
+    for (int k = 0; k < 9; ++k) g.R[k] = (k % 4 == 0) ? 1.f : 0.f;
+    g.S[0] = 1.f; g.S[1] = 0.f; g.S[2] = 0.f; g.S[3] = 1.f; g.S[4] = 0.f; g.S[5] = 1.f;
+    g.lsum = 0.f; g.qn[0] = 1.f; g.qn[1] = g.qn[2] = g.qn[3] = 0.f; g.qinv = 1.f; g.c = 0.f;
+}
+
+// Cheap plane test: beta = m_z^2 / s_zz <= T^2.
+__device__ inline bool plane_pass(const GAct& g, const SlicePose& sp, float sig2z, float tau2) {
+    const float w0 = g.mu[0] - sp.t[0], w1 = g.mu[1] - sp.t[1], w2 = g.mu[2] - sp.t[2];
+    const float n0 = sp.R[2], n1 = sp.R[5], n2 = sp.R[8];
+    const float mz = n0 * w0 + n1 * w1 + n2 * w2;
+    const float sn0 = g.S[0] * n0 + g.S[1] * n1 + g.S[2] * n2;
+    const float sn1 = g.S[1] * n0 + g.S[3] * n1 + g.S[4] * n2;
+    const float sn2 = g.S[2] * n0 + g.S[4] * n1 + g.S[5] * n2;
+    const float szz = n0 * sn0 + n1 * sn1 + n2 * sn2 + sig2z;
+    return mz * mz <= tau2 * szz;
+}
+
+struct Proj {
+    float w[3];     // mu - t (world)
+    float m[3];     // slice-frame centre
+    float s00, s01, s11, s02, s12, s22;  // S' entries (slice frame, incl. PSF)
+    float C00, C01, C11, detC;
+    float A00, A01, A11;
+    float u0, u1;   // in-plane centre u* (mm)
+    float beta;
+    float f;        // amplitude / c
+    bool keep;
+};
+
+__device__ inline void project(const GAct& g, const SlicePose& sp, const float* sig2, float tau2,
+                               Proj& p) {
+    p.w[0] = g.mu[0] - sp.t[0]; p.w[1] = g.mu[1] - sp.t[1]; p.w[2] = g.mu[2] - sp.t[2];
+    float Sr[3][3];  // Sigma_j r_b for slice axis b (column b of R)
+    for (int b = 0; b < 3; ++b) {
+        const float r0 = sp.R[b], r1 = sp.R[3 + b], r2 = sp.R[6 + b];
+        p.m[b] = r0 * p.w[0] + r1 * p.w[1] + r2 * p.w[2];
+        Sr[b][0] = g.S[0] * r0 + g.S[1] * r1 + g.S[2] * r2;
+        Sr[b][1] = g.S[1] * r0 + g.S[3] * r1 + g.S[4] * r2;
+        Sr[b][2] = g.S[2] * r0 + g.S[4] * r1 + g.S[5] * r2;
+    }
+    auto dotc = [&](int a, int b) {
+        return sp.R[a] * Sr[b][0] + sp.R[3 + a] * Sr[b][1] + sp.R[6 + a] * Sr[b][2];
+    };
+    p.s00 = dotc(0, 0) + sig2[0];
+    p.s01 = dotc(0, 1);
+    p.s11 = dotc(1, 1) + sig2[1];
+    p.s02 = dotc(0, 2);
+    p.s12 = dotc(1, 2);
+    p.s22 = dotc(2, 2) + sig2[2];
+    const float is = 1.f / p.s22;
+    p.beta = p.m[2] * p.m[2] * is;
+    p.C00 = p.s00 - p.s02 * p.s02 * is;
+    p.C01 = p.s01 - p.s02 * p.s12 * is;
+    p.C11 = p.s11 - p.s12 * p.s12 * is;
+    p.detC = p.C00 * p.C11 - p.C01 * p.C01;
+    const float id = 1.f / p.detC;
+    p.A00 = p.C11 * id;
+    p.A01 = -p.C01 * id;
+    p.A11 = p.C00 * id;
+    p.u0 = p.m[0] - p.s02 * p.m[2] * is;
+    p.u1 = p.m[1] - p.s12 * p.m[2] * is;
+    p.f = expf(g.lsum) * rsqrtf(p.detC * p.s22);
+    p.keep = (p.beta <= tau2) && (p.detC > 0.f) && (p.s22 > 0.f);
+}
+
+struct Box {
+    int kx0, kx1, ky0, ky1;
+    bool nonempty;
+};
+
+// Pixel bounding box of the footprint ellipse on slice `sg`.
+__device__ inline Box pixel_box(const Proj& p, const SliceGeo& sg, float tau2) {
+    Box bx;
+    const float r2 = fmaxf(tau2 - p.beta, 0.f);
+    const float px = p.u0 / sg.dx + 0.5f * (float)(sg.W - 1);
+    const float py = p.u1 / sg.dy + 0.5f * (float)(sg.H - 1);
+    const float hx = sqrtf(r2 * p.C00) / sg.dx + 1e-3f;
+    const float hy = sqrtf(r2 * p.C11) / sg.dy + 1e-3f;
+    const float fx0 = fmaxf(ceilf(px - hx), 0.f), fx1 = fminf(floorf(px + hx), (float)(sg.W - 1));
+    const float fy0 = fmaxf(ceilf(py - hy), 0.f), fy1 = fminf(floorf(py + hy), (float)(sg.H - 1));
+    bx.nonempty = p.keep && (fx0 <= fx1) && (fy0 <= fy1);
+    bx.kx0 = bx.nonempty ? (int)fx0 : 0;
+    bx.kx1 = bx.nonempty ? (int)fx1 : -1;
+    bx.ky0 = bx.nonempty ? (int)fy0 : 0;
+    bx.ky1 = bx.nonempty ? (int)fy1 : -1;
+    return bx;
+}
+
+__device__ inline Record make_record(const Proj& p, const SliceGeo& sg, float c, int32_t slice) {
+    Record r;
+    r.r0.x = p.u0 / sg.dx + 0.5f * (float)(sg.W - 1);
+    r.r0.y = p.u1 / sg.dy + 0.5f * (float)(sg.H - 1);
+    r.r0.z = SVR_KZ * p.beta;
+    r.r0.w = c * p.f;
+    r.r1.x = SVR_KZ * p.A00 * sg.dx * sg.dx;
+    r.r1.y = SVR_KZ * p.A01 * sg.dx * sg.dy;
+    r.r1.z = SVR_KZ * p.A11 * sg.dy * sg.dy;
+    r.r1.w = __int_as_float(slice);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// K2: slice pose.  R = Exp(omega) R0 (Rodrigues), t = t0 + tau.
+// ---------------------------------------------------------------------------
+__global__ void k_slice_pose(const SliceGeo* __restrict__ geo, const float* __restrict__ pose,
+                             SlicePose* __restrict__ out, int32_t m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const float wx = pose[6 * i], wy = pose[6 * i + 1], wz = pose[6 * i + 2];
+    const float th2 = wx * wx + wy * wy + wz * wz;
+    const float th = sqrtf(th2);
+    float A, B;
+    if (th < 1e-3f) {
+        A = 1.f - th2 * (1.f / 6.f);
+        B = 0.5f - th2 * (1.f / 24.f);
+    } else {
+        const float sh = sinf(0.5f * th);
+        A = sinf(th) / th;
+        B = 2.f * sh * sh / th2;
+    }
+    // E = I + A K + B K^2, K = [w]_x ; K^2 = w w^T - th2 I
+    float E[9];
+    E[0] = 1.f + B * (wx * wx - th2); E[1] = -A * wz + B * wx * wy;     E[2] = A * wy + B * wx * wz;
+    E[3] = A * wz + B * wx * wy;      E[4] = 1.f + B * (wy * wy - th2); E[5] = -A * wx + B * wy * wz;
+    E[6] = -A * wy + B * wx * wz;     E[7] = A * wx + B * wy * wz;      E[8] = 1.f + B * (wz * wz - th2);
+    const SliceGeo& g = geo[i];
+    SlicePose sp;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            sp.R[3 * a + b] = E[3 * a] * g.R0[b] + E[3 * a + 1] * g.R0[3 + b] + E[3 * a + 2] * g.R0[6 + b];
+    for (int k = 0; k < 3; ++k) sp.t[k] = g.t0[k] + pose[6 * i + 3 + k];
+    sp.pad[0] = sp.pad[1] = sp.pad[2] = sp.pad[3] = 0.f;
+    out[i] = sp;
+}
+
+// ---------------------------------------------------------------------------
+// K3 / K5: one thread per Gaussian, a uniform loop over the subject's slices
+// doing the cheap plane test; survivors are queued in LDS and projected in
+// dense bursts so that the expensive projection is not paid per slice by the
+// whole wave.
+// ---------------------------------------------------------------------------
+template <bool kEmit>
+__global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict__ counts,
+                                                 const int2* __restrict__ offsets,
+                                                 Record* __restrict__ rec, uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals) {
+    __shared__ uint16_t s_list[kList][kBlock];
+    const GaussBlock blk = a.blocks[blockIdx.x];
+    const SubjectInfo si = a.subj[blk.subject];
+    const int64_t j = blk.g_begin + threadIdx.x;
+    const bool valid = j < blk.g_end;
+    GAct g;
+    if (valid) activate(a, j, g); else activate_dummy(g);
+    const float tau2 = a.tau * a.tau;
+    int cnt = 0;
+    int nrec = 0, ninst = 0;
+    int64_t ro = 0, io = 0;
+    int2 cap = make_int2(0, 0);
+    if (kEmit && valid) {
+        ro = offsets[j].x;
+        io = offsets[j].y;
+        cap = counts[j];
+    }
+    const int T = a.tile;
+
+    auto flush = [&]() {
+        for (int k = 0; k < cnt; ++k) {
+            const int i = si.s_begin + (int)s_list[k][threadIdx.x];
+            const SliceGeo& sg = a.geo[i];
+            const SlicePose& sp = a.pose[i];
+            Proj p;
+            project(g, sp, sg.sig2, tau2, p);
+            const Box bx = pixel_box(p, sg, tau2);
+            if (!bx.nonempty) continue;
+            const int tx0 = bx.kx0 / T, tx1 = bx.kx1 / T, ty0 = bx.ky0 / T, ty1 = bx.ky1 / T;
+            const int nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            if (kEmit) {
+                // write only inside the slots the count pass reserved
+                if (nrec >= cap.x || ninst + nt > cap.y) continue;
+                const int64_t r = ro + nrec;
+                rec[r] = make_record(p, sg, g.c, i);
+                int64_t o = io + ninst;
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) {
+                        keys[o] = (uint32_t)(sg.tile_base + ty * sg.ntx + tx);
+                        vals[o] = (uint32_t)r;
+                        ++o;
+                    }
+            }
+            ++nrec;
+            ninst += nt;
+        }
+        cnt = 0;
+    };
+
+    for (int i = si.s_begin; i < si.s_end; ++i) {
+        const SlicePose& sp = a.pose[i];
+        const float sig2z = a.geo[i].sig2[2];
+        if (valid && plane_pass(g, sp, sig2z, tau2)) {
+            s_list[cnt][threadIdx.x] = (uint16_t)(i - si.s_begin);
+            ++cnt;
+        }
+        if (__any(cnt == kList)) flush();
+    }
+    flush();
+    if (!kEmit && valid) counts[j] = make_int2(nrec, ninst);
+    if (kEmit && valid) {
+        // pad reserved slots the emit pass did not fill (only if the two passes
+        // ever disagreed): records with slice -1, instances with a key above
+        // every tile id, so that no later stage reads them
+        for (int k = nrec; k < cap.x; ++k) {
+            Record z;
+            z.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+            z.r1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            rec[ro + k] = z;
+        }
+        for (int k = ninst; k < cap.y; ++k) {
+            keys[io + k] = 0xffffffffu;
+            vals[io + k] = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K10: projection adjoint, one thread per Gaussian over its records.
+// Record gradients are in stored units (see RecGrad); they are chained back
+// through the pixel-unit scaling, the Schur complement, the slice rotation
+// and the Gaussian activation.  Slice-pose gradients (left perturbation delta
+// of R_i and translation t_i) are pre-reduced in LDS per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_project_backward(
+    ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
+    const Record* __restrict__ rec, const RecGrad* __restrict__ rgrad, float* __restrict__ g_mean,
+    float* __restrict__ g_log_scale, float* __restrict__ g_quat, float* __restrict__ g_amp,
+    float* __restrict__ pose_acc, int use_lds) {
+    extern __shared__ float s_pose[];  // [6 * slices of the subject]
+    const GaussBlock blk = a.blocks[blockIdx.x];
+    const SubjectInfo si = a.subj[blk.subject];
+    const int ns = si.s_end - si.s_begin;
+    if (use_lds) {
+        for (int k = threadIdx.x; k < 6 * ns; k += blockDim.x) s_pose[k] = 0.f;
+        __syncthreads();
+    }
+    const int64_t j = blk.g_begin + threadIdx.x;
+    const bool valid = j < blk.g_end;
+    const float tau2 = a.tau * a.tau;
+    if (valid) {
+        GAct g;
+        activate(a, j, g);
+        float GS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // dL/dSigma_j (full-matrix, symmetric)
+        float gmu[3] = {0.f, 0.f, 0.f};
+        float gc = 0.f, glsum = 0.f;
+        const int64_t r0 = offsets[j].x;
+        const int nrec = counts[j].x;
+        for (int k = 0; k < nrec; ++k) {
+            const Record R = rec[r0 + k];
+            const RecGrad G = rgrad[r0 + k];
+            const int i = __float_as_int(R.r1.w);
+            if (i < si.s_begin || i >= si.s_end) continue;  // padding record
+            const SliceGeo& sg = a.geo[i];
+            const SlicePose& sp = a.pose[i];
+            Proj p;
+            project(g, sp, sg.sig2, tau2, p);
+            const float is = 1.f / p.s22;
+            // stored units -> natural units
+            const float dbeta = SVR_KZ * G.v[1];
+            const float du0 = G.v[2] / sg.dx, du1 = G.v[3] / sg.dy;
+            const float ga00 = SVR_KZ * sg.dx * sg.dx * G.v[4];
+            const float ga01 = 0.5f * SVR_KZ * sg.dx * sg.dy * G.v[5];
+            const float ga11 = SVR_KZ * sg.dy * sg.dy * G.v[6];
+            // A = C^-1  ->  G_C = -A G_A A
+            const float t00 = p.A00 * ga00 + p.A01 * ga01, t01 = p.A00 * ga01 + p.A01 * ga11;
+            const float t10 = p.A01 * ga00 + p.A11 * ga01, t11 = p.A01 * ga01 + p.A11 * ga11;
+            float gc00 = -(t00 * p.A00 + t01 * p.A01);
+            float gc01 = -(t00 * p.A01 + t01 * p.A11);
+            float gc11 = -(t10 * p.A01 + t11 * p.A11);
+            // amplitude a = c f, ln f = lsum - 1/2 ln det C - 1/2 ln s
+            const float gam = G.v[0] * g.c * p.f;
+            gc += G.v[0] * p.f;
+            glsum += gam;
+            gc00 -= 0.5f * gam * p.A00;
+            gc01 -= 0.5f * gam * p.A01;
+            gc11 -= 0.5f * gam * p.A11;
+            float ds = -0.5f * gam * is;
+            // beta = m_z^2 / s
+            float dm2 = dbeta * 2.f * p.m[2] * is;
+            ds -= dbeta * p.beta * is;
+            // u* = m_xy - b m_z / s
+            const float h = p.s02 * du0 + p.s12 * du1;
+            dm2 -= h * is;
+            float db0 = -du0 * p.m[2] * is, db1 = -du1 * p.m[2] * is;
+            ds += h * p.m[2] * is * is;
+            // C = C0 - b b^T / s
+            const float Gb0 = gc00 * p.s02 + gc01 * p.s12, Gb1 = gc01 * p.s02 + gc11 * p.s12;
+            db0 -= 2.f * Gb0 * is;
+            db1 -= 2.f * Gb1 * is;
+            ds += (p.s02 * Gb0 + p.s12 * Gb1) * is * is;
+            // slice-frame gradient of S' (full-matrix, symmetric)
+            const float Gp[9] = {gc00, gc01, 0.5f * db0, gc01, gc11, 0.5f * db1, 0.5f * db0, 0.5f * db1, ds};
+            // world frame: G_S = R G' R^T
+            float RG[9];
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v)
+                    RG[3 * u + v] = sp.R[3 * u] * Gp[v] + sp.R[3 * u + 1] * Gp[3 + v] + sp.R[3 * u + 2] * Gp[6 + v];
+            float Gw[6];
+            {
+                int o = 0;
+                for (int u = 0; u < 3; ++u)
+                    for (int v = u; v < 3; ++v)
+                        Gw[o++] = RG[3 * u] * sp.R[3 * v] + RG[3 * u + 1] * sp.R[3 * v + 1] + RG[3 * u + 2] * sp.R[3 * v + 2];
+            }
+            for (int q = 0; q < 6; ++q) GS[q] += Gw[q];
+            // m = R^T (mu - t): dmu = R dm, dt = -R dm
+            const float dm[3] = {du0, du1, dm2};
+            float Rdm[3];
+            for (int u = 0; u < 3; ++u) Rdm[u] = sp.R[3 * u] * dm[0] + sp.R[3 * u + 1] * dm[1] + sp.R[3 * u + 2] * dm[2];
+            for (int u = 0; u < 3; ++u) gmu[u] += Rdm[u];
+            // left perturbation of R_i: d delta = (R dm) x w + 2 (B12, B20, B01),
+            // B = G_S Sigma_j - Sigma_j G_S
+            float GSig[9];
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) {
+                    float acc = 0.f;
+                    for (int q = 0; q < 3; ++q) acc += sym(Gw, u, q) * sym(g.S, q, v);
+                    GSig[3 * u + v] = acc;
+                }
+            // B_uv = GSig_uv - GSig_vu (since Sigma G = (G Sigma)^T)
+            const float B12 = GSig[5] - GSig[7], B20 = GSig[6] - GSig[2], B01 = GSig[1] - GSig[3];
+            float pd[6];
+            pd[0] = Rdm[1] * p.w[2] - Rdm[2] * p.w[1] + 2.f * B12;
+            pd[1] = Rdm[2] * p.w[0] - Rdm[0] * p.w[2] + 2.f * B20;
+            pd[2] = Rdm[0] * p.w[1] - Rdm[1] * p.w[0] + 2.f * B01;
+            pd[3] = -Rdm[0];
+            pd[4] = -Rdm[1];
+            pd[5] = -Rdm[2];
+            if (use_lds) {
+                const int li = i - si.s_begin;
+                for (int q = 0; q < 6; ++q) atomicAdd(&s_pose[6 * li + q], pd[q]);
+            } else {
+                for (int q = 0; q < 6; ++q) atomicAdd(&pose_acc[6 * i + q], pd[q]);
+            }
+        }
+        // Sigma_j = R diag(s^2) R^T
+        float GR[9];  // G_S R_j
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v)
+                GR[3 * u + v] = sym(GS, u, 0) * g.R[v] + sym(GS, u, 1) * g.R[3 + v] + sym(GS, u, 2) * g.R[6 + v];
+        for (int k = 0; k < 3; ++k) {
+            // (R^T G R)_kk = sum_u R_uk (G R)_uk
+            const float d = g.R[k] * GR[k] + g.R[3 + k] * GR[3 + k] + g.R[6 + k] * GR[6 + k];
+            g_log_scale[3 * j + k] = glsum + 2.f * g.s2[k] * d;
+        }
+        float dR[9];  // dL/dR_j = 2 G_S R_j diag(s^2)
+        for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) dR[3 * u + v] = 2.f * GR[3 * u + v] * g.s2[v];
+        // R = (w^2 - |v|^2) I + 2 v v^T + 2 w [v]_x, differentiated in (w, v)
+        const float w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+        const float tr = dR[0] + dR[4] + dR[8];
+        const float ax = dR[7] - dR[5], ay = dR[2] - dR[6], az = dR[3] - dR[1];
+        const float vx = x, vy = y, vz = z;
+        // (G + G^T) v
+        const float sv0 = (2.f * dR[0]) * vx + (dR[1] + dR[3]) * vy + (dR[2] + dR[6]) * vz;
+        const float sv1 = (dR[1] + dR[3]) * vx + (2.f * dR[4]) * vy + (dR[5] + dR[7]) * vz;
+        const float sv2 = (dR[2] + dR[6]) * vx + (dR[5] + dR[7]) * vy + (2.f * dR[8]) * vz;
+        float gq[4];
+        gq[0] = 2.f * w * tr + 2.f * (vx * ax + vy * ay + vz * az);
+        gq[1] = -2.f * vx * tr + 2.f * sv0 + 2.f * w * ax;
+        gq[2] = -2.f * vy * tr + 2.f * sv1 + 2.f * w * ay;
+        gq[3] = -2.f * vz * tr + 2.f * sv2 + 2.f * w * az;
+        const float dp = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+        for (int k = 0; k < 4; ++k) g_quat[4 * j + k] = (gq[k] - g.qn[k] * dp) * g.qinv;
+        for (int k = 0; k < 3; ++k) g_mean[3 * j + k] = gmu[k];
+        g_amp[j] = gc;
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < 6 * ns; k += blockDim.x) {
+            const float v = s_pose[k];
+            if (v != 0.f) atomicAdd(&pose_acc[6 * (int64_t)si.s_begin + k], v);
+        }
+    }
+}
+
+// K11: d omega = J_l(omega)^T d delta, d tau = d t.
+__global__ void k_pose_chain(const float* __restrict__ pose, const float* __restrict__ acc,
+                             float* __restrict__ g_pose, int32_t m) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const float wx = pose[6 * i], wy = pose[6 * i + 1], wz = pose[6 * i + 2];
+    const float th2 = wx * wx + wy * wy + wz * wz;
+    const float th = sqrtf(th2);
+    float B, Cc;
+    if (th < 0.5f) {
+        B = 0.5f - th2 * (1.f / 24.f - th2 * (1.f / 720.f));
+        Cc = 1.f / 6.f - th2 * (1.f / 120.f - th2 * (1.f / 5040.f - th2 * (1.f / 362880.f)));
+    } else {
+        const float sh = sinf(0.5f * th);
+        B = 2.f * sh * sh / th2;
+        Cc = (th - sinf(th)) / (th2 * th);
+    }
+    // J = I + B K + C K^2, K = [w]_x, K^2 = w w^T - th2 I ; out = J^T d
+    const float d0 = acc[6 * i], d1 = acc[6 * i + 1], d2 = acc[6 * i + 2];
+    const float J[9] = {1.f + Cc * (wx * wx - th2), -B * wz + Cc * wx * wy, B * wy + Cc * wx * wz,
+                        B * wz + Cc * wx * wy, 1.f + Cc * (wy * wy - th2), -B * wx + Cc * wy * wz,
+                        -B * wy + Cc * wx * wz, B * wx + Cc * wy * wz, 1.f + Cc * (wz * wz - th2)};
+    for (int a = 0; a < 3; ++a) g_pose[6 * i + a] = J[a] * d0 + J[3 + a] * d1 + J[6 + a] * d2;
+    for (int a = 0; a < 3; ++a) g_pose[6 * i + 3 + a] = acc[6 * i + 3 + a];
+}
+
+}  // namespace
+
+hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,
+                             hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slice_pose, dim3((m + 127) / 128), dim3(128), 0, st, geo, pose, out, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st) {
+    if (a.n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cull<false>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts,
+                       (const int2*)nullptr, (Record*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
+                       uint32_t* keys, uint32_t* vals, hipStream_t st) {
+    if (a.n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cull<true>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, const_cast<int2*>(counts),
+                       offsets, rec, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
+                                   const Record* rec, const RecGrad* rgrad, float* g_mean,
+                                   float* g_log_scale, float* g_quat, float* g_amp, float* pose_acc,
+                                   int32_t max_subject_slices, hipStream_t st) {
+    if (a.n_blocks <= 0) return hipSuccess;
+    const int use_lds = (max_subject_slices <= 2048) ? 1 : 0;
+    const size_t lds = use_lds ? sizeof(float) * 6 * (size_t)max_subject_slices : 0;
+    hipLaunchKernelGGL(k_project_backward, dim3(a.n_blocks), dim3(kBlock), lds, st, a, offsets, counts,
+                       rec, rgrad, g_mean, g_log_scale, g_quat, g_amp, pose_acc, use_lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_chain(const float* pose, const float* pose_acc, float* g_pose, int32_t m,
+                             hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose_chain, dim3((m + 127) / 128), dim3(128), 0, st, pose, pose_acc, g_pose, m);
+    return hipGetLastError();
+}
+
+}  // namespace svr

@@ -1,0 +1,145 @@
+// Internal definitions shared by the libsvr HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SVR_LOG2E 1.4426950408889634f
+#define SVR_LN2 0.6931471805599453f
+// exp(-x/2) = exp2(KZ * x)
+#define SVR_KZ (-0.5f * SVR_LOG2E)
+
+// Static per-slice geometry (depends on the tile size through the tile table).
+struct SliceGeo {
+    float R0[9];
+    float t0[3];
+    float sig2[3];   // PSF variances along slice x, y, normal
+    float dx, dy;
+    int32_t H, W;
+    int32_t ntx, nty;
+    int32_t tile_base;  // first global tile id of the slice
+    int32_t subject;
+    int64_t pix_off;
+};
+
+// Per-iteration slice pose: R = Exp(omega) R0, t = t0 + tau.
+struct SlicePose {
+    float R[9];
+    float t[3];
+    float pad[4];
+};
+
+struct SubjectInfo {
+    int64_t g_begin, g_end;
+    int32_t s_begin, s_end;
+};
+
+// Block table of the per-Gaussian kernels: blocks never straddle subjects.
+struct GaussBlock {
+    int64_t g_begin, g_end;
+    int32_t subject;
+    int32_t pad;
+};
+
+// One record = one (slice, Gaussian) pair that survives culling, 32 bytes.
+//   r0 = (p*_x, p*_y, beta', amp)   centre in slice pixel units, beta' = KZ beta
+//   r1 = (A'_00, A'_01, A'_11, slice id bits)  conic in pixel units times KZ
+// The exponent of a pixel at pixel coordinates p is
+//   z = beta' + A'_00 dx^2 + 2 A'_01 dx dy + A'_11 dy^2,  d = p - p*,
+// and its value amp * max(exp2(z) - e_T, 0).
+struct Record {
+    float4 r0;
+    float4 r1;
+};
+
+// Per-record gradient accumulator (sums over the record's pixels):
+//   (d amp, d beta', d p*_x, d p*_y, d A'_00, d A'_01, d A'_11, unused)
+struct RecGrad {
+    float v[8];
+};
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (one per translation unit), all asynchronous on stream.
+// ---------------------------------------------------------------------------
+namespace svr {
+
+struct ProjectArgs {
+    const float* mean;
+    const float* log_scale;
+    const float* quat;
+    const float* amp;
+    const SliceGeo* geo;
+    const SlicePose* pose;
+    const SubjectInfo* subj;
+    const GaussBlock* blocks;
+    int32_t n_blocks;
+    int32_t tile;
+    float tau;
+};
+
+hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,
+                             hipStream_t st);
+hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st);
+hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
+                       uint32_t* keys, uint32_t* vals, hipStream_t st);
+hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
+                                   const Record* rec, const RecGrad* rgrad, float* g_mean,
+                                   float* g_log_scale, float* g_quat, float* g_amp, float* pose_acc,
+                                   int32_t max_subject_slices, hipStream_t st);
+hipError_t launch_pose_chain(const float* pose, const float* pose_acc, float* g_pose, int32_t m,
+                             hipStream_t st);
+
+// Exclusive scan of int2 counts (component-wise) -> offsets, plus totals
+// (int64 pair) written to totals[0..1].  tmp must hold scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+hipError_t launch_scan_int2(const int2* in, int2* out, int64_t n, long long* totals, void* tmp,
+                            hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
+// Buffers are ping-ponged; *result_in_alt tells where the result ended.
+size_t sort_tmp_bytes(int64_t n);
+hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
+                             bool* result_in_alt, hipStream_t st);
+
+struct RenderArgs {
+    const SliceGeo* geo;
+    const int32_t* tile_slice;   // [n_tiles]
+    const int2* ranges;          // [n_tiles] [start, end) into sorted instances
+    const uint32_t* inst_rec;    // sorted instance -> record id
+    const Record* rec;
+    const int32_t* tile_order;   // persistent mode: tiles by decreasing cost (or NULL)
+    int32_t n_tiles;
+    int32_t tile;
+    int32_t batch;
+    int32_t persistent;
+    float etau;                  // exp(-T^2/2)
+    float tau2;                  // T^2
+    int32_t n_cu;                // compute units (persistent grid size)
+};
+
+// keys >= n_tiles (emission padding) are ignored.
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, int2* ranges, int32_t n_tiles,
+                              hipStream_t st);
+hipError_t launch_mask_sum(const float* mask, int64_t n, float* partial, float* out,
+                           hipStream_t st);
+hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask,
+                          const float* msum, float* pred, float* grad_pred, float* tile_sse,
+                          unsigned long long* incut, int* work_counter, hipStream_t st);
+hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m,
+                                const float* msum, float* slice_sse, float* loss, hipStream_t st);
+hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
+                           RecGrad* rgrad, int* work_counter, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+struct AdamSeg {
+    float* p;
+    const float* g;
+    int64_t n;
+    int64_t state_off;
+    float lr_a, lr_b;     // lr for the element (pose: a for omega, b for tau)
+    int32_t pose_layout;  // 1: element e uses lr_a if e % 6 < 3 else lr_b
+};
+hipError_t launch_adam(const AdamSeg* segs, int n_segs, float* m, float* v, double beta1,
+                       double beta2, double eps, double wd, int64_t step, hipStream_t st);
+
+}  // namespace svr

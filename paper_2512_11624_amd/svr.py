@@ -1,0 +1,327 @@
+"""ctypes binding of libsvr (``include/svr.h``): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libsvr.so``; PyTorch provides
+device memory and the stream.  The functions keep the C names
+(``svr_project_bin``, ``svr_forward``, ``svr_backward``, ``svr_step``, ...);
+:class:`Context` wraps a ``svr_ctx*`` and :class:`SvrRender` exposes the
+forward/adjoint pair to ``torch.autograd``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvr.so")
+_lib = None
+_lock = threading.Lock()
+
+SVR_OK, SVR_ERR_ARG, SVR_ERR_HIP, SVR_ERR_CAPACITY, SVR_ERR_STATE, SVR_ERR_NODEVICE = 0, -1, -2, -3, -4, -5
+SVR_STATS_SYNC = 1
+SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_ALL = 1, 2, 4, 7
+
+vp = C.c_void_p
+
+
+class svr_geometry(C.Structure):
+    _fields_ = [("n_subjects", C.c_int32), ("gauss_offsets", vp), ("n_slices", C.c_int32),
+                ("slice_subject", vp), ("height", vp), ("width", vp), ("spacing", vp),
+                ("psf_fwhm", vp), ("rot0", vp), ("trans0", vp)]
+
+
+class svr_config(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("batch", C.c_int32), ("persistent", C.c_int32),
+                ("cutoff", C.c_float)]
+
+    def as_dict(self):
+        return dict(tile=self.tile, batch=self.batch, persistent=self.persistent, cutoff=self.cutoff)
+
+
+class svr_params(C.Structure):
+    _fields_ = [("mean", vp), ("log_scale", vp), ("quat", vp), ("amp", vp), ("pose", vp)]
+
+
+class svr_grads(C.Structure):
+    _fields_ = [("mean", vp), ("log_scale", vp), ("quat", vp), ("amp", vp), ("pose", vp)]
+
+
+class svr_adam(C.Structure):
+    _fields_ = [("lr", C.c_float * 6), ("beta1", C.c_double), ("beta2", C.c_double),
+                ("eps", C.c_double), ("weight_decay", C.c_double)]
+
+
+class svr_timer(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("calls", C.c_int64), ("total_ms", C.c_double)]
+
+
+class svr_stats(C.Structure):
+    _fields_ = [("n_gauss", C.c_int64), ("n_slices", C.c_int64), ("n_pixels", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_candidates", C.c_int64), ("n_records", C.c_int64),
+                ("n_instances", C.c_int64), ("n_incut", C.c_int64), ("n_evaluated", C.c_int64),
+                ("key_bits", C.c_int32), ("sort_passes", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_SIGS = {
+    "svr_abi_version": ([], C.c_int),
+    "svr_status_string": ([C.c_int], C.c_char_p),
+    "svr_ctx_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+    "svr_ctx_destroy": ([vp], C.c_int),
+    "svr_set_stream": ([vp, vp], C.c_int),
+    "svr_last_error": ([vp], C.c_char_p),
+    "svr_set_geometry": ([vp, C.POINTER(svr_geometry)], C.c_int),
+    "svr_num_pixels": ([vp], C.c_int64),
+    "svr_set_config": ([vp, C.POINTER(svr_config)], C.c_int),
+    "svr_get_config": ([vp, C.POINTER(svr_config)], C.c_int),
+    "svr_project_bin": ([vp, C.POINTER(svr_params)], C.c_int),
+    "svr_forward": ([vp, vp, vp, vp, vp, vp, vp], C.c_int),
+    "svr_backward": ([vp, vp, vp, C.POINTER(svr_grads)], C.c_int),
+    "svr_step": ([vp, C.POINTER(svr_grads), C.POINTER(svr_grads), vp, vp, C.POINTER(svr_adam),
+                  C.c_int64], C.c_int),
+    "svr_set_count_pairs": ([vp, C.c_int], C.c_int),
+    "svr_get_stats": ([vp, C.c_int, C.POINTER(svr_stats)], C.c_int),
+    "svr_sort_pairs": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
+    "svr_set_timing": ([vp, C.c_int], C.c_int),
+    "svr_get_timing": ([vp, C.POINTER(svr_timer), C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "svr_autotune": ([vp, C.POINTER(svr_params), vp, C.c_int, C.c_char_p, C.POINTER(svr_config),
+                      C.POINTER(C.c_float), C.c_int], C.c_int),
+}
+
+
+def load():
+    """Load libsvr.so (built in-tree).  Raises if it is missing: there is no
+    fallback implementation."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                                   "`python -m paper_2512_11624_amd.build`")
+            lib = C.CDLL(LIB_PATH)
+            for name, (args, res) in _SIGS.items():
+                f = getattr(lib, name)
+                f.argtypes = args
+                f.restype = res
+            _lib = lib
+    return _lib
+
+
+def declared_symbols():
+    return sorted(_SIGS)
+
+
+class SvrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{load().svr_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Context:
+    """One ``svr_ctx``.  device=-1 gives a host-only context (validation only)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load()
+        h = vp()
+        if stream is None and device >= 0:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib.svr_ctx_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+        if rc != SVR_OK:
+            raise SvrError(rc, f"svr_ctx_create(device={device})")
+        self.h = h
+        self.device = device
+        self._keep = []
+        self.n_gauss = 0
+        self.n_slices = 0
+        self.n_pixels = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().svr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != SVR_OK:
+            raise SvrError(rc, f"{what}: {load().svr_last_error(self.h).decode()}")
+
+    # -- configuration ------------------------------------------------------
+    def svr_set_stream(self, stream):
+        self._check(load().svr_set_stream(self.h, C.c_void_p(stream)), "svr_set_stream")
+
+    def svr_set_geometry(self, prob):
+        """prob: any object with the attributes of ``synth.Problem``."""
+        arrs = dict(go=_np(prob.gauss_offsets, np.int64), ss=_np(prob.slice_subject, np.int32),
+                    h=_np(prob.height, np.int32), w=_np(prob.width, np.int32),
+                    sp=_np(prob.spacing, np.float32), fw=_np(prob.psf_fwhm, np.float32),
+                    r0=_np(prob.rot0, np.float32), t0=_np(prob.trans0, np.float32))
+        g = svr_geometry(len(arrs["go"]) - 1, arrs["go"].ctypes.data, len(arrs["h"]),
+                         arrs["ss"].ctypes.data, arrs["h"].ctypes.data, arrs["w"].ctypes.data,
+                         arrs["sp"].ctypes.data, arrs["fw"].ctypes.data, arrs["r0"].ctypes.data,
+                         arrs["t0"].ctypes.data)
+        self._check(load().svr_set_geometry(self.h, C.byref(g)), "svr_set_geometry")
+        self.n_gauss = int(arrs["go"][-1])
+        self.n_slices = int(len(arrs["h"]))
+        self.n_pixels = int(load().svr_num_pixels(self.h))
+
+    def svr_set_config(self, tile=None, batch=None, persistent=None, cutoff=None):
+        cur = self.svr_get_config()
+        cfg = svr_config(cur["tile"] if tile is None else tile, cur["batch"] if batch is None else batch,
+                         cur["persistent"] if persistent is None else persistent,
+                         cur["cutoff"] if cutoff is None else cutoff)
+        self._check(load().svr_set_config(self.h, C.byref(cfg)), "svr_set_config")
+
+    def svr_get_config(self):
+        cfg = svr_config()
+        self._check(load().svr_get_config(self.h, C.byref(cfg)), "svr_get_config")
+        return cfg.as_dict()
+
+    # -- hot path ------------------------------------------------------------
+    def svr_project_bin(self, mean, log_scale, quat, amp, pose):
+        p = svr_params(_ptr(mean), _ptr(log_scale), _ptr(quat), _ptr(amp), _ptr(pose))
+        self._check(load().svr_project_bin(self.h, C.byref(p)), "svr_project_bin")
+
+    def svr_forward(self, pred, target=None, mask=None, loss=None, slice_sse=None, grad_pred=None):
+        rc = load().svr_forward(self.h, _ptr(target), _ptr(mask), _ptr(pred), _ptr(loss),
+                                _ptr(slice_sse), _ptr(grad_pred))
+        self._check(rc, "svr_forward")
+
+    def svr_backward(self, grad_pred, g_mean, g_log_scale, g_quat, g_amp, g_pose, grad_scale=None):
+        g = svr_grads(_ptr(g_mean), _ptr(g_log_scale), _ptr(g_quat), _ptr(g_amp), _ptr(g_pose))
+        self._check(load().svr_backward(self.h, _ptr(grad_pred), _ptr(grad_scale), C.byref(g)),
+                    "svr_backward")
+
+    def svr_step(self, params, grads, exp_avg, exp_avg_sq, lr, step, beta1=0.9, beta2=0.999,
+                 eps=1e-8, weight_decay=0.0):
+        """params / grads: 5-tuples (mean, log_scale, quat, amp, pose) of tensors."""
+        P = svr_grads(*[_ptr(t) for t in params])
+        G = svr_grads(*[_ptr(t) for t in grads])
+        hp = svr_adam((C.c_float * 6)(*[float(x) for x in lr]), beta1, beta2, eps, weight_decay)
+        self._check(load().svr_step(self.h, C.byref(P), C.byref(G), _ptr(exp_avg), _ptr(exp_avg_sq),
+                                    C.byref(hp), int(step)), "svr_step")
+
+    def svr_set_count_pairs(self, enable: bool):
+        self._check(load().svr_set_count_pairs(self.h, int(bool(enable))), "svr_set_count_pairs")
+
+    def svr_get_stats(self, sync: bool = False):
+        s = svr_stats()
+        self._check(load().svr_get_stats(self.h, SVR_STATS_SYNC if sync else 0, C.byref(s)),
+                    "svr_get_stats")
+        return s.as_dict()
+
+    def svr_set_timing(self, enable: bool):
+        self._check(load().svr_set_timing(self.h, int(bool(enable))), "svr_set_timing")
+
+    def svr_get_timing(self):
+        """{stage: (calls, total_ms)}; synchronises the stream."""
+        arr = (svr_timer * 32)()
+        n = C.c_int(0)
+        self._check(load().svr_get_timing(self.h, arr, 32, C.byref(n)), "svr_get_timing")
+        return {arr[k].name.decode(): (int(arr[k].calls), float(arr[k].total_ms)) for k in range(n.value)}
+
+    def svr_sort_pairs(self, keys, vals, key_bits):
+        self._check(load().svr_sort_pairs(self.h, _ptr(keys), _ptr(vals), int(keys.numel()), int(key_bits)),
+                    "svr_sort_pairs")
+
+    def svr_autotune(self, mean, log_scale, quat, amp, pose, grad_pred, flags=SVR_TUNE_ALL,
+                     cache_path=None, max_times=64):
+        p = svr_params(_ptr(mean), _ptr(log_scale), _ptr(quat), _ptr(amp), _ptr(pose))
+        out = svr_config()
+        times = (C.c_float * max_times)()
+        rc = load().svr_autotune(self.h, C.byref(p), _ptr(grad_pred), int(flags),
+                                 cache_path.encode() if cache_path else None, C.byref(out), times,
+                                 max_times)
+        self._check(rc, "svr_autotune")
+        return out.as_dict(), [t for t in times if t > 0]
+
+
+class Params:
+    """Device parameters in one flat float32 buffer, laid out like the Adam
+    state of ``svr_step``: mean (3N), log_scale (3N), quat (4N), amp (N),
+    pose (6M).  ``views()`` returns the five views."""
+
+    def __init__(self, n_gauss, n_slices, device="cuda"):
+        import torch
+        self.N, self.M = int(n_gauss), int(n_slices)
+        self.flat = torch.zeros(self.N * 11 + self.M * 6, dtype=torch.float32, device=device)
+
+    def views(self):
+        N, M, f = self.N, self.M, self.flat
+        return (f[:3 * N].view(N, 3), f[3 * N:6 * N].view(N, 3), f[6 * N:10 * N].view(N, 4),
+                f[10 * N:11 * N], f[11 * N:11 * N + 6 * M].view(M, 6))
+
+    @classmethod
+    def from_arrays(cls, mean, log_scale, quat, amp, pose, device="cuda"):
+        import torch
+        p = cls(len(amp), len(pose), device)
+        for v, a in zip(p.views(), (mean, log_scale, quat, amp, pose)):
+            v.copy_(torch.as_tensor(np.ascontiguousarray(a, np.float32)))
+        return p
+
+
+def _grad_fn():
+    import torch
+
+    class SvrRender(torch.autograd.Function):
+        """loss, pred = SvrRender.apply(ctx, mean, log_scale, quat, amp, pose, target, mask).
+
+        Forward: svr_project_bin + svr_forward (prediction, masked-MSE loss and
+        dL/dpred).  Backward: svr_backward scaled by the upstream loss gradient.
+        ``pred`` is not differentiable (gradients flow through the loss)."""
+
+        @staticmethod
+        def forward(fctx, sctx, mean, log_scale, quat, amp, pose, target, mask):
+            dev = mean.device
+            sctx.svr_project_bin(mean, log_scale, quat, amp, pose)
+            pred = torch.empty(sctx.n_pixels, dtype=torch.float32, device=dev)
+            loss = torch.empty(1, dtype=torch.float32, device=dev)
+            gpred = torch.empty_like(pred)
+            sctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
+            fctx.sctx = sctx
+            fctx.save_for_backward(gpred, mean, log_scale, quat, amp, pose)
+            fctx.mark_non_differentiable(pred)
+            return loss[0], pred
+
+        @staticmethod
+        def backward(fctx, g_loss, g_pred):
+            gpred, mean, log_scale, quat, amp, pose = fctx.saved_tensors
+            grads = [torch.empty_like(t) for t in (mean, log_scale, quat, amp, pose)]
+            scale = g_loss.reshape(1).to(torch.float32).contiguous()
+            fctx.sctx.svr_backward(gpred, *grads, grad_scale=scale)
+            return (None, *grads, None, None)
+
+    return SvrRender
+
+
+_svr_render = None
+
+
+def SvrRender():
+    global _svr_render
+    if _svr_render is None:
+        _svr_render = _grad_fn()
+    return _svr_render
+
+
+def render_loss(sctx, mean, log_scale, quat, amp, pose, target, mask):
+    return SvrRender().apply(sctx, mean, log_scale, quat, amp, pose, target, mask)

@@ -347,3 +347,29 @@ def test_batched_subjects_are_independent(oracle_lib):
     ga = oracle_lib.backward(a, g[:a.n_pixels], 3.0)
     assert np.abs(gc["mean"][:4] - ga["mean"]).max() <= 1e-14
     assert np.abs(gc["pose"][:a.n_slices] - ga["pose"]).max() <= 1e-14
+
+
+# ------------------------------------------------------------ band split ---
+def test_band_split_bounds_the_standard_evaluation(oracle_lib):
+    """Pairs within band*tau^2 of the cut are reported apart: the standard
+    gradient (which decides them by q <= tau^2) must lie within core +- bound,
+    the bound must vanish for a zero band, and with a wide band it must be
+    active (the test exercises the split)."""
+    p = synth.tiny(60, n_gauss=8, n_slices=3, size=(12, 14))
+    g = np.random.default_rng(0).standard_normal(p.n_pixels)
+    std = oracle_lib.backward(p, g, 3.0)
+    core0, b0 = oracle_lib.backward_band(p, g, 3.0, 0.0)
+    for k in std:
+        assert np.allclose(core0[k], std[k], rtol=1e-12, atol=1e-14)
+        assert np.all(b0[k] == 0.0)
+    core, b = oracle_lib.backward_band(p, g, 3.0, 0.3)
+    active = 0
+    for k in std:
+        assert np.all(np.abs(std[k] - core[k]) <= b[k] * (1 + 1e-12) + 1e-15), k
+        active += int((b[k] > 0).sum())
+    assert active > 0
+    y = oracle_lib.forward(p, 3.0)
+    yc, yb = oracle_lib.forward_band(p, 3.0, 0.3)
+    assert np.all(np.abs(y - yc) <= yb * (1 + 1e-12) + 1e-15) and yb.max() > 0
+    yc0, yb0 = oracle_lib.forward_band(p, 3.0, 0.0)
+    assert np.allclose(yc0, y, rtol=1e-13, atol=1e-15) and np.all(yb0 == 0)
