@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--forward-mode", type=int, default=0, help="0: pixel per lane, 1: record per lane")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch/persistent with svr_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -149,7 +150,8 @@ def main():
     log(f"workload: {desc}; N={prob.n_gauss} M={prob.n_slices} P={prob.n_pixels}")
 
     ctx = svr.Context(0)
-    ctx.svr_set_config(tile=args.tile, batch=args.batch, persistent=args.persistent, cutoff=3.0)
+    ctx.svr_set_config(tile=args.tile, batch=args.batch, persistent=args.persistent, cutoff=3.0,
+                       forward_mode=args.forward_mode)
     ctx.svr_set_geometry(prob)
     N, M, P = prob.n_gauss, prob.n_slices, prob.n_pixels
 
@@ -257,6 +259,7 @@ def main():
         "config": {"workload": desc, "gaussians": N, "slices": M, "pixels": P,
                    "tile": ctx.svr_get_config()["tile"], "batch": ctx.svr_get_config()["batch"],
                    "persistent": ctx.svr_get_config()["persistent"], "cutoff_sigma": 3.0,
+                   "forward_mode": ctx.svr_get_config()["forward_mode"],
                    "step": "project_bin+forward(masked MSE)+backward+AdamW", "autotuned": tuned is not None},
         "pairs": {"in_cut_per_step": n_incut, "records": st["n_records"], "instances": st["n_instances"],
                   "candidates": st["n_candidates"], "evaluated_upper_bound": st["n_evaluated"]},

@@ -108,16 +108,24 @@ int svr_set_geometry(svr_ctx* ctx, const svr_geometry* geom);
 int64_t svr_num_pixels(const svr_ctx* ctx);
 
 /* Kernel configuration of the tile stages.  tile: 8, 16 or 32 (pixels per
- * tile side); batch: Gaussian records staged in LDS per step, 32..256 and a
- * multiple of 32; persistent: 0 = one workgroup per tile, 1 = a persistent
- * grid that pulls tiles from a work queue ordered by decreasing instance
- * count; cutoff: footprint radius T in standard deviations, (0, 8].
- * Changing tile or cutoff invalidates the last svr_project_bin. */
+ * tile side); batch: Gaussian records staged in LDS per step of the
+ * pixel-per-lane forward, 32..256 and a multiple of 32; persistent: 0 = one
+ * workgroup per tile, 1 = a persistent grid that pulls tiles from a work
+ * queue ordered by decreasing instance count; cutoff: footprint radius T in
+ * standard deviations, (0, 8]; forward_mode: 0 = pixel per lane (records
+ * staged in LDS batches, deterministic summation order), 1 = record per lane
+ * (each lane walks its record's footprint box and accumulates into an LDS
+ * pixel tile with atomics; order of equal-pixel sums not fixed), 2 = record
+ * on lanes (a wave spreads one record's footprint box over its lanes and
+ * accumulates into its own LDS copy of the tile; deterministic).
+ * Default {16, 128, 0, 3.0, 0}.  Changing tile or cutoff invalidates the last
+ * svr_project_bin. */
 typedef struct {
     int32_t tile;
     int32_t batch;
     int32_t persistent;
     float cutoff;
+    int32_t forward_mode;
 } svr_config;
 
 int svr_set_config(svr_ctx* ctx, const svr_config* cfg);
@@ -248,8 +256,9 @@ int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuner (batched launch).  Times the forward and backward tile kernels
- * on the current bins for every tile size in {8,16,32}, LDS batch in
- * {32,64,128,256} and persistent in {0,1} (those allowed by flags), picks the
+ * on the current bins for every tile size in {8,16,32}, forward mode in
+ * {0,1,2}, LDS batch in {32,64,128,256} (mode 0) and persistent in {0,1}
+ * (those allowed by flags), picks the
  * fastest and makes it the context's configuration (re-binning when the tile
  * size changes).  params/grad_pred as in svr_project_bin / svr_backward
  * (grad_pred may be any DEVICE buffer of P floats).  Results are cached in the
@@ -261,7 +270,8 @@ int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
 #define SVR_TUNE_TILE 1
 #define SVR_TUNE_BATCH 2
 #define SVR_TUNE_PERSISTENT 4
-#define SVR_TUNE_ALL 7
+#define SVR_TUNE_MODE 8
+#define SVR_TUNE_ALL 15
 int svr_autotune(svr_ctx* ctx, const svr_params* params, const float* grad_pred, int flags,
                  const char* cache_path, svr_config* out, float* times_ms, int max_times);
 

@@ -8,9 +8,10 @@ baseline leg use it to judge the HIP path.  The product path never imports it.
 * ``optim`` -- masked-MSE loss and AdamW written from their definitions.
 """
 from .core import (build, load, forward, forward_pixels, backward, backward_subset,
-                   backward_band, forward_band, num_threads, problem_arrays)
+                   backward_band, forward_band, backward_subset_band, num_threads,
+                   problem_arrays)
 from .optim import masked_mse, adamw_step, StepLR
 
 __all__ = ["build", "load", "forward", "forward_pixels", "backward", "backward_subset",
-           "backward_band", "forward_band",
+           "backward_band", "forward_band", "backward_subset_band",
            "num_threads", "problem_arrays", "masked_mse", "adamw_step", "StepLR"]

@@ -56,8 +56,9 @@ def load():
             lib.ora_backward_subset.argtypes = [P, C.c_double, vp, C.c_int64, vp, vp, vp, vp, vp]
             lib.ora_backward_band.argtypes = [P, C.c_double, C.c_double, vp] + [vp] * 10
             lib.ora_forward_band.argtypes = [P, C.c_double, C.c_double, vp, vp]
+            lib.ora_backward_subset_band.argtypes = [P, C.c_double, C.c_double, vp, C.c_int64, vp] + [vp] * 8
             for f in ("ora_forward", "ora_forward_pixels", "ora_backward", "ora_backward_subset",
-                      "ora_backward_band", "ora_forward_band", "ora_num_threads"):
+                      "ora_backward_band", "ora_forward_band", "ora_backward_subset_band", "ora_num_threads"):
                 getattr(lib, f).restype = C.c_int
             _lib = lib
     return _lib
@@ -179,3 +180,19 @@ def forward_band(prob, tau=3.0, band=1e-3, params=None, pose=None):
     if rc != 0:
         raise RuntimeError("ora_forward_band failed")
     return core, bnd
+
+
+def backward_subset_band(prob, grad_pred, gauss_idx, tau=3.0, band=1e-3, params=None, pose=None):
+    a = problem_arrays(prob, params, pose)
+    s = _struct(a)
+    idx = np.ascontiguousarray(gauss_idx, np.int64)
+    k = len(idx)
+    g = np.ascontiguousarray(grad_pred, np.float64)
+    mk = lambda: dict(mean=np.zeros((k, 3)), log_scale=np.zeros((k, 3)), quat=np.zeros((k, 4)), amp=np.zeros(k))
+    out, bnd = mk(), mk()
+    keys = ("mean", "log_scale", "quat", "amp")
+    rc = load().ora_backward_subset_band(C.byref(s), float(tau), float(band), g.ctypes.data, k, idx.ctypes.data,
+                                         *[out[q].ctypes.data for q in keys], *[bnd[q].ctypes.data for q in keys])
+    if rc != 0:
+        raise RuntimeError("ora_backward_subset_band failed")
+    return out, bnd

@@ -634,3 +634,34 @@ int ora_forward_band(const ora_problem* p, double tau, double band, double* pred
     free(S);
     return 0;
 }
+
+/* Band-split gradient for a subset of Gaussians (no pose output). */
+int ora_backward_subset_band(const ora_problem* p, double tau, double band, const double* grad_pred,
+                             int64_t n_sel, const int64_t* gauss_idx, double* g_mean,
+                             double* g_log_scale, double* g_quat, double* g_amp, double* b_mean,
+                             double* b_log_scale, double* b_quat, double* b_amp) {
+    ora_gauss* G = make_gauss(p);
+    ora_slice* S = make_slices(p);
+    if (!G || !S) { free(G); free(S); return -1; }
+    size_t nb = 11 + 6 * (size_t)p->n_slices;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* bloc = (double*)calloc(nb, sizeof(double));
+        if (!bloc) fail = 1;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t e = 0; e < n_sel; ++e) {
+            if (!bloc) continue;
+            memset(bloc, 0, nb * sizeof(double));
+            gauss_backward(p, G, S, gauss_idx[e], tau, grad_pred, g_mean + 3 * e, g_log_scale + 3 * e,
+                           g_quat + 4 * e, g_amp + e, NULL, NULL, band, bloc);
+            for (int a = 0; a < 3; ++a) { b_mean[3 * e + a] = bloc[a]; b_log_scale[3 * e + a] = bloc[3 + a]; }
+            for (int a = 0; a < 4; ++a) b_quat[4 * e + a] = bloc[6 + a];
+            b_amp[e] = bloc[10];
+        }
+        free(bloc);
+    }
+    free(G);
+    free(S);
+    return fail ? -1 : 0;
+}

@@ -79,6 +79,10 @@ int ora_backward_band(const ora_problem* p, double tau, double band, const doubl
                       double* b_amp, double* b_pose);
 int ora_forward_band(const ora_problem* p, double tau, double band, double* pred_core,
                      double* b_pred);
+int ora_backward_subset_band(const ora_problem* p, double tau, double band, const double* grad_pred,
+                             int64_t n_sel, const int64_t* gauss_idx, double* g_mean,
+                             double* g_log_scale, double* g_quat, double* g_amp, double* b_mean,
+                             double* b_log_scale, double* b_quat, double* b_amp);
 
 int ora_num_threads(void);
 

@@ -59,7 +59,7 @@ struct svr_ctx {
     std::vector<int64_t> pix_off;
     int32_t max_subject_slices = 0;
 
-    svr_config cfg{16, 128, 0, 3.0f};
+    svr_config cfg{16, 128, 0, 3.0f, 0};
 
     // tile tables (host)
     int32_t n_tiles = 0, key_bits = 1;
@@ -76,8 +76,9 @@ struct svr_ctx {
     DevBuf<long long> d_totals;
     long long* h_totals = nullptr;
     DevBuf<Record> d_rec;
-    DevBuf<RecGrad> d_rgrad;
-    DevBuf<uint32_t> d_keys, d_vals, d_keys2, d_vals2;
+    DevBuf<int2> d_rec_inst;
+    DevBuf<float4> d_inst_grad;
+    DevBuf<uint32_t> d_keys, d_vals, d_keys2, d_vals2, d_idx, d_idx2;
     DevBuf<char> d_sort_tmp;
     DevBuf<int2> d_ranges;
     DevBuf<float> d_tile_sse, d_partial, d_msum, d_slice_sse, d_pose_acc;
@@ -91,6 +92,7 @@ struct svr_ctx {
     bool binned = false;
     int64_t n_rec = 0, n_inst = 0, n_cand = 0;
     const uint32_t* sorted_vals = nullptr;
+    const uint32_t* sorted_idx = nullptr;
     svr_params params{};
     bool count_pairs = false;
     bool incut_pending = false;
@@ -167,7 +169,7 @@ int enter(svr_ctx* c) {
 bool valid_config(const svr_config& g) {
     return (g.tile == 8 || g.tile == 16 || g.tile == 32) && g.batch >= 32 && g.batch <= 256 &&
            (g.batch % 32) == 0 && (g.persistent == 0 || g.persistent == 1) && g.cutoff > 0.f &&
-           g.cutoff <= 8.f && isfinite(g.cutoff);
+           g.cutoff <= 8.f && isfinite(g.cutoff) && (g.forward_mode >= 0 && g.forward_mode <= 2);
 }
 
 // Builds host tile tables and (if a device is present) uploads every table.
@@ -196,10 +198,12 @@ int build_tables(svr_ctx* c) {
     }
     if (tiles > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "tile count %lld exceeds 2^31-1", (long long)tiles);
     c->n_tiles = (int32_t)tiles;
-    // 2^key_bits > n_tiles, so the all-ones padding key sorts after every tile
+    // tile part: 2^bits > n_tiles, so the all-ones padding key sorts after
+    // every tile; plus the size-class bits below it
     int kb = 1;
     while (kb < 32 && (1LL << kb) <= tiles) ++kb;
-    c->key_bits = kb;
+    if (kb + kClassBits > 32) return fail(c, SVR_ERR_CAPACITY, "tile count %lld too large for the sort key", (long long)tiles);
+    c->key_bits = kb + kClassBits;
     std::vector<int32_t> tile_slice((size_t)tiles);
     for (int i = 0; i < c->M; ++i)
         for (int t = 0; t < geo[i].ntx * geo[i].nty; ++t) tile_slice[geo[i].tile_base + t] = i;
@@ -323,12 +327,14 @@ RenderArgs render_args(svr_ctx* c) {
     a.tile_slice = c->d_tile_slice.p;
     a.ranges = c->d_ranges.p;
     a.inst_rec = c->sorted_vals;
+    a.inst_idx = c->sorted_idx;
     a.rec = c->d_rec.p;
     a.tile_order = c->cfg.persistent ? c->tile_order : nullptr;
     a.n_tiles = c->n_tiles;
     a.tile = c->cfg.tile;
     a.batch = c->cfg.batch;
     a.persistent = c->cfg.persistent;
+    a.forward_mode = c->cfg.forward_mode;
     a.tau2 = c->cfg.cutoff * c->cfg.cutoff;
     a.etau = expf(-0.5f * a.tau2);
     a.n_cu = c->n_cu;
@@ -391,24 +397,29 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     }
     c->n_cand = cand;
     HIPCHK(c, ensure(c->d_rec, (size_t)nrec));
-    HIPCHK(c, ensure(c->d_rgrad, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_rec_inst, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_inst_grad, 2 * (size_t)ninst));
     HIPCHK(c, ensure(c->d_keys, (size_t)ninst));
     HIPCHK(c, ensure(c->d_vals, (size_t)ninst));
     HIPCHK(c, ensure(c->d_keys2, (size_t)ninst));
     HIPCHK(c, ensure(c->d_vals2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_idx, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_idx2, (size_t)ninst));
     HIPCHK(c, ensure(c->d_sort_tmp, sort_tmp_bytes(ninst)));
     {
         StageScope sc(c, ST_EMIT);
-        HIPCHK(c, launch_emit(pa, c->d_counts.p, c->d_offsets.p, c->d_rec.p, c->d_keys.p, c->d_vals.p, st));
+        HIPCHK(c, launch_emit(pa, c->d_counts.p, c->d_offsets.p, c->d_rec.p, c->d_rec_inst.p, c->d_keys.p,
+                              c->d_vals.p, st));
     }
     bool alt = false;
     {
         StageScope sc(c, ST_SORT);
         HIPCHK(c, launch_radix_sort(c->d_keys.p, c->d_vals.p, c->d_keys2.p, c->d_vals2.p, ninst, c->key_bits,
-                                    c->d_sort_tmp.p, &alt, st));
+                                    c->d_sort_tmp.p, &alt, st, c->d_idx.p, c->d_idx2.p));
     }
     const uint32_t* sk = alt ? c->d_keys2.p : c->d_keys.p;
     c->sorted_vals = alt ? c->d_vals2.p : c->d_vals.p;
+    c->sorted_idx = alt ? c->d_idx2.p : c->d_idx.p;
     {
         StageScope sc(c, ST_TILE_RANGES);
         HIPCHK(c, launch_tile_ranges(sk, ninst, c->d_ranges.p, c->n_tiles, st));
@@ -481,7 +492,8 @@ int svr_ctx_destroy(svr_ctx* c) {
         (void)hipStreamSynchronize(c->stream);
         release(c->d_geo); release(c->d_pose); release(c->d_subj); release(c->d_blocks);
         release(c->d_tile_slice); release(c->d_counts); release(c->d_offsets); release(c->d_scan_tmp);
-        release(c->d_totals); release(c->d_rec); release(c->d_rgrad); release(c->d_keys);
+        release(c->d_totals); release(c->d_rec); release(c->d_rec_inst); release(c->d_inst_grad);
+        release(c->d_idx); release(c->d_idx2); release(c->d_keys);
         release(c->d_vals); release(c->d_keys2); release(c->d_vals2); release(c->d_sort_tmp);
         release(c->d_ranges); release(c->d_tile_sse); release(c->d_partial); release(c->d_msum);
         release(c->d_slice_sse); release(c->d_pose_acc); release(c->d_work); release(c->d_incut);
@@ -577,8 +589,8 @@ int svr_set_config(svr_ctx* c, const svr_config* cfg) {
     c->err.clear();
     if (!cfg) return fail(c, SVR_ERR_ARG, "config is NULL");
     if (!valid_config(*cfg))
-        return fail(c, SVR_ERR_ARG, "invalid config (tile %d, batch %d, persistent %d, cutoff %g)", cfg->tile,
-                    cfg->batch, cfg->persistent, (double)cfg->cutoff);
+        return fail(c, SVR_ERR_ARG, "invalid config (tile %d, batch %d, persistent %d, cutoff %g, forward_mode %d)",
+                    cfg->tile, cfg->batch, cfg->persistent, (double)cfg->cutoff, cfg->forward_mode);
     const bool retile = cfg->tile != c->cfg.tile;
     const bool recut = cfg->cutoff != c->cfg.cutoff;
     const bool repersist = cfg->persistent != c->cfg.persistent;
@@ -670,20 +682,19 @@ int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, co
     HIPCHK(c, ensure(c->d_work, 4));
     {
         StageScope sc(c, ST_ZERO);
-        HIPCHK(c, launch_fill_zero(c->d_rgrad.p, sizeof(RecGrad) * (size_t)c->n_rec, st));
         HIPCHK(c, launch_fill_zero(c->d_pose_acc.p, sizeof(float) * 6 * (size_t)c->M, st));
     }
     RenderArgs ra = render_args(c);
     {
         StageScope sc(c, ST_BACKWARD);
-        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_rgrad.p, c->d_work.p, st));
+        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_inst_grad.p, c->d_work.p, st));
     }
     ProjectArgs pa = project_args(c);
     {
         StageScope sc(c, ST_PROJECT_BACKWARD);
-        HIPCHK(c, launch_project_backward(pa, c->d_offsets.p, c->d_counts.p, c->d_rec.p, c->d_rgrad.p,
-                                          out->mean, out->log_scale, out->quat, out->amp, c->d_pose_acc.p,
-                                          c->max_subject_slices, st));
+        HIPCHK(c, launch_project_backward(pa, c->d_offsets.p, c->d_counts.p, c->d_rec.p, c->d_rec_inst.p,
+                                          c->d_inst_grad.p, c->n_inst, out->mean, out->log_scale, out->quat,
+                                          out->amp, c->d_pose_acc.p, c->max_subject_slices, st));
     }
     {
         StageScope sc(c, ST_POSE_CHAIN);
@@ -853,7 +864,7 @@ static void tune_cache_load(svr_ctx* c, const char* path) {
     if (!f) return;
     char key[128];
     svr_config g;
-    while (fscanf(f, "%127s %d %d %d %f", key, &g.tile, &g.batch, &g.persistent, &g.cutoff) == 5)
+    while (fscanf(f, "%127s %d %d %d %f %d", key, &g.tile, &g.batch, &g.persistent, &g.cutoff, &g.forward_mode) == 6)
         if (valid_config(g)) c->tune_cache[key] = g;
     fclose(f);
 }
@@ -864,8 +875,8 @@ static void tune_cache_save(svr_ctx* c, const char* path) {
     FILE* f = fopen(tmp.c_str(), "w");
     if (!f) return;
     for (auto& kv : c->tune_cache)
-        fprintf(f, "%s %d %d %d %.6g\n", kv.first.c_str(), kv.second.tile, kv.second.batch, kv.second.persistent,
-                (double)kv.second.cutoff);
+        fprintf(f, "%s %d %d %d %.6g %d\n", kv.first.c_str(), kv.second.tile, kv.second.batch, kv.second.persistent,
+                (double)kv.second.cutoff, kv.second.forward_mode);
     fclose(f);
     rename(tmp.c_str(), path);
 }
@@ -916,6 +927,7 @@ int svr_autotune(svr_ctx* c, const svr_params* params, const float* grad_pred, i
     std::vector<int> batches =
         (flags & SVR_TUNE_BATCH) ? std::vector<int>{32, 64, 128, 256} : std::vector<int>{base.batch};
     std::vector<int> pers = (flags & SVR_TUNE_PERSISTENT) ? std::vector<int>{0, 1} : std::vector<int>{base.persistent};
+    std::vector<int> modes = (flags & SVR_TUNE_MODE) ? std::vector<int>{0, 1, 2} : std::vector<int>{base.forward_mode};
     float best = 1e30f;
     svr_config best_cfg = base;
     int nt = 0;
@@ -931,8 +943,10 @@ int svr_autotune(svr_ctx* c, const svr_params* params, const float* grad_pred, i
                 status = project_bin_impl(c, params);
                 if (status != SVR_OK) break;
             }
-            for (int B : batches) {
+            for (int FM : modes)
+            for (int B : (FM == 0 ? batches : std::vector<int>{base.batch})) {
                 c->cfg.batch = B;
+                c->cfg.forward_mode = FM;
                 float tbest = 1e30f;
                 for (int rep = 0; rep < 4; ++rep) {
                     if (hipEventRecord(e0, st) != hipSuccess) { status = SVR_ERR_HIP; break; }

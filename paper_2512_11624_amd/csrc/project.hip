@@ -135,6 +135,15 @@ struct Box {
     bool nonempty;
 };
 
+// Size class of an instance's clipped footprint box (0: <= 4 px ... 7: > 256
+// px).  It forms the low bits of the sort key, so that each tile's instances
+// come out grouped by size and the record-per-lane tile kernels see waves of
+// similar per-lane work.
+__device__ inline uint32_t area_class(int a) {
+    const uint32_t lg = 32u - __clz((unsigned)max(a - 1, 1));  // ceil(log2(a)) for a >= 2
+    return (uint32_t)min(max((int)lg - 2, 0), (1 << kClassBits) - 1);
+}
+
 // Pixel bounding box of the footprint ellipse on slice `sg`.
 __device__ inline Box pixel_box(const Proj& p, const SliceGeo& sg, float tau2) {
     Box bx;
@@ -209,7 +218,8 @@ __global__ void k_slice_pose(const SliceGeo* __restrict__ geo, const float* __re
 template <bool kEmit>
 __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict__ counts,
                                                  const int2* __restrict__ offsets,
-                                                 Record* __restrict__ rec, uint32_t* __restrict__ keys,
+                                                 Record* __restrict__ rec, int2* __restrict__ rec_inst,
+                                                 uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals) {
     __shared__ uint16_t s_list[kList][kBlock];
     const GaussBlock blk = a.blocks[blockIdx.x];
@@ -246,13 +256,18 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
                 if (nrec >= cap.x || ninst + nt > cap.y) continue;
                 const int64_t r = ro + nrec;
                 rec[r] = make_record(p, sg, g.c, i);
+                rec_inst[r] = make_int2((int)(io + ninst), nt);
                 int64_t o = io + ninst;
-                for (int ty = ty0; ty <= ty1; ++ty)
+                for (int ty = ty0; ty <= ty1; ++ty) {
+                    const int ch = min(bx.ky1, ty * T + T - 1) - max(bx.ky0, ty * T) + 1;
                     for (int tx = tx0; tx <= tx1; ++tx) {
-                        keys[o] = (uint32_t)(sg.tile_base + ty * sg.ntx + tx);
+                        const int cw = min(bx.kx1, tx * T + T - 1) - max(bx.kx0, tx * T) + 1;
+                        keys[o] = ((uint32_t)(sg.tile_base + ty * sg.ntx + tx) << kClassBits) |
+                                  area_class(cw * ch);
                         vals[o] = (uint32_t)r;
                         ++o;
                     }
+                }
             }
             ++nrec;
             ninst += nt;
@@ -280,6 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
             z.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
             z.r1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
             rec[ro + k] = z;
+            rec_inst[ro + k] = make_int2(0, 0);
         }
         for (int k = ninst; k < cap.y; ++k) {
             keys[io + k] = 0xffffffffu;
@@ -297,9 +313,9 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
-    const Record* __restrict__ rec, const RecGrad* __restrict__ rgrad, float* __restrict__ g_mean,
-    float* __restrict__ g_log_scale, float* __restrict__ g_quat, float* __restrict__ g_amp,
-    float* __restrict__ pose_acc, int use_lds) {
+    const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
+    int64_t n_inst, float* __restrict__ g_mean, float* __restrict__ g_log_scale, float* __restrict__ g_quat,
+    float* __restrict__ g_amp, float* __restrict__ pose_acc, int use_lds) {
     extern __shared__ float s_pose[];  // [6 * slices of the subject]
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
@@ -321,9 +337,17 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         const int nrec = counts[j].x;
         for (int k = 0; k < nrec; ++k) {
             const Record R = rec[r0 + k];
-            const RecGrad G = rgrad[r0 + k];
             const int i = __float_as_int(R.r1.w);
             if (i < si.s_begin || i >= si.s_end) continue;  // padding record
+            // sum the record's per-instance moments (contiguous emission slots)
+            const int2 ri = rec_inst[r0 + k];
+            struct { float v[8]; } G;
+            for (int q = 0; q < 8; ++q) G.v[q] = 0.f;
+            for (int64_t e = ri.x; e < (int64_t)ri.x + ri.y && e < n_inst; ++e) {
+                const float4 u = inst_grad[2 * e], w = inst_grad[2 * e + 1];
+                G.v[0] += u.x; G.v[1] += u.y; G.v[2] += u.z; G.v[3] += u.w;
+                G.v[4] += w.x; G.v[5] += w.y; G.v[6] += w.z;
+            }
             const SliceGeo& sg = a.geo[i];
             const SlicePose& sp = a.pose[i];
             Proj p;
@@ -486,27 +510,28 @@ hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* 
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cull<false>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts,
-                       (const int2*)nullptr, (Record*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+                       (const int2*)nullptr, (Record*)nullptr, (int2*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       uint32_t* keys, uint32_t* vals, hipStream_t st) {
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cull<true>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, const_cast<int2*>(counts),
-                       offsets, rec, keys, vals);
+                       offsets, rec, rec_inst, keys, vals);
     return hipGetLastError();
 }
 
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
-                                   const Record* rec, const RecGrad* rgrad, float* g_mean,
-                                   float* g_log_scale, float* g_quat, float* g_amp, float* pose_acc,
-                                   int32_t max_subject_slices, hipStream_t st) {
+                                   const Record* rec, const int2* rec_inst, const float4* inst_grad,
+                                   int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,
+                                   float* g_amp, float* pose_acc, int32_t max_subject_slices,
+                                   hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     const int use_lds = (max_subject_slices <= 2048) ? 1 : 0;
     const size_t lds = use_lds ? sizeof(float) * 6 * (size_t)max_subject_slices : 0;
     hipLaunchKernelGGL(k_project_backward, dim3(a.n_blocks), dim3(kBlock), lds, st, a, offsets, counts,
-                       rec, rgrad, g_mean, g_log_scale, g_quat, g_amp, pose_acc, use_lds);
+                       rec, rec_inst, inst_grad, n_inst, g_mean, g_log_scale, g_quat, g_amp, pose_acc, use_lds);
     return hipGetLastError();
 }
 

@@ -10,11 +10,15 @@
 // costs 5 FMA, one exp2 and the window max(e - e_T, 0).  Every pixel sums its
 // records in the sorted (deterministic) order.
 //
+// Forward, record per lane (the alternative mode): each lane owns one instance
+// and walks its record's footprint box inside the tile, accumulating into an
+// LDS pixel tile with ds_add_f32; only box pixels are evaluated.
+//
 // Adjoint (record per lane): the tile's upstream gradients are staged in LDS;
 // each lane owns one instance and walks the pixels of its record's footprint
 // box inside the tile, accumulating the seven moment sums it needs in
-// registers (no cross-lane reduction), then adds them to the record's
-// gradient with one atomic per component.
+// registers (no cross-lane reduction), and writes them to the instance's
+// emission slot (no atomics).
 #include "svr_internal.h"
 
 namespace svr {
@@ -32,10 +36,10 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, int2
                               uint32_t n_tiles) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const uint32_t k = keys[s];
+    const uint32_t k = keys[s] >> kClassBits;  // tile id
     if (k >= n_tiles) return;
-    if (s == 0 || keys[s - 1] != k) ranges[k].x = (int)s;
-    if (s == n - 1 || keys[s + 1] != k) ranges[k].y = (int)(s + 1);
+    if (s == 0 || (keys[s - 1] >> kClassBits) != k) ranges[k].x = (int)s;
+    if (s == n - 1 || (keys[s + 1] >> kClassBits) != k) ranges[k].y = (int)(s + 1);
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
@@ -255,91 +259,310 @@ __global__ __launch_bounds__(T * T / PPT) void k_forward(RenderArgs a, const flo
     }
 }
 
-template <int T, int PPT>
-__global__ __launch_bounds__(T * T / PPT) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
-                                                          const float* __restrict__ grad_scale,
-                                                          RecGrad* __restrict__ rgrad,
-                                                          int* __restrict__ work_counter) {
-    constexpr int NT = T * T / PPT;
-    constexpr int NW = NT / 64;
+// Footprint box of one record inside one tile, for record-per-lane kernels.
+struct LaneBox {
+    float pxl, pyl;             // record centre in tile-local pixel coordinates
+    float bz, am, a00, a01, a11;
+    int x0, x1, y0, y1;         // inclusive tile-local box, empty if x0 > x1 or y0 > y1
+};
+
+__device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, int ymax, float tau2k) {
+    LaneBox b;
+    b.pxl = R.r0.x - (float)tx0;
+    b.pyl = R.r0.y - (float)ty0;
+    b.bz = R.r0.z;
+    b.am = R.r0.w;
+    b.a00 = R.r1.x;
+    b.a01 = R.r1.y;
+    b.a11 = R.r1.z;
+    const float det = b.a00 * b.a11 - b.a01 * b.a01;
+    const float rk = tau2k - b.bz;  // KZ (T^2 - beta) <= 0 inside the footprint
+    const float hx = sqrtf(fmaxf(rk * b.a11 / det, 0.f)) + 1e-3f;
+    const float hy = sqrtf(fmaxf(rk * b.a00 / det, 0.f)) + 1e-3f;
+    // clamp in float before converting (the centre can be far outside the tile)
+    b.x0 = (int)fmaxf(ceilf(b.pxl - hx), 0.f);
+    b.x1 = (int)fminf(floorf(b.pxl + hx), (float)xmax);
+    b.y0 = (int)fmaxf(ceilf(b.pyl - hy), 0.f);
+    b.y1 = (int)fminf(floorf(b.pyl + hy), (float)ymax);
+    return b;
+}
+
+// Visits the box's pixels row by row in one flattened loop (a lane's cost is
+// its own w*h, and the wave runs to the largest w*h, not max(w) * max(h)).
+// body(x, y, dx, dy, e) with e = exp2(z) of the record at that pixel.
+template <class F>
+__device__ inline void walk_box(const LaneBox& b, F&& body) {
+    const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
+    const int n = (w > 0 && h > 0) ? w * h : 0;
+    int x = b.x0, y = b.y0;
+    float dy = (float)y - b.pyl;
+    float zy = fmaf(b.a11 * dy, dy, b.bz);
+    float bx = 2.f * b.a01 * dy;
+    for (int k = 0; k < n; ++k) {
+        const float dx = (float)x - b.pxl;
+        const float z = fmaf(dx, fmaf(b.a00, dx, bx), zy);
+        body(x, y, dx, dy, __builtin_amdgcn_exp2f(z));
+        if (++x > b.x1) {
+            x = b.x0;
+            ++y;
+            dy = (float)y - b.pyl;
+            zy = fmaf(b.a11 * dy, dy, b.bz);
+            bx = 2.f * b.a01 * dy;
+        }
+    }
+}
+
+// Forward, record per lane: every lane walks its record's box inside the tile
+// and adds a * max(e - e_T, 0) into an LDS pixel accumulator (ds_add_f32).
+template <int T, bool kLoss, bool kCount>
+__global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* __restrict__ target,
+                                                     const float* __restrict__ mask,
+                                                     const float* __restrict__ msum,
+                                                     float* __restrict__ pred, float* __restrict__ grad,
+                                                     float* __restrict__ tile_sse,
+                                                     unsigned long long* __restrict__ incut,
+                                                     int* __restrict__ work_counter) {
+    constexpr int NT = 256, NW = 4;
+    __shared__ float s_acc[T * T];
+    __shared__ float s_red[NW];
+    __shared__ unsigned int s_cnt[NW];
+    __shared__ int s_next;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const float etau = a.etau;
+    const float tau2k = SVR_KZ * a.tau2;
+    const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
+    int iter = 0;
+    while (true) {
+        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
+        if (tile < 0) break;
+        const TileCoord tc = tile_coord(a, tile);
+        const int2 rg = a.ranges[tile];
+        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
+        __syncthreads();
+        for (int p = tid; p < T * T; p += NT) s_acc[p] = 0.f;
+        __syncthreads();
+        unsigned int cnt = 0;
+        const int n = rg.y - rg.x;
+        for (int s = tid; s < n; s += NT) {
+            const Record R = a.rec[a.inst_rec[rg.x + s]];
+            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+            walk_box(b, [&](int x, int y, float, float, float e) {
+                const float v = e - etau;
+                if (v > 0.f) {
+                    atomicAdd(&s_acc[y * T + x], b.am * v);
+                    if (kCount) ++cnt;
+                }
+            });
+        }
+        __syncthreads();
+        float sq = 0.f;
+        for (int p = tid; p < T * T; p += NT) {
+            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
+            if (px < tc.W && py < tc.H) {
+                const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
+                const float acc = s_acc[p];
+                pred[pi] = acc;
+                if (kLoss) {
+                    const float m = mask[pi];
+                    const float r = acc - target[pi];
+                    sq = fmaf(m * r, r, sq);
+                    if (grad) grad[pi] = 2.f * m * r * inv_msum;
+                }
+            }
+        }
+        if (kLoss || kCount) {
+            for (int o = 32; o > 0; o >>= 1) {
+                sq += __shfl_xor(sq, o, 64);
+                if (kCount) cnt += __shfl_xor(cnt, o, 64);
+            }
+            if (lane == 0) {
+                s_red[wv] = sq;
+                s_cnt[wv] = cnt;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                float t = 0.f;
+                unsigned long long c = 0;
+                for (int q = 0; q < NW; ++q) {
+                    t += s_red[q];
+                    c += s_cnt[q];
+                }
+                if (kLoss) tile_sse[tile] = t;
+                if (kCount && c) atomicAdd(incut, c);
+            }
+        }
+    }
+}
+
+// Forward, record on lanes: each wave takes the tile's instances one at a
+// time (wave-uniform record, loaded through the scalar cache, the next one
+// prefetched); its 64 lanes cover the instance's clipped box, 64 pixels per
+// pass, and add a * max(e - e_T, 0) into the wave's own LDS copy of the tile
+// with a plain read-modify-write (lanes hit distinct pixels and no other wave
+// touches that copy).  The four copies are summed in a fixed order, so the
+// result needs no atomics and is deterministic.
+template <int T, bool kLoss, bool kCount>
+__global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* __restrict__ target,
+                                                     const float* __restrict__ mask,
+                                                     const float* __restrict__ msum,
+                                                     float* __restrict__ pred, float* __restrict__ grad,
+                                                     float* __restrict__ tile_sse,
+                                                     unsigned long long* __restrict__ incut,
+                                                     int* __restrict__ work_counter) {
+    constexpr int NT = 256, NW = 4;
+    __shared__ float s_acc[NW][T * T];
+    __shared__ float s_red[NW];
+    __shared__ unsigned int s_cnt[NW];
+    __shared__ int s_next;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float etau = a.etau;
+    const float tau2k = SVR_KZ * a.tau2;
+    const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
+    float* acc = s_acc[wv];
+    int iter = 0;
+    while (true) {
+        int tile = next_tile<NT>(a, work_counter, iter, &s_next);
+        tile = __builtin_amdgcn_readfirstlane(tile);
+        if (tile < 0) break;
+        const TileCoord tc = tile_coord(a, tile);
+        const int2 rg = a.ranges[tile];
+        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
+        __syncthreads();
+        for (int p = tid; p < NW * T * T; p += NT) (&s_acc[0][0])[p] = 0.f;
+        __syncthreads();
+        unsigned int cnt = 0;
+        // instances of this wave: rg.x + wv, rg.x + wv + NW, ...
+        int s = rg.x + wv;
+        Record nxt;
+        if (s < rg.y) nxt = a.rec[a.inst_rec[s]];
+        while (s < rg.y) {
+            const Record R = nxt;
+            const int sn = s + NW;
+            if (sn < rg.y) nxt = a.rec[a.inst_rec[sn]];
+            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+            const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
+            const int area = (w > 0 && h > 0) ? w * h : 0;
+            const float inv_w = 1.f / (float)max(w, 1);
+            for (int c = 0; c < area; c += 64) {
+                const int idx = c + lane;
+                const int yy = (int)(((float)idx + 0.5f) * inv_w);
+                const int xx = idx - yy * w;
+                const int x = b.x0 + xx, y = b.y0 + yy;
+                const float dx = (float)x - b.pxl, dy = (float)y - b.pyl;
+                const float z = fmaf(dx, fmaf(b.a00, dx, 2.f * b.a01 * dy), fmaf(b.a11 * dy, dy, b.bz));
+                const float v = __builtin_amdgcn_exp2f(z) - etau;
+                if (idx < area && yy < h && xx >= 0 && xx < w && v > 0.f) {
+                    float* dst = acc + y * T + x;
+                    *dst = fmaf(b.am, v, *dst);
+                    if (kCount) ++cnt;
+                }
+            }
+            s = sn;
+        }
+        __syncthreads();
+        float sq = 0.f;
+        for (int p = tid; p < T * T; p += NT) {
+            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
+            if (px < tc.W && py < tc.H) {
+                const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
+                const float y = ((s_acc[0][p] + s_acc[1][p]) + s_acc[2][p]) + s_acc[3][p];
+                pred[pi] = y;
+                if (kLoss) {
+                    const float m = mask[pi];
+                    const float r = y - target[pi];
+                    sq = fmaf(m * r, r, sq);
+                    if (grad) grad[pi] = 2.f * m * r * inv_msum;
+                }
+            }
+        }
+        if (kLoss || kCount) {
+            for (int o = 32; o > 0; o >>= 1) {
+                sq += __shfl_xor(sq, o, 64);
+                if (kCount) cnt += __shfl_xor(cnt, o, 64);
+            }
+            if (lane == 0) {
+                s_red[wv] = sq;
+                s_cnt[wv] = cnt;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                float t = 0.f;
+                unsigned long long cc = 0;
+                for (int q = 0; q < NW; ++q) {
+                    t += s_red[q];
+                    cc += s_cnt[q];
+                }
+                if (kLoss) tile_sse[tile] = t;
+                if (kCount && cc) atomicAdd(incut, cc);
+            }
+        }
+    }
+}
+
+// Adjoint, record per lane: the tile's upstream gradient is staged in LDS;
+// every lane walks its record's box and sums, with t = g e (inside the cut):
+//   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
+//   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
+// from which the gradient with respect to the stored record fields follows
+// (dz/d field, times amp ln 2).  The result goes to the instance's emission
+// slot, so no atomics are needed.
+template <int T>
+__global__ __launch_bounds__(256) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
+                                                  const float* __restrict__ grad_scale,
+                                                  float4* __restrict__ inst_grad,
+                                                  int* __restrict__ work_counter) {
+    constexpr int NT = 256;
     __shared__ float s_g[T * T];
     __shared__ int s_next;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wv = tid >> 6;
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float scale = grad_scale ? grad_scale[0] : 1.f;
     int iter = 0;
     while (true) {
         const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
-        if (tile == -1 || tile == -2) break;
+        if (tile < 0) break;
         const TileCoord tc = tile_coord(a, tile);
         const int2 rg = a.ranges[tile];
+        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
         __syncthreads();
         for (int p = tid; p < T * T; p += NT) {
             const int px = tc.x0 + p % T, py = tc.y0 + p / T;
-            float g = 0.f;
-            if (px < tc.W && py < tc.H) g = grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale;
-            s_g[p] = g;
+            s_g[p] = (px < tc.W && py < tc.H) ? grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale : 0.f;
         }
         __syncthreads();
         const int n = rg.y - rg.x;
-        for (int c0 = wv * 64; c0 < n; c0 += NW * 64) {
-            const int s = c0 + lane;
-            if (s >= n) continue;
-            const uint32_t rid = a.inst_rec[rg.x + s];
-            const Record R = a.rec[rid];
-            const float pxl = R.r0.x - (float)tc.x0, pyl = R.r0.y - (float)tc.y0;
-            const float bz = R.r0.z, am = R.r0.w;
-            const float a00 = R.r1.x, a01 = R.r1.y, a11 = R.r1.z;
-            const float det = a00 * a11 - a01 * a01;
-            const float rk = tau2k - bz;  // KZ (T^2 - beta) <= 0
-            const float hx = sqrtf(fmaxf(rk * a11 / det, 0.f)) + 1e-3f;
-            const float hy = sqrtf(fmaxf(rk * a00 / det, 0.f)) + 1e-3f;
-            const int x0 = max((int)ceilf(pxl - hx), 0), x1 = min((int)floorf(pxl + hx), T - 1);
-            const int y0 = max((int)ceilf(pyl - hy), 0), y1 = min((int)floorf(pyl + hy), T - 1);
+        for (int s = tid; s < n; s += NT) {
+            const uint32_t e_slot = a.inst_idx[rg.x + s];
+            const Record R = a.rec[a.inst_rec[rg.x + s]];
+            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
             float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-            if (x0 <= x1 && y0 <= y1) {
-                const float a01x2 = 2.f * a01;
-                for (int y = y0; y <= y1; ++y) {
-                    const float dy = (float)y - pyl;
-                    const float zy = fmaf(a11 * dy, dy, bz);
-                    const float bx = a01x2 * dy;
-                    for (int x = x0; x <= x1; ++x) {
-                        const float dx = (float)x - pxl;
-                        const float z = fmaf(dx, fmaf(a00, dx, bx), zy);
-                        const float e = __builtin_amdgcn_exp2f(z);
-                        const float g = s_g[y * T + x];
-                        const float v = e - etau;
-                        Sa = fmaf(g, fmaxf(v, 0.f), Sa);
-                        const float t = (v > 0.f) ? g * e : 0.f;
-                        const float tx = t * dx;
-                        S0 += t;
-                        Sx += tx;
-                        Sy = fmaf(t, dy, Sy);
-                        Sxx = fmaf(tx, dx, Sxx);
-                        Sxy = fmaf(tx, dy, Sxy);
-                        Syy = fmaf(t * dy, dy, Syy);
-                    }
-                }
-            }
-            // dz/d(stored) with t = g e, times amp * ln 2
-            const float k2 = am * SVR_LN2;
-            const float dbz = k2 * S0;
-            const float dpx = -2.f * k2 * (a00 * Sx + a01 * Sy);
-            const float dpy = -2.f * k2 * (a01 * Sx + a11 * Sy);
-            const float da00 = k2 * Sxx, da01 = 2.f * k2 * Sxy, da11 = k2 * Syy;
-            float* dst = rgrad[rid].v;
-            if (Sa != 0.f) unsafeAtomicAdd(dst + 0, Sa);
-            if (S0 != 0.f) {
-                unsafeAtomicAdd(dst + 1, dbz);
-                unsafeAtomicAdd(dst + 2, dpx);
-                unsafeAtomicAdd(dst + 3, dpy);
-                unsafeAtomicAdd(dst + 4, da00);
-                unsafeAtomicAdd(dst + 5, da01);
-                unsafeAtomicAdd(dst + 6, da11);
-            }
+            walk_box(b, [&](int x, int y, float dx, float dy, float e) {
+                const float g = s_g[y * T + x];
+                const float v = e - etau;
+                Sa = fmaf(g, fmaxf(v, 0.f), Sa);
+                const float t = (v > 0.f) ? g * e : 0.f;
+                const float tx = t * dx, ty = t * dy;
+                S0 += t;
+                Sx += tx;
+                Sy += ty;
+                Sxx = fmaf(tx, dx, Sxx);
+                Sxy = fmaf(tx, dy, Sxy);
+                Syy = fmaf(ty, dy, Syy);
+            });
+            const float k2 = b.am * SVR_LN2;
+            float4 g0, g1;
+            g0.x = Sa;
+            g0.y = k2 * S0;
+            g0.z = -2.f * k2 * (b.a00 * Sx + b.a01 * Sy);
+            g0.w = -2.f * k2 * (b.a01 * Sx + b.a11 * Sy);
+            g1.x = k2 * Sxx;
+            g1.y = 2.f * k2 * Sxy;
+            g1.z = k2 * Syy;
+            g1.w = 0.f;
+            inst_grad[2 * (int64_t)e_slot] = g0;
+            inst_grad[2 * (int64_t)e_slot + 1] = g1;
         }
     }
 }
@@ -418,6 +641,48 @@ hipError_t launch_mask_sum(const float* mask, int64_t n, float* partial, float* 
     return hipGetLastError();
 }
 
+template <int T>
+hipError_t fwd_rol_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
+                            float* pred, float* grad, float* tile_sse, unsigned long long* incut,
+                            int* work_counter, int grid, hipStream_t st) {
+    const bool loss = target != nullptr;
+    const bool count = incut != nullptr;
+    if (loss && count)
+        hipLaunchKernelGGL((k_forward_rol<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else if (loss)
+        hipLaunchKernelGGL((k_forward_rol<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else if (count)
+        hipLaunchKernelGGL((k_forward_rol<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else
+        hipLaunchKernelGGL((k_forward_rol<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t fwd_rpl_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
+                            float* pred, float* grad, float* tile_sse, unsigned long long* incut,
+                            int* work_counter, int grid, hipStream_t st) {
+    const bool loss = target != nullptr;
+    const bool count = incut != nullptr;
+    if (loss && count)
+        hipLaunchKernelGGL((k_forward_rpl<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else if (loss)
+        hipLaunchKernelGGL((k_forward_rpl<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else if (count)
+        hipLaunchKernelGGL((k_forward_rpl<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    else
+        hipLaunchKernelGGL((k_forward_rpl<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask, const float* msum,
                           float* pred, float* grad_pred, float* tile_sse, unsigned long long* incut,
                           int* work_counter, hipStream_t st) {
@@ -425,6 +690,24 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
     if (a.persistent) {
         hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
         if (e != hipSuccess) return e;
+    }
+    if (a.forward_mode == 2) {
+        const int grid = grid_for(a, 256);
+        switch (a.tile) {
+            case 8: return fwd_rol_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 16: return fwd_rol_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 32: return fwd_rol_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.forward_mode == 1) {
+        const int grid = grid_for(a, 256);
+        switch (a.tile) {
+            case 8: return fwd_rpl_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 16: return fwd_rpl_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 32: return fwd_rpl_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            default: return hipErrorInvalidValue;
+        }
     }
     switch (a.tile) {
         case 8: return fwd_dispatch<8, 1>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid_for(a, 64), st);
@@ -443,21 +726,22 @@ hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int3
 }
 
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           RecGrad* rgrad, int* work_counter, hipStream_t st) {
+                           float4* inst_grad, int* work_counter, hipStream_t st) {
     if (a.n_tiles <= 0) return hipSuccess;
     if (a.persistent) {
         hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
         if (e != hipSuccess) return e;
     }
+    const int grid = grid_for(a, 256);
     switch (a.tile) {
         case 8:
-            hipLaunchKernelGGL((k_backward<8, 1>), dim3(grid_for(a, 64)), dim3(64), 0, st, a, grad_pred, grad_scale, rgrad, work_counter);
+            hipLaunchKernelGGL((k_backward<8>), dim3(grid), dim3(256), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
             break;
         case 16:
-            hipLaunchKernelGGL((k_backward<16, 1>), dim3(grid_for(a, 256)), dim3(256), 0, st, a, grad_pred, grad_scale, rgrad, work_counter);
+            hipLaunchKernelGGL((k_backward<16>), dim3(grid), dim3(256), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
             break;
         case 32:
-            hipLaunchKernelGGL((k_backward<32, 4>), dim3(grid_for(a, 256)), dim3(256), 0, st, a, grad_pred, grad_scale, rgrad, work_counter);
+            hipLaunchKernelGGL((k_backward<32>), dim3(grid), dim3(256), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
             break;
         default: return hipErrorInvalidValue;
     }

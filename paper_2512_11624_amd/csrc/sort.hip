@@ -1,4 +1,7 @@
-// Stable LSD radix sort of 32-bit (key, value) pairs for tile binning.
+// Stable LSD radix sort of 32-bit (key, value) pairs for tile binning.  The
+// binning sort also carries each pair's input position as a second payload
+// (generated on the first pass), so later stages can find an instance's
+// emission slot without an inverse permutation.
 //
 // Each pass sorts on an 8-bit digit:
 //   1. upsweep: per-block digit histogram in LDS  -> hist[digit * nblocks + block]
@@ -40,10 +43,13 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const uint32_t* __restrict
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
 }
 
+template <int kIdx>  // 0: no second payload; 1: second payload read; 2: second payload = input index
 __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restrict__ keys_in,
                                                         const uint32_t* __restrict__ vals_in,
                                                         uint32_t* __restrict__ keys_out,
-                                                        uint32_t* __restrict__ vals_out, int64_t n,
+                                                        uint32_t* __restrict__ vals_out,
+                                                        const uint32_t* __restrict__ idx_in,
+                                                        uint32_t* __restrict__ idx_out, int64_t n,
                                                         int shift, int nbits,
                                                         const int* __restrict__ offs, int nb) {
     __shared__ int s_cnt[kWaves][kRadix];
@@ -52,6 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
     __shared__ int s_wsum[kWaves];
     __shared__ uint32_t s_k[kItems];
     __shared__ uint32_t s_v[kItems];
+    __shared__ uint32_t s_x[kIdx ? kItems : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int q = 0; q < kWaves; ++q) s_cnt[q][tid] = 0;
@@ -60,13 +67,15 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
 
     const int64_t base = (int64_t)blockIdx.x * kItems;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t kk[kIters], vv[kIters];
+    uint32_t kk[kIters], vv[kIters], xx[kIdx ? kIters : 1];
     int rk[kIters];
     for (int it = 0; it < kIters; ++it) {
         const int64_t i = base + (int64_t)w * (kIters * 64) + (int64_t)it * 64 + lane;
         const bool valid = i < n;
         const uint32_t key = valid ? keys_in[i] : 0u;
         const uint32_t val = valid ? vals_in[i] : 0u;
+        if (kIdx == 1) xx[it] = valid ? idx_in[i] : 0u;
+        if (kIdx == 2) xx[it] = (uint32_t)i;
         const int d = (int)((key >> shift) & (kRadix - 1));
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
@@ -114,6 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
             const int pos = s_dstart[d] + s_cnt[w][d] + rk[it];
             s_k[pos] = kk[it];
             s_v[pos] = vv[it];
+            if (kIdx) s_x[pos] = xx[it];
         }
     }
     __syncthreads();
@@ -125,6 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
         const int64_t g = (int64_t)s_gofs[d] + (p - s_dstart[d]);
         keys_out[g] = key;
         vals_out[g] = s_v[p];
+        if (kIdx) idx_out[g] = s_x[p];
     }
 }
 
@@ -140,9 +151,9 @@ size_t sort_tmp_bytes(int64_t n) {
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              int64_t n, int key_bits, void* tmp, bool* result_in_alt,
-                             hipStream_t st) {
+                             hipStream_t st, uint32_t* idx, uint32_t* idx_alt) {
     *result_in_alt = false;
-    if (n <= 1 || key_bits <= 0) return hipSuccess;
+    if (n <= 0 || key_bits <= 0) return hipSuccess;
     const int64_t nb = (n + kItems - 1) / kItems;
     const int64_t nh = nb * kRadix;
     int* hist = (int*)tmp;
@@ -151,18 +162,29 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
     a = (a + 255) & ~(size_t)255;
     void* stmp = (char*)tmp + a;
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    uint32_t *xi = idx, *xo = idx_alt;
     bool alt = false;
+    bool first = true;
     for (int shift = 0; shift < key_bits; shift += 8) {
         const int nbits = (key_bits - shift) < 8 ? (key_bits - shift) : 8;
         hipLaunchKernelGGL(k_upsweep, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n, shift, hist, (int)nb);
         hipError_t e = launch_scan_int(hist, offs, nh, nullptr, stmp, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_downsweep, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo, n,
-                           shift, nbits, (const int*)offs, (int)nb);
+        if (!idx)
+            hipLaunchKernelGGL(k_downsweep<0>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                               (const uint32_t*)nullptr, (uint32_t*)nullptr, n, shift, nbits, (const int*)offs, (int)nb);
+        else if (first)
+            hipLaunchKernelGGL(k_downsweep<2>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                               (const uint32_t*)nullptr, xo, n, shift, nbits, (const int*)offs, (int)nb);
+        else
+            hipLaunchKernelGGL(k_downsweep<1>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                               (const uint32_t*)xi, xo, n, shift, nbits, (const int*)offs, (int)nb);
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
+        t = xi; xi = xo; xo = t;
         alt = !alt;
+        first = false;
     }
     *result_in_alt = alt;
     return hipGetLastError();

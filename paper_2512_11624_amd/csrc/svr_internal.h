@@ -8,6 +8,9 @@
 // exp(-x/2) = exp2(KZ * x)
 #define SVR_KZ (-0.5f * SVR_LOG2E)
 
+// Instance sort key = (global tile id << kClassBits) | footprint size class.
+constexpr int kClassBits = 3;
+
 // Static per-slice geometry (depends on the tile size through the tile table).
 struct SliceGeo {
     float R0[9];
@@ -51,11 +54,10 @@ struct Record {
     float4 r1;
 };
 
-// Per-record gradient accumulator (sums over the record's pixels):
-//   (d amp, d beta', d p*_x, d p*_y, d A'_00, d A'_01, d A'_11, unused)
-struct RecGrad {
-    float v[8];
-};
+// Per-instance gradient (sums over the instance's pixels), two float4 per
+// instance at its emission slot:
+//   (d amp, d beta', d p*_x, d p*_y | d A'_00, d A'_01, d A'_11, unused)
+// A record's instances occupy the contiguous slots rec_inst[r] = (first, count).
 
 // ---------------------------------------------------------------------------
 // Host-side launchers (one per translation unit), all asynchronous on stream.
@@ -80,11 +82,12 @@ hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* 
                              hipStream_t st);
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st);
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       uint32_t* keys, uint32_t* vals, hipStream_t st);
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
-                                   const Record* rec, const RecGrad* rgrad, float* g_mean,
-                                   float* g_log_scale, float* g_quat, float* g_amp, float* pose_acc,
-                                   int32_t max_subject_slices, hipStream_t st);
+                                   const Record* rec, const int2* rec_inst, const float4* inst_grad,
+                                   int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,
+                                   float* g_amp, float* pose_acc, int32_t max_subject_slices,
+                                   hipStream_t st);
 hipError_t launch_pose_chain(const float* pose, const float* pose_acc, float* g_pose, int32_t m,
                              hipStream_t st);
 
@@ -95,23 +98,28 @@ hipError_t launch_scan_int2(const int2* in, int2* out, int64_t n, long long* tot
                             hipStream_t st);
 
 // Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
-// Buffers are ping-ponged; *result_in_alt tells where the result ended.
+// Buffers are ping-ponged; *result_in_alt tells where the result ended.  When
+// idx/idx_alt are given, the input position of every pair travels with it
+// (ending in the same buffer parity as keys).
 size_t sort_tmp_bytes(int64_t n);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
-                             bool* result_in_alt, hipStream_t st);
+                             bool* result_in_alt, hipStream_t st, uint32_t* idx = nullptr,
+                             uint32_t* idx_alt = nullptr);
 
 struct RenderArgs {
     const SliceGeo* geo;
     const int32_t* tile_slice;   // [n_tiles]
     const int2* ranges;          // [n_tiles] [start, end) into sorted instances
     const uint32_t* inst_rec;    // sorted instance -> record id
+    const uint32_t* inst_idx;    // sorted instance -> emission slot
     const Record* rec;
     const int32_t* tile_order;   // persistent mode: tiles by decreasing cost (or NULL)
     int32_t n_tiles;
     int32_t tile;
     int32_t batch;
     int32_t persistent;
+    int32_t forward_mode;        // 0: pixel per lane, 1: record per lane
     float etau;                  // exp(-T^2/2)
     float tau2;                  // T^2
     int32_t n_cu;                // compute units (persistent grid size)
@@ -128,7 +136,7 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
 hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m,
                                 const float* msum, float* slice_sse, float* loss, hipStream_t st);
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           RecGrad* rgrad, int* work_counter, hipStream_t st);
+                           float4* inst_grad, int* work_counter, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 struct AdamSeg {

@@ -21,7 +21,7 @@ _lock = threading.Lock()
 
 SVR_OK, SVR_ERR_ARG, SVR_ERR_HIP, SVR_ERR_CAPACITY, SVR_ERR_STATE, SVR_ERR_NODEVICE = 0, -1, -2, -3, -4, -5
 SVR_STATS_SYNC = 1
-SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_ALL = 1, 2, 4, 7
+SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_MODE, SVR_TUNE_ALL = 1, 2, 4, 8, 15
 
 vp = C.c_void_p
 
@@ -34,10 +34,11 @@ class svr_geometry(C.Structure):
 
 class svr_config(C.Structure):
     _fields_ = [("tile", C.c_int32), ("batch", C.c_int32), ("persistent", C.c_int32),
-                ("cutoff", C.c_float)]
+                ("cutoff", C.c_float), ("forward_mode", C.c_int32)]
 
     def as_dict(self):
-        return dict(tile=self.tile, batch=self.batch, persistent=self.persistent, cutoff=self.cutoff)
+        return dict(tile=self.tile, batch=self.batch, persistent=self.persistent, cutoff=self.cutoff,
+                    forward_mode=self.forward_mode)
 
 
 class svr_params(C.Structure):
@@ -184,11 +185,12 @@ class Context:
         self.n_slices = int(len(arrs["h"]))
         self.n_pixels = int(load().svr_num_pixels(self.h))
 
-    def svr_set_config(self, tile=None, batch=None, persistent=None, cutoff=None):
+    def svr_set_config(self, tile=None, batch=None, persistent=None, cutoff=None, forward_mode=None):
         cur = self.svr_get_config()
         cfg = svr_config(cur["tile"] if tile is None else tile, cur["batch"] if batch is None else batch,
                          cur["persistent"] if persistent is None else persistent,
-                         cur["cutoff"] if cutoff is None else cutoff)
+                         cur["cutoff"] if cutoff is None else cutoff,
+                         cur["forward_mode"] if forward_mode is None else forward_mode)
         self._check(load().svr_set_config(self.h, C.byref(cfg)), "svr_set_config")
 
     def svr_get_config(self):

@@ -432,3 +432,30 @@ def tiny(seed: int, n_gauss: int = 6, n_slices: int = 2, size=(9, 11), spacing=(
     mu, ls, q, c, sp, fw, rot, trans, pose = _f32(mu, ls, q, c, sp, fw, rot, trans, pose)
     return Problem(mu, ls, q, c, np.array([0, n_gauss], np.int64), subj, H, W, sp, fw,
                    rot, trans, pose, mask, name="tiny")
+
+
+def head_observation(problem: Problem, seed: int, snr: float = 20.0, thickness_samples: int = 5):
+    """Synthetic observed slices of the head phantom (not of its Gaussian fit):
+    the piecewise-constant phantom times its bias field, averaged over
+    ``thickness_samples`` points across the slice thickness at every pixel
+    centre of the true pose, with Rician noise at the given SNR.  An input
+    only: it involves no Gaussian-model arithmetic."""
+    axes = problem.extra["axes"]
+    bp = problem.extra["bias"]
+    out = []
+    offs = (np.arange(thickness_samples) - (thickness_samples - 1) / 2) / thickness_samples
+    for i in range(problem.n_slices):
+        R = Rotation.from_rotvec(problem.pose[i, :3].astype(np.float64)).as_matrix() @ problem.rot0[i].reshape(3, 3)
+        normal = R[:, 2]
+        th = float(problem.psf_fwhm[i, 2])
+        pos = pixel_world_positions(problem.rot0, problem.trans0, problem.pose, problem.height, problem.width,
+                                    problem.spacing, slice_ids=[i])[0]
+        acc = np.zeros(len(pos))
+        for o in offs:
+            x = pos + (o * th) * normal[None, :]
+            acc += head_intensity(x, axes) * head_bias(x, bp, axes)
+        out.append(acc / thickness_samples)
+    clean = np.concatenate(out)
+    m = problem.mask > 0
+    sigma = float(clean[m].mean()) / snr if m.any() else 0.05
+    return rician(clean, seed, sigma)

@@ -83,16 +83,19 @@ def test_cube_forward_backward_parity(ctx):
     """Cube phantom (2,000 Gaussians, 48 slices of 32x32): every output block."""
     prob = synth.config1(0)
     params, pose, target = _setup(prob)
-    out = _run(ctx, prob, params, pose, target, cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0))
+    out = _run(ctx, prob, params, pose, target, cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=0))
     ref = _oracle(prob, params, pose, target)
     _compare(out, ref)
 
 
-@pytest.mark.parametrize("tile,batch,persistent", [(8, 32, 0), (16, 64, 1), (32, 256, 0), (32, 96, 1)])
-def test_cube_parity_all_configs(ctx, tile, batch, persistent):
+@pytest.mark.parametrize("tile,batch,persistent,mode", [(8, 32, 0, 0), (16, 64, 1, 0), (32, 256, 0, 0), (32, 96, 1, 0),
+                                                        (8, 128, 1, 1), (16, 128, 0, 1), (32, 128, 1, 1),
+                                                        (8, 128, 0, 2), (16, 128, 1, 2), (32, 128, 0, 2)])
+def test_cube_parity_all_configs(ctx, tile, batch, persistent, mode):
     prob = synth.config1(0, n_gauss=800)
     params, pose, target = _setup(prob, seed=3)
-    out = _run(ctx, prob, params, pose, target, cfg=dict(tile=tile, batch=batch, persistent=persistent, cutoff=3.0))
+    out = _run(ctx, prob, params, pose, target,
+               cfg=dict(tile=tile, batch=batch, persistent=persistent, cutoff=3.0, forward_mode=mode))
     ref = _oracle(prob, params, pose, target)
     _compare(out, ref)
 
@@ -104,8 +107,9 @@ def test_ragged_slices_and_subjects(ctx):
             synth.config1(6, n_gauss=500, size=45, n_per_stack=4, n_stacks=2)]
     prob = synth.concat(subs)
     params, pose, target = _setup(prob, seed=5)
-    for tile in (8, 16, 32):
-        out = _run(ctx, prob, params, pose, target, cfg=dict(tile=tile, batch=128, persistent=tile == 16, cutoff=3.0))
+    for tile, mode in ((8, 0), (16, 1), (32, 0), (32, 1), (16, 2), (32, 2)):
+        out = _run(ctx, prob, params, pose, target,
+                   cfg=dict(tile=tile, batch=128, persistent=int(tile == 16), cutoff=3.0, forward_mode=mode))
         ref = _oracle(prob, params, pose, target)
         _compare(out, ref)
 
@@ -245,3 +249,43 @@ def test_autograd_function(ctx):
     core, bnd = ref["grad_band"]
     for k, t in zip(("mean", "log_scale", "quat", "amp", "pose"), dev):
         print(check_band(t.grad.cpu().numpy(), 3.0 * core[k], 3.0 * bnd[k], k))
+
+
+# --------------------------------------------------------------- full size ---
+# The full workloads in the launch configurations the benchmark uses.  The
+# oracle (FP64, OpenMP) is fast enough to evaluate every pixel and every
+# gradient at these sizes, so every output block is compared in full.
+
+BENCH_CONFIGS = [dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2),
+                 dict(tile=32, batch=128, persistent=1, cutoff=3.0, forward_mode=1),
+                 dict(tile=16, batch=128, persistent=1, cutoff=3.0, forward_mode=0)]
+
+
+@pytest.fixture(scope="module")
+def head_full():
+    prob = synth.config2(0)
+    target = synth.head_observation(prob, 5, thickness_samples=3)
+    params = synth.perturb_params(prob, 7, d_mu=0.2, d_ls=0.05, d_q=0.05, d_c=0.02)
+    pose = np.zeros((prob.n_slices, 6), np.float32)      # identity pose initialisation
+    ref = _oracle(prob, params, pose, target)
+    return prob, params, pose, target, ref
+
+
+@pytest.mark.parametrize("cfg", BENCH_CONFIGS, ids=["tile16-rol", "tile32-rpl-persistent", "tile16-pixel-persistent"])
+def test_head_full_size_parity(ctx, head_full, cfg):
+    """Head phantom at full size: 500k Gaussians, 128 slices of 256x256."""
+    prob, params, pose, target, ref = head_full
+    out = _run(ctx, prob, params, pose, target, cfg=cfg)
+    _compare(out, ref)
+
+
+def test_stress_full_size_parity(ctx):
+    """Differentiation stress at full size: 1.2M Gaussians, 240 slices of
+    320x320 with interleaved motion segments; all 240 six-DoF pose gradients."""
+    prob = synth.config3(0)
+    params = synth.perturb_params(prob, 3, d_mu=0.1, d_ls=0.03, d_q=0.03, d_c=0.01)
+    pose = prob.pose + np.random.default_rng(4).normal(0, 0.002, prob.pose.shape).astype(np.float32)
+    target = (0.6 * prob.mask + synth.gaussian_noise(8, prob.n_pixels, 0.05)).astype(np.float32)
+    out = _run(ctx, prob, params, pose, target, cfg=BENCH_CONFIGS[0])
+    ref = _oracle(prob, params, pose, target)
+    _compare(out, ref)

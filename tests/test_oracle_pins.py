@@ -373,3 +373,44 @@ def test_band_split_bounds_the_standard_evaluation(oracle_lib):
     assert np.all(np.abs(y - yc) <= yb * (1 + 1e-12) + 1e-15) and yb.max() > 0
     yc0, yb0 = oracle_lib.forward_band(p, 3.0, 0.0)
     assert np.allclose(yc0, y, rtol=1e-13, atol=1e-15) and np.all(yb0 == 0)
+
+
+def test_p8_fd_stress_subproblem(oracle_lib):
+    """Central differences on the differentiation-stress geometry: the 500
+    Gaussians nearest the head centre, crops of a few slices through them,
+    interleaved-segment motion; a sample of parameters of every block and all
+    six pose coordinates of every cropped slice."""
+    W = 48   # the central 48x48 pixels of 320x320 slices: same centres and spacing
+    full = synth.config3(0, n_gauss=60000, n_per_stack=40, size=W)
+    d = np.linalg.norm(full.mean, axis=1)
+    near = np.argsort(d)[:500]
+    sel = np.array([19, 20, 60, 100, 139, 180, 221])      # slices through the centre of several stacks
+    sub = synth.Problem(full.mean[near], full.log_scale[near], full.quat[near], full.amp[near],
+                        np.array([0, 500], np.int64), np.zeros(len(sel), np.int32), np.full(len(sel), W, np.int32),
+                        np.full(len(sel), W, np.int32), full.spacing[sel], full.psf_fwhm[sel], full.rot0[sel],
+                        full.trans0[sel], full.pose[sel], np.ones(len(sel) * W * W, np.float32))
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(sub.n_pixels)
+    tau = np.inf
+    an = oracle_lib.backward(sub, g, tau)
+    base = dict(mean=sub.mean.astype(np.float64), log_scale=sub.log_scale.astype(np.float64),
+                quat=sub.quat.astype(np.float64), amp=sub.amp.astype(np.float64), pose=sub.pose.astype(np.float64))
+
+    def loss(vals):
+        y = oracle_lib.forward(sub, tau, params=(vals["mean"], vals["log_scale"], vals["quat"], vals["amp"]),
+                               pose=vals["pose"])
+        return g @ y
+
+    picks = {k: [tuple(rng.integers(0, s) for s in base[k].shape) for _ in range(12)] for k in
+             ("mean", "log_scale", "quat", "amp")}
+    picks["pose"] = [(i, c) for i in range(len(sel)) for c in range(6)]
+    for name, idxs in picks.items():
+        scale = max(np.abs(an[name]).max(), 1e-12)
+        for idx in idxs:
+            h = 1e-6 * max(1.0, abs(base[name][idx]))
+            vp = {k: v.copy() for k, v in base.items()}
+            vm = {k: v.copy() for k, v in base.items()}
+            vp[name][idx] += h
+            vm[name][idx] -= h
+            fd = (loss(vp) - loss(vm)) / (2 * h)
+            assert abs(fd - an[name][idx]) <= 1e-6 * scale, (name, idx, fd, an[name][idx], scale)
