@@ -82,7 +82,7 @@ struct svr_ctx {
     DevBuf<char> d_sort_tmp;
     DevBuf<int2> d_ranges;
     DevBuf<float> d_tile_sse, d_partial, d_msum, d_slice_sse, d_pose_acc;
-    DevBuf<int> d_work;
+    DevBuf<int> d_work, d_fallback;
     DevBuf<unsigned long long> d_incut;
     DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
     DevBuf<char> d_tsort_tmp;
@@ -396,6 +396,7 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
         cand += (c->gauss_off[s + 1] - c->gauss_off[s]) * (int64_t)ns;
     }
     c->n_cand = cand;
+    HIPCHK(c, ensure(c->d_fallback, (size_t)std::max(c->n_blocks, 1)));
     HIPCHK(c, ensure(c->d_rec, (size_t)nrec));
     HIPCHK(c, ensure(c->d_rec_inst, (size_t)nrec));
     HIPCHK(c, ensure(c->d_inst_grad, 2 * (size_t)ninst));
@@ -409,7 +410,7 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     {
         StageScope sc(c, ST_EMIT);
         HIPCHK(c, launch_emit(pa, c->d_counts.p, c->d_offsets.p, c->d_rec.p, c->d_rec_inst.p, c->d_keys.p,
-                              c->d_vals.p, st));
+                              c->d_vals.p, c->d_fallback.p, st));
     }
     bool alt = false;
     {
@@ -497,6 +498,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_vals); release(c->d_keys2); release(c->d_vals2); release(c->d_sort_tmp);
         release(c->d_ranges); release(c->d_tile_sse); release(c->d_partial); release(c->d_msum);
         release(c->d_slice_sse); release(c->d_pose_acc); release(c->d_work); release(c->d_incut);
+        release(c->d_fallback);
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
         if (c->h_totals) (void)hipHostFree(c->h_totals);

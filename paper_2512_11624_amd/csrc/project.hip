@@ -162,6 +162,14 @@ __device__ inline Box pixel_box(const Proj& p, const SliceGeo& sg, float tau2) {
     return bx;
 }
 
+// A record that contributes nothing (slice -1, zero amplitude, no instances).
+__device__ inline Record null_record() {
+    Record z;
+    z.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    z.r1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+    return z;
+}
+
 __device__ inline Record make_record(const Proj& p, const SliceGeo& sg, float c, int32_t slice) {
     Record r;
     r.r0.x = p.u0 / sg.dx + 0.5f * (float)(sg.W - 1);
@@ -220,8 +228,9 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
                                                  const int2* __restrict__ offsets,
                                                  Record* __restrict__ rec, int2* __restrict__ rec_inst,
                                                  uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals) {
+                                                 uint32_t* __restrict__ vals, const int* __restrict__ only) {
     __shared__ uint16_t s_list[kList][kBlock];
+    if (kEmit && only && only[blockIdx.x] == 0) return;  // emitted by the coalesced path
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
     const int64_t j = blk.g_begin + threadIdx.x;
@@ -248,7 +257,15 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
             Proj p;
             project(g, sp, sg.sig2, tau2, p);
             const Box bx = pixel_box(p, sg, tau2);
-            if (!bx.nonempty) continue;
+            if (!bx.nonempty) {
+                // the plane crosses the footprint outside the slice: a null record
+                if (kEmit && nrec < cap.x) {
+                    rec[ro + nrec] = null_record();
+                    rec_inst[ro + nrec] = make_int2(0, 0);
+                }
+                ++nrec;
+                continue;
+            }
             const int tx0 = bx.kx0 / T, tx1 = bx.kx1 / T, ty0 = bx.ky0 / T, ty1 = bx.ky1 / T;
             const int nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
             if (kEmit) {
@@ -291,10 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
         // ever disagreed): records with slice -1, instances with a key above
         // every tile id, so that no later stage reads them
         for (int k = nrec; k < cap.x; ++k) {
-            Record z;
-            z.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-            z.r1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-            rec[ro + k] = z;
+            rec[ro + k] = null_record();
             rec_inst[ro + k] = make_int2(0, 0);
         }
         for (int k = ninst; k < cap.y; ++k) {
@@ -305,60 +319,212 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// K10: projection adjoint, one thread per Gaussian over its records.
-// Record gradients are in stored units (see RecGrad); they are chained back
-// through the pixel-unit scaling, the Schur complement, the slice rotation
-// and the Gaussian activation.  Slice-pose gradients (left perturbation delta
-// of R_i and translation t_i) are pre-reduced in LDS per block.
+// K5 (coalesced): the block's records occupy one contiguous range (Gaussian
+// major, slice minor).  The uniform slice loop only runs the plane test and
+// drops each survivor's (Gaussian, slice) into an LDS list at its final
+// position (offsets of the count pass); then every thread of the block
+// projects one list entry at a time -- dense work, no divergence on the
+// survivor pattern -- and records, instance ranges and instance keys are
+// written with neighbouring lanes on neighbouring addresses.  Blocks whose
+// record range exceeds the LDS list fall back to the per-lane path.
 // ---------------------------------------------------------------------------
+constexpr int kEmitCap = 6144;  // list entries per block
+
+__global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __restrict__ counts,
+                                                 const int2* __restrict__ offsets, Record* __restrict__ rec,
+                                                 int2* __restrict__ rec_inst, uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals, int* __restrict__ fallback) {
+    __shared__ uint32_t s_list[kEmitCap];
+    __shared__ int s_wsum[kBlock / 64];
+    __shared__ int s_pad_from;  // first instance slot (block-relative) left unwritten
+    const GaussBlock blk = a.blocks[blockIdx.x];
+    const SubjectInfo si = a.subj[blk.subject];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int ng = (int)(blk.g_end - blk.g_begin);
+    const int64_t R0 = offsets[blk.g_begin].x, I0 = offsets[blk.g_begin].y;
+    const int64_t R1 = offsets[blk.g_end - 1].x + counts[blk.g_end - 1].x;
+    const int64_t I1 = offsets[blk.g_end - 1].y + counts[blk.g_end - 1].y;
+    const int nrec_blk = (int)(R1 - R0);
+    if (nrec_blk > kEmitCap) {
+        if (tid == 0) fallback[blockIdx.x] = 1;
+        return;
+    }
+    if (tid == 0) {
+        fallback[blockIdx.x] = 0;
+        s_pad_from = (int)(I1 - I0);
+    }
+    const int64_t j = blk.g_begin + tid;
+    const bool valid = tid < ng;
+    GAct g;
+    if (valid) activate(a, j, g); else activate_dummy(g);
+    const float tau2 = a.tau * a.tau;
+    int loff = 0, lcap = 0, k = 0;
+    if (valid) {
+        loff = (int)(offsets[j].x - R0);
+        lcap = counts[j].x;
+    }
+    for (int i = si.s_begin; i < si.s_end; ++i) {
+        const SlicePose& sp = a.pose[i];
+        const float sig2z = a.geo[i].sig2[2];
+        if (valid && plane_pass(g, sp, sig2z, tau2)) {
+            if (k < lcap) s_list[loff + k] = ((uint32_t)tid << 16) | (uint32_t)(i - si.s_begin);
+            ++k;
+        }
+    }
+    // slots the plane test did not fill again (only if the passes ever disagreed)
+    for (int q = k; q < lcap; ++q) s_list[loff + q] = 0xffffffffu;
+    __syncthreads();
+    const int T = a.tile;
+    int64_t ibase = I0;
+    for (int t0 = 0; t0 < nrec_blk; t0 += kBlock) {
+        const int t = t0 + tid;
+        const uint32_t e = (t < nrec_blk) ? s_list[t] : 0xffffffffu;
+        Record R = null_record();
+        Box bx;
+        bx.nonempty = false;
+        int nt = 0, sl = -1;
+        const SliceGeo* sgp = nullptr;
+        if (e != 0xffffffffu) {
+            const int jl = (int)(e >> 16);
+            sl = si.s_begin + (int)(e & 0xffffu);
+            GAct gj;
+            activate(a, blk.g_begin + jl, gj);
+            sgp = &a.geo[sl];
+            Proj p;
+            project(gj, a.pose[sl], sgp->sig2, tau2, p);
+            bx = pixel_box(p, *sgp, tau2);
+            if (bx.nonempty) {
+                R = make_record(p, *sgp, gj.c, sl);
+                nt = (bx.kx1 / T - bx.kx0 / T + 1) * (bx.ky1 / T - bx.ky0 / T + 1);
+            }
+        }
+        // block exclusive scan of instance counts
+        int incl = nt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) s_wsum[w] = incl;
+        __syncthreads();
+        int wbase = 0, tot = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            if (q < w) wbase += s_wsum[q];
+            tot += s_wsum[q];
+        }
+        __syncthreads();
+        int64_t o = ibase + wbase + incl - nt;
+        if (nt > 0 && o + nt > I1) {  // never write past the block's reserved instances
+            atomicMin(&s_pad_from, (int)(min(o, I1) - I0));
+            nt = 0;
+        }
+        if (t < nrec_blk) {
+            rec[R0 + t] = nt > 0 ? R : null_record();
+            rec_inst[R0 + t] = make_int2((int)o, nt);
+        }
+        if (nt > 0) {
+            const int tx0 = bx.kx0 / T, tx1 = bx.kx1 / T, ty0 = bx.ky0 / T, ty1 = bx.ky1 / T;
+            for (int ty = ty0; ty <= ty1; ++ty) {
+                const int ch = min(bx.ky1, ty * T + T - 1) - max(bx.ky0, ty * T) + 1;
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const int cw = min(bx.kx1, tx * T + T - 1) - max(bx.kx0, tx * T) + 1;
+                    keys[o] = ((uint32_t)(sgp->tile_base + ty * sgp->ntx + tx) << kClassBits) | area_class(cw * ch);
+                    vals[o] = (uint32_t)(R0 + t);
+                    ++o;
+                }
+            }
+        }
+        ibase += tot;
+    }
+    // pad reserved instances nobody wrote (only if the passes ever disagreed)
+    __syncthreads();
+    const int64_t pad0 = min(ibase, I0 + (int64_t)s_pad_from);
+    for (int64_t q = pad0 + tid; q < I1; q += kBlock) {
+        keys[q] = 0xffffffffu;
+        vals[q] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K10: projection adjoint.  One workgroup per block of Gaussians (never
+// straddling subjects); its records are contiguous (Gaussian-major emission),
+// so thread k of the block takes the block's records k, k + 256, ... and all
+// record, instance-slot and gradient reads are coalesced.  A record's owning
+// Gaussian is found by binary search over the block's record offsets in LDS.
+// Each record's gradient (sum of its instance slots, in stored units) is
+// chained back through the pixel-unit scaling, the Schur complement and the
+// slice rotation to
+//   dL/dSigma_j (symmetric), dL/dmu_j, dL/dc_j and the direct sqrt(det) term,
+// reduced over lanes of the same Gaussian with a segmented shuffle scan and
+// added once per segment into LDS accumulators; the slice-pose gradient
+// (left perturbation delta and translation) goes to per-block LDS slice
+// accumulators.  Finally thread j chains dL/dSigma_j to the log-scales and
+// the quaternion and writes the Gaussian's gradient.
+// ---------------------------------------------------------------------------
+constexpr int kGAcc = 11;  // GS (6), gmu (3), gc, glsum
+
 __global__ __launch_bounds__(kBlock) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
     const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
     int64_t n_inst, float* __restrict__ g_mean, float* __restrict__ g_log_scale, float* __restrict__ g_quat,
     float* __restrict__ g_amp, float* __restrict__ pose_acc, int use_lds) {
     extern __shared__ float s_pose[];  // [6 * slices of the subject]
+    __shared__ int s_roff[kBlock + 1];  // record offsets of the block's Gaussians, relative to the first
+    __shared__ float s_gacc[kGAcc][kBlock];
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
     const int ns = si.s_end - si.s_begin;
-    if (use_lds) {
-        for (int k = threadIdx.x; k < 6 * ns; k += blockDim.x) s_pose[k] = 0.f;
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int ng = (int)(blk.g_end - blk.g_begin);
+    const int64_t R0 = offsets[blk.g_begin].x;
+    {
+        const int64_t j = blk.g_begin + tid;
+        if (tid < ng) s_roff[tid] = (int)(offsets[j].x - R0);
+        if (tid == ng - 1) s_roff[ng] = (int)(offsets[j].x + counts[j].x - R0);
+        for (int q = 0; q < kGAcc; ++q) s_gacc[q][tid] = 0.f;
     }
-    const int64_t j = blk.g_begin + threadIdx.x;
-    const bool valid = j < blk.g_end;
+    if (use_lds)
+        for (int k = tid; k < 6 * ns; k += blockDim.x) s_pose[k] = 0.f;
+    __syncthreads();
+    const int nrec_blk = s_roff[ng];
     const float tau2 = a.tau * a.tau;
-    if (valid) {
-        GAct g;
-        activate(a, j, g);
-        float GS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // dL/dSigma_j (full-matrix, symmetric)
-        float gmu[3] = {0.f, 0.f, 0.f};
-        float gc = 0.f, glsum = 0.f;
-        const int64_t r0 = offsets[j].x;
-        const int nrec = counts[j].x;
-        for (int k = 0; k < nrec; ++k) {
-            const Record R = rec[r0 + k];
-            const int i = __float_as_int(R.r1.w);
-            if (i < si.s_begin || i >= si.s_end) continue;  // padding record
-            // sum the record's per-instance moments (contiguous emission slots)
-            const int2 ri = rec_inst[r0 + k];
-            struct { float v[8]; } G;
-            for (int q = 0; q < 8; ++q) G.v[q] = 0.f;
+    for (int base = 0; base < nrec_blk; base += kBlock) {
+        const int lr = base + tid;
+        const bool valid = lr < nrec_blk;
+        // owning Gaussian: largest g with s_roff[g] <= lr
+        int g = 0;
+        if (valid) {
+            int lo = 0, hi = ng - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_roff[mid] <= lr) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+        }
+        float acc[kGAcc];
+        for (int q = 0; q < kGAcc; ++q) acc[q] = 0.f;
+        const Record R = valid ? rec[R0 + lr] : Record{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+        const int i = __float_as_int(R.r1.w);
+        if (valid && i >= si.s_begin && i < si.s_end) {
+            GAct ga;
+            activate(a, blk.g_begin + g, ga);
+            const int2 ri = rec_inst[R0 + lr];
+            float G[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             for (int64_t e = ri.x; e < (int64_t)ri.x + ri.y && e < n_inst; ++e) {
                 const float4 u = inst_grad[2 * e], w = inst_grad[2 * e + 1];
-                G.v[0] += u.x; G.v[1] += u.y; G.v[2] += u.z; G.v[3] += u.w;
-                G.v[4] += w.x; G.v[5] += w.y; G.v[6] += w.z;
+                G[0] += u.x; G[1] += u.y; G[2] += u.z; G[3] += u.w;
+                G[4] += w.x; G[5] += w.y; G[6] += w.z;
             }
             const SliceGeo& sg = a.geo[i];
             const SlicePose& sp = a.pose[i];
             Proj p;
-            project(g, sp, sg.sig2, tau2, p);
+            project(ga, sp, sg.sig2, tau2, p);
             const float is = 1.f / p.s22;
             // stored units -> natural units
-            const float dbeta = SVR_KZ * G.v[1];
-            const float du0 = G.v[2] / sg.dx, du1 = G.v[3] / sg.dy;
-            const float ga00 = SVR_KZ * sg.dx * sg.dx * G.v[4];
-            const float ga01 = 0.5f * SVR_KZ * sg.dx * sg.dy * G.v[5];
-            const float ga11 = SVR_KZ * sg.dy * sg.dy * G.v[6];
+            const float dbeta = SVR_KZ * G[1];
+            const float du0 = G[2] / sg.dx, du1 = G[3] / sg.dy;
+            const float ga00 = SVR_KZ * sg.dx * sg.dx * G[4];
+            const float ga01 = 0.5f * SVR_KZ * sg.dx * sg.dy * G[5];
+            const float ga11 = SVR_KZ * sg.dy * sg.dy * G[6];
             // A = C^-1  ->  G_C = -A G_A A
             const float t00 = p.A00 * ga00 + p.A01 * ga01, t01 = p.A00 * ga01 + p.A01 * ga11;
             const float t10 = p.A01 * ga00 + p.A11 * ga01, t11 = p.A01 * ga01 + p.A11 * ga11;
@@ -366,9 +532,9 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
             float gc01 = -(t00 * p.A01 + t01 * p.A11);
             float gc11 = -(t10 * p.A01 + t11 * p.A11);
             // amplitude a = c f, ln f = lsum - 1/2 ln det C - 1/2 ln s
-            const float gam = G.v[0] * g.c * p.f;
-            gc += G.v[0] * p.f;
-            glsum += gam;
+            const float gam = G[0] * ga.c * p.f;
+            acc[9] = G[0] * p.f;
+            acc[10] = gam;
             gc00 -= 0.5f * gam * p.A00;
             gc01 -= 0.5f * gam * p.A01;
             gc11 -= 0.5f * gam * p.A11;
@@ -393,29 +559,28 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
             for (int u = 0; u < 3; ++u)
                 for (int v = 0; v < 3; ++v)
                     RG[3 * u + v] = sp.R[3 * u] * Gp[v] + sp.R[3 * u + 1] * Gp[3 + v] + sp.R[3 * u + 2] * Gp[6 + v];
-            float Gw[6];
             {
                 int o = 0;
                 for (int u = 0; u < 3; ++u)
                     for (int v = u; v < 3; ++v)
-                        Gw[o++] = RG[3 * u] * sp.R[3 * v] + RG[3 * u + 1] * sp.R[3 * v + 1] + RG[3 * u + 2] * sp.R[3 * v + 2];
+                        acc[o++] = RG[3 * u] * sp.R[3 * v] + RG[3 * u + 1] * sp.R[3 * v + 1] + RG[3 * u + 2] * sp.R[3 * v + 2];
             }
-            for (int q = 0; q < 6; ++q) GS[q] += Gw[q];
             // m = R^T (mu - t): dmu = R dm, dt = -R dm
             const float dm[3] = {du0, du1, dm2};
             float Rdm[3];
             for (int u = 0; u < 3; ++u) Rdm[u] = sp.R[3 * u] * dm[0] + sp.R[3 * u + 1] * dm[1] + sp.R[3 * u + 2] * dm[2];
-            for (int u = 0; u < 3; ++u) gmu[u] += Rdm[u];
+            acc[6] = Rdm[0];
+            acc[7] = Rdm[1];
+            acc[8] = Rdm[2];
             // left perturbation of R_i: d delta = (R dm) x w + 2 (B12, B20, B01),
             // B = G_S Sigma_j - Sigma_j G_S
             float GSig[9];
             for (int u = 0; u < 3; ++u)
                 for (int v = 0; v < 3; ++v) {
-                    float acc = 0.f;
-                    for (int q = 0; q < 3; ++q) acc += sym(Gw, u, q) * sym(g.S, q, v);
-                    GSig[3 * u + v] = acc;
+                    float t = 0.f;
+                    for (int q = 0; q < 3; ++q) t += sym(acc, u, q) * sym(ga.S, q, v);
+                    GSig[3 * u + v] = t;
                 }
-            // B_uv = GSig_uv - GSig_vu (since Sigma G = (G Sigma)^T)
             const float B12 = GSig[5] - GSig[7], B20 = GSig[6] - GSig[2], B01 = GSig[1] - GSig[3];
             float pd[6];
             pd[0] = Rdm[1] * p.w[2] - Rdm[2] * p.w[1] + 2.f * B12;
@@ -431,6 +596,29 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
                 for (int q = 0; q < 6; ++q) atomicAdd(&pose_acc[6 * i + q], pd[q]);
             }
         }
+        // segmented inclusive scan over lanes sharing the same Gaussian
+        const int key = valid ? g : -1;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int k2 = __shfl_up(key, o, 64);
+            const bool take = lane >= o && k2 == key;
+            for (int q = 0; q < kGAcc; ++q) {
+                const float v2 = __shfl_up(acc[q], o, 64);
+                if (take) acc[q] += v2;
+            }
+        }
+        const int knext = __shfl_down(key, 1, 64);
+        const bool tail = valid && (lane == 63 || knext != key);
+        if (tail)
+            for (int q = 0; q < kGAcc; ++q) atomicAdd(&s_gacc[q][g], acc[q]);
+    }
+    __syncthreads();
+    if (tid < ng) {
+        const int64_t j = blk.g_begin + tid;
+        GAct g;
+        activate(a, j, g);
+        float GS[6];
+        for (int q = 0; q < 6; ++q) GS[q] = s_gacc[q][tid];
+        const float glsum = s_gacc[10][tid];
         // Sigma_j = R diag(s^2) R^T
         float GR[9];  // G_S R_j
         for (int u = 0; u < 3; ++u)
@@ -448,24 +636,22 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         const float w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
         const float tr = dR[0] + dR[4] + dR[8];
         const float ax = dR[7] - dR[5], ay = dR[2] - dR[6], az = dR[3] - dR[1];
-        const float vx = x, vy = y, vz = z;
-        // (G + G^T) v
-        const float sv0 = (2.f * dR[0]) * vx + (dR[1] + dR[3]) * vy + (dR[2] + dR[6]) * vz;
-        const float sv1 = (dR[1] + dR[3]) * vx + (2.f * dR[4]) * vy + (dR[5] + dR[7]) * vz;
-        const float sv2 = (dR[2] + dR[6]) * vx + (dR[5] + dR[7]) * vy + (2.f * dR[8]) * vz;
+        const float sv0 = (2.f * dR[0]) * x + (dR[1] + dR[3]) * y + (dR[2] + dR[6]) * z;
+        const float sv1 = (dR[1] + dR[3]) * x + (2.f * dR[4]) * y + (dR[5] + dR[7]) * z;
+        const float sv2 = (dR[2] + dR[6]) * x + (dR[5] + dR[7]) * y + (2.f * dR[8]) * z;
         float gq[4];
-        gq[0] = 2.f * w * tr + 2.f * (vx * ax + vy * ay + vz * az);
-        gq[1] = -2.f * vx * tr + 2.f * sv0 + 2.f * w * ax;
-        gq[2] = -2.f * vy * tr + 2.f * sv1 + 2.f * w * ay;
-        gq[3] = -2.f * vz * tr + 2.f * sv2 + 2.f * w * az;
+        gq[0] = 2.f * w * tr + 2.f * (x * ax + y * ay + z * az);
+        gq[1] = -2.f * x * tr + 2.f * sv0 + 2.f * w * ax;
+        gq[2] = -2.f * y * tr + 2.f * sv1 + 2.f * w * ay;
+        gq[3] = -2.f * z * tr + 2.f * sv2 + 2.f * w * az;
         const float dp = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
         for (int k = 0; k < 4; ++k) g_quat[4 * j + k] = (gq[k] - g.qn[k] * dp) * g.qinv;
-        for (int k = 0; k < 3; ++k) g_mean[3 * j + k] = gmu[k];
-        g_amp[j] = gc;
+        for (int k = 0; k < 3; ++k) g_mean[3 * j + k] = s_gacc[6 + k][tid];
+        g_amp[j] = s_gacc[9][tid];
     }
     if (use_lds) {
         __syncthreads();
-        for (int k = threadIdx.x; k < 6 * ns; k += blockDim.x) {
+        for (int k = tid; k < 6 * ns; k += blockDim.x) {
             const float v = s_pose[k];
             if (v != 0.f) atomicAdd(&pose_acc[6 * (int64_t)si.s_begin + k], v);
         }
@@ -510,15 +696,18 @@ hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* 
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cull<false>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts,
-                       (const int2*)nullptr, (Record*)nullptr, (int2*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+                       (const int2*)nullptr, (Record*)nullptr, (int2*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                       (const int*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       int2* rec_inst, uint32_t* keys, uint32_t* vals, hipStream_t st) {
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts, offsets, rec, rec_inst, keys, vals,
+                       fallback);
     hipLaunchKernelGGL(k_cull<true>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, const_cast<int2*>(counts),
-                       offsets, rec, rec_inst, keys, vals);
+                       offsets, rec, rec_inst, keys, vals, (const int*)fallback);
     return hipGetLastError();
 }
 

@@ -394,13 +394,16 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
     }
 }
 
-// Forward, record on lanes: each wave takes the tile's instances one at a
-// time (wave-uniform record, loaded through the scalar cache, the next one
-// prefetched); its 64 lanes cover the instance's clipped box, 64 pixels per
-// pass, and add a * max(e - e_T, 0) into the wave's own LDS copy of the tile
-// with a plain read-modify-write (lanes hit distinct pixels and no other wave
-// touches that copy).  The four copies are summed in a fixed order, so the
-// result needs no atomics and is deterministic.
+// Forward, record on lanes: a batch of the tile's records is staged in LDS
+// (footprint box and the exponent as a quadratic in box-local pixel
+// coordinates).  Each half-wave (32 lanes) then takes one instance at a time,
+// spreads the instance's box over its lanes (32 pixels per pass) and adds
+// a * max(e - e_T, 0) into its own LDS copy of the tile with a plain
+// read-modify-write: the lanes of one half-wave hit distinct pixels and no
+// other half-wave touches that copy.  The eight copies are summed in a fixed
+// order, so the result needs no atomics and is deterministic.  Instances are
+// grouped by footprint size in the sort, so the two halves of a wave see
+// similar boxes.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* __restrict__ target,
                                                      const float* __restrict__ mask,
@@ -409,56 +412,74 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                                                      float* __restrict__ tile_sse,
                                                      unsigned long long* __restrict__ incut,
                                                      int* __restrict__ work_counter) {
-    constexpr int NT = 256, NW = 4;
-    __shared__ float s_acc[NW][T * T];
+    constexpr int NT = 256, NW = 4, NH = 8;
+    __shared__ float s_acc[NH][T * T];
+    __shared__ float4 s_rec[kMaxBatch][2];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
     __shared__ int s_next;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tid = threadIdx.x, lane = tid & 63, hl = tid & 31;
+    const int wv = tid >> 6, half = tid >> 5;
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
-    float* acc = s_acc[wv];
+    float* acc = s_acc[half];
     int iter = 0;
     while (true) {
-        int tile = next_tile<NT>(a, work_counter, iter, &s_next);
-        tile = __builtin_amdgcn_readfirstlane(tile);
+        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
         if (tile < 0) break;
         const TileCoord tc = tile_coord(a, tile);
         const int2 rg = a.ranges[tile];
         const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
         __syncthreads();
-        for (int p = tid; p < NW * T * T; p += NT) (&s_acc[0][0])[p] = 0.f;
-        __syncthreads();
+        for (int p = tid; p < NH * T * T; p += NT) (&s_acc[0][0])[p] = 0.f;
         unsigned int cnt = 0;
-        // instances of this wave: rg.x + wv, rg.x + wv + NW, ...
-        int s = rg.x + wv;
-        Record nxt;
-        if (s < rg.y) nxt = a.rec[a.inst_rec[s]];
-        while (s < rg.y) {
-            const Record R = nxt;
-            const int sn = s + NW;
-            if (sn < rg.y) nxt = a.rec[a.inst_rec[sn]];
-            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-            const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
-            const int area = (w > 0 && h > 0) ? w * h : 0;
-            const float inv_w = 1.f / (float)max(w, 1);
-            for (int c = 0; c < area; c += 64) {
-                const int idx = c + lane;
-                const int yy = (int)(((float)idx + 0.5f) * inv_w);
-                const int xx = idx - yy * w;
-                const int x = b.x0 + xx, y = b.y0 + yy;
-                const float dx = (float)x - b.pxl, dy = (float)y - b.pyl;
-                const float z = fmaf(dx, fmaf(b.a00, dx, 2.f * b.a01 * dy), fmaf(b.a11 * dy, dy, b.bz));
-                const float v = __builtin_amdgcn_exp2f(z) - etau;
-                if (idx < area && yy < h && xx >= 0 && xx < w && v > 0.f) {
-                    float* dst = acc + y * T + x;
-                    *dst = fmaf(b.am, v, *dst);
-                    if (kCount) ++cnt;
+        for (int b0 = rg.x; b0 < rg.y; b0 += a.batch) {
+            const int nb = min(a.batch, rg.y - b0);
+            __syncthreads();
+            for (int q = tid; q < nb; q += NT) {
+                const Record R = a.rec[a.inst_rec[b0 + q]];
+                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+                // exponent at box-local (u, v) = (x - x0, y - y0): expand around the box origin
+                const float PX = b.pxl - (float)b.x0, PY = b.pyl - (float)b.y0;
+                float4 c0, c1;
+                c0.x = b.bz + PX * (b.a00 * PX + 2.f * b.a01 * PY) + b.a11 * PY * PY;
+                c0.y = -2.f * (b.a00 * PX + b.a01 * PY);
+                c0.z = -2.f * (b.a01 * PX + b.a11 * PY);
+                c0.w = b.a00;
+                c1.x = 2.f * b.a01;
+                c1.y = b.a11;
+                c1.z = b.am;
+                c1.w = __int_as_float((b.x0 & 0xff) | ((b.y0 & 0xff) << 8) | ((w & 0xff) << 16) | ((h & 0xff) << 24));
+                s_rec[q][0] = c0;
+                s_rec[q][1] = c1;
+            }
+            __syncthreads();
+            for (int q = half; q < nb; q += NH) {
+                const float4 c0 = s_rec[q][0], c1 = s_rec[q][1];
+                const int pk = __float_as_int(c1.w);
+                const int x0 = pk & 0xff, y0 = (pk >> 8) & 0xff, w = (pk >> 16) & 0xff, h = (pk >> 24) & 0xff;
+                const int area = w * h;
+                const float inv_w = 1.f / (float)max(w, 1);
+                for (int c = 0; c < area; c += 32) {
+                    const int idx = c + hl;
+                    const int yy = (int)(((float)idx + 0.5f) * inv_w);
+                    const int xx = idx - yy * w;
+                    const float u = (float)xx, v = (float)yy;
+                    float z = fmaf(c0.y, u, c0.x);
+                    z = fmaf(c0.z, v, z);
+                    z = fmaf(c0.w * u, u, z);
+                    z = fmaf(c1.x * u, v, z);
+                    z = fmaf(c1.y * v, v, z);
+                    const float e = __builtin_amdgcn_exp2f(z) - etau;
+                    if (idx < area && yy < h && xx >= 0 && xx < w && e > 0.f) {
+                        float* dst = acc + (y0 + yy) * T + (x0 + xx);
+                        *dst = fmaf(c1.z, e, *dst);
+                        if (kCount) ++cnt;
+                    }
                 }
             }
-            s = sn;
         }
         __syncthreads();
         float sq = 0.f;
@@ -466,7 +487,8 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
             const int px = tc.x0 + p % T, py = tc.y0 + p / T;
             if (px < tc.W && py < tc.H) {
                 const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
-                const float y = ((s_acc[0][p] + s_acc[1][p]) + s_acc[2][p]) + s_acc[3][p];
+                const float y = (((s_acc[0][p] + s_acc[1][p]) + (s_acc[2][p] + s_acc[3][p])) +
+                                 ((s_acc[4][p] + s_acc[5][p]) + (s_acc[6][p] + s_acc[7][p])));
                 pred[pi] = y;
                 if (kLoss) {
                     const float m = mask[pi];

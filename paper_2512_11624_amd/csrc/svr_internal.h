@@ -81,8 +81,9 @@ struct ProjectArgs {
 hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,
                              hipStream_t st);
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st);
+// fallback: int per Gaussian block (scratch, written by the first kernel)
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       int2* rec_inst, uint32_t* keys, uint32_t* vals, hipStream_t st);
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
                                    const Record* rec, const int2* rec_inst, const float4* inst_grad,
                                    int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,
