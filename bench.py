@@ -58,6 +58,10 @@ def make_workload(name, seed=0):
     elif name == "head-stress":
         prob = synth.config3(seed)
         desc = "head phantom, 1.2M Gaussians, 6 stacks x 40 slices of 320x320 px at 0.7x0.7x3 mm"
+    elif name == "batched":
+        prob = synth.config4(seed)
+        desc = ("16 cube subjects, Gaussians log-uniform 1.5e5-1.5e6 (8.2M total), 3-9 stacks of 20-48 slices, "
+                "192-320 px, thickness 2.5-4.5 mm, one persistent launch")
     elif name == "cube":
         prob = synth.config1(seed)
         desc = "cube phantom, 2,000 Gaussians, 3 stacks x 16 slices of 32x32 px at 1x1x3 mm"
@@ -122,12 +126,61 @@ def cpu_baseline(prob, params, pose, target, budget_s=15.0):
                        f"slices ({n_in} in-cut pairs, {dt:.1f} s)")
 
 
+def sequential_subjects(prob, par, target, mask, cfg, steps, warmup):
+    """The same iteration run subject by subject (one context per subject, the
+    configuration tuned for the batch), as 16 independent reconstructions
+    would: returns the time of one round over all subjects."""
+    import torch
+    from paper_2512_11624_amd import svr, synth
+    N0 = par.N
+    po = prob.pix_offset
+    runs = []
+    for k in range(prob.n_subjects):
+        sub = synth.subject(prob, k)
+        g0, g1 = int(prob.gauss_offsets[k]), int(prob.gauss_offsets[k + 1])
+        sl = np.nonzero(prob.slice_subject == k)[0]
+        p0, p1 = int(po[sl[0]]), int(po[sl[-1] + 1])
+        c = svr.Context(0)
+        c.svr_set_config(**cfg)
+        c.svr_set_geometry(sub)
+        v = par.views()
+        sp = svr.Params.from_arrays(v[0][g0:g1].cpu().numpy(), v[1][g0:g1].cpu().numpy(),
+                                    v[2][g0:g1].cpu().numpy(), v[3][g0:g1].cpu().numpy(),
+                                    v[4][sl[0]:sl[-1] + 1].cpu().numpy())
+        P = p1 - p0
+        runs.append(dict(ctx=c, par=sp, grad=svr.Params(sp.N, sp.M), m=torch.zeros_like(sp.flat),
+                         v=torch.zeros_like(sp.flat), t=target[p0:p1], mk=mask[p0:p1],
+                         pred=torch.empty(P, device="cuda"), g=torch.empty(P, device="cuda"),
+                         loss=torch.empty(1, device="cuda"), it=0))
+
+    def one_round():
+        for r in runs:
+            r["it"] += 1
+            c = r["ctx"]
+            c.svr_project_bin(*r["par"].views())
+            c.svr_forward(r["pred"], r["t"], r["mk"], loss=r["loss"], grad_pred=r["g"])
+            c.svr_backward(r["g"], *r["grad"].views())
+            c.svr_step(r["par"].views(), r["grad"].views(), r["m"], r["v"], LR, r["it"])
+
+    for _ in range(warmup):
+        one_round()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_round()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    for r in runs:
+        r["ctx"].close()
+    return dict(ms_per_round=ms, subjects=len(runs))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="head", choices=["head", "head-stress", "cube"])
+    ap.add_argument("--workload", default="head", choices=["head", "head-stress", "cube", "batched"])
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--persistent", type=int, default=0)
@@ -191,8 +244,7 @@ def main():
     if args.autotune:
         ctx.svr_project_bin(*par.views())
         ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
-        tuned, times = ctx.svr_autotune(*par.views(), gpred, cache_path=os.path.join(ROOT, "gpurun_out", "autotune.txt")
-                                        if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+        tuned, times = ctx.svr_autotune(*par.views(), gpred)
         log(f"autotune: {tuned} ({len(times)} trials, best {min(times):.3f} ms)")
 
     for _ in range(args.warmup):
@@ -235,8 +287,14 @@ def main():
                         frac=round(achieved / peak, 6), traffic=None, kernel=dominant,
                         avg_ms=round(stages[dominant]["avg_ms"], 5), work_per_launch=work)
 
+    sequential = None
+    if args.workload == "batched":
+        sequential = sequential_subjects(prob, par, target, mask, ctx.svr_get_config(), args.steps, args.warmup)
+        sequential["batched_speedup"] = sequential["ms_per_round"] / ms_per_step
+        log(f"sequential: {sequential}")
+
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "batched":
         try:
             cpu = cpu_baseline(prob, init, np.zeros((M, 6), np.float32), target_np)
             log(f"cpu baseline: {cpu}")
@@ -268,6 +326,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if sequential is not None:
+        out["sequential_16_runs"] = sequential
     print(json.dumps(out), flush=True)
     ctx.close()
 

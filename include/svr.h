@@ -275,6 +275,63 @@ int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
 int svr_autotune(svr_ctx* ctx, const svr_params* params, const float* grad_pred, int flags,
                  const char* cache_path, svr_config* out, float* times_ms, int max_times);
 
+/* ------------------------------------------------------------------------ */
+/* Learned pose proposal.  A small CNN maps a 128x128 crop of an observed
+ * slice (its 32x32 centre upsampled x4, bilinear) plus the slice's nominal
+ * placement (stack rotation R0, 9 floats, and nominal centre t0 / 16 mm, 3
+ * floats) to a 6-DoF pose delta (omega, tau) that initialises the
+ * slice's pose; the plain pose optimisation stays the judge (a proposal is
+ * only kept where it lowers the slice's forward-model error).  Architecture:
+ * 6 x [3x3 conv, stride 2, pad 1, ReLU] with 32, 32, 64, 64, 128, 128
+ * channels (128^2 -> 2^2), flatten (512) || placement (12), FC 524 -> 256
+ * (ReLU), FC 256 -> 6.  Every layer runs as an implicit GEMM on BF16 MFMA
+ * with FP32 accumulation; master weights, activations and Adam state are
+ * FP32.  Targets/outputs are in the caller's units (the training code uses
+ * scaled pose units).  All array arguments are DEVICE float32 pointers in
+ * NCHW / row-major layout, except the HOST arrays of get/set_params. */
+typedef struct svr_posenet svr_posenet;
+
+/* Create with He-normal weights from `seed` on GPU `device`, enqueueing on
+ * `hip_stream`; max_batch bounds B in every call (1..65536). */
+int svr_posenet_create(svr_posenet** out, int device, void* hip_stream, uint64_t seed, int max_batch);
+int svr_posenet_destroy(svr_posenet* net);
+int64_t svr_posenet_num_params(const svr_posenet* net);
+/* Flat parameter vector: per conv layer weight [Co,Ci,3,3] then bias [Co];
+ * fc1 weight [256,524], bias [256]; fc2 weight [6,256], bias [6]. */
+int svr_posenet_get_params(svr_posenet* net, float* host_out);
+int svr_posenet_set_params(svr_posenet* net, const float* host_in);
+/* slices [B,H,W] -> crops [B,128,128]: the centred 32x32 window upsampled x4. */
+int svr_posenet_prepare(svr_posenet* net, const float* slices, int B, int H, int W, float* crops);
+/* crops [B,1,128,128], placement [B,12] -> out [B,6]. */
+int svr_posenet_forward(svr_posenet* net, const float* crops, const float* orient, int B, float* out);
+/* One Adam step (betas 0.9/0.999, eps 1e-8) on loss = mean_b sum_c (y-t)^2;
+ * loss [1] (DEVICE, may be NULL) receives the batch loss before the step. */
+int svr_posenet_train_step(svr_posenet* net, const float* crops, const float* orient, const float* target,
+                           int B, float lr, float* loss);
+/* Loss and the full parameter gradient (grads_out [num_params], DEVICE),
+ * without updating the weights. */
+int svr_posenet_grads(svr_posenet* net, const float* crops, const float* orient, const float* target, int B,
+                      float* loss, float* grads_out);
+
+/* Layer primitives of the network (on the given hipStream_t), exposed for
+ * verification.  conv: x [B,Ci,H,W], w [Co,Ci,3,3], b [Co] (may be NULL),
+ * y [B,Co,(H+1)/2,(W+1)/2]; relu = 1 applies max(.,0).  dgrad/wgrad take dy
+ * (gradient w.r.t. y) and y (the ReLU output, NULL for no ReLU); dgrad writes
+ * dx [B,Ci,H,W], wgrad writes dw [Co,Ci,3,3] and db [Co] (may be NULL).
+ * linear: x [B,Fin], w [Fout,Fin], b [Fout], y [B,Fout]. */
+int svr_conv3x3s2_forward(void* hip_stream, const float* x, const float* w, const float* b, float* y, int B,
+                          int Ci, int H, int W, int Co, int relu);
+int svr_conv3x3s2_dgrad(void* hip_stream, const float* dy, const float* y, const float* w, float* dx, int B,
+                        int Ci, int H, int W, int Co);
+int svr_conv3x3s2_wgrad(void* hip_stream, const float* dy, const float* y, const float* x, float* dw, float* db,
+                        int B, int Ci, int H, int W, int Co);
+int svr_linear_forward(void* hip_stream, const float* x, const float* w, const float* b, float* y, int B,
+                       int Fin, int Fout, int relu);
+int svr_linear_dgrad(void* hip_stream, const float* dy, const float* y, const float* w, float* dx, int B,
+                     int Fin, int Fout);
+int svr_linear_wgrad(void* hip_stream, const float* dy, const float* y, const float* x, float* dw, float* db,
+                     int B, int Fin, int Fout);
+
 #ifdef __cplusplus
 }
 #endif

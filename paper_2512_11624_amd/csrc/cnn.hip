@@ -1,0 +1,590 @@
+// Pose-proposal CNN on BF16 MFMA (gfx950): 6 x [3x3 conv, stride 2, pad 1,
+// ReLU] with channels 32, 32, 64, 64, 128, 128 on a 1x128x128 crop, then
+// FC 524 -> 256 (ReLU) -> 6 on the flattened 128x2x2 features concatenated
+// with the slice's nominal placement (stack rotation R0, 9 floats, and the
+// nominal centre t0 / 16 mm, 3 floats).  Every convolution and linear layer
+// -- forward, input gradient and weight gradient -- is one implicit GEMM on
+// v_mfma_f32_16x16x32_bf16: operands are rounded to BF16 (round to nearest
+// even) when staged into LDS, products accumulate in FP32, master weights and
+// activations stay FP32.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <random>
+#include <vector>
+
+#include "svr.h"
+#include "svr_internal.h"
+
+namespace svr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ inline unsigned short f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+constexpr int BM = 64, BN = 64, BK = 32;
+
+// C[M][N] = sum_k A[M][K] B[K][N]; loaders return 0 outside their operand.
+template <class LA, class LB, class EP>
+__global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K) {
+    __shared__ __attribute__((aligned(16))) unsigned short sA[BM][BK];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[BN][BK];  // transposed: [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    floatx4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column lr, k offset lk
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        us8 va, vb;
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + lk + e;
+            va[e] = f2bf(la(m0 + lr, k));
+            vb[e] = f2bf(lb(k, n0 + lr));
+        }
+        __syncthreads();
+        *reinterpret_cast<us8*>(&sA[lr][lk]) = va;
+        *reinterpret_cast<us8*>(&sB[lr][lk]) = vb;
+        __syncthreads();
+        const int ko = 8 * (lane >> 4);
+        for (int i = 0; i < 2; ++i) {
+            const us8 a = *reinterpret_cast<const us8*>(&sA[wm * 32 + i * 16 + (lane & 15)][ko]);
+            for (int j = 0; j < 2; ++j) {
+                const us8 b = *reinterpret_cast<const us8*>(&sB[wn * 32 + j * 16 + (lane & 15)][ko]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                    __builtin_bit_cast(bf16x8, b), acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < N) ep(row, col, acc[i][j][r]);
+            }
+}
+
+// ---- convolution 3x3, stride 2, pad 1, NCHW, OH = (H+1)/2 --------------------
+struct ConvShape {
+    int B, Ci, H, W, Co, OH, OW;
+};
+
+// forward: A = im2col(in) [B*OH*OW][Ci*9], B = W^T
+struct LConvIn {
+    const float* x;
+    ConvShape s;
+    __device__ float operator()(int m, int k) const {
+        if (m >= s.B * s.OH * s.OW || k >= s.Ci * 9) return 0.f;
+        const int ow = m % s.OW, t = m / s.OW, oh = t % s.OH, n = t / s.OH;
+        const int kw = k % 3, t2 = k / 3, kh = t2 % 3, ci = t2 / 3;
+        const int ih = 2 * oh + kh - 1, iw = 2 * ow + kw - 1;
+        if (ih < 0 || ih >= s.H || iw < 0 || iw >= s.W) return 0.f;
+        return x[(((int64_t)n * s.Ci + ci) * s.H + ih) * s.W + iw];
+    }
+};
+struct LConvW {  // B[k][co] = W[co][k]
+    const float* w;
+    int Co, Kc;
+    __device__ float operator()(int k, int co) const { return (k < Kc && co < Co) ? w[(int64_t)co * Kc + k] : 0.f; }
+};
+struct EConvOut {
+    float* y;
+    const float* bias;
+    ConvShape s;
+    int relu;
+    __device__ void operator()(int m, int co, float v) const {
+        const int ow = m % s.OW, t = m / s.OW, oh = t % s.OH, n = t / s.OH;
+        v += bias ? bias[co] : 0.f;
+        if (relu) v = fmaxf(v, 0.f);
+        y[(((int64_t)n * s.Co + co) * s.OH + oh) * s.OW + ow] = v;
+    }
+};
+
+// upstream gradient through the ReLU (mask = output > 0; out NULL = identity)
+__device__ inline float dmask(const float* dy, const float* out, int64_t idx) {
+    const float g = dy[idx];
+    return (out && !(out[idx] > 0.f)) ? 0.f : g;
+}
+
+// input gradient: A[m=(n,ih,iw)][k=(co,kh,kw)] = dOut at oh = (ih+1-kh)/2 when integral
+struct LConvDOut {
+    const float* dy;
+    const float* out;
+    ConvShape s;
+    __device__ float operator()(int m, int k) const {
+        if (m >= s.B * s.H * s.W || k >= s.Co * 9) return 0.f;
+        const int iw = m % s.W, t = m / s.W, ih = t % s.H, n = t / s.H;
+        const int kw = k % 3, t2 = k / 3, kh = t2 % 3, co = t2 / 3;
+        const int ph = ih + 1 - kh, pw = iw + 1 - kw;
+        if (ph < 0 || pw < 0 || (ph & 1) || (pw & 1)) return 0.f;
+        const int oh = ph >> 1, ow = pw >> 1;
+        if (oh >= s.OH || ow >= s.OW) return 0.f;
+        return dmask(dy, out, (((int64_t)n * s.Co + co) * s.OH + oh) * s.OW + ow);
+    }
+};
+struct LConvWT {  // B[k=(co,kh,kw)][ci] = W[co][ci][kh][kw]
+    const float* w;
+    ConvShape s;
+    __device__ float operator()(int k, int ci) const {
+        if (k >= s.Co * 9 || ci >= s.Ci) return 0.f;
+        const int kk = k % 9, co = k / 9;
+        return w[((int64_t)co * s.Ci + ci) * 9 + kk];
+    }
+};
+struct EConvDIn {
+    float* dx;
+    ConvShape s;
+    __device__ void operator()(int m, int ci, float v) const {
+        const int iw = m % s.W, t = m / s.W, ih = t % s.H, n = t / s.H;
+        dx[(((int64_t)n * s.Ci + ci) * s.H + ih) * s.W + iw] = v;
+    }
+};
+
+// weight gradient: M = Co, N = Ci*9 (+1 bias column), K = B*OH*OW
+struct LConvDOutT {  // A[co][m] = masked dOut
+    const float* dy;
+    const float* out;
+    ConvShape s;
+    __device__ float operator()(int co, int m) const {
+        if (co >= s.Co || m >= s.B * s.OH * s.OW) return 0.f;
+        const int ow = m % s.OW, t = m / s.OW, oh = t % s.OH, n = t / s.OH;
+        return dmask(dy, out, (((int64_t)n * s.Co + co) * s.OH + oh) * s.OW + ow);
+    }
+};
+struct LConvInB {  // B[m][k] = im2col(in)[m][k], column Ci*9 = 1 (bias)
+    LConvIn c;
+    __device__ float operator()(int m, int k) const {
+        if (k == c.s.Ci * 9) return m < c.s.B * c.s.OH * c.s.OW ? 1.f : 0.f;
+        return c(m, k);
+    }
+};
+struct EWGrad {
+    float* dw;
+    float* db;
+    int Kc;
+    __device__ void operator()(int co, int k, float v) const {
+        if (k < Kc) dw[(int64_t)co * Kc + k] = v;
+        else if (db) db[co] = v;
+    }
+};
+
+// ---- linear layers: x [B][Fin], W [Fout][Fin] ----------------------------------
+struct LMat {  // row-major [R][C], optional second block for columns >= C1 (concatenation)
+    const float* a;
+    int R, C;
+    const float* a2;
+    int C1, C2;
+    __device__ float operator()(int r, int c) const {
+        if (r >= R) return 0.f;
+        if (a2) {
+            if (c < C1) return a[(int64_t)r * C1 + c];
+            if (c < C1 + C2) return a2[(int64_t)r * C2 + (c - C1)];
+            return 0.f;
+        }
+        return c < C ? a[(int64_t)r * C + c] : 0.f;
+    }
+};
+struct LMatT {  // B[k][n] = W[n][k]
+    const float* w;
+    int N, K;
+    __device__ float operator()(int k, int n) const { return (k < K && n < N) ? w[(int64_t)n * K + k] : 0.f; }
+};
+struct LMasked {  // A[r][c] = masked dy[r][c]
+    const float* dy;
+    const float* out;
+    int R, C;
+    __device__ float operator()(int r, int c) const {
+        return (r < R && c < C) ? dmask(dy, out, (int64_t)r * C + c) : 0.f;
+    }
+};
+struct LMaskedT {  // A[o][b] = masked dy[b][o]
+    const float* dy;
+    const float* out;
+    int Bn, F;
+    __device__ float operator()(int o, int b) const {
+        return (o < F && b < Bn) ? dmask(dy, out, (int64_t)b * F + o) : 0.f;
+    }
+};
+struct LMatB {  // B[b][i] = x[b][i] (with concatenation), column Fin = 1 (bias)
+    LMat x;
+    int Fin;
+    __device__ float operator()(int b, int i) const {
+        if (i == Fin) return b < x.R ? 1.f : 0.f;
+        return x(b, i);
+    }
+};
+struct EStore {
+    float* y;
+    const float* bias;
+    int N, relu;
+    __device__ void operator()(int r, int c, float v) const {
+        v += bias ? bias[c] : 0.f;
+        if (relu) v = fmaxf(v, 0.f);
+        y[(int64_t)r * N + c] = v;
+    }
+};
+
+template <class LA, class LB, class EP>
+hipError_t gemm(LA la, LB lb, EP ep, int M, int N, int K, hipStream_t st) {
+    if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+    hipLaunchKernelGGL((k_gemm<LA, LB, EP>), grid, dim3(256), 0, st, la, lb, ep, M, N, K);
+    return hipGetLastError();
+}
+
+ConvShape conv_shape(int B, int Ci, int H, int W, int Co) {
+    return ConvShape{B, Ci, H, W, Co, (H + 1) / 2, (W + 1) / 2};
+}
+
+hipError_t conv_fwd(const float* x, const float* w, const float* b, float* y, ConvShape s, int relu, hipStream_t st) {
+    return gemm(LConvIn{x, s}, LConvW{w, s.Co, s.Ci * 9}, EConvOut{y, b, s, relu}, s.B * s.OH * s.OW, s.Co, s.Ci * 9, st);
+}
+hipError_t conv_dgrad(const float* dy, const float* out, const float* w, float* dx, ConvShape s, hipStream_t st) {
+    return gemm(LConvDOut{dy, out, s}, LConvWT{w, s}, EConvDIn{dx, s}, s.B * s.H * s.W, s.Ci, s.Co * 9, st);
+}
+hipError_t conv_wgrad(const float* dy, const float* out, const float* x, float* dw, float* db, ConvShape s,
+                      hipStream_t st) {
+    return gemm(LConvDOutT{dy, out, s}, LConvInB{LConvIn{x, s}}, EWGrad{dw, db, s.Ci * 9}, s.Co, s.Ci * 9 + 1,
+                s.B * s.OH * s.OW, st);
+}
+hipError_t lin_fwd(LMat x, const float* w, const float* b, float* y, int Bn, int Fin, int Fout, int relu,
+                   hipStream_t st) {
+    return gemm(x, LMatT{w, Fout, Fin}, EStore{y, b, Fout, relu}, Bn, Fout, Fin, st);
+}
+hipError_t lin_dgrad(const float* dy, const float* out, const float* w, float* dx, int Bn, int Fin, int Fout,
+                     hipStream_t st) {
+    // dX[b][i] = sum_o dYm[b][o] W[o][i]
+    return gemm(LMasked{dy, out, Bn, Fout}, LMat{w, Fout, Fin, nullptr, 0, 0}, EStore{dx, nullptr, Fin, 0}, Bn, Fin,
+                Fout, st);
+}
+hipError_t lin_wgrad(const float* dy, const float* out, LMat x, float* dw, float* db, int Bn, int Fin, int Fout,
+                     hipStream_t st) {
+    return gemm(LMaskedT{dy, out, Bn, Fout}, LMatB{x, Fin}, EWGrad{dw, db, Fin}, Fout, Fin + 1, Bn, st);
+}
+
+// ---- small element-wise kernels --------------------------------------------------
+// Bilinear x4 upsampling of an H x W slice to a (4H) x (4W) crop, optionally
+// centre-cropped / padded to 128 x 128, scaled by 1/scale.
+__global__ void k_prepare(const float* __restrict__ slices, int B, int H, int W, float* __restrict__ crops) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)B * 128 * 128) return;
+    const int x = (int)(idx % 128), y = (int)((idx / 128) % 128), b = (int)(idx / (128 * 128));
+    // crop pixel -> source coordinate (centred): 4x upsampling of the slice
+    const float sx = ((float)x + 0.5f) * 0.25f - 0.5f + 0.5f * (float)(W - 32);
+    const float sy = ((float)y + 0.5f) * 0.25f - 0.5f + 0.5f * (float)(H - 32);
+    const float fx = fminf(fmaxf(sx, 0.f), (float)(W - 1)), fy = fminf(fmaxf(sy, 0.f), (float)(H - 1));
+    const int x0 = (int)floorf(fx), y0 = (int)floorf(fy);
+    const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
+    const float ax = fx - (float)x0, ay = fy - (float)y0;
+    const float* s = slices + (int64_t)b * H * W;
+    const float v = (1.f - ay) * ((1.f - ax) * s[y0 * W + x0] + ax * s[y0 * W + x1]) +
+                    ay * ((1.f - ax) * s[y1 * W + x0] + ax * s[y1 * W + x1]);
+    crops[idx] = v;
+}
+
+// MSE on the 6 outputs: loss = mean_b sum_c (y - t)^2 ; dy = 2 (y - t) / B
+__global__ void k_mse6(const float* __restrict__ y, const float* __restrict__ t, int B, float* __restrict__ dy,
+                       float* __restrict__ loss) {
+    __shared__ float s[256];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < B * 6; i += 256) {
+        const float r = y[i] - t[i];
+        dy[i] = 2.f * r / (float)B;
+        acc += r * r;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && loss) loss[0] = s[0] / (float)B;
+}
+
+}  // namespace
+}  // namespace svr
+
+using namespace svr;
+
+// ---------------------------------------------------------------------------
+struct svr_posenet {
+    int device;
+    hipStream_t stream;
+    int max_batch;
+    std::vector<int64_t> off;  // parameter offsets: conv w/b x6, fc1 w/b, fc2 w/b
+    int64_t n_params = 0;
+    float* params = nullptr;
+    float* grads = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    int64_t step = 0;
+    float* act[7] = {};      // a0 (input view), a1..a6
+    float* dact[7] = {};
+    float* h = nullptr;      // fc1 output [B,256]
+    float* dh = nullptr;
+    float* y = nullptr;      // [B,6]
+    float* dy = nullptr;
+    float* dfeat = nullptr;  // [B,524]
+};
+
+namespace {
+const int kCh[7] = {1, 32, 32, 64, 64, 128, 128};
+const int kSide[7] = {128, 64, 32, 16, 8, 4, 2};
+constexpr int kFeat = 128 * 2 * 2, kOrient = 12, kHidden = 256, kOut = 6;
+
+hipError_t net_forward(svr_posenet* net, const float* crops, const float* orient, int B) {
+    hipStream_t st = net->stream;
+    const float* x = crops;
+    for (int l = 0; l < 6; ++l) {
+        ConvShape s = conv_shape(B, kCh[l], kSide[l], kSide[l], kCh[l + 1]);
+        hipError_t e = conv_fwd(x, net->params + net->off[2 * l], net->params + net->off[2 * l + 1], net->act[l + 1],
+                                s, 1, st);
+        if (e != hipSuccess) return e;
+        x = net->act[l + 1];
+    }
+    LMat feat{net->act[6], B, kFeat + kOrient, orient, kFeat, kOrient};
+    hipError_t e = lin_fwd(feat, net->params + net->off[12], net->params + net->off[13], net->h, B, kFeat + kOrient,
+                           kHidden, 1, st);
+    if (e != hipSuccess) return e;
+    return lin_fwd(LMat{net->h, B, kHidden, nullptr, 0, 0}, net->params + net->off[14], net->params + net->off[15],
+                   net->y, B, kHidden, kOut, 0, st);
+}
+
+hipError_t net_backward(svr_posenet* net, const float* crops, const float* orient, int B) {
+    hipStream_t st = net->stream;
+    float* g = net->grads;
+    hipError_t e;
+    // fc2 (no activation on y)
+    e = lin_wgrad(net->dy, nullptr, LMat{net->h, B, kHidden, nullptr, 0, 0}, g + net->off[14], g + net->off[15], B,
+                  kHidden, kOut, st);
+    if (e != hipSuccess) return e;
+    e = lin_dgrad(net->dy, nullptr, net->params + net->off[14], net->dh, B, kHidden, kOut, st);
+    if (e != hipSuccess) return e;
+    // fc1 (ReLU on h)
+    LMat feat{net->act[6], B, kFeat + kOrient, orient, kFeat, kOrient};
+    e = lin_wgrad(net->dh, net->h, feat, g + net->off[12], g + net->off[13], B, kFeat + kOrient, kHidden, st);
+    if (e != hipSuccess) return e;
+    e = lin_dgrad(net->dh, net->h, net->params + net->off[12], net->dfeat, B, kFeat + kOrient, kHidden, st);
+    if (e != hipSuccess) return e;
+    // the first 512 feature gradients (row stride 524) are d a6 ([B,128,2,2] flattened)
+    e = hipMemcpy2DAsync(net->dact[6], sizeof(float) * kFeat, net->dfeat, sizeof(float) * (kFeat + kOrient),
+                         sizeof(float) * kFeat, B, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    for (int l = 5; l >= 0; --l) {
+        ConvShape s = conv_shape(B, kCh[l], kSide[l], kSide[l], kCh[l + 1]);
+        const float* in = l == 0 ? crops : net->act[l];
+        e = conv_wgrad(net->dact[l + 1], net->act[l + 1], in, g + net->off[2 * l], g + net->off[2 * l + 1], s, st);
+        if (e != hipSuccess) return e;
+        if (l > 0) {
+            e = conv_dgrad(net->dact[l + 1], net->act[l + 1], net->params + net->off[2 * l], net->dact[l], s, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+}  // namespace
+
+extern "C" {
+
+int svr_posenet_create(svr_posenet** out, int device, void* stream, uint64_t seed, int max_batch) {
+    if (!out || max_batch < 1 || max_batch > 65536) return SVR_ERR_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SVR_ERR_HIP;
+    if (hipSetDevice(device) != hipSuccess) return SVR_ERR_HIP;
+    svr_posenet* net = new (std::nothrow) svr_posenet();
+    if (!net) return SVR_ERR_CAPACITY;
+    net->device = device;
+    net->stream = (hipStream_t)stream;
+    net->max_batch = max_batch;
+    int64_t o = 0;
+    std::vector<int64_t> fan;
+    for (int l = 0; l < 6; ++l) {
+        net->off.push_back(o);
+        o += (int64_t)kCh[l + 1] * kCh[l] * 9;
+        fan.push_back(kCh[l] * 9);
+        net->off.push_back(o);
+        o += kCh[l + 1];
+        fan.push_back(0);
+    }
+    net->off.push_back(o); o += (int64_t)kHidden * (kFeat + kOrient); fan.push_back(kFeat + kOrient);
+    net->off.push_back(o); o += kHidden; fan.push_back(0);
+    net->off.push_back(o); o += (int64_t)kOut * kHidden; fan.push_back(kHidden);
+    net->off.push_back(o); o += kOut; fan.push_back(0);
+    net->off.push_back(o);
+    net->n_params = o;
+    std::vector<float> h((size_t)o, 0.f);
+    std::mt19937_64 rng(seed);
+    for (size_t t = 0; t + 1 < net->off.size(); ++t) {
+        if (fan[t] == 0) continue;  // biases start at 0
+        const double sd = (t == 14) ? 0.01 : sqrt(2.0 / fan[t]);   // He init; small last layer
+        std::normal_distribution<double> nd(0.0, sd);
+        for (int64_t k = net->off[t]; k < net->off[t + 1]; ++k) h[(size_t)k] = (float)nd(rng);
+    }
+    bool ok = hipMalloc((void**)&net->params, o * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&net->grads, o * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&net->m, o * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&net->v, o * sizeof(float)) == hipSuccess;
+    for (int l = 1; l <= 6 && ok; ++l) {
+        const size_t sz = (size_t)max_batch * kCh[l] * kSide[l] * kSide[l] * sizeof(float);
+        ok = hipMalloc((void**)&net->act[l], sz) == hipSuccess && hipMalloc((void**)&net->dact[l], sz) == hipSuccess;
+    }
+    ok = ok && hipMalloc((void**)&net->h, (size_t)max_batch * kHidden * 4) == hipSuccess &&
+         hipMalloc((void**)&net->dh, (size_t)max_batch * kHidden * 4) == hipSuccess &&
+         hipMalloc((void**)&net->y, (size_t)max_batch * kOut * 4) == hipSuccess &&
+         hipMalloc((void**)&net->dy, (size_t)max_batch * kOut * 4) == hipSuccess &&
+         hipMalloc((void**)&net->dfeat, (size_t)max_batch * (kFeat + kOrient) * 4) == hipSuccess;
+    ok = ok && hipMemcpy(net->params, h.data(), o * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(net->m, 0, o * sizeof(float)) == hipSuccess && hipMemset(net->v, 0, o * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        svr_posenet_destroy(net);
+        return SVR_ERR_HIP;
+    }
+    *out = net;
+    return SVR_OK;
+}
+
+int svr_posenet_destroy(svr_posenet* net) {
+    if (!net) return SVR_OK;
+    (void)hipSetDevice(net->device);
+    (void)hipStreamSynchronize(net->stream);
+    float* bufs[] = {net->params, net->grads, net->m, net->v, net->h, net->dh, net->y, net->dy, net->dfeat};
+    for (float* b : bufs)
+        if (b) (void)hipFree(b);
+    for (int l = 1; l <= 6; ++l) {
+        if (net->act[l]) (void)hipFree(net->act[l]);
+        if (net->dact[l]) (void)hipFree(net->dact[l]);
+    }
+    delete net;
+    return SVR_OK;
+}
+
+int64_t svr_posenet_num_params(const svr_posenet* net) { return net ? net->n_params : 0; }
+
+int svr_posenet_get_params(svr_posenet* net, float* host_out) {
+    if (!net || !host_out) return SVR_ERR_ARG;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    if (hipMemcpyAsync(host_out, net->params, net->n_params * 4, hipMemcpyDeviceToHost, net->stream) != hipSuccess ||
+        hipStreamSynchronize(net->stream) != hipSuccess)
+        return SVR_ERR_HIP;
+    return SVR_OK;
+}
+
+int svr_posenet_set_params(svr_posenet* net, const float* host_in) {
+    if (!net || !host_in) return SVR_ERR_ARG;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    if (hipMemcpyAsync(net->params, host_in, net->n_params * 4, hipMemcpyHostToDevice, net->stream) != hipSuccess ||
+        hipStreamSynchronize(net->stream) != hipSuccess)
+        return SVR_ERR_HIP;
+    return SVR_OK;
+}
+
+int svr_posenet_prepare(svr_posenet* net, const float* slices, int B, int H, int W, float* crops) {
+    if (!net || !slices || !crops || B < 0 || H < 1 || W < 1) return SVR_ERR_ARG;
+    if (B == 0) return SVR_OK;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    const int64_t n = (int64_t)B * 128 * 128;
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, net->stream, slices, B, H, W, crops);
+    return hipGetLastError() == hipSuccess ? SVR_OK : SVR_ERR_HIP;
+}
+
+int svr_posenet_forward(svr_posenet* net, const float* crops, const float* orient, int B, float* out) {
+    if (!net || !crops || !orient || !out || B < 1 || B > net->max_batch) return SVR_ERR_ARG;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    if (net_forward(net, crops, orient, B) != hipSuccess) return SVR_ERR_HIP;
+    if (hipMemcpyAsync(out, net->y, (size_t)B * kOut * 4, hipMemcpyDeviceToDevice, net->stream) != hipSuccess)
+        return SVR_ERR_HIP;
+    return SVR_OK;
+}
+
+int svr_posenet_train_step(svr_posenet* net, const float* crops, const float* orient, const float* target, int B,
+                           float lr, float* loss) {
+    if (!net || !crops || !orient || !target || B < 1 || B > net->max_batch || !(lr > 0.f)) return SVR_ERR_ARG;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    if (net_forward(net, crops, orient, B) != hipSuccess) return SVR_ERR_HIP;
+    hipLaunchKernelGGL(k_mse6, dim3(1), dim3(256), 0, net->stream, (const float*)net->y, target, B, net->dy, loss);
+    if (hipGetLastError() != hipSuccess) return SVR_ERR_HIP;
+    if (net_backward(net, crops, orient, B) != hipSuccess) return SVR_ERR_HIP;
+    AdamSeg seg;
+    seg.p = net->params;
+    seg.g = net->grads;
+    seg.n = net->n_params;
+    seg.state_off = 0;
+    seg.lr_a = seg.lr_b = lr;
+    seg.pose_layout = 0;
+    net->step += 1;
+    if (launch_adam(&seg, 1, net->m, net->v, 0.9, 0.999, 1e-8, 0.0, net->step, net->stream) != hipSuccess)
+        return SVR_ERR_HIP;
+    return SVR_OK;
+}
+
+int svr_posenet_grads(svr_posenet* net, const float* crops, const float* orient, const float* target, int B,
+                      float* loss, float* grads_out) {
+    if (!net || !crops || !orient || !target || !grads_out || B < 1 || B > net->max_batch) return SVR_ERR_ARG;
+    if (hipSetDevice(net->device) != hipSuccess) return SVR_ERR_HIP;
+    if (net_forward(net, crops, orient, B) != hipSuccess) return SVR_ERR_HIP;
+    hipLaunchKernelGGL(k_mse6, dim3(1), dim3(256), 0, net->stream, (const float*)net->y, target, B, net->dy, loss);
+    if (hipGetLastError() != hipSuccess) return SVR_ERR_HIP;
+    if (net_backward(net, crops, orient, B) != hipSuccess) return SVR_ERR_HIP;
+    if (hipMemcpyAsync(grads_out, net->grads, net->n_params * 4, hipMemcpyDeviceToDevice, net->stream) != hipSuccess)
+        return SVR_ERR_HIP;
+    return SVR_OK;
+}
+
+// ---- layer primitives (DEVICE pointers, caller's stream) -------------------------
+int svr_conv3x3s2_forward(void* stream, const float* x, const float* w, const float* b, float* y, int B, int Ci,
+                          int H, int W, int Co, int relu) {
+    if (!x || !w || !y || B < 1 || Ci < 1 || H < 1 || W < 1 || Co < 1) return SVR_ERR_ARG;
+    return conv_fwd(x, w, b, y, conv_shape(B, Ci, H, W, Co), relu, (hipStream_t)stream) == hipSuccess ? SVR_OK
+                                                                                                      : SVR_ERR_HIP;
+}
+
+int svr_conv3x3s2_dgrad(void* stream, const float* dy, const float* y, const float* w, float* dx, int B, int Ci,
+                        int H, int W, int Co) {
+    if (!dy || !w || !dx || B < 1 || Ci < 1 || H < 1 || W < 1 || Co < 1) return SVR_ERR_ARG;
+    return conv_dgrad(dy, y, w, dx, conv_shape(B, Ci, H, W, Co), (hipStream_t)stream) == hipSuccess ? SVR_OK
+                                                                                                   : SVR_ERR_HIP;
+}
+
+int svr_conv3x3s2_wgrad(void* stream, const float* dy, const float* y, const float* x, float* dw, float* db, int B,
+                        int Ci, int H, int W, int Co) {
+    if (!dy || !x || !dw || B < 1 || Ci < 1 || H < 1 || W < 1 || Co < 1) return SVR_ERR_ARG;
+    return conv_wgrad(dy, y, x, dw, db, conv_shape(B, Ci, H, W, Co), (hipStream_t)stream) == hipSuccess ? SVR_OK
+                                                                                                       : SVR_ERR_HIP;
+}
+
+int svr_linear_forward(void* stream, const float* x, const float* w, const float* b, float* y, int B, int Fin,
+                       int Fout, int relu) {
+    if (!x || !w || !y || B < 1 || Fin < 1 || Fout < 1) return SVR_ERR_ARG;
+    return lin_fwd(LMat{x, B, Fin, nullptr, 0, 0}, w, b, y, B, Fin, Fout, relu, (hipStream_t)stream) == hipSuccess
+               ? SVR_OK
+               : SVR_ERR_HIP;
+}
+
+int svr_linear_dgrad(void* stream, const float* dy, const float* y, const float* w, float* dx, int B, int Fin,
+                     int Fout) {
+    if (!dy || !w || !dx || B < 1 || Fin < 1 || Fout < 1) return SVR_ERR_ARG;
+    return lin_dgrad(dy, y, w, dx, B, Fin, Fout, (hipStream_t)stream) == hipSuccess ? SVR_OK : SVR_ERR_HIP;
+}
+
+int svr_linear_wgrad(void* stream, const float* dy, const float* y, const float* x, float* dw, float* db, int B,
+                     int Fin, int Fout) {
+    if (!dy || !x || !dw || B < 1 || Fin < 1 || Fout < 1) return SVR_ERR_ARG;
+    return lin_wgrad(dy, y, LMat{x, B, Fin, nullptr, 0, 0}, dw, db, B, Fin, Fout, (hipStream_t)stream) == hipSuccess
+               ? SVR_OK
+               : SVR_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""Reconstruction driver on top of the svr C ABI: volume read-out / PSNR and
+the fitting loop.  Argument marshalling and control flow only -- every
+numerical step (forward model, loss, adjoint, AdamW, read-out) runs in the
+HIP kernels of libsvr.
+
+* Volume read-out (target resolution 0.5 mm, Sec. 3.2 of the paper): the
+  volume V(x) = sum_j c_j exp(-1/2 d^T Sigma_j^-1 d) on a voxel grid is the
+  forward model with a zero PSF evaluated on axis-aligned grid planes (each
+  z-plane of the grid is a "slice" with identity rotation and zero motion),
+  so the same project_bin / forward kernels produce it.  PSNR (Sec. 3.3) is
+  10 log10(MAX^2 / MSE) over a mask, MAX the largest ground-truth value in
+  the mask; the masked MSE comes from the forward kernel's loss epilogue.
+* Fitting (App. A.1): AdamW with per-group learning rates and a StepLR that
+  halves every 200 iterations; poses start at the nominal (identity) pose.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import svr
+from .synth import Problem
+
+PAPER_LR = (2.5e-2, 2.5e-2, 1e-2, 1e-2, 2.5e-3, 1e-1)   # mean, log-scale, quat, amp, rotation, translation
+
+
+def volume_grid(shape, spacing, centre=(0.0, 0.0, 0.0)):
+    """Geometry of a voxel grid of shape (nz, ny, nx) and isotropic spacing:
+    one axial slice per z-plane, zero PSF, zero motion.  Voxel (k, r, c) sits
+    at centre + ((c-(nx-1)/2) h, (r-(ny-1)/2) h, (k-(nz-1)/2) h)."""
+    nz, ny, nx = (int(s) for s in shape)
+    h = float(spacing)
+    cz = np.asarray(centre, np.float64)
+    z = cz[2] + (np.arange(nz) - (nz - 1) / 2.0) * h
+    rot0 = np.tile(np.eye(3).reshape(1, 9), (nz, 1)).astype(np.float32)
+    trans0 = np.stack([np.full(nz, cz[0]), np.full(nz, cz[1]), z], axis=1).astype(np.float32)
+    return Problem(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), np.zeros((0, 4), np.float32),
+                   np.zeros(0, np.float32), np.array([0, 0], np.int64), np.zeros(nz, np.int32),
+                   np.full(nz, ny, np.int32), np.full(nz, nx, np.int32), np.full((nz, 2), h, np.float32),
+                   np.zeros((nz, 3), np.float32), rot0, trans0, np.zeros((nz, 6), np.float32),
+                   np.ones(nz * ny * nx, np.float32), name="grid")
+
+
+def voxel_centres(shape, spacing, centre=(0.0, 0.0, 0.0)):
+    nz, ny, nx = (int(s) for s in shape)
+    h = float(spacing)
+    c = np.asarray(centre, np.float64)
+    zz, yy, xx = np.meshgrid((np.arange(nz) - (nz - 1) / 2.0) * h + c[2], (np.arange(ny) - (ny - 1) / 2.0) * h + c[1],
+                             (np.arange(nx) - (nx - 1) / 2.0) * h + c[0], indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+
+
+class VolumeProbe:
+    """PSNR of the current Gaussians against a ground-truth volume on a grid.
+
+    ``gt`` and ``mask`` are flat arrays over the grid (z-major, then rows,
+    then columns).  ``cutoff`` is the footprint radius used for the read-out
+    (the fitted model's own window by default)."""
+
+    def __init__(self, n_gauss, shape, spacing, centre, gt, mask, device=0, cutoff=3.0, tile=16):
+        import torch
+        self.grid = volume_grid(shape, spacing, centre)
+        g = self.grid
+        self.geom = Problem(g.mean, g.log_scale, g.quat, g.amp, np.array([0, n_gauss], np.int64), g.slice_subject,
+                            g.height, g.width, g.spacing, g.psf_fwhm, g.rot0, g.trans0, g.pose, g.mask)
+        self.ctx = svr.Context(device)
+        self.ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=cutoff, forward_mode=2)
+        self.ctx.svr_set_geometry(self.geom)
+        self.P = self.geom.n_pixels
+        dev = torch.device("cuda", device)
+        self.gt = torch.as_tensor(np.ascontiguousarray(gt, np.float32), device=dev)
+        self.mask = torch.as_tensor(np.ascontiguousarray(mask, np.float32), device=dev)
+        m = np.asarray(mask) > 0
+        self.max_gt = float(np.asarray(gt)[m].max()) if m.any() else 1.0
+        self.pose = torch.zeros((self.geom.n_slices, 6), dtype=torch.float32, device=dev)
+        self.vol = torch.empty(self.P, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+
+    def render(self, mean, log_scale, quat, amp):
+        """The volume at the grid voxels (device tensor, flat)."""
+        self.ctx.svr_project_bin(mean, log_scale, quat, amp, self.pose)
+        self.ctx.svr_forward(self.vol)
+        return self.vol
+
+    def psnr(self, mean, log_scale, quat, amp):
+        self.ctx.svr_project_bin(mean, log_scale, quat, amp, self.pose)
+        self.ctx.svr_forward(self.vol, self.gt, self.mask, loss=self.loss)
+        mse = float(self.loss.item())
+        return 10.0 * math.log10(self.max_gt ** 2 / max(mse, 1e-30))
+
+    def close(self):
+        self.ctx.close()
+
+
+@dataclass
+class FitResult:
+    times: list = field(default_factory=list)       # seconds of fitting (read-out excluded)
+    iters: list = field(default_factory=list)
+    psnr: list = field(default_factory=list)
+    loss: list = field(default_factory=list)
+    final_psnr: float = float("nan")
+    seconds: float = 0.0
+
+
+def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
+        psnr_target=None, callback=None):
+    """Runs n_iter fitting iterations of project_bin + forward + backward +
+    AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
+    covers the iterations only; the PSNR read-out every ``psnr_every``
+    iterations is timed out.  Stops early once ``psnr_target`` is reached."""
+    import torch
+    N, M = params.N, params.M
+    grad = svr.Params(N, M, device=params.flat.device)
+    m = torch.zeros_like(params.flat)
+    v = torch.zeros_like(params.flat)
+    P = ctx.n_pixels
+    dev = params.flat.device
+    pred = torch.empty(P, device=dev)
+    gpred = torch.empty(P, device=dev)
+    loss = torch.empty(1, device=dev)
+    res = FitResult()
+    elapsed = 0.0
+    torch.cuda.synchronize()
+    for it in range(1, n_iter + 1):
+        t0 = time.perf_counter()
+        scale = gamma ** ((it - 1) // step_lr)
+        ctx.svr_project_bin(*params.views())
+        ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
+        ctx.svr_backward(gpred, *grad.views())
+        ctx.svr_step(params.views(), grad.views(), m, v, [x * scale for x in lr], it)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        if probe is not None and (it % psnr_every == 0 or it == n_iter):
+            p = probe.psnr(*params.views()[:4])
+            res.times.append(elapsed)
+            res.iters.append(it)
+            res.psnr.append(p)
+            res.loss.append(float(loss.item()))
+            if callback:
+                callback(it, elapsed, p, float(loss.item()))
+            if psnr_target is not None and p >= psnr_target:
+                break
+    res.seconds = elapsed
+    res.final_psnr = res.psnr[-1] if res.psnr else float("nan")
+    return res
+
+
+def time_to_target(res: FitResult, target):
+    """First fitting time at which the PSNR reached ``target`` (inf if never)."""
+    for t, p in zip(res.times, res.psnr):
+        if p >= target:
+            return t
+    return float("inf")

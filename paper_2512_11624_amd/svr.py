@@ -89,6 +89,21 @@ _SIGS = {
     "svr_sort_pairs": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
     "svr_set_timing": ([vp, C.c_int], C.c_int),
     "svr_get_timing": ([vp, C.POINTER(svr_timer), C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "svr_posenet_create": ([C.POINTER(vp), C.c_int, vp, C.c_uint64, C.c_int], C.c_int),
+    "svr_posenet_destroy": ([vp], C.c_int),
+    "svr_posenet_num_params": ([vp], C.c_int64),
+    "svr_posenet_get_params": ([vp, vp], C.c_int),
+    "svr_posenet_set_params": ([vp, vp], C.c_int),
+    "svr_posenet_prepare": ([vp, vp, C.c_int, C.c_int, C.c_int, vp], C.c_int),
+    "svr_posenet_forward": ([vp, vp, vp, C.c_int, vp], C.c_int),
+    "svr_posenet_train_step": ([vp, vp, vp, vp, C.c_int, C.c_float, vp], C.c_int),
+    "svr_posenet_grads": ([vp, vp, vp, vp, C.c_int, vp, vp], C.c_int),
+    "svr_conv3x3s2_forward": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_conv3x3s2_dgrad": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_conv3x3s2_wgrad": ([vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_linear_forward": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_linear_dgrad": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_linear_wgrad": ([vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int], C.c_int),
     "svr_autotune": ([vp, C.POINTER(svr_params), vp, C.c_int, C.c_char_p, C.POINTER(svr_config),
                       C.POINTER(C.c_float), C.c_int], C.c_int),
 }
@@ -262,6 +277,11 @@ class Params:
     state of ``svr_step``: mean (3N), log_scale (3N), quat (4N), amp (N),
     pose (6M).  ``views()`` returns the five views."""
 
+    def clone(self):
+        p = Params(self.N, self.M, device=self.flat.device)
+        p.flat.copy_(self.flat)
+        return p
+
     def __init__(self, n_gauss, n_slices, device="cuda"):
         import torch
         self.N, self.M = int(n_gauss), int(n_slices)
@@ -327,3 +347,110 @@ def SvrRender():
 
 def render_loss(sctx, mean, log_scale, quat, amp, pose, target, mask):
     return SvrRender().apply(sctx, mean, log_scale, quat, amp, pose, target, mask)
+
+
+class PoseNet:
+    """The pose-proposal CNN (``svr_posenet_*``): argument marshalling only."""
+
+    def __init__(self, device=0, seed=0, max_batch=256, stream=None):
+        import torch
+        lib = load()
+        h = vp()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib.svr_posenet_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None, int(seed),
+                                    int(max_batch))
+        if rc != SVR_OK:
+            raise SvrError(rc, "svr_posenet_create")
+        self.h = h
+        self.device = device
+        self.max_batch = max_batch
+        self.n_params = int(lib.svr_posenet_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().svr_posenet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, what):
+        if rc != SVR_OK:
+            raise SvrError(rc, what)
+
+    def get_params(self):
+        out = np.zeros(self.n_params, np.float32)
+        self._chk(load().svr_posenet_get_params(self.h, out.ctypes.data), "svr_posenet_get_params")
+        return out
+
+    def set_params(self, arr):
+        a = np.ascontiguousarray(arr, np.float32)
+        assert a.size == self.n_params
+        self._chk(load().svr_posenet_set_params(self.h, a.ctypes.data), "svr_posenet_set_params")
+
+    def prepare(self, slices, crops):
+        B, H, W = slices.shape
+        self._chk(load().svr_posenet_prepare(self.h, _ptr(slices), B, H, W, _ptr(crops)), "svr_posenet_prepare")
+
+    def forward(self, crops, orient, out):
+        self._chk(load().svr_posenet_forward(self.h, _ptr(crops), _ptr(orient), int(crops.shape[0]), _ptr(out)),
+                  "svr_posenet_forward")
+
+    def train_step(self, crops, orient, target, lr, loss=None):
+        self._chk(load().svr_posenet_train_step(self.h, _ptr(crops), _ptr(orient), _ptr(target), int(crops.shape[0]),
+                                                float(lr), _ptr(loss)), "svr_posenet_train_step")
+
+    def grads(self, crops, orient, target, loss, grads_out):
+        self._chk(load().svr_posenet_grads(self.h, _ptr(crops), _ptr(orient), _ptr(target), int(crops.shape[0]),
+                                           _ptr(loss), _ptr(grads_out)), "svr_posenet_grads")
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def conv3x3s2_forward(x, w, b, y, relu):
+    B, Ci, H, W = x.shape
+    rc = load().svr_conv3x3s2_forward(_stream(), _ptr(x), _ptr(w), _ptr(b), _ptr(y), B, Ci, H, W, w.shape[0], int(relu))
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_conv3x3s2_forward")
+
+
+def conv3x3s2_dgrad(dy, y, w, dx):
+    B, Ci, H, W = dx.shape
+    rc = load().svr_conv3x3s2_dgrad(_stream(), _ptr(dy), _ptr(y), _ptr(w), _ptr(dx), B, Ci, H, W, w.shape[0])
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_conv3x3s2_dgrad")
+
+
+def conv3x3s2_wgrad(dy, y, x, dw, db):
+    B, Ci, H, W = x.shape
+    rc = load().svr_conv3x3s2_wgrad(_stream(), _ptr(dy), _ptr(y), _ptr(x), _ptr(dw), _ptr(db), B, Ci, H, W,
+                                    dw.shape[0])
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_conv3x3s2_wgrad")
+
+
+def linear_forward(x, w, b, y, relu):
+    rc = load().svr_linear_forward(_stream(), _ptr(x), _ptr(w), _ptr(b), _ptr(y), x.shape[0], x.shape[1], w.shape[0],
+                                   int(relu))
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_linear_forward")
+
+
+def linear_dgrad(dy, y, w, dx):
+    rc = load().svr_linear_dgrad(_stream(), _ptr(dy), _ptr(y), _ptr(w), _ptr(dx), dy.shape[0], w.shape[1], w.shape[0])
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_linear_dgrad")
+
+
+def linear_wgrad(dy, y, x, dw, db):
+    rc = load().svr_linear_wgrad(_stream(), _ptr(dy), _ptr(y), _ptr(x), _ptr(dw), _ptr(db), dy.shape[0], x.shape[1],
+                                 dw.shape[0])
+    if rc != SVR_OK:
+        raise SvrError(rc, "svr_linear_wgrad")
