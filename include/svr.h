@@ -231,9 +231,9 @@ int svr_get_stats(svr_ctx* ctx, int flags, svr_stats* out);
 
 /* Stable radix sort used by tile binning, exposed for verification: sorts the
  * n (key, value) pairs in place by the low key_bits bits of the key (1..32),
- * keeping the input order of equal keys.  keys/vals are DEVICE uint32 [n];
- * scratch is owned by the context.  Keys with bits set above key_bits give
- * an unspecified order.  Errors: SVR_ERR_ARG for null pointers with n > 0,
+ * keeping the input order of equal keys; bits above key_bits are ignored for
+ * the order and kept in the output.  keys/vals are DEVICE uint32 [n];
+ * scratch is owned by the context.  Errors: SVR_ERR_ARG for null pointers with n > 0,
  * n < 0 or key_bits outside 1..32. */
 int svr_sort_pairs(svr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits);
 

@@ -760,7 +760,7 @@ int svr_get_stats(svr_ctx* c, int flags, svr_stats* out) {
     out->n_pixels = c->P;
     out->n_tiles = c->n_tiles;
     out->key_bits = c->key_bits;
-    out->sort_passes = (c->key_bits + 7) / 8;
+    out->sort_passes = (c->key_bits + radix_digit_bits(c->key_bits) - 1) / radix_digit_bits(c->key_bits);
     out->n_candidates = c->binned ? c->n_cand : 0;
     out->n_records = c->binned ? c->n_rec : 0;
     out->n_instances = c->binned ? c->n_inst : 0;

@@ -395,15 +395,18 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
 }
 
 // Forward, record on lanes: a batch of the tile's records is staged in LDS
-// (footprint box and the exponent as a quadratic in box-local pixel
-// coordinates).  Each half-wave (32 lanes) then takes one instance at a time,
-// spreads the instance's box over its lanes (32 pixels per pass) and adds
-// a * max(e - e_T, 0) into its own LDS copy of the tile with a plain
-// read-modify-write: the lanes of one half-wave hit distinct pixels and no
-// other half-wave touches that copy.  The eight copies are summed in a fixed
-// order, so the result needs no atomics and is deterministic.  Instances are
-// grouped by footprint size in the sort, so the two halves of a wave see
-// similar boxes.
+// (footprint box, 1/width and the exponent as a quadratic in box-local pixel
+// coordinates).  Each half-wave (32 lanes) then
+// takes one instance at a time, spreads the instance's box over its lanes
+// (32 pixels per pass: pixel k of the box is row floor((k + 1/2) / w), which
+// a float reciprocal gets exactly for boxes of at most 32 x 32) and adds
+// a * max(e - e_T, 0) into its own LDS copy of the tile with a
+// no-return LDS add: the lanes of one half-wave hit distinct pixels, no other
+// half-wave touches that copy, and one wave's LDS operations complete in
+// issue order, so every copy is summed in instance order.  The eight copies
+// are then summed in a fixed order: deterministic, with no global atomics.
+// Instances are grouped by footprint size in the sort, so the two halves of
+// a wave see similar boxes.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* __restrict__ target,
                                                      const float* __restrict__ mask,
@@ -413,8 +416,9 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                                                      unsigned long long* __restrict__ incut,
                                                      int* __restrict__ work_counter) {
     constexpr int NT = 256, NW = 4, NH = 8;
-    __shared__ float s_acc[NH][T * T];
-    __shared__ float4 s_rec[kMaxBatch][2];
+    constexpr int kCopy = T * T + 8;  // copy stride: successive copies start 8 banks apart
+    __shared__ float s_acc[NH * kCopy];
+    __shared__ float4 s_rec[kMaxBatch][3];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
     __shared__ int s_next;
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
-    float* acc = s_acc[half];
+    float* acc = s_acc + half * kCopy;
     int iter = 0;
     while (true) {
         const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
@@ -432,7 +436,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
         const int2 rg = a.ranges[tile];
         const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
         __syncthreads();
-        for (int p = tid; p < NH * T * T; p += NT) (&s_acc[0][0])[p] = 0.f;
+        for (int p = tid; p < NH * kCopy; p += NT) s_acc[p] = 0.f;
         unsigned int cnt = 0;
         for (int b0 = rg.x; b0 < rg.y; b0 += a.batch) {
             const int nb = min(a.batch, rg.y - b0);
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                 const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
                 // exponent at box-local (u, v) = (x - x0, y - y0): expand around the box origin
                 const float PX = b.pxl - (float)b.x0, PY = b.pyl - (float)b.y0;
-                float4 c0, c1;
+                float4 c0, c1, c2;
                 c0.x = b.bz + PX * (b.a00 * PX + 2.f * b.a01 * PY) + b.a11 * PY * PY;
                 c0.y = -2.f * (b.a00 * PX + b.a01 * PY);
                 c0.z = -2.f * (b.a01 * PX + b.a11 * PY);
@@ -451,31 +455,36 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                 c1.x = 2.f * b.a01;
                 c1.y = b.a11;
                 c1.z = b.am;
-                c1.w = __int_as_float((b.x0 & 0xff) | ((b.y0 & 0xff) << 8) | ((w & 0xff) << 16) | ((h & 0xff) << 24));
+                c1.w = __int_as_float(w * h);
+                const float rw = __builtin_amdgcn_rcpf((float)max(w, 1));
+                c2.x = rw;
+                c2.y = 0.5f * rw;
+                c2.z = (float)w;
+                c2.w = __int_as_float(b.y0 * T + b.x0);  // offset of the box origin in a copy
                 s_rec[q][0] = c0;
                 s_rec[q][1] = c1;
+                s_rec[q][2] = c2;
             }
             __syncthreads();
             for (int q = half; q < nb; q += NH) {
-                const float4 c0 = s_rec[q][0], c1 = s_rec[q][1];
-                const int pk = __float_as_int(c1.w);
-                const int x0 = pk & 0xff, y0 = (pk >> 8) & 0xff, w = (pk >> 16) & 0xff, h = (pk >> 24) & 0xff;
-                const int area = w * h;
-                const float inv_w = 1.f / (float)max(w, 1);
+                const float4 c0 = s_rec[q][0], c1 = s_rec[q][1], c2 = s_rec[q][2];
+                const int area = __float_as_int(c1.w);
+                // small integers are exact in float: pixel k of the box sits at
+                // row v = trunc((k + 1/2) / w), column u = k - v w, and at
+                // offset org + k + v (T - w) in the copy
+                const float farea = (float)area, fskip = (float)T - c2.z;
+                const float base = (float)__float_as_int(c2.w) + (float)hl;
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // staged values in registers before the pixel loop
                 for (int c = 0; c < area; c += 32) {
-                    const int idx = c + hl;
-                    const int yy = (int)(((float)idx + 0.5f) * inv_w);
-                    const int xx = idx - yy * w;
-                    const float u = (float)xx, v = (float)yy;
-                    float z = fmaf(c0.y, u, c0.x);
-                    z = fmaf(c0.z, v, z);
-                    z = fmaf(c0.w * u, u, z);
-                    z = fmaf(c1.x * u, v, z);
-                    z = fmaf(c1.y * v, v, z);
+                    const float fk = (float)(c + hl);
+                    const float v = truncf(fmaf(fk, c2.x, c2.y));
+                    const float u = fmaf(-v, c2.z, fk);
+                    float z = fmaf(c0.w, u, fmaf(c1.x, v, c0.y));
+                    z = fmaf(z, u, c0.x);
+                    z = fmaf(fmaf(c1.y, v, c0.z), v, z);
                     const float e = __builtin_amdgcn_exp2f(z) - etau;
-                    if (idx < area && yy < h && xx >= 0 && xx < w && e > 0.f) {
-                        float* dst = acc + (y0 + yy) * T + (x0 + xx);
-                        *dst = fmaf(c1.z, e, *dst);
+                    if (fk < farea && e > 0.f) {
+                        atomicAdd(acc + (int)fmaf(v, fskip, base + (float)c), c1.z * e);
                         if (kCount) ++cnt;
                     }
                 }
@@ -487,14 +496,15 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
             const int px = tc.x0 + p % T, py = tc.y0 + p / T;
             if (px < tc.W && py < tc.H) {
                 const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
-                const float y = (((s_acc[0][p] + s_acc[1][p]) + (s_acc[2][p] + s_acc[3][p])) +
-                                 ((s_acc[4][p] + s_acc[5][p]) + (s_acc[6][p] + s_acc[7][p])));
+                const float* r = s_acc + p;
+                const float y = (((r[0] + r[kCopy]) + (r[2 * kCopy] + r[3 * kCopy])) +
+                                 ((r[4 * kCopy] + r[5 * kCopy]) + (r[6 * kCopy] + r[7 * kCopy])));
                 pred[pi] = y;
                 if (kLoss) {
                     const float m = mask[pi];
-                    const float r = y - target[pi];
-                    sq = fmaf(m * r, r, sq);
-                    if (grad) grad[pi] = 2.f * m * r * inv_msum;
+                    const float rr = y - target[pi];
+                    sq = fmaf(m * rr, rr, sq);
+                    if (grad) grad[pi] = 2.f * m * rr * inv_msum;
                 }
             }
         }

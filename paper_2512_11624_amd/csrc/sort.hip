@@ -3,7 +3,8 @@
 // (generated on the first pass), so later stages can find an instance's
 // emission slot without an inverse permutation.
 //
-// Each pass sorts on an 8-bit digit:
+// The key is cut into as few digits of 8 to 10 bits as cover it (a 16-bit key
+// takes two 8-bit passes, a 19-bit key two 10-bit passes).  Each pass:
 //   1. upsweep: per-block digit histogram in LDS  -> hist[digit * nblocks + block]
 //   2. exclusive scan of hist (digit-major), giving every (digit, block) its
 //      global output offset
@@ -27,23 +28,30 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kIters = 16;
 constexpr int kItems = kThreads * kIters;  // 4096 keys per block
-constexpr int kRadix = 256;
+constexpr int kMaxDigitBits = 10;
 
+template <int kBits>
 __global__ __launch_bounds__(kThreads) void k_upsweep(const uint32_t* __restrict__ keys, int64_t n,
-                                                      int shift, int* __restrict__ hist, int nb) {
+                                                      int shift, int nbits, int* __restrict__ hist, int nb) {
+    constexpr int kRadix = 1 << kBits, D = kRadix / kThreads;
+    const uint32_t dmask = (1u << nbits) - 1u;
     __shared__ int s_h[kRadix];
-    s_h[threadIdx.x] = 0;
+    for (int j = 0; j < D; ++j) s_h[threadIdx.x * D + j] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kItems;
     for (int k = 0; k < kIters; ++k) {
         const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (kRadix - 1)], 1);
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & dmask], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = s_h[threadIdx.x];
+    for (int j = 0; j < D; ++j) {
+        const int d = j * kThreads + threadIdx.x;  // coalesced over the block index for fixed j
+        hist[(int64_t)d * nb + blockIdx.x] = s_h[d];
+    }
 }
 
-template <int kIdx>  // 0: no second payload; 1: second payload read; 2: second payload = input index
+// kIdx: 0 no second payload; 1 second payload read; 2 second payload = input index
+template <int kBits, int kIdx>
 __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restrict__ keys_in,
                                                         const uint32_t* __restrict__ vals_in,
                                                         uint32_t* __restrict__ keys_out,
@@ -52,6 +60,8 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
                                                         uint32_t* __restrict__ idx_out, int64_t n,
                                                         int shift, int nbits,
                                                         const int* __restrict__ offs, int nb) {
+    constexpr int kRadix = 1 << kBits, D = kRadix / kThreads;
+    const uint32_t dmask = (1u << nbits) - 1u;  // bits of the key above the sorted ones are ignored
     __shared__ int s_cnt[kWaves][kRadix];
     __shared__ int s_dstart[kRadix];
     __shared__ int s_gofs[kRadix];
@@ -61,8 +71,12 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
     __shared__ uint32_t s_x[kIdx ? kItems : 1];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int q = 0; q < kWaves; ++q) s_cnt[q][tid] = 0;
-    s_gofs[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    for (int q = 0; q < kWaves; ++q)
+        for (int j = 0; j < D; ++j) s_cnt[q][j * kThreads + tid] = 0;
+    for (int j = 0; j < D; ++j) {
+        const int d = j * kThreads + tid;
+        s_gofs[d] = offs[(int64_t)d * nb + blockIdx.x];
+    }
     __syncthreads();
 
     const int64_t base = (int64_t)blockIdx.x * kItems;
@@ -76,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
         const uint32_t val = valid ? vals_in[i] : 0u;
         if (kIdx == 1) xx[it] = valid ? idx_in[i] : 0u;
         if (kIdx == 2) xx[it] = (uint32_t)i;
-        const int d = (int)((key >> shift) & (kRadix - 1));
+        const int d = (int)((key >> shift) & dmask);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
             const bool bit = (d >> b) & 1;
@@ -98,28 +112,38 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
         rk[it] = valid ? basec + rank : -1;
     }
     __syncthreads();
-    // exclusive prefix over waves for every digit, and digit totals
-    int tot = 0;
-    for (int q = 0; q < kWaves; ++q) {
-        const int c = s_cnt[q][tid];
-        s_cnt[q][tid] = tot;
-        tot += c;
+    // exclusive prefix over waves for every digit (thread owns digits
+    // tid*D .. tid*D+D-1), then an exclusive scan of the digit totals
+    int tots[D];
+    int local = 0;
+    for (int j = 0; j < D; ++j) {
+        const int d = tid * D + j;
+        int tot = 0;
+        for (int q = 0; q < kWaves; ++q) {
+            const int c = s_cnt[q][d];
+            s_cnt[q][d] = tot;
+            tot += c;
+        }
+        tots[j] = tot;
+        local += tot;
     }
-    // exclusive scan of totals over digits (one digit per thread)
-    int incl = tot;
+    int incl = local;
     for (int o = 1; o < 64; o <<= 1) {
         const int u = __shfl_up(incl, o, 64);
         if (lane >= o) incl += u;
     }
     if (lane == 63) s_wsum[w] = incl;
     __syncthreads();
-    int wbase = 0;
-    for (int q = 0; q < w; ++q) wbase += s_wsum[q];
-    s_dstart[tid] = wbase + incl - tot;
+    int run = incl - local;
+    for (int q = 0; q < w; ++q) run += s_wsum[q];
+    for (int j = 0; j < D; ++j) {
+        s_dstart[tid * D + j] = run;
+        run += tots[j];
+    }
     __syncthreads();
     for (int it = 0; it < kIters; ++it) {
         if (rk[it] >= 0) {
-            const int d = (int)((kk[it] >> shift) & (kRadix - 1));
+            const int d = (int)((kk[it] >> shift) & dmask);
             const int pos = s_dstart[d] + s_cnt[w][d] + rk[it];
             s_k[pos] = kk[it];
             s_v[pos] = vv[it];
@@ -131,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
     const int nvalid = rem < kItems ? (int)rem : kItems;
     for (int p = tid; p < nvalid; p += kThreads) {
         const uint32_t key = s_k[p];
-        const int d = (int)((key >> shift) & (kRadix - 1));
+        const int d = (int)((key >> shift) & dmask);
         const int64_t g = (int64_t)s_gofs[d] + (p - s_dstart[d]);
         keys_out[g] = key;
         vals_out[g] = s_v[p];
@@ -139,11 +163,37 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
     }
 }
 
+template <int kBits>
+hipError_t sort_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, const uint32_t* xi,
+                     uint32_t* xo, int idx_mode, int64_t n, int shift, int nbits, int* hist, int* offs,
+                     void* stmp, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_upsweep<kBits>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n, shift, nbits, hist, nb);
+    hipError_t e = launch_scan_int(hist, offs, (int64_t)nb << kBits, nullptr, stmp, st);
+    if (e != hipSuccess) return e;
+    if (idx_mode == 0)
+        hipLaunchKernelGGL((k_downsweep<kBits, 0>), dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                           (const uint32_t*)nullptr, (uint32_t*)nullptr, n, shift, nbits, (const int*)offs, nb);
+    else if (idx_mode == 2)
+        hipLaunchKernelGGL((k_downsweep<kBits, 2>), dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                           (const uint32_t*)nullptr, xo, n, shift, nbits, (const int*)offs, nb);
+    else
+        hipLaunchKernelGGL((k_downsweep<kBits, 1>), dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
+                           xi, xo, n, shift, nbits, (const int*)offs, nb);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int radix_digit_bits(int key_bits) {
+    if (key_bits <= 8) return 8;
+    const int passes = (key_bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    const int width = (key_bits + passes - 1) / passes;
+    return width < 8 ? 8 : width;
+}
 
 size_t sort_tmp_bytes(int64_t n) {
     const int64_t nb = (n + kItems - 1) / kItems;
-    const int64_t nh = nb * kRadix;
+    const int64_t nh = nb << kMaxDigitBits;
     size_t a = sizeof(int) * (size_t)nh * 2;  // hist + offsets
     a = (a + 255) & ~(size_t)255;
     return a + scan_tmp_bytes(nh) + 256;
@@ -155,30 +205,28 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
     *result_in_alt = false;
     if (n <= 0 || key_bits <= 0) return hipSuccess;
     const int64_t nb = (n + kItems - 1) / kItems;
-    const int64_t nh = nb * kRadix;
+    const int64_t nh = nb << kMaxDigitBits;
     int* hist = (int*)tmp;
     int* offs = hist + nh;
     size_t a = sizeof(int) * (size_t)nh * 2;
     a = (a + 255) & ~(size_t)255;
     void* stmp = (char*)tmp + a;
+    const int width = radix_digit_bits(key_bits);
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     uint32_t *xi = idx, *xo = idx_alt;
     bool alt = false;
     bool first = true;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        const int nbits = (key_bits - shift) < 8 ? (key_bits - shift) : 8;
-        hipLaunchKernelGGL(k_upsweep, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, n, shift, hist, (int)nb);
-        hipError_t e = launch_scan_int(hist, offs, nh, nullptr, stmp, st);
+    for (int shift = 0; shift < key_bits; shift += width) {
+        const int nbits = (key_bits - shift) < width ? (key_bits - shift) : width;
+        const int mode = !idx ? 0 : (first ? 2 : 1);
+        hipError_t e;
+        switch (width) {
+            case 8: e = sort_pass<8>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
+            case 9: e = sort_pass<9>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
+            case 10: e = sort_pass<10>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
+            default: return hipErrorInvalidValue;
+        }
         if (e != hipSuccess) return e;
-        if (!idx)
-            hipLaunchKernelGGL(k_downsweep<0>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                               (const uint32_t*)nullptr, (uint32_t*)nullptr, n, shift, nbits, (const int*)offs, (int)nb);
-        else if (first)
-            hipLaunchKernelGGL(k_downsweep<2>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                               (const uint32_t*)nullptr, xo, n, shift, nbits, (const int*)offs, (int)nb);
-        else
-            hipLaunchKernelGGL(k_downsweep<1>, dim3((unsigned)nb), dim3(kThreads), 0, st, ki, vi, ko, vo,
-                               (const uint32_t*)xi, xo, n, shift, nbits, (const int*)offs, (int)nb);
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;

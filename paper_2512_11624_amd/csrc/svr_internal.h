@@ -98,11 +98,14 @@ size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_scan_int2(const int2* in, int2* out, int64_t n, long long* totals, void* tmp,
                             hipStream_t st);
 
-// Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
+// Stable LSD radix sort of (key, value) pairs on the low key_bits bits
+// (higher bits are ignored).
 // Buffers are ping-ponged; *result_in_alt tells where the result ended.  When
 // idx/idx_alt are given, the input position of every pair travels with it
 // (ending in the same buffer parity as keys).
 size_t sort_tmp_bytes(int64_t n);
+// Digit width (8..10 bits) the sort uses for a key of key_bits bits.
+int radix_digit_bits(int key_bits);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
                              bool* result_in_alt, hipStream_t st, uint32_t* idx = nullptr,

@@ -162,3 +162,133 @@ def accept(ctx, params4, pose_zero, pose_prop, target, mask):
     ctx.svr_forward(pred, target, mask, loss=loss, slice_sse=sse1)
     keep = (sse1 < sse0).unsqueeze(1)
     return torch.where(keep, pose_prop, pose_zero), keep.squeeze(1)
+
+
+# ---------------------------------------------------------------------------
+# Evaluation: seconds to the plain method's PSNR, learned vs identity init
+# ---------------------------------------------------------------------------
+
+def _grid_probe(n_gauss, gt_params, shape=(64, 64, 64), h=0.5, half=16.0, device=0):
+    """Volume probe over the cube on a 0.5 mm grid; the ground-truth volume is
+    the library's read-out of the true Gaussians with a wide window (6 sigma)."""
+    import torch
+    from . import recon
+    gt_probe = recon.VolumeProbe(n_gauss, shape, h, (0, 0, 0), np.zeros(1), np.zeros(1), device=device, cutoff=6.0)
+    gt = gt_probe.render(*[torch.as_tensor(a, device="cuda") for a in gt_params]).cpu().numpy().copy()
+    gt_probe.close()
+    c = recon.voxel_centres(shape, h)
+    vmask = np.all(np.abs(c) <= half, axis=1).astype(np.float32)
+    return recon.VolumeProbe(n_gauss, shape, h, (0, 0, 0), gt, vmask, device=device)
+
+
+def observe(geo, gt_params, seed, noise=0.01, device=0):
+    """Observed slices of one subject: the library forward of the true
+    Gaussians at the true motion with a 6-sigma window, plus N(0, noise^2)."""
+    import torch
+    ctx = svr.Context(device)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=6.0, forward_mode=2)
+    ctx.svr_set_geometry(geo)
+    pred = torch.empty(geo.n_pixels, device="cuda")
+    ctx.svr_project_bin(*[torch.as_tensor(a, device="cuda") for a in gt_params],
+                        torch.as_tensor(geo.pose, device="cuda"))
+    ctx.svr_forward(pred)
+    torch.cuda.synchronize()
+    ctx.close()
+    return pred + torch.as_tensor(synth.gaussian_noise(seed, geo.n_pixels, noise), device="cuda")
+
+
+def evaluate_subject(net, seed, n_iter=300, psnr_every=10, tmpl=None, device=0, lr=None):
+    """One held-out subject (cube geometry and motion of the given seed, volume
+    = template perturbation of the seed): fits from the template with identity
+    poses (plain) and from the network's accepted proposals (learned).  The
+    learned clock includes the network and the acceptance forwards."""
+    import torch
+    from . import recon
+    tmpl = tmpl if tmpl is not None else template()
+    geo = synth.config1(seed)
+    gt = subject_params(tmpl, seed)
+    target = observe(geo, gt, seed, device=device)
+    mask = torch.as_tensor(geo.mask, device="cuda")
+    probe = _grid_probe(tmpl.n_gauss, gt, device=device)
+    ctx = svr.Context(device)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_geometry(geo)
+    lr = lr or recon.PAPER_LR
+    init = [tmpl.mean, tmpl.log_scale, tmpl.quat, tmpl.amp]
+    zero = np.zeros((geo.n_slices, 6), np.float32)
+
+    plain = recon.fit(ctx, svr.Params.from_arrays(*init, zero), target, mask, n_iter, lr=lr, probe=probe,
+                      psnr_every=psnr_every)
+
+    params = svr.Params.from_arrays(*init, zero)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs = target.view(geo.n_slices, int(geo.height[0]), int(geo.width[0]))
+    prop = propose(net, obs, torch.as_tensor(placement(geo), device="cuda"))
+    pose0, keep = accept(ctx, params.views()[:4], params.views()[4].clone(), prop, target, mask)
+    params.views()[4].copy_(pose0)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    learned = recon.fit(ctx, params, target, mask, n_iter, lr=lr, probe=probe, psnr_every=psnr_every)
+    learned.times = [t + t_init for t in learned.times]
+    learned.seconds += t_init
+
+    goal = plain.final_psnr - 0.1
+    true_pose = geo.pose.astype(np.float64)
+    err0 = np.abs(true_pose).mean(0)
+    err1 = np.abs(pose0.cpu().numpy().astype(np.float64) - true_pose).mean(0)
+    probe.close()
+    ctx.close()
+    return dict(seed=seed, plain_final_psnr=plain.final_psnr, learned_final_psnr=learned.final_psnr,
+                target_psnr=goal, t_plain=recon.time_to_target(plain, goal),
+                t_learned=recon.time_to_target(learned, goal), t_init=t_init,
+                accepted=int(keep.sum().item()), n_slices=geo.n_slices,
+                pose_err_identity=[float(x) for x in err0], pose_err_proposed=[float(x) for x in err1])
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import torch
+    ap = argparse.ArgumentParser(description="Train the pose network on simulated slices and compare time to "
+                                             "the plain method's PSNR with and without its proposals.")
+    ap.add_argument("--volumes", type=int, default=1000)
+    ap.add_argument("--renders", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--iters", type=int, default=300)
+    ap.add_argument("--subjects", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slices, plac, labels = simulate(a.volumes, a.renders, seed=a.seed)
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t0
+    log(f"simulated {slices.shape[0]} slices in {t_sim:.1f} s")
+    net = svr.PoseNet(0, seed=a.seed, max_batch=a.batch)
+    hist, t_train = train(net, slices, plac, labels, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    log(f"trained in {t_train:.1f} s")
+    del slices, plac, labels
+    tmpl = template()
+    rows = []
+    for s in range(100, 100 + a.subjects):
+        r = evaluate_subject(net, s, n_iter=a.iters, tmpl=tmpl)
+        rows.append(r)
+        log(json.dumps(r))
+    tp = np.array([r["t_plain"] for r in rows])
+    tl = np.array([r["t_learned"] for r in rows])
+    out = dict(metric="seconds to the plain method's PSNR - 0.1 dB", n_subjects=len(rows),
+               median_t_plain=float(np.median(tp)), median_t_learned=float(np.median(tl)),
+               learned_faster=int(np.sum(tl < tp)), learned_reached=int(np.sum(np.isfinite(tl))),
+               mean_accepted=float(np.mean([r["accepted"] / r["n_slices"] for r in rows])),
+               train_seconds=t_train, simulate_seconds=t_sim, train_loss=hist,
+               n_train=a.volumes * a.renders * 48)
+    print(json.dumps(out), flush=True)
+    net.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -192,22 +192,31 @@ def test_incut_pair_count_brackets(ctx):
 
 def test_radix_sort_matches_stable_argsort(ctx):
     """The binning sort is a stable LSD radix sort: bit-exact against numpy's
-    stable argsort, for several key widths, sizes spanning many blocks with a
-    ragged tail, and heavy key duplication."""
+    stable argsort, for key widths that take one to four passes of 8- to
+    10-bit digits, sizes spanning many blocks with a ragged tail, and heavy
+    key duplication.  Bits above key_bits are ignored (cases with "hi"): the
+    order is that of the low bits, and the keys travel unchanged."""
     rng = np.random.default_rng(0)
-    for n, bits in [(1, 8), (5000, 3), (4096 * 7 + 123, 15), (300001, 20), (70000, 32), (100, 9)]:
+    cases = [(1, 8, False), (5000, 3, False), (4096 * 7 + 123, 15, False), (300001, 20, False),
+             (70000, 32, False), (100, 9, False), (200003, 19, False), (90001, 11, False),
+             (150000, 30, False), (4096 * 3 + 17, 16, True), (100000, 19, True), (5000, 5, True)]
+    for n, bits, high in cases:
         hi = 2 ** bits
         keys = rng.integers(0, min(hi, 2**32 - 1), size=n, dtype=np.uint64).astype(np.uint32)
         if n > 1000:
             keys[: n // 3] = keys[0]
+        if high:
+            keys |= rng.integers(0, 2**32 - 1, size=n, dtype=np.uint64).astype(np.uint32) & ~np.uint32(hi - 1)
+            keys[rng.integers(0, n, size=max(n // 50, 1))] = 0xFFFFFFFF
         vals = np.arange(n, dtype=np.uint32)
         k = torch.from_numpy(keys.view(np.int32).copy()).cuda()
         v = torch.from_numpy(vals.view(np.int32).copy()).cuda()
         ctx.svr_sort_pairs(k, v, bits)
         torch.cuda.synchronize()
-        order = np.argsort(keys, kind="stable")
-        assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order])
-        assert np.array_equal(v.cpu().numpy().view(np.uint32), vals[order])
+        low = keys & np.uint32(hi - 1) if bits < 32 else keys
+        order = np.argsort(low, kind="stable")
+        assert np.array_equal(k.cpu().numpy().view(np.uint32), keys[order]), (n, bits, high)
+        assert np.array_equal(v.cpu().numpy().view(np.uint32), vals[order]), (n, bits, high)
 
 
 def test_adam_step_matches_oracle(ctx):

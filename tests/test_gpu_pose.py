@@ -1,0 +1,77 @@
+"""Learned pose proposal end to end on the GPU: simulated training data from
+the library's own forward, training on the BF16-MFMA network, and the
+acceptance rule (a proposal is kept for a slice only where it lowers that
+slice's forward-model error)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from helpers import check_close  # noqa: E402
+from paper_2512_11624_amd import pose, svr, synth  # noqa: E402
+
+
+def test_simulated_slices_match_oracle():
+    """A training slice is the forward model of the perturbed template at the
+    drawn motion (checked against the oracle at the same window)."""
+    geo = pose.template()
+    prm = pose.subject_params(geo, 1000)
+    mot = pose.random_motion(np.random.default_rng(5), geo.n_slices, 15.0, 8.0)
+    ctx = svr.Context(0)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_geometry(geo)
+    pred = torch.empty(geo.n_pixels, device="cuda")
+    ctx.svr_project_bin(*[torch.as_tensor(a).cuda() for a in prm], torch.as_tensor(mot).cuda())
+    ctx.svr_forward(pred)
+    ref = oracle.forward(geo, 3.0, params=prm, pose=mot)
+    torch.cuda.synchronize()
+    print(check_close(pred.cpu().numpy(), ref, "simulated slices"))
+    ctx.close()
+
+
+def test_training_learns_and_acceptance_never_worsens():
+    slices, plac, labels = pose.simulate(40, 2, seed=7)
+    assert slices.shape == (40 * 2 * 48, 32, 32)
+    lab = labels.cpu().numpy()
+    identity_loss = float(np.mean(np.sum(lab * lab, axis=1)))
+    net = svr.PoseNet(0, seed=1, max_batch=128)
+    hist, secs = pose.train(net, slices, plac, labels, epochs=4, batch=128, lr=1e-3)
+    print("identity loss", identity_loss, "train loss", hist, "seconds", secs)
+    assert hist[-1] < hist[0]
+    assert hist[-1] < 0.8 * identity_loss
+
+    tmpl = pose.template()
+    geo = synth.config1(101)
+    gt = pose.subject_params(tmpl, 101)
+    target = pose.observe(geo, gt, 101)
+    mask = torch.as_tensor(geo.mask).cuda()
+    ctx = svr.Context(0)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_geometry(geo)
+    params = svr.Params.from_arrays(tmpl.mean, tmpl.log_scale, tmpl.quat, tmpl.amp,
+                                    np.zeros((geo.n_slices, 6), np.float32))
+    obs = target.view(geo.n_slices, 32, 32)
+    prop = pose.propose(net, obs, torch.as_tensor(pose.placement(geo)).cuda())
+    assert torch.isfinite(prop).all()
+    zero = params.views()[4].clone()
+    chosen, keep = pose.accept(ctx, params.views()[:4], zero, prop, target, mask)
+    # per-slice errors of the three pose sets, recomputed
+    pred = torch.empty(geo.n_pixels, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    sse = {}
+    for name, p in (("zero", zero), ("prop", prop), ("chosen", chosen)):
+        s = torch.empty(geo.n_slices, device="cuda")
+        ctx.svr_project_bin(*params.views()[:4], p)
+        ctx.svr_forward(pred, target, mask, loss=loss, slice_sse=s)
+        sse[name] = s.cpu().numpy()
+    k = keep.cpu().numpy()
+    assert np.array_equal(sse["chosen"][k], sse["prop"][k])
+    assert np.array_equal(sse["chosen"][~k], sse["zero"][~k])
+    assert np.all(sse["chosen"] <= sse["zero"])
+    print("accepted", int(k.sum()), "of", geo.n_slices)
+    ctx.close()
+    net.close()
