@@ -135,13 +135,13 @@ struct Box {
     bool nonempty;
 };
 
-// Size class of an instance's clipped footprint box (0: <= 4 px ... 7: > 256
-// px).  It forms the low bits of the sort key, so that each tile's instances
-// come out grouped by size and the record-per-lane tile kernels see waves of
-// similar per-lane work.
+// Size class of an instance's clipped footprint box (0: <= 16 px, 1: <= 64,
+// 2: <= 256, 3: larger).  It forms the low bits of the sort key, so that each
+// tile's instances come out grouped by size and the record-per-lane tile
+// kernels see waves of similar per-lane work.
 __device__ inline uint32_t area_class(int a) {
-    const uint32_t lg = 32u - __clz((unsigned)max(a - 1, 1));  // ceil(log2(a)) for a >= 2
-    return (uint32_t)min(max((int)lg - 2, 0), (1 << kClassBits) - 1);
+    const int lg = 32 - __clz((unsigned)max(a - 1, 1));  // ceil(log2(a)) for a >= 2
+    return (uint32_t)min(max((lg - 3) >> 1, 0), (1 << kClassBits) - 1);
 }
 
 // Pixel bounding box of the footprint ellipse on slice `sg`.
@@ -454,13 +454,40 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
 // chained back through the pixel-unit scaling, the Schur complement and the
 // slice rotation to
 //   dL/dSigma_j (symmetric), dL/dmu_j, dL/dc_j and the direct sqrt(det) term,
-// reduced over lanes of the same Gaussian with a segmented shuffle scan and
+// reduced over lanes of the same Gaussian with a segmented DPP scan and
 // added once per segment into LDS accumulators; the slice-pose gradient
 // (left perturbation delta and translation) goes to per-block LDS slice
 // accumulators.  Finally thread j chains dL/dSigma_j to the log-scales and
 // the quaternion and writes the Gaussian's gradient.
 // ---------------------------------------------------------------------------
 constexpr int kGAcc = 11;  // GS (6), gmu (3), gc, glsum
+constexpr int kGAct = 11;  // staged activation: mu (3), Sigma (6), lsum, c
+
+// One step of an inclusive sum over runs of equal keys across a wave (keys
+// non-decreasing over lanes): lanes take the value kCtrl moves to them when
+// it comes from a lane with the same key.  row_shr:n (0x110 + n) shifts
+// inside 16-lane rows; row_bcast:15 (0x142, rows 1 and 3) and row_bcast:31
+// (0x143, rows 2 and 3) carry a row's last lane into the following rows.
+// Lanes without a source keep old = 0 (value) or -2 (key, never a real key).
+template <int kCtrl, int kRowMask, int kN>
+__device__ inline void seg_scan_step(float (&v)[kN], int key) {
+    const int src_key = __builtin_amdgcn_update_dpp(-2, key, kCtrl, kRowMask, 0xf, false);
+    const bool take = src_key == key;
+    for (int q = 0; q < kN; ++q) {
+        const float t = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), kCtrl, kRowMask, 0xf, false));
+        v[q] += take ? t : 0.f;
+    }
+}
+
+template <int kN>
+__device__ inline void seg_scan(float (&v)[kN], int key) {
+    seg_scan_step<0x111, 0xf>(v, key);
+    seg_scan_step<0x112, 0xf>(v, key);
+    seg_scan_step<0x114, 0xf>(v, key);
+    seg_scan_step<0x118, 0xf>(v, key);
+    seg_scan_step<0x142, 0xa>(v, key);
+    seg_scan_step<0x143, 0xc>(v, key);
+}
 
 __global__ __launch_bounds__(kBlock) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
@@ -470,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     extern __shared__ float s_pose[];  // [6 * slices of the subject]
     __shared__ int s_roff[kBlock + 1];  // record offsets of the block's Gaussians, relative to the first
     __shared__ float s_gacc[kGAcc][kBlock];
+    __shared__ float s_act[kGAct][kBlock];
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
     const int ns = si.s_end - si.s_begin;
@@ -481,6 +509,14 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         if (tid < ng) s_roff[tid] = (int)(offsets[j].x - R0);
         if (tid == ng - 1) s_roff[ng] = (int)(offsets[j].x + counts[j].x - R0);
         for (int q = 0; q < kGAcc; ++q) s_gacc[q][tid] = 0.f;
+        if (tid < ng) {
+            GAct g;
+            activate(a, j, g);
+            for (int k = 0; k < 3; ++k) s_act[k][tid] = g.mu[k];
+            for (int k = 0; k < 6; ++k) s_act[3 + k][tid] = g.S[k];
+            s_act[9][tid] = g.lsum;
+            s_act[10][tid] = g.c;
+        }
     }
     if (use_lds)
         for (int k = tid; k < 6 * ns; k += blockDim.x) s_pose[k] = 0.f;
@@ -505,8 +541,11 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         const Record R = valid ? rec[R0 + lr] : Record{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
         const int i = __float_as_int(R.r1.w);
         if (valid && i >= si.s_begin && i < si.s_end) {
-            GAct ga;
-            activate(a, blk.g_begin + g, ga);
+            GAct ga;  // only the fields the projection and its adjoint read
+            for (int k = 0; k < 3; ++k) ga.mu[k] = s_act[k][g];
+            for (int k = 0; k < 6; ++k) ga.S[k] = s_act[3 + k][g];
+            ga.lsum = s_act[9][g];
+            ga.c = s_act[10][g];
             const int2 ri = rec_inst[R0 + lr];
             float G[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             for (int64_t e = ri.x; e < (int64_t)ri.x + ri.y && e < n_inst; ++e) {
@@ -598,14 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         }
         // segmented inclusive scan over lanes sharing the same Gaussian
         const int key = valid ? g : -1;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int k2 = __shfl_up(key, o, 64);
-            const bool take = lane >= o && k2 == key;
-            for (int q = 0; q < kGAcc; ++q) {
-                const float v2 = __shfl_up(acc[q], o, 64);
-                if (take) acc[q] += v2;
-            }
-        }
+        seg_scan(acc, key);
         const int knext = __shfl_down(key, 1, 64);
         const bool tail = valid && (lane == 63 || knext != key);
         if (tail)

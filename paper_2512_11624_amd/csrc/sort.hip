@@ -3,8 +3,10 @@
 // (generated on the first pass), so later stages can find an instance's
 // emission slot without an inverse permutation.
 //
-// The key is cut into as few digits of 8 to 10 bits as cover it (a 16-bit key
-// takes two 8-bit passes, a 19-bit key two 10-bit passes).  Each pass:
+// The key is cut into as few digits of 8 or 9 bits as cover it (a 16-bit key
+// takes two 8-bit passes, an 18-bit key two 9-bit passes; wider digits make
+// the histogram scan and the per-block LDS footprint grow faster than a pass
+// costs).  Each pass:
 //   1. upsweep: per-block digit histogram in LDS  -> hist[digit * nblocks + block]
 //   2. exclusive scan of hist (digit-major), giving every (digit, block) its
 //      global output offset
@@ -28,7 +30,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kIters = 16;
 constexpr int kItems = kThreads * kIters;  // 4096 keys per block
-constexpr int kMaxDigitBits = 10;
+constexpr int kMaxDigitBits = 9;
 
 template <int kBits>
 __global__ __launch_bounds__(kThreads) void k_upsweep(const uint32_t* __restrict__ keys, int64_t n,
@@ -223,7 +225,6 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
         switch (width) {
             case 8: e = sort_pass<8>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
             case 9: e = sort_pass<9>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
-            case 10: e = sort_pass<10>(ki, vi, ko, vo, xi, xo, mode, n, shift, nbits, hist, offs, stmp, (int)nb, st); break;
             default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;

@@ -9,7 +9,7 @@
 #define SVR_KZ (-0.5f * SVR_LOG2E)
 
 // Instance sort key = (global tile id << kClassBits) | footprint size class.
-constexpr int kClassBits = 3;
+constexpr int kClassBits = 2;
 
 // Static per-slice geometry (depends on the tile size through the tile table).
 struct SliceGeo {
@@ -104,7 +104,7 @@ hipError_t launch_scan_int2(const int2* in, int2* out, int64_t n, long long* tot
 // idx/idx_alt are given, the input position of every pair travels with it
 // (ending in the same buffer parity as keys).
 size_t sort_tmp_bytes(int64_t n);
-// Digit width (8..10 bits) the sort uses for a key of key_bits bits.
+// Digit width (8 or 9 bits) the sort uses for a key of key_bits bits.
 int radix_digit_bits(int key_bits);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,

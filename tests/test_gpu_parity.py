@@ -192,14 +192,15 @@ def test_incut_pair_count_brackets(ctx):
 
 def test_radix_sort_matches_stable_argsort(ctx):
     """The binning sort is a stable LSD radix sort: bit-exact against numpy's
-    stable argsort, for key widths that take one to four passes of 8- to
-    10-bit digits, sizes spanning many blocks with a ragged tail, and heavy
+    stable argsort, for key widths that take one to four passes of 8- or
+    9-bit digits, sizes spanning many blocks with a ragged tail, and heavy
     key duplication.  Bits above key_bits are ignored (cases with "hi"): the
     order is that of the low bits, and the keys travel unchanged."""
     rng = np.random.default_rng(0)
     cases = [(1, 8, False), (5000, 3, False), (4096 * 7 + 123, 15, False), (300001, 20, False),
              (70000, 32, False), (100, 9, False), (200003, 19, False), (90001, 11, False),
-             (150000, 30, False), (4096 * 3 + 17, 16, True), (100000, 19, True), (5000, 5, True)]
+             (150000, 30, False), (4096 * 3 + 17, 16, True), (100000, 19, True), (5000, 5, True),
+             (100000, 17, False), (4096 * 5 + 1, 18, True), (3000, 9, True)]
     for n, bits, high in cases:
         hi = 2 ** bits
         keys = rng.integers(0, min(hi, 2**32 - 1), size=n, dtype=np.uint64).astype(np.uint32)
