@@ -18,6 +18,8 @@ Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -45,8 +47,42 @@ BYTES_SORT_INST_PASS = 20.0   # upsweep key read 4 + downsweep key/value read 8 
 BYTES_EMIT = (32.0, 8.0)      # per record, per instance
 
 
+# kernel source of each timed stage: a committed counter record is used only
+# while these files are unchanged
+STAGE_SOURCES = {"forward_tile": "render.hip", "backward_tile": "render.hip", "sort": "sort.hip",
+                 "emit": "project.hip", "cull_count": "project.hip", "project_backward": "project.hip"}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_digest(stage):
+    h = hashlib.sha256()
+    for f in (STAGE_SOURCES[stage], "svr_internal.h"):
+        with open(os.path.join(ROOT, "paper_2512_11624_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage, tile, workload):
+    """HBM bytes per launch of the stage's kernel, from the rocprofv3
+    FETCH_SIZE / WRITE_SIZE summaries committed under profiles/ (lines
+    "traffic-record: key=value ..."), or None when no record matches this
+    stage, tile and workload or the kernel source changed since it was taken."""
+    if stage not in STAGE_SOURCES:
+        return None
+    digest = source_digest(stage)
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        with open(fn) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if (kv.get("stage") == stage and kv.get("tile") == str(tile) and kv.get("workload") == workload
+                        and kv.get("source") == digest):
+                    return float(kv["bytes_per_launch"])
+    return None
 
 
 def make_workload(name, seed=0):
@@ -188,6 +224,8 @@ def main():
                     help="0: pixel per lane, 1: record per lane, 2: record on lanes")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch/persistent with svr_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB device to device three times (calibrates the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
@@ -199,6 +237,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {a.numel() * 4} bytes x3")
+        return
     dev = torch.device("cuda:0")
     prob, desc = make_workload(args.workload)
     log(f"workload: {desc}; N={prob.n_gauss} M={prob.n_slices} P={prob.n_pixels}")
@@ -284,8 +330,9 @@ def main():
     roofline = None
     if rl:
         bound, achieved, peak, unit, work = rl
+        traffic = measured_traffic(dominant, ctx.svr_get_config()["tile"], args.workload)
         roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
-                        frac=round(achieved / peak, 6), traffic=None, kernel=dominant,
+                        frac=round(achieved / peak, 6), traffic=traffic, kernel=dominant,
                         avg_ms=round(stages[dominant]["avg_ms"], 5), work_per_launch=work)
 
     sequential = None

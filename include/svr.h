@@ -116,9 +116,9 @@ int64_t svr_num_pixels(const svr_ctx* ctx);
  * staged in LDS batches, deterministic summation order), 1 = record per lane
  * (each lane walks its record's footprint box and accumulates into an LDS
  * pixel tile with atomics; order of equal-pixel sums not fixed), 2 = record
- * on lanes (a wave spreads one record's footprint box over its lanes and
- * accumulates into its own LDS copy of the tile; deterministic).
- * Default {16, 128, 0, 3.0, 0}.  Changing tile or cutoff invalidates the last
+ * on lanes (16-lane groups spread one record's footprint box over their
+ * lanes and accumulate into their own LDS copy of the tile; deterministic).
+ * Default {16, 128, 0, 3.0, 2}.  Changing tile or cutoff invalidates the last
  * svr_project_bin. */
 typedef struct {
     int32_t tile;
@@ -318,7 +318,10 @@ int svr_posenet_grads(svr_posenet* net, const float* crops, const float* orient,
  * y [B,Co,(H+1)/2,(W+1)/2]; relu = 1 applies max(.,0).  dgrad/wgrad take dy
  * (gradient w.r.t. y) and y (the ReLU output, NULL for no ReLU); dgrad writes
  * dx [B,Ci,H,W], wgrad writes dw [Co,Ci,3,3] and db [Co] (may be NULL).
- * linear: x [B,Fin], w [Fout,Fin], b [Fout], y [B,Fout]. */
+ * linear: x [B,Fin], w [Fout,Fin], b [Fout], y [B,Fout].  The weight-gradient
+ * calls split long reductions over several workgroups and take a 25 MB
+ * stream-ordered workspace (hipMallocAsync / hipFreeAsync on the stream) for
+ * the partial sums, which are added in a fixed order. */
 int svr_conv3x3s2_forward(void* hip_stream, const float* x, const float* w, const float* b, float* y, int B,
                           int Ci, int H, int W, int Co, int relu);
 int svr_conv3x3s2_dgrad(void* hip_stream, const float* dy, const float* y, const float* w, float* dx, int B,

@@ -11,6 +11,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <random>
 #include <vector>
 
@@ -35,8 +36,11 @@ __device__ inline unsigned short f2bf(float x) {
 constexpr int BM = 64, BN = 64, BK = 32;
 
 // C[M][N] = sum_k A[M][K] B[K][N]; loaders return 0 outside their operand.
+// blockIdx.z selects the K range [z kz, (z+1) kz) (kz a multiple of BK): with
+// several ranges (split K) the epilogue stores partial sums and a second
+// kernel adds them in a fixed order.
 template <class LA, class LB, class EP>
-__global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K) {
+__global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kz) {
     __shared__ __attribute__((aligned(16))) unsigned short sA[BM][BK];
     __shared__ __attribute__((aligned(16))) unsigned short sB[BN][BK];  // transposed: [n][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -46,7 +50,8 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column lr, k offset lk
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kb = blockIdx.z * kz, ke = min(K, kb + kz);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         us8 va, vb;
         for (int e = 0; e < 8; ++e) {
             const int k = k0 + lk + e;
@@ -236,13 +241,56 @@ struct EStore {
     }
 };
 
+// split-K partial sums: ws[z][row][col]
+struct EPartial {
+    float* ws;
+    int M, N;
+    __device__ void operator()(int row, int col, float v) const {
+        ws[((int64_t)blockIdx.z * M + row) * N + col] = v;
+    }
+};
+
+template <class EP>
+__global__ void k_splitk_sum(const float* __restrict__ ws, int splits, int M, int N, EP ep) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)M * N;
+    if (idx >= mn) return;
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += ws[z * mn + idx];
+    ep((int)(idx / N), (int)(idx % N), v);
+}
+
+// Splits K when the output has too few 64x64 tiles to fill the chip and
+// there is workspace (ws_floats floats) for the partial sums.
 template <class LA, class LB, class EP>
-hipError_t gemm(LA la, LB lb, EP ep, int M, int N, int K, hipStream_t st) {
+hipError_t gemm(LA la, LB lb, EP ep, int M, int N, int K, hipStream_t st, float* ws = nullptr,
+                size_t ws_floats = 0) {
     if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-    dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
-    hipLaunchKernelGGL((k_gemm<LA, LB, EP>), grid, dim3(256), 0, st, la, lb, ep, M, N, K);
+    const int gx = (M + BM - 1) / BM, gy = (N + BN - 1) / BN, tiles = gx * gy;
+    const int ksteps = (K + BK - 1) / BK;
+    int splits = 1;
+    if (ws && tiles < 512 && ksteps >= 16) {
+        splits = std::min(ksteps / 8, (1024 + tiles - 1) / tiles);
+        splits = (int)std::min<size_t>((size_t)splits, ws_floats / ((size_t)M * N));
+    }
+    if (splits < 2) {
+        hipLaunchKernelGGL((k_gemm<LA, LB, EP>), dim3(gx, gy, 1), dim3(256), 0, st, la, lb, ep, M, N, K, ksteps * BK);
+        return hipGetLastError();
+    }
+    const int kz = ((ksteps + splits - 1) / splits) * BK;
+    splits = (K + kz - 1) / kz;
+    hipLaunchKernelGGL((k_gemm<LA, LB, EPartial>), dim3(gx, gy, splits), dim3(256), 0, st, la, lb,
+                       EPartial{ws, M, N}, M, N, K, kz);
+    const int64_t mn = (int64_t)M * N;
+    hipLaunchKernelGGL((k_splitk_sum<EP>), dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, (const float*)ws,
+                       splits, M, N, ep);
     return hipGetLastError();
 }
+
+// workspace that covers every split-K GEMM gemm() sets up: at most
+// ceil(1024 / tiles) splits of an M x N output with tiles = its 64x64 tiles,
+// so splits * M * N <= (1024 / tiles + 1) * tiles * 4096
+constexpr size_t kSplitWs = (size_t)(1024 + 512) * BM * BN;
 
 ConvShape conv_shape(int B, int Ci, int H, int W, int Co) {
     return ConvShape{B, Ci, H, W, Co, (H + 1) / 2, (W + 1) / 2};
@@ -255,9 +303,9 @@ hipError_t conv_dgrad(const float* dy, const float* out, const float* w, float* 
     return gemm(LConvDOut{dy, out, s}, LConvWT{w, s}, EConvDIn{dx, s}, s.B * s.H * s.W, s.Ci, s.Co * 9, st);
 }
 hipError_t conv_wgrad(const float* dy, const float* out, const float* x, float* dw, float* db, ConvShape s,
-                      hipStream_t st) {
+                      hipStream_t st, float* ws, size_t ws_floats) {
     return gemm(LConvDOutT{dy, out, s}, LConvInB{LConvIn{x, s}}, EWGrad{dw, db, s.Ci * 9}, s.Co, s.Ci * 9 + 1,
-                s.B * s.OH * s.OW, st);
+                s.B * s.OH * s.OW, st, ws, ws_floats);
 }
 hipError_t lin_fwd(LMat x, const float* w, const float* b, float* y, int Bn, int Fin, int Fout, int relu,
                    hipStream_t st) {
@@ -270,8 +318,9 @@ hipError_t lin_dgrad(const float* dy, const float* out, const float* w, float* d
                 Fout, st);
 }
 hipError_t lin_wgrad(const float* dy, const float* out, LMat x, float* dw, float* db, int Bn, int Fin, int Fout,
-                     hipStream_t st) {
-    return gemm(LMaskedT{dy, out, Bn, Fout}, LMatB{x, Fin}, EWGrad{dw, db, Fin}, Fout, Fin + 1, Bn, st);
+                     hipStream_t st, float* ws, size_t ws_floats) {
+    return gemm(LMaskedT{dy, out, Bn, Fout}, LMatB{x, Fin}, EWGrad{dw, db, Fin}, Fout, Fin + 1, Bn, st, ws,
+                ws_floats);
 }
 
 // ---- small element-wise kernels --------------------------------------------------
@@ -313,6 +362,17 @@ __global__ void k_mse6(const float* __restrict__ y, const float* __restrict__ t,
     if (threadIdx.x == 0 && loss) loss[0] = s[0] / (float)B;
 }
 
+// Runs f(ws) with a stream-ordered split-K workspace (for the stand-alone
+// layer entry points; the network owns its workspace).
+template <class F>
+int with_split_ws(hipStream_t st, F&& f) {
+    float* ws = nullptr;
+    if (hipMallocAsync((void**)&ws, kSplitWs * sizeof(float), st) != hipSuccess) return SVR_ERR_HIP;
+    const hipError_t e = f(ws);
+    const hipError_t e2 = hipFreeAsync(ws, st);
+    return (e == hipSuccess && e2 == hipSuccess) ? SVR_OK : SVR_ERR_HIP;
+}
+
 }  // namespace
 }  // namespace svr
 
@@ -337,6 +397,7 @@ struct svr_posenet {
     float* y = nullptr;      // [B,6]
     float* dy = nullptr;
     float* dfeat = nullptr;  // [B,524]
+    float* ws = nullptr;     // split-K partial sums, kSplitWs floats
 };
 
 namespace {
@@ -368,13 +429,14 @@ hipError_t net_backward(svr_posenet* net, const float* crops, const float* orien
     hipError_t e;
     // fc2 (no activation on y)
     e = lin_wgrad(net->dy, nullptr, LMat{net->h, B, kHidden, nullptr, 0, 0}, g + net->off[14], g + net->off[15], B,
-                  kHidden, kOut, st);
+                  kHidden, kOut, st, net->ws, kSplitWs);
     if (e != hipSuccess) return e;
     e = lin_dgrad(net->dy, nullptr, net->params + net->off[14], net->dh, B, kHidden, kOut, st);
     if (e != hipSuccess) return e;
     // fc1 (ReLU on h)
     LMat feat{net->act[6], B, kFeat + kOrient, orient, kFeat, kOrient};
-    e = lin_wgrad(net->dh, net->h, feat, g + net->off[12], g + net->off[13], B, kFeat + kOrient, kHidden, st);
+    e = lin_wgrad(net->dh, net->h, feat, g + net->off[12], g + net->off[13], B, kFeat + kOrient, kHidden, st,
+                  net->ws, kSplitWs);
     if (e != hipSuccess) return e;
     e = lin_dgrad(net->dh, net->h, net->params + net->off[12], net->dfeat, B, kFeat + kOrient, kHidden, st);
     if (e != hipSuccess) return e;
@@ -385,7 +447,8 @@ hipError_t net_backward(svr_posenet* net, const float* crops, const float* orien
     for (int l = 5; l >= 0; --l) {
         ConvShape s = conv_shape(B, kCh[l], kSide[l], kSide[l], kCh[l + 1]);
         const float* in = l == 0 ? crops : net->act[l];
-        e = conv_wgrad(net->dact[l + 1], net->act[l + 1], in, g + net->off[2 * l], g + net->off[2 * l + 1], s, st);
+        e = conv_wgrad(net->dact[l + 1], net->act[l + 1], in, g + net->off[2 * l], g + net->off[2 * l + 1], s, st,
+                       net->ws, kSplitWs);
         if (e != hipSuccess) return e;
         if (l > 0) {
             e = conv_dgrad(net->dact[l + 1], net->act[l + 1], net->params + net->off[2 * l], net->dact[l], s, st);
@@ -445,7 +508,8 @@ int svr_posenet_create(svr_posenet** out, int device, void* stream, uint64_t see
          hipMalloc((void**)&net->dh, (size_t)max_batch * kHidden * 4) == hipSuccess &&
          hipMalloc((void**)&net->y, (size_t)max_batch * kOut * 4) == hipSuccess &&
          hipMalloc((void**)&net->dy, (size_t)max_batch * kOut * 4) == hipSuccess &&
-         hipMalloc((void**)&net->dfeat, (size_t)max_batch * (kFeat + kOrient) * 4) == hipSuccess;
+         hipMalloc((void**)&net->dfeat, (size_t)max_batch * (kFeat + kOrient) * 4) == hipSuccess &&
+         hipMalloc((void**)&net->ws, kSplitWs * sizeof(float)) == hipSuccess;
     ok = ok && hipMemcpy(net->params, h.data(), o * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(net->m, 0, o * sizeof(float)) == hipSuccess && hipMemset(net->v, 0, o * sizeof(float)) == hipSuccess;
     if (!ok) {
@@ -460,7 +524,7 @@ int svr_posenet_destroy(svr_posenet* net) {
     if (!net) return SVR_OK;
     (void)hipSetDevice(net->device);
     (void)hipStreamSynchronize(net->stream);
-    float* bufs[] = {net->params, net->grads, net->m, net->v, net->h, net->dh, net->y, net->dy, net->dfeat};
+    float* bufs[] = {net->params, net->grads, net->m, net->v, net->h, net->dh, net->y, net->dy, net->dfeat, net->ws};
     for (float* b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 1; l <= 6; ++l) {
@@ -561,8 +625,9 @@ int svr_conv3x3s2_dgrad(void* stream, const float* dy, const float* y, const flo
 int svr_conv3x3s2_wgrad(void* stream, const float* dy, const float* y, const float* x, float* dw, float* db, int B,
                         int Ci, int H, int W, int Co) {
     if (!dy || !x || !dw || B < 1 || Ci < 1 || H < 1 || W < 1 || Co < 1) return SVR_ERR_ARG;
-    return conv_wgrad(dy, y, x, dw, db, conv_shape(B, Ci, H, W, Co), (hipStream_t)stream) == hipSuccess ? SVR_OK
-                                                                                                       : SVR_ERR_HIP;
+    return with_split_ws((hipStream_t)stream, [&](float* ws) {
+        return conv_wgrad(dy, y, x, dw, db, conv_shape(B, Ci, H, W, Co), (hipStream_t)stream, ws, kSplitWs);
+    });
 }
 
 int svr_linear_forward(void* stream, const float* x, const float* w, const float* b, float* y, int B, int Fin,
@@ -582,9 +647,10 @@ int svr_linear_dgrad(void* stream, const float* dy, const float* y, const float*
 int svr_linear_wgrad(void* stream, const float* dy, const float* y, const float* x, float* dw, float* db, int B,
                      int Fin, int Fout) {
     if (!dy || !x || !dw || B < 1 || Fin < 1 || Fout < 1) return SVR_ERR_ARG;
-    return lin_wgrad(dy, y, LMat{x, B, Fin, nullptr, 0, 0}, dw, db, B, Fin, Fout, (hipStream_t)stream) == hipSuccess
-               ? SVR_OK
-               : SVR_ERR_HIP;
+    return with_split_ws((hipStream_t)stream, [&](float* ws) {
+        return lin_wgrad(dy, y, LMat{x, B, Fin, nullptr, 0, 0}, dw, db, B, Fin, Fout, (hipStream_t)stream, ws,
+                         kSplitWs);
+    });
 }
 
 }  // extern "C"

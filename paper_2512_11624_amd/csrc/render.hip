@@ -396,16 +396,18 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
 
 // Forward, record on lanes: a batch of the tile's records is staged in LDS
 // (footprint box, 1/width and the exponent as a quadratic in box-local pixel
-// coordinates).  Each half-wave (32 lanes) then
-// takes one instance at a time, spreads the instance's box over its lanes
-// (32 pixels per pass: pixel k of the box is row floor((k + 1/2) / w), which
-// a float reciprocal gets exactly for boxes of at most 32 x 32) and adds
+// coordinates).  Each group of 16 lanes (one DPP row) then takes one instance
+// at a time, spreads the instance's box over its lanes (16 pixels per pass:
+// pixel k of the box is row floor((k + 1/2) / w), which a float reciprocal
+// gets exactly for boxes of at most 32 x 32) and adds
 // a * max(e - e_T, 0) into its own LDS copy of the tile with a plain
 // read-modify-write (measured faster here than LDS float atomics): the lanes
-// of one half-wave hit distinct pixels and no other half-wave touches that
-// copy.  The eight copies are then summed in a fixed order, so the result
-// needs no atomics and is deterministic.
-// Instances are grouped by footprint size in the sort, so the two halves of
+// of one group hit distinct pixels and no other group touches that copy.
+// The sixteen copies are then summed in a fixed order, so the result needs
+// no atomics and is deterministic.  Footprints are small (tens of pixels),
+// so 16-lane groups waste fewer lanes on a box's last pass than half-waves
+// and spread the per-instance set-up over four instances per instruction.
+// Instances are grouped by footprint size in the sort, so the four groups of
 // a wave see similar boxes.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* __restrict__ target,
@@ -415,19 +417,19 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                                                      float* __restrict__ tile_sse,
                                                      unsigned long long* __restrict__ incut,
                                                      int* __restrict__ work_counter) {
-    constexpr int NT = 256, NW = 4, NH = 8;
+    constexpr int NT = 256, NW = 4, NG = 16, NH = NT / NG;
     constexpr int kCopy = T * T + 8;  // copy stride: successive copies start 8 banks apart
     __shared__ float s_acc[NH * kCopy];
     __shared__ float4 s_rec[kMaxBatch][3];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
     __shared__ int s_next;
-    const int tid = threadIdx.x, lane = tid & 63, hl = tid & 31;
-    const int wv = tid >> 6, half = tid >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, hl = tid & (NG - 1);
+    const int wv = tid >> 6, grp = tid / NG;
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
-    float* acc = s_acc + half * kCopy;
+    float* acc = s_acc + grp * kCopy;
     int iter = 0;
     while (true) {
         const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                 s_rec[q][2] = c2;
             }
             __syncthreads();
-            for (int q = half; q < nb; q += NH) {
+            for (int q = grp; q < nb; q += NH) {
                 const float4 c0 = s_rec[q][0], c1 = s_rec[q][1], c2 = s_rec[q][2];
                 const int area = __float_as_int(c1.w);
                 // small integers are exact in float: pixel k of the box sits at
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                 const float farea = (float)area, fskip = (float)T - c2.z;
                 const float base = (float)__float_as_int(c2.w) + (float)hl;
                 __builtin_amdgcn_s_waitcnt(0xc07f);  // staged values in registers before the pixel loop
-                for (int c = 0; c < area; c += 32) {
+                for (int c = 0; c < area; c += NG) {
                     const float fk = (float)(c + hl);
                     const float v = truncf(fmaf(fk, c2.x, c2.y));
                     const float u = fmaf(-v, c2.z, fk);
@@ -498,8 +500,11 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
             if (px < tc.W && py < tc.H) {
                 const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
                 const float* r = s_acc + p;
-                const float y = (((r[0] + r[kCopy]) + (r[2 * kCopy] + r[3 * kCopy])) +
-                                 ((r[4 * kCopy] + r[5 * kCopy]) + (r[6 * kCopy] + r[7 * kCopy])));
+                float part[NH / 2];
+                for (int q = 0; q < NH / 2; ++q) part[q] = r[(2 * q) * kCopy] + r[(2 * q + 1) * kCopy];
+                for (int h = NH / 4; h > 0; h >>= 1)
+                    for (int q = 0; q < h; ++q) part[q] = part[2 * q] + part[2 * q + 1];
+                const float y = part[0];
                 pred[pi] = y;
                 if (kLoss) {
                     const float m = mask[pi];

@@ -10,7 +10,7 @@
 //   1. upsweep: per-block digit histogram in LDS  -> hist[digit * nblocks + block]
 //   2. exclusive scan of hist (digit-major), giving every (digit, block) its
 //      global output offset
-//   3. downsweep: every wave ranks its 1024 keys in input order with ballot
+//   3. downsweep: every wave ranks its 512 keys in input order with ballot
 //      "match" masks (lanes holding the same digit), keeps per-wave digit
 //      counters in LDS, scatters the block's keys into LDS in digit order and
 //      writes them out with coalesced runs per digit.
@@ -28,8 +28,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kIters = 16;
-constexpr int kItems = kThreads * kIters;  // 4096 keys per block
+constexpr int kIters = 8;
+constexpr int kItems = kThreads * kIters;  // 2048 keys per block (a block's LDS then allows 4-5 blocks per CU)
 constexpr int kMaxDigitBits = 9;
 
 template <int kBits>
@@ -37,18 +37,24 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const uint32_t* __restrict
                                                       int shift, int nbits, int* __restrict__ hist, int nb) {
     constexpr int kRadix = 1 << kBits, D = kRadix / kThreads;
     const uint32_t dmask = (1u << nbits) - 1u;
-    __shared__ int s_h[kRadix];
-    for (int j = 0; j < D; ++j) s_h[threadIdx.x * D + j] = 0;
+    // one histogram per wave: neighbouring keys often share a digit, and the
+    // LDS serialises atomics on one address
+    __shared__ int s_h[kWaves][kRadix];
+    const int w = threadIdx.x >> 6;
+    for (int q = 0; q < kWaves; ++q)
+        for (int j = 0; j < D; ++j) s_h[q][threadIdx.x * D + j] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kItems;
     for (int k = 0; k < kIters; ++k) {
         const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & dmask], 1);
+        if (i < n) atomicAdd(&s_h[w][(keys[i] >> shift) & dmask], 1);
     }
     __syncthreads();
     for (int j = 0; j < D; ++j) {
         const int d = j * kThreads + threadIdx.x;  // coalesced over the block index for fixed j
-        hist[(int64_t)d * nb + blockIdx.x] = s_h[d];
+        int c = 0;
+        for (int q = 0; q < kWaves; ++q) c += s_h[q][d];
+        hist[(int64_t)d * nb + blockIdx.x] = c;
     }
 }
 

@@ -123,7 +123,7 @@ struct RenderArgs {
     int32_t tile;
     int32_t batch;
     int32_t persistent;
-    int32_t forward_mode;        // 0: pixel per lane, 1: record per lane
+    int32_t forward_mode;        // 0: pixel per lane, 1: record per lane, 2: record on lanes
     float etau;                  // exp(-T^2/2)
     float tau2;                  // T^2
     int32_t n_cu;                // compute units (persistent grid size)

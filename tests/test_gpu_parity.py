@@ -83,9 +83,11 @@ def test_cube_forward_backward_parity(ctx):
     """Cube phantom (2,000 Gaussians, 48 slices of 32x32): every output block."""
     prob = synth.config1(0)
     params, pose, target = _setup(prob)
-    out = _run(ctx, prob, params, pose, target, cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=0))
     ref = _oracle(prob, params, pose, target)
-    _compare(out, ref)
+    for fm in (0, 2):
+        out = _run(ctx, prob, params, pose, target,
+                   cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=fm))
+        _compare(out, ref)
 
 
 @pytest.mark.parametrize("tile,batch,persistent,mode", [(8, 32, 0, 0), (16, 64, 1, 0), (32, 256, 0, 0), (32, 96, 1, 0),
@@ -107,7 +109,7 @@ def test_ragged_slices_and_subjects(ctx):
             synth.config1(6, n_gauss=500, size=45, n_per_stack=4, n_stacks=2)]
     prob = synth.concat(subs)
     params, pose, target = _setup(prob, seed=5)
-    for tile, mode in ((8, 0), (16, 1), (32, 0), (32, 1), (16, 2), (32, 2)):
+    for tile, mode in ((8, 0), (16, 1), (32, 0), (32, 1), (16, 2), (32, 2), (8, 2)):
         out = _run(ctx, prob, params, pose, target,
                    cfg=dict(tile=tile, batch=128, persistent=int(tile == 16), cutoff=3.0, forward_mode=mode))
         ref = _oracle(prob, params, pose, target)
@@ -158,6 +160,7 @@ def test_backward_with_random_upstream(ctx):
     prob = synth.config1(1, n_gauss=1000)
     params, pose, _ = _setup(prob, seed=11)
     g = np.random.default_rng(12).standard_normal(prob.n_pixels).astype(np.float32)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
     ctx.svr_set_geometry(prob)
     dev = gpu_params(params, pose)
     ctx.svr_project_bin(*dev)
