@@ -83,6 +83,7 @@ struct svr_ctx {
     DevBuf<int2> d_ranges;
     DevBuf<float> d_tile_sse, d_partial, d_msum, d_slice_sse, d_pose_acc;
     DevBuf<int> d_work, d_fallback;
+    DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     DevBuf<unsigned long long> d_incut;
     DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
     DevBuf<char> d_tsort_tmp;
@@ -318,6 +319,8 @@ ProjectArgs project_args(svr_ctx* c) {
     a.n_blocks = c->n_blocks;
     a.tile = c->cfg.tile;
     a.tau = c->cfg.cutoff;
+    a.smask = c->d_smask.p;
+    a.smask_words = std::max((c->max_subject_slices + 31) / 32, 1);
     return a;
 }
 
@@ -371,6 +374,7 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
         StageScope sc(c, ST_SLICE_POSE);
         HIPCHK(c, launch_slice_pose(c->d_geo.p, p->pose, c->d_pose.p, c->M, st));
     }
+    HIPCHK(c, ensure(c->d_smask, (size_t)std::max<int64_t>(c->N, 1) * (size_t)std::max((c->max_subject_slices + 31) / 32, 1)));
     ProjectArgs pa = project_args(c);
     {
         StageScope sc(c, ST_CULL_COUNT);

@@ -292,12 +292,19 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
         cnt = 0;
     };
 
+    uint32_t word = 0;
     for (int i = si.s_begin; i < si.s_end; ++i) {
         const SlicePose& sp = a.pose[i];
         const float sig2z = a.geo[i].sig2[2];
+        const int li = i - si.s_begin;
         if (valid && plane_pass(g, sp, sig2z, tau2)) {
-            s_list[cnt][threadIdx.x] = (uint16_t)(i - si.s_begin);
+            s_list[cnt][threadIdx.x] = (uint16_t)li;
             ++cnt;
+            word |= 1u << (li & 31);
+        }
+        if (!kEmit && valid && ((li & 31) == 31 || i == si.s_end - 1)) {
+            a.smask[j * a.smask_words + (li >> 5)] = word;
+            word = 0;
         }
         if (__any(cnt == kList)) flush();
     }
@@ -335,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
                                                  int2* __restrict__ rec_inst, uint32_t* __restrict__ keys,
                                                  uint32_t* __restrict__ vals, int* __restrict__ fallback) {
     __shared__ uint32_t s_list[kEmitCap];
+    __shared__ float s_act[11][kBlock];
     __shared__ int s_wsum[kBlock / 64];
     __shared__ int s_pad_from;  // first instance slot (block-relative) left unwritten
     const GaussBlock blk = a.blocks[blockIdx.x];
@@ -355,19 +363,28 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
     }
     const int64_t j = blk.g_begin + tid;
     const bool valid = tid < ng;
-    GAct g;
-    if (valid) activate(a, j, g); else activate_dummy(g);
+    if (valid) {  // the block's activations, read by every survivor of the Gaussian
+        GAct g;
+        activate(a, j, g);
+        for (int q = 0; q < 3; ++q) s_act[q][tid] = g.mu[q];
+        for (int q = 0; q < 6; ++q) s_act[3 + q][tid] = g.S[q];
+        s_act[9][tid] = g.lsum;
+        s_act[10][tid] = g.c;
+    }
     const float tau2 = a.tau * a.tau;
     int loff = 0, lcap = 0, k = 0;
     if (valid) {
         loff = (int)(offsets[j].x - R0);
         lcap = counts[j].x;
     }
-    for (int i = si.s_begin; i < si.s_end; ++i) {
-        const SlicePose& sp = a.pose[i];
-        const float sig2z = a.geo[i].sig2[2];
-        if (valid && plane_pass(g, sp, sig2z, tau2)) {
-            if (k < lcap) s_list[loff + k] = ((uint32_t)tid << 16) | (uint32_t)(i - si.s_begin);
+    // survivors of the count pass's plane test, in slice order
+    const int nwords = (si.s_end - si.s_begin + 31) >> 5;
+    for (int wd = 0; wd < nwords; ++wd) {
+        uint32_t m = valid ? a.smask[j * a.smask_words + wd] : 0u;
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            if (k < lcap) s_list[loff + k] = ((uint32_t)tid << 16) | (uint32_t)(wd * 32 + b);
             ++k;
         }
     }
@@ -387,8 +404,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
         if (e != 0xffffffffu) {
             const int jl = (int)(e >> 16);
             sl = si.s_begin + (int)(e & 0xffffu);
-            GAct gj;
-            activate(a, blk.g_begin + jl, gj);
+            GAct gj;  // the fields projection and record read
+            for (int q = 0; q < 3; ++q) gj.mu[q] = s_act[q][jl];
+            for (int q = 0; q < 6; ++q) gj.S[q] = s_act[3 + q][jl];
+            gj.lsum = s_act[9][jl];
+            gj.c = s_act[10][jl];
             sgp = &a.geo[sl];
             Proj p;
             project(gj, a.pose[sl], sgp->sig2, tau2, p);

@@ -76,6 +76,10 @@ struct ProjectArgs {
     int32_t n_blocks;
     int32_t tile;
     float tau;
+    // plane-test survivors from the count pass: bit (i - first slice of the
+    // subject) of word [j * smask_words + (i - first) / 32] for Gaussian j
+    uint32_t* smask;
+    int32_t smask_words;
 };
 
 hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,

@@ -160,13 +160,29 @@ def time_to_target(res: FitResult, target):
 # Fetal-scale convergence run: the head phantom fitted from its slices
 # ---------------------------------------------------------------------------
 
-def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None):
+def amplitude_lr(lr, kappa):
+    """The paper's learning rates (App. A.1) with the amplitude rate scaled by
+    kappa: its amplitudes are intensities (its mixture is normalised per
+    point), while here an amplitude is an intensity times the density
+    normalisation kappa of the unnormalised sum, so the same relative step
+    needs a rate kappa times smaller."""
+    out = list(lr)
+    out[3] = lr[3] * kappa
+    return tuple(out)
+
+
+def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
+                     known_poses=False):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
     tissue times the bias field, averaged across the slice thickness, Rician
     noise at SNR 20).  PSNR is measured against the phantom on a 0.5 mm grid
-    over the head's bounding box, inside the head.  Returns the FitResult."""
+    over the head's bounding box, inside the head.  ``known_poses`` starts
+    the poses at the truth and keeps them there (pose rates 0), separating
+    the volume fit from motion correction.  Returns the FitResult, with the
+    PSNR of the generating mixture itself (the representation's ceiling
+    against the phantom) in ``gt_psnr``."""
     import torch
     from . import synth
     prob = synth.config2(seed)
@@ -184,17 +200,32 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     rng = np.random.default_rng(seed + 2)
     mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)
     amp = np.full_like(prob.amp, prob.amp.mean())
-    params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, np.zeros((prob.n_slices, 6), np.float32))
+    pose0 = prob.pose if known_poses else np.zeros((prob.n_slices, 6), np.float32)
+    params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, pose0)
     dev = torch.device("cuda", device)
+    # amplitude = intensity x kappa for the generating mixture
+    inten = synth.head_intensity(prob.mean.astype(np.float64), axes) * \
+        synth.head_bias(prob.mean.astype(np.float64), prob.extra["bias"], axes)
+    kappa = float(np.median(prob.amp / np.maximum(inten, 1e-6)))
+    lr = amplitude_lr(PAPER_LR, kappa) if scale_amp_lr else PAPER_LR
+    if known_poses:
+        lr = lr[:4] + (0.0, 0.0)
+    gt = svr.Params.from_arrays(*prob.params(), prob.pose)
+    gt_psnr = probe.psnr(*gt.views()[:4])
+    del gt
     p0 = probe.psnr(*params.views()[:4])
     if log:
-        log(f"head: N={prob.n_gauss} M={prob.n_slices} P={prob.n_pixels} grid={shape}; initial PSNR {p0:.2f} dB")
+        log(f"head: N={prob.n_gauss} M={prob.n_slices} P={prob.n_pixels} grid={shape}; initial PSNR {p0:.2f} dB, "
+            f"generating mixture {gt_psnr:.2f} dB")
+    if log:
+        log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
-              probe=probe, psnr_every=psnr_every,
+              lr=lr, probe=probe, psnr_every=psnr_every,
               callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
     res.initial_psnr = p0
+    res.gt_psnr = gt_psnr
     res.pose_err = dict(rot_deg_identity=float(np.degrees(np.abs(true_pose[:, :3]).mean())),
                         rot_deg_fitted=float(np.degrees(np.abs(est[:, :3] - true_pose[:, :3]).mean())),
                         trans_mm_identity=float(np.abs(true_pose[:, 3:]).mean()),
@@ -210,10 +241,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="Head-phantom convergence run (PSNR against the phantom).")
     ap.add_argument("--iters", type=int, default=2000)
     ap.add_argument("--psnr-every", type=int, default=50)
+    ap.add_argument("--paper-amp-lr", action="store_true", help="use the paper's amplitude rate unscaled")
+    ap.add_argument("--known-poses", action="store_true", help="poses fixed at the truth")
     a = ap.parse_args(argv)
-    res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True))
+    res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
+                           scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses)
     print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0,
-                          fit_seconds=res.seconds, initial_psnr=res.initial_psnr, final_psnr=res.final_psnr,
+                          known_poses=a.known_poses, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),
           flush=True)
