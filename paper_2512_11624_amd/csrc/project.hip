@@ -514,13 +514,18 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
     int64_t n_inst, float* __restrict__ g_mean, float* __restrict__ g_log_scale, float* __restrict__ g_quat,
     float* __restrict__ g_amp, float* __restrict__ pose_acc, int use_lds) {
-    extern __shared__ float s_pose[];  // [6 * slices of the subject]
+    // dynamic LDS: per-slice pose sums [6 * ns] floats, then this pass's
+    // fixed-point pose sums [6 * ns] int64 (8-byte aligned: 6 * ns floats is
+    // a multiple of 8 bytes)
+    extern __shared__ float s_pose[];
+    __shared__ float s_wmax[kBlock / 64];
     __shared__ int s_roff[kBlock + 1];  // record offsets of the block's Gaussians, relative to the first
     __shared__ float s_gacc[kGAcc][kBlock];
     __shared__ float s_act[kGAct][kBlock];
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
     const int ns = si.s_end - si.s_begin;
+    unsigned long long* s_ipose = reinterpret_cast<unsigned long long*>(s_pose + 6 * ns);
     const int tid = threadIdx.x, lane = tid & 63;
     const int ng = (int)(blk.g_end - blk.g_begin);
     const int64_t R0 = offsets[blk.g_begin].x;
@@ -539,13 +544,19 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         }
     }
     if (use_lds)
-        for (int k = tid; k < 6 * ns; k += blockDim.x) s_pose[k] = 0.f;
+        for (int k = tid; k < 6 * ns; k += blockDim.x) {
+            s_pose[k] = 0.f;
+            s_ipose[k] = 0ull;
+        }
     __syncthreads();
     const int nrec_blk = s_roff[ng];
     const float tau2 = a.tau * a.tau;
     for (int base = 0; base < nrec_blk; base += kBlock) {
         const int lr = base + tid;
         const bool valid = lr < nrec_blk;
+        bool has_pose = false;
+        int li = 0;
+        float pd[6];
         // owning Gaussian: largest g with s_roff[g] <= lr
         int g = 0;
         if (valid) {
@@ -641,7 +652,6 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
                     GSig[3 * u + v] = t;
                 }
             const float B12 = GSig[5] - GSig[7], B20 = GSig[6] - GSig[2], B01 = GSig[1] - GSig[3];
-            float pd[6];
             pd[0] = Rdm[1] * p.w[2] - Rdm[2] * p.w[1] + 2.f * B12;
             pd[1] = Rdm[2] * p.w[0] - Rdm[0] * p.w[2] + 2.f * B20;
             pd[2] = Rdm[0] * p.w[1] - Rdm[1] * p.w[0] + 2.f * B01;
@@ -649,8 +659,8 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
             pd[4] = -Rdm[1];
             pd[5] = -Rdm[2];
             if (use_lds) {
-                const int li = i - si.s_begin;
-                for (int q = 0; q < 6; ++q) atomicAdd(&s_pose[6 * li + q], pd[q]);
+                li = i - si.s_begin;
+                has_pose = true;
             } else {
                 for (int q = 0; q < 6; ++q) atomicAdd(&pose_acc[6 * i + q], pd[q]);
             }
@@ -662,6 +672,40 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         const bool tail = valid && (lane == 63 || knext != key);
         if (tail)
             for (int q = 0; q < kGAcc; ++q) atomicAdd(&s_gacc[q][g], acc[q]);
+        if (use_lds) {
+            // Pose sums per slice.  LDS float atomics are slow on this GPU and
+            // integer ones are not, so each pass adds its values in fixed point:
+            // quantum 2^(e - 40) with 2^e > the pass's largest |value|, exact
+            // sums of up to 256 values below 2^49 quanta; the slice's owner
+            // thread then adds the pass total to its float sum.
+            float m = 0.f;
+            if (has_pose)
+                for (int q = 0; q < 6; ++q) m = fmaxf(m, fabsf(pd[q]));
+            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+            if (lane == 0) s_wmax[tid >> 6] = m;
+            __syncthreads();
+            m = fmaxf(fmaxf(s_wmax[0], s_wmax[1]), fmaxf(s_wmax[2], s_wmax[3]));
+            if (!isfinite(m)) {  // keep a non-finite gradient visible (rare path)
+                if (has_pose)
+                    for (int q = 0; q < 6; ++q) atomicAdd(&s_pose[6 * li + q], pd[q]);
+                m = 0.f;
+                has_pose = false;
+            }
+            const int ex = m > 0.f ? ilogbf(m) + 1 : 0;
+            const float to_q = ldexpf(1.f, 40 - ex);
+            if (has_pose)
+                for (int q = 0; q < 6; ++q)
+                    atomicAdd(&s_ipose[6 * li + q], (unsigned long long)llrintf(pd[q] * to_q));
+            __syncthreads();
+            const double from_q = ldexp(1.0, ex - 40);
+            for (int k = tid; k < 6 * ns; k += kBlock) {
+                const long long v = (long long)s_ipose[k];
+                if (v != 0) {
+                    s_pose[k] += (float)((double)v * from_q);
+                    s_ipose[k] = 0ull;
+                }
+            }
+        }
     }
     __syncthreads();
     if (tid < ng) {
@@ -769,8 +813,8 @@ hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, co
                                    float* g_amp, float* pose_acc, int32_t max_subject_slices,
                                    hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
-    const int use_lds = (max_subject_slices <= 2048) ? 1 : 0;
-    const size_t lds = use_lds ? sizeof(float) * 6 * (size_t)max_subject_slices : 0;
+    const int use_lds = (max_subject_slices <= 512) ? 1 : 0;  // dynamic LDS 72 B per slice
+    const size_t lds = use_lds ? (sizeof(float) + sizeof(unsigned long long)) * 6 * (size_t)max_subject_slices : 0;
     hipLaunchKernelGGL(k_project_backward, dim3(a.n_blocks), dim3(kBlock), lds, st, a, offsets, counts,
                        rec, rec_inst, inst_grad, n_inst, g_mean, g_log_scale, g_quat, g_amp, pose_acc, use_lds);
     return hipGetLastError();

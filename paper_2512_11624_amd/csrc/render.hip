@@ -575,8 +575,19 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
             const Record R = a.rec[a.inst_rec[rg.x + s]];
             const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
             float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-            walk_box(b, [&](int x, int y, float dx, float dy, float e) {
-                const float g = s_g[y * T + x];
+            // the box row by row in one flattened loop (a lane's cost is its own
+            // w*h): dx and the LDS index step by one along a row; a row change
+            // resets them and advances the row terms of the exponent
+            const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
+            const int n = (w > 0 && h > 0) ? w * h : 0;
+            const float dx0 = (float)b.x0 - b.pxl;
+            float dx = dx0, dy = (float)b.y0 - b.pyl;
+            const float b2a01 = 2.f * b.a01;
+            float zy = fmaf(b.a11 * dy, dy, b.bz), bx = b2a01 * dy;
+            int gi = b.y0 * T + b.x0, left = w;
+            for (int k = 0; k < n; ++k) {
+                const float g = s_g[gi];
+                const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bx), zy));
                 const float v = e - etau;
                 Sa = fmaf(g, fmaxf(v, 0.f), Sa);
                 const float t = (v > 0.f) ? g * e : 0.f;
@@ -587,7 +598,15 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
                 Sxx = fmaf(tx, dx, Sxx);
                 Sxy = fmaf(tx, dy, Sxy);
                 Syy = fmaf(ty, dy, Syy);
-            });
+                // next pixel, without a branch: zy(dy + 1) = zy + a11 (2 dy + 1)
+                const bool wrap = --left == 0;
+                left = wrap ? w : left;
+                gi += wrap ? T - w + 1 : 1;
+                zy = wrap ? fmaf(b.a11, fmaf(2.f, dy, 1.f), zy) : zy;
+                bx = wrap ? bx + b2a01 : bx;
+                dy = wrap ? dy + 1.f : dy;
+                dx = wrap ? dx0 : dx + 1.f;
+            }
             const float k2 = b.am * SVR_LN2;
             float4 g0, g1;
             g0.x = Sa;
