@@ -539,20 +539,32 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
 }
 
 // Adjoint, record per lane: the tile's upstream gradient is staged in LDS;
-// every lane walks its record's box and sums, with t = g e (inside the cut):
+// every lane walks one instance's box and sums, with t = g e (inside the cut):
 //   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
 //   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
 // from which the gradient with respect to the stored record fields follows
 // (dz/d field, times amp ln 2).  The result goes to the instance's emission
-// slot, so no atomics are needed.
+// slot, so no atomics are needed.  The walk is rows outer, columns inner,
+// with per-row sums folded in with dy (three accumulations per pixel instead
+// of seven).  A wave runs each loop as long as its largest trip count, so
+// each round of up to 256 instances is first ordered by (box height, box
+// width) with a counting sort in LDS, and lane j walks the j-th box: the
+// lanes of a wave then have boxes of the same shape.  Which lane walks which
+// instance changes no instance's sum, so the result stays deterministic.
 template <int T, int NT>
 __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
                                                  const float* __restrict__ grad_scale,
                                                  float4* __restrict__ inst_grad,
                                                  int* __restrict__ work_counter) {
+    constexpr int kB = (T + 1) * (T + 1);
     __shared__ float s_g[T * T];
+    __shared__ float4 s_box[NT][2];
+    __shared__ uint32_t s_slot[NT];
+    __shared__ int s_hist[kB + 1];
+    __shared__ int s_perm[NT];
+    __shared__ int s_wsum[NT / 64];
     __shared__ int s_next;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float scale = grad_scale ? grad_scale[0] : 1.f;
@@ -568,57 +580,107 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
             const int px = tc.x0 + p % T, py = tc.y0 + p / T;
             s_g[p] = (px < tc.W && py < tc.H) ? grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale : 0.f;
         }
-        __syncthreads();
         const int n = rg.y - rg.x;
-        for (int s = tid; s < n; s += NT) {
-            const uint32_t e_slot = a.inst_idx[rg.x + s];
-            const Record R = a.rec[a.inst_rec[rg.x + s]];
-            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-            float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-            // the box row by row in one flattened loop (a lane's cost is its own
-            // w*h): dx and the LDS index step by one along a row; a row change
-            // resets them and advances the row terms of the exponent
-            const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
-            const int n = (w > 0 && h > 0) ? w * h : 0;
-            const float dx0 = (float)b.x0 - b.pxl;
-            float dx = dx0, dy = (float)b.y0 - b.pyl;
-            const float b2a01 = 2.f * b.a01;
-            float zy = fmaf(b.a11 * dy, dy, b.bz), bx = b2a01 * dy;
-            int gi = b.y0 * T + b.x0, left = w;
-            for (int k = 0; k < n; ++k) {
-                const float g = s_g[gi];
-                const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bx), zy));
-                const float v = e - etau;
-                Sa = fmaf(g, fmaxf(v, 0.f), Sa);
-                const float t = (v > 0.f) ? g * e : 0.f;
-                const float tx = t * dx, ty = t * dy;
-                S0 += t;
-                Sx += tx;
-                Sy += ty;
-                Sxx = fmaf(tx, dx, Sxx);
-                Sxy = fmaf(tx, dy, Sxy);
-                Syy = fmaf(ty, dy, Syy);
-                // next pixel, without a branch: zy(dy + 1) = zy + a11 (2 dy + 1)
-                const bool wrap = --left == 0;
-                left = wrap ? w : left;
-                gi += wrap ? T - w + 1 : 1;
-                zy = wrap ? fmaf(b.a11, fmaf(2.f, dy, 1.f), zy) : zy;
-                bx = wrap ? bx + b2a01 : bx;
-                dy = wrap ? dy + 1.f : dy;
-                dx = wrap ? dx0 : dx + 1.f;
+        for (int r0 = 0; r0 < n; r0 += NT) {
+            const int cnt = min(NT, n - r0);
+            __syncthreads();
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+            __syncthreads();
+            int bucket = 0, pos = 0;
+            if (tid < cnt) {
+                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
+                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+                const bool empty = w == 0 || h == 0;
+                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+                bucket = empty ? 0 : (h * (T + 1) + w);
+                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                           ((y1 + 1) << 24)));
+                s_slot[tid] = a.inst_idx[rg.x + r0 + tid];
+                pos = atomicAdd(&s_hist[bucket], 1);
             }
-            const float k2 = b.am * SVR_LN2;
-            float4 g0, g1;
-            g0.x = Sa;
-            g0.y = k2 * S0;
-            g0.z = -2.f * k2 * (b.a00 * Sx + b.a01 * Sy);
-            g0.w = -2.f * k2 * (b.a01 * Sx + b.a11 * Sy);
-            g1.x = k2 * Sxx;
-            g1.y = 2.f * k2 * Sxy;
-            g1.z = k2 * Syy;
-            g1.w = 0.f;
-            inst_grad[2 * (int64_t)e_slot] = g0;
-            inst_grad[2 * (int64_t)e_slot + 1] = g1;
+            __syncthreads();
+            {   // exclusive scan of the bucket counts: thread t takes a run of ceil(kB / NT)
+                const int per = (kB + NT - 1) / NT;
+                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+                int local = 0;
+                for (int k = kb; k < ke; ++k) local += s_hist[k];
+                int incl = local;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int u = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += u;
+                }
+                if (lane == 63) s_wsum[wv] = incl;
+                __syncthreads();
+                int run = incl - local;
+                for (int q = 0; q < wv; ++q) run += s_wsum[q];
+                for (int k = kb; k < ke; ++k) {
+                    const int c = s_hist[k];
+                    s_hist[k] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            if (tid < cnt) s_perm[s_hist[bucket] + pos] = tid;
+            __syncthreads();
+            if (tid < cnt) {
+                const int q = s_perm[tid];
+                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
+                const int pk = __float_as_int(p1.w);
+                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+                const float pxl = p0.x, pyl = p0.y, bz = p0.z, am = p0.w;
+                const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
+                float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
+                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+                const int hh = (w > 0 && h > 0) ? h : 0;
+                const float dx0 = (float)bx0 - pxl;
+                const float b2a01 = 2.f * a01;
+                float dy = (float)by0 - pyl;
+                int gr = by0 * T + bx0;
+                for (int r = 0; r < hh; ++r) {
+                    const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
+                    float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
+                    int gi = gr;
+                    for (int c = 0; c < w; ++c) {
+                        const float g = s_g[gi];
+                        const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
+                        const float v = e - etau;
+                        Sa = fmaf(g, fmaxf(v, 0.f), Sa);
+                        const float t = (v > 0.f) ? g * e : 0.f;
+                        const float tx = t * dx;
+                        R0 += t;
+                        R1 += tx;
+                        R2 = fmaf(tx, dx, R2);
+                        dx += 1.f;
+                        ++gi;
+                    }
+                    S0 += R0;
+                    Sx += R1;
+                    Sxx += R2;
+                    Sy = fmaf(dy, R0, Sy);
+                    Sxy = fmaf(dy, R1, Sxy);
+                    Syy = fmaf(dy * dy, R0, Syy);
+                    dy += 1.f;
+                    gr += T;
+                }
+                const float k2 = am * SVR_LN2;
+                float4 g0, g1;
+                g0.x = Sa;
+                g0.y = k2 * S0;
+                g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
+                g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
+                g1.x = k2 * Sxx;
+                g1.y = 2.f * k2 * Sxy;
+                g1.z = k2 * Syy;
+                g1.w = 0.f;
+                const uint32_t e_slot = s_slot[q];
+                inst_grad[2 * (int64_t)e_slot] = g0;
+                inst_grad[2 * (int64_t)e_slot + 1] = g1;
+            }
         }
     }
 }
