@@ -220,7 +220,7 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--persistent", type=int, default=0)
-    ap.add_argument("--forward-mode", type=int, default=2,
+    ap.add_argument("--forward-mode", type=int, default=1,
                     help="0: pixel per lane, 1: record per lane, 2: record on lanes")
     ap.add_argument("--autotune", action="store_true", help="pick tile/batch/persistent with svr_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")

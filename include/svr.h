@@ -114,11 +114,12 @@ int64_t svr_num_pixels(const svr_ctx* ctx);
  * queue ordered by decreasing instance count; cutoff: footprint radius T in
  * standard deviations, (0, 8]; forward_mode: 0 = pixel per lane (records
  * staged in LDS batches, deterministic summation order), 1 = record per lane
- * (each lane walks its record's footprint box and accumulates into an LDS
- * pixel tile with atomics; order of equal-pixel sums not fixed), 2 = record
+ * (each lane walks one record's footprint box and adds fixed-point terms to
+ * an LDS pixel tile with integer atomics: exact per round of 256 records,
+ * deterministic), 2 = record
  * on lanes (16-lane groups spread one record's footprint box over their
  * lanes and accumulate into their own LDS copy of the tile; deterministic).
- * Default {16, 128, 0, 3.0, 2}.  Changing tile or cutoff invalidates the last
+ * Default {16, 128, 0, 3.0, 1}.  Changing tile or cutoff invalidates the last
  * svr_project_bin. */
 typedef struct {
     int32_t tile;

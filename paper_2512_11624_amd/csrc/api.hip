@@ -59,7 +59,7 @@ struct svr_ctx {
     std::vector<int64_t> pix_off;
     int32_t max_subject_slices = 0;
 
-    svr_config cfg{16, 128, 0, 3.0f, 2};
+    svr_config cfg{16, 128, 0, 3.0f, 1};
 
     // tile tables (host)
     int32_t n_tiles = 0, key_bits = 1;

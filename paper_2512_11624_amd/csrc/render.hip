@@ -287,33 +287,17 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
     return b;
 }
 
-// Visits the box's pixels row by row in one flattened loop (a lane's cost is
-// its own w*h, and the wave runs to the largest w*h, not max(w) * max(h)).
-// body(x, y, dx, dy, e) with e = exp2(z) of the record at that pixel.
-template <class F>
-__device__ inline void walk_box(const LaneBox& b, F&& body) {
-    const int w = b.x1 - b.x0 + 1, h = b.y1 - b.y0 + 1;
-    const int n = (w > 0 && h > 0) ? w * h : 0;
-    int x = b.x0, y = b.y0;
-    float dy = (float)y - b.pyl;
-    float zy = fmaf(b.a11 * dy, dy, b.bz);
-    float bx = 2.f * b.a01 * dy;
-    for (int k = 0; k < n; ++k) {
-        const float dx = (float)x - b.pxl;
-        const float z = fmaf(dx, fmaf(b.a00, dx, bx), zy);
-        body(x, y, dx, dy, __builtin_amdgcn_exp2f(z));
-        if (++x > b.x1) {
-            x = b.x0;
-            ++y;
-            dy = (float)y - b.pyl;
-            zy = fmaf(b.a11 * dy, dy, b.bz);
-            bx = 2.f * b.a01 * dy;
-        }
-    }
-}
-
-// Forward, record per lane: every lane walks its record's box inside the tile
-// and adds a * max(e - e_T, 0) into an LDS pixel accumulator (ds_add_f32).
+// Forward, record per lane with exact integer accumulation.  Per round of up
+// to 256 of the tile's instances: the boxes are counting-sorted by shape in
+// LDS (a wave's lanes then walk boxes of one shape), each lane walks one box
+// rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum) to
+// the pixel's int32 LDS sum with an integer LDS atomic (float LDS atomics are
+// slow on this GPU, integer ones are not).  The quantum is 2^(e - 30) with
+// 2^e above the round's sum of |a|, so no pixel's round sum can overflow and
+// the rounding error per term is below 2^-31 of that sum.  Integer sums do
+// not depend on the order of the adds; each pixel's owner thread then adds
+// the round's total to its float sum in round order, so the result is
+// deterministic.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* __restrict__ target,
                                                      const float* __restrict__ mask,
@@ -323,7 +307,14 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
                                                      unsigned long long* __restrict__ incut,
                                                      int* __restrict__ work_counter) {
     constexpr int NT = 256, NW = 4;
+    constexpr int kB = (T + 1) * (T + 1);
     __shared__ float s_acc[T * T];
+    __shared__ int s_iacc[T * T];
+    __shared__ float4 s_box[NT][2];
+    __shared__ int s_hist[kB];
+    __shared__ int s_perm[NT];
+    __shared__ int s_wsum[NW];
+    __shared__ float s_fsum[NW];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
     __shared__ int s_next;
@@ -339,20 +330,101 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
         const int2 rg = a.ranges[tile];
         const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
         __syncthreads();
-        for (int p = tid; p < T * T; p += NT) s_acc[p] = 0.f;
-        __syncthreads();
+        for (int p = tid; p < T * T; p += NT) {
+            s_acc[p] = 0.f;
+            s_iacc[p] = 0;
+        }
         unsigned int cnt = 0;
         const int n = rg.y - rg.x;
-        for (int s = tid; s < n; s += NT) {
-            const Record R = a.rec[a.inst_rec[rg.x + s]];
-            const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-            walk_box(b, [&](int x, int y, float, float, float e) {
-                const float v = e - etau;
-                if (v > 0.f) {
-                    atomicAdd(&s_acc[y * T + x], b.am * v);
-                    if (kCount) ++cnt;
+        for (int r0 = 0; r0 < n; r0 += NT) {
+            const int nb = min(NT, n - r0);
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+            __syncthreads();
+            int bucket = 0, pos = 0;
+            float absa = 0.f;
+            if (tid < nb) {
+                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
+                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+                const bool empty = w == 0 || h == 0;
+                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+                bucket = empty ? 0 : (h * (T + 1) + w);
+                absa = empty ? 0.f : fabsf(b.am);
+                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                           ((y1 + 1) << 24)));
+                pos = atomicAdd(&s_hist[bucket], 1);
+            }
+            for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
+            if (lane == 0) s_fsum[wv] = absa;
+            __syncthreads();
+            const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
+            {
+                const int per = (kB + NT - 1) / NT;
+                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+                int local = 0;
+                for (int k = kb; k < ke; ++k) local += s_hist[k];
+                int incl = local;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int u = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += u;
                 }
-            });
+                if (lane == 63) s_wsum[wv] = incl;
+                __syncthreads();
+                int run = incl - local;
+                for (int q = 0; q < wv; ++q) run += s_wsum[q];
+                for (int k = kb; k < ke; ++k) {
+                    const int c = s_hist[k];
+                    s_hist[k] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            if (tid < nb) s_perm[s_hist[bucket] + pos] = tid;
+            __syncthreads();
+            // quantum: the round's sum of |a| spans 2^30 quanta
+            const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
+            const float to_q = ldexpf(1.f, 30 - ex);
+            if (tid < nb) {
+                const int q = s_perm[tid];
+                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
+                const int pk = __float_as_int(p1.w);
+                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+                const float amq = p0.w * to_q;
+                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+                const int hh = (w > 0 && h > 0) ? h : 0;
+                const float dx0 = (float)bx0 - p0.x;
+                float dy = (float)by0 - p0.y;
+                int gr = by0 * T + bx0;
+                for (int r = 0; r < hh; ++r) {
+                    const float zy = fmaf(p1.z * dy, dy, p0.z), bxl = 2.f * p1.y * dy;
+                    float dx = dx0;
+                    int gi = gr;
+                    for (int c = 0; c < w; ++c) {
+                        const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
+                        if (v > 0.f) {
+                            atomicAdd(&s_iacc[gi], __float2int_rn(amq * v));
+                            if (kCount) ++cnt;
+                        }
+                        dx += 1.f;
+                        ++gi;
+                    }
+                    dy += 1.f;
+                    gr += T;
+                }
+            }
+            __syncthreads();
+            const float from_q = ldexpf(1.f, ex - 30);
+            for (int p = tid; p < T * T; p += NT) {
+                const int v = s_iacc[p];
+                if (v != 0) {
+                    s_acc[p] += (float)v * from_q;
+                    s_iacc[p] = 0;
+                }
+            }
         }
         __syncthreads();
         float sq = 0.f;

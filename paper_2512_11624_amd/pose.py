@@ -77,7 +77,7 @@ def simulate(n_volumes, renders_per_volume, seed=0, max_deg=15.0, max_mm=8.0, no
     import torch
     geo = template()
     ctx = svr.Context(device)
-    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
     ctx.svr_set_geometry(geo)
     M, P = geo.n_slices, geo.n_pixels
     pl = torch.as_tensor(placement(geo), device="cuda")
@@ -186,7 +186,7 @@ def observe(geo, gt_params, seed, noise=0.01, device=0):
     Gaussians at the true motion with a 6-sigma window, plus N(0, noise^2)."""
     import torch
     ctx = svr.Context(device)
-    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=6.0, forward_mode=2)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=6.0, forward_mode=1)
     ctx.svr_set_geometry(geo)
     pred = torch.empty(geo.n_pixels, device="cuda")
     ctx.svr_project_bin(*[torch.as_tensor(a, device="cuda") for a in gt_params],
@@ -211,7 +211,7 @@ def evaluate_subject(net, seed, n_iter=300, psnr_every=10, tmpl=None, device=0, 
     mask = torch.as_tensor(geo.mask, device="cuda")
     probe = _grid_probe(tmpl.n_gauss, gt, device=device)
     ctx = svr.Context(device)
-    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
     ctx.svr_set_geometry(geo)
     lr = lr or recon.PAPER_LR
     init = [tmpl.mean, tmpl.log_scale, tmpl.quat, tmpl.amp]

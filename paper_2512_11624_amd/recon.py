@@ -67,7 +67,7 @@ class VolumeProbe:
         self.geom = Problem(g.mean, g.log_scale, g.quat, g.amp, np.array([0, n_gauss], np.int64), g.slice_subject,
                             g.height, g.width, g.spacing, g.psf_fwhm, g.rot0, g.trans0, g.pose, g.mask)
         self.ctx = svr.Context(device)
-        self.ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=cutoff, forward_mode=2)
+        self.ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=cutoff, forward_mode=1)
         self.ctx.svr_set_geometry(self.geom)
         self.P = self.geom.n_pixels
         dev = torch.device("cuda", device)
@@ -195,7 +195,7 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     vmask = (np.linalg.norm(c / axes[None, :], axis=1) <= 1.0).astype(np.float32)
     probe = VolumeProbe(prob.n_gauss, shape, h, (0, 0, 0), gt, vmask, device=device, tile=tile)
     ctx = svr.Context(device)
-    ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=3.0, forward_mode=2)
+    ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
     ctx.svr_set_geometry(prob)
     rng = np.random.default_rng(seed + 2)
     mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)

@@ -155,6 +155,26 @@ def test_empty_and_degenerate(ctx):
     assert torch.all(pred == 0)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_forward_is_deterministic(ctx, mode):
+    """Forward modes 0 and 2 sum in a fixed order and mode 1 sums exact
+    integers per round: repeating a forward (after a fresh binning) gives the
+    same bits."""
+    prob = synth.config1(2, n_gauss=1500)
+    params, pose, _ = _setup(prob, seed=13)
+    ctx.svr_set_config(tile=16, batch=128, persistent=1, cutoff=3.0, forward_mode=mode)
+    ctx.svr_set_geometry(prob)
+    dev = gpu_params(params, pose)
+    outs = []
+    for _ in range(3):
+        ctx.svr_project_bin(*dev)
+        pred = torch.empty(prob.n_pixels, device="cuda")
+        ctx.svr_forward(pred)
+        outs.append(pred)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
 def test_backward_with_random_upstream(ctx):
     """Adjoint alone: an arbitrary seeded upstream gradient (not a loss gradient)."""
     prob = synth.config1(1, n_gauss=1000)
@@ -269,8 +289,8 @@ def test_autograd_function(ctx):
 # oracle (FP64, OpenMP) is fast enough to evaluate every pixel and every
 # gradient at these sizes, so every output block is compared in full.
 
-BENCH_CONFIGS = [dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=2),
-                 dict(tile=32, batch=128, persistent=1, cutoff=3.0, forward_mode=1),
+BENCH_CONFIGS = [dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1),
+                 dict(tile=32, batch=128, persistent=1, cutoff=3.0, forward_mode=2),
                  dict(tile=16, batch=128, persistent=1, cutoff=3.0, forward_mode=0)]
 
 
@@ -284,7 +304,7 @@ def head_full():
     return prob, params, pose, target, ref
 
 
-@pytest.mark.parametrize("cfg", BENCH_CONFIGS, ids=["tile16-rol", "tile32-rpl-persistent", "tile16-pixel-persistent"])
+@pytest.mark.parametrize("cfg", BENCH_CONFIGS, ids=["tile16-rpl", "tile32-rol-persistent", "tile16-pixel-persistent"])
 def test_head_full_size_parity(ctx, head_full, cfg):
     """Head phantom at full size: 500k Gaussians, 128 slices of 256x256."""
     prob, params, pose, target, ref = head_full
