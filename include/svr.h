@@ -130,6 +130,31 @@ typedef struct {
 } svr_config;
 
 int svr_set_config(svr_ctx* ctx, const svr_config* cfg);
+
+/* Data term of the objective, used by svr_forward's loss outputs (default
+ * SVR_LOSS_MSE):
+ *   SVR_LOSS_MSE  masked mean squared error L = sum m (y - I)^2 / sum m,
+ *                 grad_pred = 2 m (y - I) / sum m, slice_sse = per-slice
+ *                 sums of m (y - I)^2;
+ *   SVR_LOSS_L1   the paper's L1 data term (Sec. 2.5, Eq. 7) with the mask,
+ *                 L = sum m |y - I| (not normalised), grad_pred =
+ *                 m sign(y - I) (0 where y = I), slice_sse = per-slice sums
+ *                 of m |y - I|.
+ * Errors: SVR_ERR_ARG for an unknown kind. */
+#define SVR_LOSS_MSE 0
+#define SVR_LOSS_L1 1
+int svr_set_loss(svr_ctx* ctx, int kind);
+
+/* Scale regulariser of Eq. 7 (Sec. 2.5): for the n Gaussians' scales
+ * s = exp(log_scale) [n,3] (DEVICE), adds lambda sum_j ||s_j - s_target||^2
+ * to loss[0] (DEVICE, may be NULL) and 2 lambda (s - s_target) s to
+ * g_log_scale [n,3] (DEVICE), both in place, on the context's stream.  Call it
+ * after svr_backward, which overwrites the gradients.  The paper uses
+ * lambda = 2.5e-3 and s_target = 1.6 mm with its L1 term.  Errors:
+ * SVR_ERR_ARG for n < 0, NULL arrays with n > 0, lambda < 0 or not finite,
+ * s_target <= 0 or not finite. */
+int svr_scale_regularizer(svr_ctx* ctx, const float* log_scale, int64_t n, float lambda, float s_target,
+                          float* g_log_scale, float* loss);
 int svr_get_config(const svr_ctx* ctx, svr_config* cfg);
 
 /* ------------------------------------------------------------------------ */

@@ -9,6 +9,12 @@ Test infrastructure only.
   p <- p (1 - lr wd), first/second moments with bias correction,
   p <- p - lr m_hat / (sqrt(v_hat) + eps).
 * StepLR: the learning rate halves every 200 iterations (App. A.1).
+* The paper's own objective (Sec. 2.5, Eq. 7): an L1 data term summed over the
+  slices' pixels, L = sum_p m_p |y_p - I_p| (the mask m as on the rest of this
+  path), with subgradient dL/dy_p = m_p sign(y_p - I_p) (0 where y = I), plus
+  a scale regulariser lambda sum_j ||s_j - s_target||^2 on the scales
+  s = exp(log s), whose gradient with respect to the log-scales is
+  2 lambda (s - s_target) s.
 """
 from __future__ import annotations
 
@@ -48,3 +54,24 @@ class StepLR:
     def lr(self, it):
         """Learning rate used by iteration ``it`` (0-based)."""
         return self.base_lr * self.gamma ** (it // self.step_size)
+
+
+def masked_l1(pred, target, mask, pix_offset):
+    """Eq. 7's data term with the mask: (loss, dL/dy, per-slice sums)."""
+    y = np.asarray(pred, np.float64)
+    t = np.asarray(target, np.float64)
+    m = np.asarray(mask, np.float64)
+    r = y - t
+    ab = m * np.abs(r)
+    loss = ab.sum()
+    grad = m * np.sign(r)
+    po = np.asarray(pix_offset, np.int64)
+    per_slice = np.array([ab[po[i]:po[i + 1]].sum() for i in range(len(po) - 1)])
+    return loss, grad, per_slice
+
+
+def scale_regularizer(log_scale, lam, s_target):
+    """Eq. 7's regulariser: (value, d value / d log_scale) for scales exp(log_scale)."""
+    s = np.exp(np.asarray(log_scale, np.float64))
+    d = s - float(s_target)
+    return float(lam) * float(np.sum(d * d)), 2.0 * float(lam) * d * s

@@ -83,6 +83,8 @@ struct svr_ctx {
     DevBuf<int2> d_ranges;
     DevBuf<float> d_tile_sse, d_partial, d_msum, d_slice_sse, d_pose_acc;
     DevBuf<int> d_work, d_fallback;
+    int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
+    DevBuf<float> d_regpart;      // scale-regulariser block partials
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     DevBuf<unsigned long long> d_incut;
     DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
@@ -338,6 +340,7 @@ RenderArgs render_args(svr_ctx* c) {
     a.batch = c->cfg.batch;
     a.persistent = c->cfg.persistent;
     a.forward_mode = c->cfg.forward_mode;
+    a.loss_kind = c->loss_kind;
     a.tau2 = c->cfg.cutoff * c->cfg.cutoff;
     a.etau = expf(-0.5f * a.tau2);
     a.n_cu = c->n_cu;
@@ -505,6 +508,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_fallback);
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
+        release(c->d_regpart); release(c->d_smask);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -668,7 +672,8 @@ int svr_forward(svr_ctx* c, const float* target, const float* mask, float* pred,
     if (want_loss) {
         StageScope sc(c, ST_LOSS);
         float* sse = slice_sse ? slice_sse : c->d_slice_sse.p;
-        HIPCHK(c, launch_loss_finalize(c->d_tile_sse.p, c->d_geo.p, c->M, c->d_msum.p, sse, loss, st));
+        HIPCHK(c, launch_loss_finalize(c->d_tile_sse.p, c->d_geo.p, c->M,
+                                       c->loss_kind == SVR_LOSS_MSE ? c->d_msum.p : nullptr, sse, loss, st));
     }
     c->incut_pending = c->count_pairs;
     return SVR_OK;
@@ -746,6 +751,30 @@ int svr_step(svr_ctx* c, const svr_grads* p, const svr_grads* g, float* m, float
     add(p->pose, g->pose, 6 * M, hp->lr[4], hp->lr[5], 1);
     StageScope sc(c, ST_ADAM);
     HIPCHK(c, launch_adam(s, ns, m, v, hp->beta1, hp->beta2, hp->eps, hp->weight_decay, step, c->stream));
+    return SVR_OK;
+}
+
+int svr_set_loss(svr_ctx* c, int kind) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (kind != SVR_LOSS_MSE && kind != SVR_LOSS_L1) return fail(c, SVR_ERR_ARG, "unknown loss kind %d", kind);
+    c->loss_kind = kind;
+    return SVR_OK;
+}
+
+int svr_scale_regularizer(svr_ctx* c, const float* log_scale, int64_t n, float lambda, float s_target,
+                          float* g_log_scale, float* loss) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (n < 0) return fail(c, SVR_ERR_ARG, "n < 0");
+    if (n > 0 && (!log_scale || !g_log_scale)) return fail(c, SVR_ERR_ARG, "log_scale or g_log_scale is NULL");
+    if (!(lambda >= 0.f) || !isfinite(lambda) || !(s_target > 0.f) || !isfinite(s_target))
+        return fail(c, SVR_ERR_ARG, "lambda must be finite and >= 0, s_target finite and > 0");
+    if (n == 0) return SVR_OK;
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    HIPCHK(c, ensure(c->d_regpart, (size_t)kRegBlocks));
+    HIPCHK(c, launch_scale_reg(log_scale, n, lambda, s_target, g_log_scale, loss, c->d_regpart.p, c->stream));
     return SVR_OK;
 }
 

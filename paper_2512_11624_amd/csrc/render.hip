@@ -85,6 +85,20 @@ __global__ __launch_bounds__(256) void k_slice_sse(const float* __restrict__ til
     if (threadIdx.x == 0) slice_sse[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
+// Per-pixel data term of the loss (r = y - I, mask m): kind 0 the masked mean
+// squared error (m r^2, gradient 2 m r / sum m), kind 1 the masked L1 term of
+// Eq. 7 (m |r|, subgradient m sign r, 0 at r = 0).
+__device__ inline void loss_term(int kind, float m, float r, float inv_msum, float& acc, float* gp) {
+    if (kind == 0) {
+        acc = fmaf(m * r, r, acc);
+        if (gp) *gp = 2.f * m * r * inv_msum;
+    } else {
+        acc = fmaf(m, fabsf(r), acc);
+        if (gp) *gp = r > 0.f ? m : (r < 0.f ? -m : 0.f);
+    }
+}
+
+// loss = sum of the per-slice sums, divided by the mask sum (msum != NULL) or not.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ slice_sse, int m,
                                               const float* __restrict__ msum, float* __restrict__ loss) {
     __shared__ float s[4];
@@ -94,8 +108,13 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ slice_ss
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const float ms = msum[0];
-        loss[0] = ms > 0.f ? (s[0] + s[1] + s[2] + s[3]) / ms : 0.f;
+        const float tot = s[0] + s[1] + s[2] + s[3];
+        if (msum) {
+            const float ms = msum[0];
+            loss[0] = ms > 0.f ? tot / ms : 0.f;
+        } else {
+            loss[0] = tot;
+        }
     }
 }
 
@@ -230,8 +249,7 @@ __global__ __launch_bounds__(T * T / PPT) void k_forward(RenderArgs a, const flo
                 if (kLoss) {
                     const float m = mask[pi];
                     const float r = acc[k] - target[pi];
-                    sq = fmaf(m * r, r, sq);
-                    if (grad) grad[pi] = 2.f * m * r * inv_msum;
+                    loss_term(a.loss_kind, m, r, inv_msum, sq, grad ? grad + pi : nullptr);
                 }
             }
         }
@@ -437,8 +455,7 @@ __global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* 
                 if (kLoss) {
                     const float m = mask[pi];
                     const float r = acc - target[pi];
-                    sq = fmaf(m * r, r, sq);
-                    if (grad) grad[pi] = 2.f * m * r * inv_msum;
+                    loss_term(a.loss_kind, m, r, inv_msum, sq, grad ? grad + pi : nullptr);
                 }
             }
         }
@@ -581,8 +598,7 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
                 if (kLoss) {
                     const float m = mask[pi];
                     const float rr = y - target[pi];
-                    sq = fmaf(m * rr, rr, sq);
-                    if (grad) grad[pi] = 2.f * m * rr * inv_msum;
+                    loss_term(a.loss_kind, m, rr, inv_msum, sq, grad ? grad + pi : nullptr);
                 }
             }
         }
@@ -905,6 +921,45 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
         case 32: return fwd_dispatch<32, 4>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid_for(a, 256), st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Scale regulariser of Eq. 7 on s = exp(log s): g += 2 lambda (s - s_t) s per
+// log-scale, and the block's share of lambda sum (s - s_t)^2 into partial[].
+__global__ __launch_bounds__(256) void k_scale_reg(const float* __restrict__ log_scale, int64_t n3, float lambda,
+                                                   float s_target, float* __restrict__ g,
+                                                   float* __restrict__ partial) {
+    __shared__ float s[4];
+    float acc = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3; i += stride) {
+        const float sc = expf(log_scale[i]);
+        const float d = sc - s_target;
+        g[i] += 2.f * lambda * d * sc;
+        acc = fmaf(d, d, acc);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = lambda * (s[0] + s[1] + s[2] + s[3]);
+}
+
+__global__ void k_add_sum(const float* __restrict__ partial, int n, float* __restrict__ out) {
+    __shared__ float s[4];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] += s[0] + s[1] + s[2] + s[3];
+}
+
+hipError_t launch_scale_reg(const float* log_scale, int64_t n, float lambda, float s_target, float* g, float* loss,
+                            float* partial, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nb = kRegBlocks;
+    hipLaunchKernelGGL(k_scale_reg, dim3(nb), dim3(256), 0, st, log_scale, 3 * n, lambda, s_target, g, partial);
+    if (loss) hipLaunchKernelGGL(k_add_sum, dim3(1), dim3(256), 0, st, (const float*)partial, nb, loss);
+    return hipGetLastError();
 }
 
 hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m, const float* msum,

@@ -128,6 +128,7 @@ struct RenderArgs {
     int32_t batch;
     int32_t persistent;
     int32_t forward_mode;        // 0: pixel per lane, 1: record per lane, 2: record on lanes
+    int32_t loss_kind;           // 0: masked mean squared error, 1: masked L1 sum
     float etau;                  // exp(-T^2/2)
     float tau2;                  // T^2
     int32_t n_cu;                // compute units (persistent grid size)
@@ -141,6 +142,11 @@ hipError_t launch_mask_sum(const float* mask, int64_t n, float* partial, float* 
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask,
                           const float* msum, float* pred, float* grad_pred, float* tile_sse,
                           unsigned long long* incut, int* work_counter, hipStream_t st);
+// Scale regulariser (adds to g [n,3] and, if loss != NULL, to loss[0]);
+// partial holds kRegBlocks floats.
+constexpr int kRegBlocks = 512;
+hipError_t launch_scale_reg(const float* log_scale, int64_t n, float lambda, float s_target, float* g, float* loss,
+                            float* partial, hipStream_t st);
 hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m,
                                 const float* msum, float* slice_sse, float* loss, hipStream_t st);
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,

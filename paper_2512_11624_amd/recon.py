@@ -106,13 +106,24 @@ class FitResult:
 
 
 def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
-        psnr_target=None, callback=None):
+        psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum"):
     """Runs n_iter fitting iterations of project_bin + forward + backward +
     AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
     covers the iterations only; the PSNR read-out every ``psnr_every``
-    iterations is timed out.  Stops early once ``psnr_target`` is reached."""
+    iterations is timed out.  Stops early once ``psnr_target`` is reached.
+    ``objective``: "mse" (masked mean squared error) or "l1+reg", the paper's
+    Eq. 7 (masked L1 sum plus reg_lambda sum ||s - s_target||^2).
+    ``reg_reading``: "sum" weighs the sums as written in Eq. 7; "mean" reads
+    reg_lambda as weighting the mean L1 per masked pixel against the mean
+    penalty per Gaussian, i.e. applies reg_lambda * sum(mask) / N to the sums."""
     import torch
+    if objective not in ("mse", "l1+reg"):
+        raise ValueError(f"unknown objective {objective}")
+    if reg_reading not in ("sum", "mean"):
+        raise ValueError(f"unknown reg_reading {reg_reading}")
+    ctx.svr_set_loss(svr.SVR_LOSS_L1 if objective == "l1+reg" else svr.SVR_LOSS_MSE)
     N, M = params.N, params.M
+    lam = reg_lambda * float(mask.sum().item()) / N if reg_reading == "mean" else reg_lambda
     grad = svr.Params(N, M, device=params.flat.device)
     m = torch.zeros_like(params.flat)
     v = torch.zeros_like(params.flat)
@@ -130,6 +141,8 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
         ctx.svr_project_bin(*params.views())
         ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
         ctx.svr_backward(gpred, *grad.views())
+        if objective == "l1+reg":
+            ctx.svr_scale_regularizer(params.views()[1], lam, s_target, grad.views()[1], loss)
         ctx.svr_step(params.views(), grad.views(), m, v, [x * scale for x in lr], it)
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
@@ -172,7 +185,7 @@ def amplitude_lr(lr, kappa):
 
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
-                     known_poses=False):
+                     known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum"):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -180,7 +193,8 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     noise at SNR 20).  PSNR is measured against the phantom on a 0.5 mm grid
     over the head's bounding box, inside the head.  ``known_poses`` starts
     the poses at the truth and keeps them there (pose rates 0), separating
-    the volume fit from motion correction.  Returns the FitResult, with the
+    the volume fit from motion correction.  ``objective``, ``reg_lambda``,
+    ``s_target`` and ``reg_reading`` are passed to fit.  Returns the FitResult, with the
     PSNR of the generating mixture itself (the representation's ceiling
     against the phantom) in ``gt_psnr``."""
     import torch
@@ -220,8 +234,8 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     if log:
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
-              lr=lr, probe=probe, psnr_every=psnr_every,
-              callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
+              lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
+              s_target=s_target, reg_reading=reg_reading, callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
     res.initial_psnr = p0
@@ -243,11 +257,17 @@ def main(argv=None):
     ap.add_argument("--psnr-every", type=int, default=50)
     ap.add_argument("--paper-amp-lr", action="store_true", help="use the paper's amplitude rate unscaled")
     ap.add_argument("--known-poses", action="store_true", help="poses fixed at the truth")
+    ap.add_argument("--objective", choices=("mse", "l1+reg"), default="mse")
+    ap.add_argument("--reg-lambda", type=float, default=2.5e-3)
+    ap.add_argument("--s-target", type=float, default=1.6)
+    ap.add_argument("--reg-reading", choices=("sum", "mean"), default="sum")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
-                           scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses)
+                           scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
+                           reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading)
     print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0,
-                          known_poses=a.known_poses, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
+                          reg_reading=a.reg_reading, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),

@@ -22,6 +22,7 @@ _lock = threading.Lock()
 SVR_OK, SVR_ERR_ARG, SVR_ERR_HIP, SVR_ERR_CAPACITY, SVR_ERR_STATE, SVR_ERR_NODEVICE = 0, -1, -2, -3, -4, -5
 SVR_STATS_SYNC = 1
 SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_MODE, SVR_TUNE_ALL = 1, 2, 4, 8, 15
+SVR_LOSS_MSE, SVR_LOSS_L1 = 0, 1
 
 vp = C.c_void_p
 
@@ -104,6 +105,8 @@ _SIGS = {
     "svr_linear_forward": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, C.c_int], C.c_int),
     "svr_linear_dgrad": ([vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int], C.c_int),
     "svr_linear_wgrad": ([vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int], C.c_int),
+    "svr_set_loss": ([vp, C.c_int], C.c_int),
+    "svr_scale_regularizer": ([vp, vp, C.c_int64, C.c_float, C.c_float, vp, vp], C.c_int),
     "svr_autotune": ([vp, C.POINTER(svr_params), vp, C.c_int, C.c_char_p, C.POINTER(svr_config),
                       C.POINTER(C.c_float), C.c_int], C.c_int),
 }
@@ -164,6 +167,7 @@ class Context:
         self._keep = []
         self.n_gauss = 0
         self.n_slices = 0
+        self.n_subjects = 0
         self.n_pixels = 0
 
     def close(self):
@@ -197,6 +201,7 @@ class Context:
                          arrs["t0"].ctypes.data)
         self._check(load().svr_set_geometry(self.h, C.byref(g)), "svr_set_geometry")
         self.n_gauss = int(arrs["go"][-1])
+        self.n_subjects = int(len(arrs["go"]) - 1)
         self.n_slices = int(len(arrs["h"]))
         self.n_pixels = int(load().svr_num_pixels(self.h))
 
@@ -236,6 +241,15 @@ class Context:
         hp = svr_adam((C.c_float * 6)(*[float(x) for x in lr]), beta1, beta2, eps, weight_decay)
         self._check(load().svr_step(self.h, C.byref(P), C.byref(G), _ptr(exp_avg), _ptr(exp_avg_sq),
                                     C.byref(hp), int(step)), "svr_step")
+
+    def svr_set_loss(self, kind):
+        """kind: SVR_LOSS_MSE (0) or SVR_LOSS_L1 (1)."""
+        self._check(load().svr_set_loss(self.h, int(kind)), "svr_set_loss")
+
+    def svr_scale_regularizer(self, log_scale, lam, s_target, g_log_scale, loss=None):
+        self._check(load().svr_scale_regularizer(self.h, _ptr(log_scale), int(log_scale.shape[0]), float(lam),
+                                                 float(s_target), _ptr(g_log_scale), _ptr(loss)),
+                    "svr_scale_regularizer")
 
     def svr_set_count_pairs(self, enable: bool):
         self._check(load().svr_set_count_pairs(self.h, int(bool(enable))), "svr_set_count_pairs")

@@ -322,3 +322,47 @@ def test_stress_full_size_parity(ctx):
     out = _run(ctx, prob, params, pose, target, cfg=BENCH_CONFIGS[0])
     ref = _oracle(prob, params, pose, target)
     _compare(out, ref)
+
+
+# --------------------------------------------------- the paper's objective ---
+
+def test_l1_data_term_matches_oracle(ctx):
+    """Eq. 7's L1 term (SVR_LOSS_L1): loss, per-slice sums and the subgradient
+    m sign(y - I) against the oracle.  The sign is decided in each side's own
+    precision; it may differ only where the oracle's |y - I| is within the
+    forward's FP32 error."""
+    prob = synth.config1(0, n_gauss=1200)
+    params, pose, target = _setup(prob, seed=21)
+    ctx.svr_set_loss(svr.SVR_LOSS_L1)
+    try:
+        out = _run(ctx, prob, params, pose, target,
+                   cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1))
+    finally:
+        ctx.svr_set_loss(svr.SVR_LOSS_MSE)
+    y = oracle.forward(prob, 3.0, params=params, pose=pose)
+    loss, g, per_slice = oracle.masked_l1(y, target, prob.mask, prob.pix_offset)
+    assert abs(out["loss"] - loss) <= 1e-4 * abs(loss), (out["loss"], loss)
+    print(check_close(out["sse"], per_slice, "per-slice L1"))
+    r = np.abs(y - target)
+    undecided = r <= 1e-5 * np.abs(y).max()
+    mism = (out["gpred"] != g) & ~undecided
+    assert not mism.any(), np.nonzero(mism)[0][:10]
+    assert np.all(np.isin(out["gpred"], (-1.0, 0.0, 1.0)))
+
+
+def test_scale_regularizer_matches_oracle(ctx):
+    """Eq. 7's regulariser: value added to the loss and gradient added to the
+    log-scale gradient, against the oracle."""
+    rng = np.random.default_rng(22)
+    n = 70001
+    ls = rng.uniform(np.log(0.3), np.log(3.0), size=(n, 3)).astype(np.float32)
+    g0 = rng.standard_normal((n, 3)).astype(np.float32)
+    val, g = oracle.scale_regularizer(ls.astype(np.float64), 2.5e-3, 1.6)
+    lsd, gd = to_dev(ls), to_dev(g0)
+    loss = torch.tensor([0.25], device="cuda")
+    ctx.svr_scale_regularizer(lsd, 2.5e-3, 1.6, gd, loss)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - (0.25 + val)) <= 1e-4 * (0.25 + val)
+    print(check_close(gd.cpu().numpy() - g0, g, "regulariser gradient"))
+    with pytest.raises(svr.SvrError):
+        ctx.svr_scale_regularizer(lsd, -1.0, 1.6, gd, loss)
