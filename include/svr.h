@@ -158,6 +158,44 @@ int svr_scale_regularizer(svr_ctx* ctx, const float* log_scale, int64_t n, float
 int svr_get_config(const svr_ctx* ctx, svr_config* cfg);
 
 /* ------------------------------------------------------------------------ */
+/* Content-adaptive initialisation of the means (Sec. 2.5, Eq. 6).  Each
+ * pixel of the current geometry gets the weight
+ *   w = floor(2^20 ((1 - lambda_init) ||grad I|| / gmax + lambda_init))
+ * if mask > 0 (0 otherwise), where ||grad I|| is the in-slice gradient
+ * magnitude of image in intensity per mm (central differences inside the
+ * slice, one-sided on its border, 0 along an axis of length 1) and gmax its
+ * largest value over the subject's masked pixels (if gmax = 0 the weight is
+ * floor(2^20 lambda_init)).  The weights are computed in FP64 with each
+ * operation rounded once, so they are exact integers that any conforming
+ * implementation reproduces.
+ *
+ * svr_init_cdf writes the inclusive cumulative weights, restarting at each
+ * subject's first pixel, to cdf [P] (DEVICE int64), and each subject's total
+ * weight to totals [n_subjects] (HOST, may be NULL).  Synchronous.
+ *
+ * svr_init_means draws a pixel for every Gaussian j of subject s from its
+ * subject's weights: with W the subject's total and u = u[j] [N,4] (DEVICE,
+ * uniforms in [0, 1), 16-byte aligned), t = min(floor(u.x W), W - 1) and the
+ * pixel is the first whose cumulative weight exceeds t; the mean is the
+ * pixel centre moved by ((u.y - 1/2) dx, (u.z - 1/2) dy, (u.w - 1/2) FWHM_z)
+ * in the slice frame, mapped to the world by the slice pose pose [M,6]
+ * (DEVICE, as in svr_params).  Writes mean [N,3] (DEVICE), and if not NULL
+ * pixel [N] (DEVICE int64, global pixel index) and value [N] (DEVICE, image
+ * at that pixel).  Synchronous up to the final sampling launch, which is
+ * asynchronous on the context's stream; uses about 16 B of device scratch
+ * per pixel, kept until the context is destroyed.
+ *
+ * image [P] and mask [P] (DEVICE, mask may be NULL = all pixels) must be
+ * finite.  Errors: SVR_ERR_STATE without geometry; SVR_ERR_ARG for NULL
+ * image / cdf / pose / u / mean, lambda_init outside [0, 1], a misaligned u,
+ * or a subject with Gaussians whose weights are all 0 (every pixel masked
+ * out, or lambda_init = 0 on a constant image). */
+int svr_init_cdf(svr_ctx* ctx, const float* image, const float* mask, float lambda_init, int64_t* cdf,
+                 int64_t* totals);
+int svr_init_means(svr_ctx* ctx, const float* image, const float* mask, const float* pose, float lambda_init,
+                   const float* u, float* mean, int64_t* pixel, float* value);
+
+/* ------------------------------------------------------------------------ */
 /* Parameters: DEVICE pointers, float32.
  *   mean [N,3], log_scale [N,3], quat [N,4] (w,x,y,z, nonzero), amp [N],
  *   pose [M,6] = (omega_x, omega_y, omega_z [rad], tau_x, tau_y, tau_z [mm]). */

@@ -6,12 +6,15 @@ baseline leg use it to judge the HIP path.  The product path never imports it.
 * ``core``  -- ctypes wrapper of the C oracle (world frame, FP64, OpenMP).
 * ``brute`` -- NumPy brute force over every (slice, pixel, Gaussian) triple.
 * ``optim`` -- masked-MSE and L1 losses, the scale regulariser and AdamW.
+* ``init``  -- content-adaptive sampling of the initial means (Eq. 6).
 """
 from .core import (build, load, forward, forward_pixels, backward, backward_subset,
                    backward_band, forward_band, backward_subset_band, num_threads,
                    problem_arrays)
 from .optim import masked_mse, masked_l1, scale_regularizer, adamw_step, StepLR
+from .init import adaptive_means, sampling_weights, sampling_cdf, gradient_magnitude
 
 __all__ = ["build", "load", "forward", "forward_pixels", "backward", "backward_subset",
            "backward_band", "forward_band", "backward_subset_band",
-           "num_threads", "problem_arrays", "masked_mse", "masked_l1", "scale_regularizer", "adamw_step", "StepLR"]
+           "num_threads", "problem_arrays", "masked_mse", "masked_l1", "scale_regularizer", "adamw_step", "StepLR",
+           "adaptive_means", "sampling_weights", "sampling_cdf", "gradient_magnitude"]

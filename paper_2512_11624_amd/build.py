@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsvr.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "project.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "cnn.hip"]
+SOURCES = ["api.hip", "project.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "cnn.hip", "init.hip"]
 ARCH = "gfx950"
 
 

@@ -86,6 +86,12 @@ struct svr_ctx {
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
+    // content-adaptive initialisation (allocated on first use)
+    DevBuf<InitSlice> d_init_tab;
+    DevBuf<SlicePose> d_init_pose;
+    DevBuf<int64_t> d_init_subpix, d_init_cdf, d_init_bsum, d_init_base, d_init_total;
+    DevBuf<double> d_init_g;
+    DevBuf<unsigned long long> d_init_gmax;
     DevBuf<unsigned long long> d_incut;
     DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
     DevBuf<char> d_tsort_tmp;
@@ -509,6 +515,9 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
         release(c->d_regpart); release(c->d_smask);
+        release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
+        release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
+        release(c->d_init_gmax);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -775,6 +784,95 @@ int svr_scale_regularizer(svr_ctx* c, const float* log_scale, int64_t n, float l
     if (rc != SVR_OK) return rc;
     HIPCHK(c, ensure(c->d_regpart, (size_t)kRegBlocks));
     HIPCHK(c, launch_scale_reg(log_scale, n, lambda, s_target, g_log_scale, loss, c->d_regpart.p, c->stream));
+    return SVR_OK;
+}
+
+namespace {
+// Uploads the per-slice and per-subject tables of the initialisation and runs
+// the weight / cumulative-weight kernels into cdf [P]; copies the subjects'
+// totals to host_total (synchronous).
+int init_cdf(svr_ctx* c, const float* image, const float* mask, float lambda, int64_t* cdf,
+             std::vector<int64_t>& host_total) {
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!image) return fail(c, SVR_ERR_ARG, "image is NULL");
+    if (!(lambda >= 0.f && lambda <= 1.f)) return fail(c, SVR_ERR_ARG, "lambda_init must be in [0, 1]");
+    const int32_t S = c->n_subjects, M = c->M;
+    std::vector<InitSlice> tab(M);
+    int32_t max_hw = 1;
+    for (int i = 0; i < M; ++i) {
+        const double dx = c->spacing[2 * i], dy = c->spacing[2 * i + 1];
+        tab[i].inv2_x = 0.5 / dx;
+        tab[i].inv1_x = 1.0 / dx;
+        tab[i].inv2_y = 0.5 / dy;
+        tab[i].inv1_y = 1.0 / dy;
+        tab[i].thick = c->fwhm[3 * i + 2];
+        tab[i].pad = 0;
+        max_hw = (int32_t)std::min<int64_t>(std::max<int64_t>(max_hw, (int64_t)c->H[i] * c->W[i]), 1 << 30);
+    }
+    std::vector<int64_t> sub_pix(S + 1, 0);
+    {
+        int i = 0;
+        for (int s = 0; s < S; ++s) {
+            sub_pix[s] = c->pix_off[i];
+            while (i < M && c->slice_subject[i] == s) ++i;
+        }
+        sub_pix[S] = c->P;
+    }
+    hipStream_t st = c->stream;
+    const int64_t nb = init_scan_blocks(c->P);
+    HIPCHK(c, ensure(c->d_init_tab, (size_t)M));
+    HIPCHK(c, ensure(c->d_init_subpix, (size_t)S + 1));
+    HIPCHK(c, ensure(c->d_init_g, (size_t)c->P));
+    HIPCHK(c, ensure(c->d_init_gmax, (size_t)S));
+    HIPCHK(c, ensure(c->d_init_bsum, (size_t)nb));
+    HIPCHK(c, ensure(c->d_init_base, (size_t)S));
+    HIPCHK(c, ensure(c->d_init_total, (size_t)S));
+    HIPCHK(c, hipMemcpyAsync(c->d_init_tab.p, tab.data(), tab.size() * sizeof(InitSlice), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->d_init_subpix.p, sub_pix.data(), sub_pix.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(c, launch_init_cdf(c->d_geo.p, c->d_init_tab.p, M, max_hw, c->d_init_subpix.p, S, c->P, image, mask,
+                              lambda, c->d_init_g.p, c->d_init_gmax.p, cdf, c->d_init_bsum.p, c->d_init_base.p,
+                              c->d_init_total.p, st));
+    host_total.assign(S, 0);
+    HIPCHK(c, hipMemcpyAsync(host_total.data(), c->d_init_total.p, S * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return SVR_OK;
+}
+}  // namespace
+
+int svr_init_cdf(svr_ctx* c, const float* image, const float* mask, float lambda_init, int64_t* cdf,
+                 int64_t* totals) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!cdf) return fail(c, SVR_ERR_ARG, "cdf is NULL");
+    std::vector<int64_t> tot;
+    rc = init_cdf(c, image, mask, lambda_init, cdf, tot);
+    if (rc != SVR_OK) return rc;
+    if (totals) memcpy(totals, tot.data(), tot.size() * sizeof(int64_t));
+    return SVR_OK;
+}
+
+int svr_init_means(svr_ctx* c, const float* image, const float* mask, const float* pose, float lambda_init,
+                   const float* u, float* mean, int64_t* pixel, float* value) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (c->N == 0) return SVR_OK;
+    if (!pose || !u || !mean) return fail(c, SVR_ERR_ARG, "pose, u or mean is NULL");
+    if (((uintptr_t)u & 15) != 0) return fail(c, SVR_ERR_ARG, "u must be 16-byte aligned");
+    HIPCHK(c, ensure(c->d_init_cdf, (size_t)c->P));
+    std::vector<int64_t> tot;
+    rc = init_cdf(c, image, mask, lambda_init, c->d_init_cdf.p, tot);
+    if (rc != SVR_OK) return rc;
+    for (int s = 0; s < c->n_subjects; ++s)
+        if (c->gauss_off[s + 1] > c->gauss_off[s] && tot[s] <= 0)
+            return fail(c, SVR_ERR_ARG, "subject %d has Gaussians but no pixel with positive weight", s);
+    hipStream_t st = c->stream;
+    HIPCHK(c, ensure(c->d_init_pose, (size_t)c->M));
+    HIPCHK(c, launch_slice_pose(c->d_geo.p, pose, c->d_init_pose.p, c->M, st));
+    HIPCHK(c, launch_init_sample(c->d_geo.p, c->d_init_pose.p, c->d_init_tab.p, c->d_subj.p, c->n_subjects,
+                                 c->d_init_subpix.p, c->d_init_cdf.p, c->d_init_total.p, image, u, c->N, mean,
+                                 pixel, value, st));
     return SVR_OK;
 }
 

@@ -43,6 +43,15 @@ struct GaussBlock {
     int32_t pad;
 };
 
+// Per-slice constants of the content-adaptive initialisation: reciprocals of
+// the difference steps (1/(2 dx), 1/dx, 1/(2 dy), 1/dy, rounded once in FP64
+// on the host) and the through-plane PSF FWHM (the slab of the jitter).
+struct InitSlice {
+    double inv2_x, inv1_x, inv2_y, inv1_y;
+    float thick;
+    int32_t pad;
+};
+
 // One record = one (slice, Gaussian) pair that survives culling, 32 bytes.
 //   r0 = (p*_x, p*_y, beta', amp)   centre in slice pixel units, beta' = KZ beta
 //   r1 = (A'_00, A'_01, A'_11, slice id bits)  conic in pixel units times KZ
@@ -163,5 +172,20 @@ struct AdamSeg {
 };
 hipError_t launch_adam(const AdamSeg* segs, int n_segs, float* m, float* v, double beta1,
                        double beta2, double eps, double wd, int64_t step, hipStream_t st);
+
+// Content-adaptive initialisation (Eq. 6).  sub_pix [s_n+1]: first pixel of
+// each subject (sub_pix[s_n] = P).  launch_init_cdf writes the per-subject
+// inclusive cumulative weights to cdf [P] and each subject's total weight to
+// total [s_n]; scratch: g [P], gmax_bits [s_n], bsum [init_scan_blocks(P)],
+// base [s_n].
+int64_t init_scan_blocks(int64_t P);
+hipError_t launch_init_cdf(const SliceGeo* geo, const InitSlice* tab, int32_t m, int32_t max_hw,
+                           const int64_t* sub_pix, int32_t s_n, int64_t P, const float* image, const float* mask,
+                           float lambda, double* g, unsigned long long* gmax_bits, int64_t* cdf, int64_t* bsum,
+                           int64_t* base, int64_t* total, hipStream_t st);
+hipError_t launch_init_sample(const SliceGeo* geo, const SlicePose* pose, const InitSlice* tab,
+                              const SubjectInfo* subj, int32_t s_n, const int64_t* sub_pix, const int64_t* cdf,
+                              const int64_t* total, const float* image, const float* u, int64_t N, float* mean,
+                              int64_t* pixel, float* value, hipStream_t st);
 
 }  // namespace svr

@@ -161,6 +161,38 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     return res
 
 
+def adaptive_init(ctx, target, mask, n_gauss, n_slices, lambda_init=0.0, seed=0, scale=1.6, pose=None):
+    """Content-adaptive initialisation (Sec. 2.5, Eq. 6) for the context's
+    geometry: means drawn by svr_init_means from the observed slices
+    (lambda_init = 0 favours edges only, 1 is uniform over the mask),
+    isotropic scales of ``scale`` mm (the target scale of Eq. 7), identity
+    rotations, and amplitudes equal to the sampled intensities times the one
+    factor that best fits (least squares over the mask) the slices rendered
+    from them to the observed slices; that scalar is computed on the host
+    from one rendered pass.  Returns (svr.Params on the target's device, that
+    factor)."""
+    import torch
+    from . import synth
+    dev = target.device
+    p = svr.Params(n_gauss, n_slices, device=dev)
+    mean, log_scale, quat, amp, pz = p.views()
+    if pose is not None:
+        pz.copy_(pose)
+    u = torch.as_tensor(synth.init_uniforms(seed, n_gauss), device=dev)
+    ctx.svr_init_means(target, mask, pz, lambda_init, u, mean, None, amp)
+    log_scale.fill_(math.log(scale))
+    quat[:, 0] = 1.0
+    pred = torch.empty(ctx.n_pixels, dtype=torch.float32, device=dev)
+    ctx.svr_project_bin(*p.views())
+    ctx.svr_forward(pred)
+    y = pred.cpu().numpy().astype(np.float64)
+    t = target.cpu().numpy().astype(np.float64)
+    m = mask.cpu().numpy().astype(np.float64)
+    k = float((m * y * t).sum() / max((m * y * y).sum(), 1e-30))
+    amp.mul_(k)
+    return p, k
+
+
 def time_to_target(res: FitResult, target):
     """First fitting time at which the PSNR reached ``target`` (inf if never)."""
     for t, p in zip(res.times, res.psnr):
@@ -185,7 +217,8 @@ def amplitude_lr(lr, kappa):
 
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
-                     known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum"):
+                     known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
+                     init="jitter", psf=True):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -194,7 +227,12 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     over the head's bounding box, inside the head.  ``known_poses`` starts
     the poses at the truth and keeps them there (pose rates 0), separating
     the volume fit from motion correction.  ``objective``, ``reg_lambda``,
-    ``s_target`` and ``reg_reading`` are passed to fit.  Returns the FitResult, with the
+    ``s_target`` and ``reg_reading`` are passed to fit.  ``init``: "jitter"
+    (the generating means moved by 0.3 mm, amplitudes at their mean),
+    "adaptive" (Eq. 6 with lambda_init = 0, as in the paper) or "uniform"
+    (lambda_init = 1), both from the observed slices via adaptive_init.
+    ``psf=False`` fits with a zero PSF (the slices are still acquired with
+    it), the paper's PSF ablation.  Returns the FitResult, with the
     PSNR of the generating mixture itself (the representation's ceiling
     against the phantom) in ``gt_psnr``."""
     import torch
@@ -209,18 +247,31 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     vmask = (np.linalg.norm(c / axes[None, :], axis=1) <= 1.0).astype(np.float32)
     probe = VolumeProbe(prob.n_gauss, shape, h, (0, 0, 0), gt, vmask, device=device, tile=tile)
     ctx = svr.Context(device)
+    if init not in ("jitter", "adaptive", "uniform"):
+        raise ValueError(f"unknown init {init}")
     ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
-    ctx.svr_set_geometry(prob)
-    rng = np.random.default_rng(seed + 2)
-    mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)
-    amp = np.full_like(prob.amp, prob.amp.mean())
-    pose0 = prob.pose if known_poses else np.zeros((prob.n_slices, 6), np.float32)
-    params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, pose0)
+    fit_geom = prob
+    if not psf:
+        import copy
+        fit_geom = copy.copy(prob)
+        fit_geom.psf_fwhm = np.zeros_like(prob.psf_fwhm)
+    ctx.svr_set_geometry(fit_geom)
     dev = torch.device("cuda", device)
-    # amplitude = intensity x kappa for the generating mixture
+    pose0 = prob.pose if known_poses else np.zeros((prob.n_slices, 6), np.float32)
+    if init == "jitter":
+        rng = np.random.default_rng(seed + 2)
+        mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)
+        amp = np.full_like(prob.amp, prob.amp.mean())
+        params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, pose0)
+    else:
+        params, kappa_init = adaptive_init(ctx, torch.as_tensor(target, device=dev),
+                                           torch.as_tensor(prob.mask, device=dev), prob.n_gauss, prob.n_slices,
+                                           0.0 if init == "adaptive" else 1.0, seed + 2, s_target,
+                                           torch.as_tensor(pose0, device=dev))
+    # amplitude = intensity x kappa (generating mixture, or the init's factor)
     inten = synth.head_intensity(prob.mean.astype(np.float64), axes) * \
         synth.head_bias(prob.mean.astype(np.float64), prob.extra["bias"], axes)
-    kappa = float(np.median(prob.amp / np.maximum(inten, 1e-6)))
+    kappa = float(np.median(prob.amp / np.maximum(inten, 1e-6))) if init == "jitter" else kappa_init
     lr = amplitude_lr(PAPER_LR, kappa) if scale_amp_lr else PAPER_LR
     if known_poses:
         lr = lr[:4] + (0.0, 0.0)
@@ -235,7 +286,8 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
               lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
-              s_target=s_target, reg_reading=reg_reading, callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
+              s_target=s_target, reg_reading=reg_reading,
+              callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
     res.initial_psnr = p0
@@ -261,13 +313,16 @@ def main(argv=None):
     ap.add_argument("--reg-lambda", type=float, default=2.5e-3)
     ap.add_argument("--s-target", type=float, default=1.6)
     ap.add_argument("--reg-reading", choices=("sum", "mean"), default="sum")
+    ap.add_argument("--init", choices=("jitter", "adaptive", "uniform"), default="jitter")
+    ap.add_argument("--no-psf", action="store_true", help="fit with a zero PSF")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
                            scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
-                           reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading)
+                           reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading,
+                           init=a.init, psf=not a.no_psf)
     print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0,
                           known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
-                          reg_reading=a.reg_reading, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),

@@ -107,6 +107,8 @@ _SIGS = {
     "svr_linear_wgrad": ([vp, vp, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int], C.c_int),
     "svr_set_loss": ([vp, C.c_int], C.c_int),
     "svr_scale_regularizer": ([vp, vp, C.c_int64, C.c_float, C.c_float, vp, vp], C.c_int),
+    "svr_init_cdf": ([vp, vp, vp, C.c_float, vp, C.POINTER(C.c_int64)], C.c_int),
+    "svr_init_means": ([vp, vp, vp, vp, C.c_float, vp, vp, vp, vp], C.c_int),
     "svr_autotune": ([vp, C.POINTER(svr_params), vp, C.c_int, C.c_char_p, C.POINTER(svr_config),
                       C.POINTER(C.c_float), C.c_int], C.c_int),
 }
@@ -250,6 +252,18 @@ class Context:
         self._check(load().svr_scale_regularizer(self.h, _ptr(log_scale), int(log_scale.shape[0]), float(lam),
                                                  float(s_target), _ptr(g_log_scale), _ptr(loss)),
                     "svr_scale_regularizer")
+
+    def svr_init_cdf(self, image, mask, lambda_init, cdf):
+        """Cumulative Eq. 6 weights into cdf [P] (int64, device); returns the
+        subjects' totals as a list."""
+        tot = (C.c_int64 * max(1, self.n_subjects))()
+        self._check(load().svr_init_cdf(self.h, _ptr(image), _ptr(mask), float(lambda_init), _ptr(cdf), tot),
+                    "svr_init_cdf")
+        return [int(tot[k]) for k in range(self.n_subjects)]
+
+    def svr_init_means(self, image, mask, pose, lambda_init, u, mean, pixel=None, value=None):
+        self._check(load().svr_init_means(self.h, _ptr(image), _ptr(mask), _ptr(pose), float(lambda_init),
+                                          _ptr(u), _ptr(mean), _ptr(pixel), _ptr(value)), "svr_init_means")
 
     def svr_set_count_pairs(self, enable: bool):
         self._check(load().svr_set_count_pairs(self.h, int(bool(enable))), "svr_set_count_pairs")

@@ -459,3 +459,29 @@ def head_observation(problem: Problem, seed: int, snr: float = 20.0, thickness_s
     m = problem.mask > 0
     sigma = float(clean[m].mean()) / snr if m.any() else 0.05
     return rician(clean, seed, sigma)
+
+
+def init_uniforms(seed: int, n: int) -> np.ndarray:
+    """Uniform draws in [0, 1) for the content-adaptive initialisation, [n,4]
+    float32: pixel choice, column offset, row offset, through-plane offset."""
+    return np.random.default_rng(seed).random((n, 4), dtype=np.float32)
+
+
+def textured_image(problem: Problem, seed: int) -> np.ndarray:
+    """A slice image [P] with homogeneous regions and sharp edges: a few
+    random-intensity discs per slice over a constant background, plus weak
+    noise (float32)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(problem.n_pixels, np.float32)
+    po = problem.pix_offset
+    for i in range(problem.n_slices):
+        h, w = int(problem.height[i]), int(problem.width[i])
+        rr, cc = np.mgrid[0:h, 0:w].astype(np.float64)
+        img = np.full((h, w), 0.2)
+        for _ in range(4):
+            r0, c0 = rng.uniform(0, h), rng.uniform(0, w)
+            rad = rng.uniform(0.15, 0.4) * min(h, w)
+            img[(rr - r0) ** 2 + (cc - c0) ** 2 <= rad * rad] = rng.uniform(0.3, 1.0)
+        img += rng.normal(0.0, 0.01, (h, w))
+        out[po[i]:po[i + 1]] = img.ravel()
+    return out

@@ -100,6 +100,8 @@ def test_host_only_context_config_and_state_errors():
     assert lib.svr_sort_pairs(ctx.h, None, None, 5, 8) == svr.SVR_ERR_ARG
     assert lib.svr_sort_pairs(ctx.h, dummy, dummy, 5, 33) == svr.SVR_ERR_ARG
     assert b"key_bits" in lib.svr_last_error(ctx.h)
+    assert lib.svr_init_cdf(ctx.h, dummy, None, 0.5, dummy, None) == svr.SVR_ERR_NODEVICE
+    assert lib.svr_init_means(ctx.h, dummy, None, dummy, 0.5, dummy, dummy, None, None) == svr.SVR_ERR_NODEVICE
 
 
 def test_capacity_error_on_too_many_subject_slices():
