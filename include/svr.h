@@ -253,6 +253,57 @@ int svr_forward(svr_ctx* ctx, const float* target, const float* mask, float* pre
 int svr_backward(svr_ctx* ctx, const float* grad_pred, const float* grad_scale,
                  const svr_grads* out);
 
+/* ------------------------------------------------------------------------ */
+/* The paper's normalised Top-K forward model (Eqs. 2 and 5 with the Top-K
+ * neighbour sets of Sec. 2.5), as an alternative to the windowed model of
+ * svr_project_bin / svr_forward.  For pixel p of slice i at
+ * x = R_i u_p + t_i:
+ *   y_p = sigma_i N_p / (D_p + delta),  N_p = sum_j c_j e_j,  D_p = sum_j e_j,
+ *   e_j = exp(-1/2 v^T Sigma_obs^-1 v),  v = x - mu_j,
+ *   Sigma_obs = Sigma_j + R_i Sigma_PSF R_i^T,
+ * the sums over the K means of the slice's subject nearest to x (L2), as in
+ * Eq. 5 without the sqrt(det) factor of the windowed model.
+ *
+ * svr_topk_build computes those neighbour lists for the current geometry
+ * from mean [N,3] and pose [M,6] (DEVICE) for every pixel with mask > 0
+ * (mask [P] DEVICE, NULL = every pixel) and writes them to nbr [P,K]
+ * (DEVICE int32, caller-owned, global Gaussian ids in no particular order;
+ * a pixel outside the mask gets -1 in every entry and is predicted as 0, so
+ * pass the same mask to the forward).
+ * The paper refreshes its neighbour index every 50 epochs: the lists are
+ * then reused with changing parameters until the next build.  The context
+ * also keeps the inverse lists (the pixels holding each Gaussian, 8 B per
+ * list entry plus sort space, about 4 x 4 B x P x K in total) for the
+ * adjoint.  Synchronous.  Errors: SVR_ERR_STATE without geometry;
+ * SVR_ERR_ARG for NULL pointers, K outside [1, 1024] or a subject with
+ * slices and fewer than K Gaussians; SVR_ERR_CAPACITY when P*K exceeds
+ * 2^31-1 or the search cannot complete for some pixel (more than 2,560
+ * means within reach of one pixel, or fewer than K within about 60 times
+ * the mean neighbour distance).
+ *
+ * svr_topk_forward evaluates the model with params (svr_params), sigma [M]
+ * (DEVICE, per-slice intensity scalars of Sec. 2.4, NULL = all 1), delta > 0
+ * and the nbr / K of the last build, writing pred [P].  With target and
+ * mask (DEVICE [P]) it also writes the loss of the context's loss kind
+ * (svr_set_loss: masked MSE or L1) to loss [1] and dL/dy to grad_pred [P];
+ * either may be NULL.  It keeps N_p / (D_p + delta) and D_p + delta per pixel
+ * for the adjoint.
+ *
+ * svr_topk_backward writes the gradient of sum_p g_p y_p, g = grad_pred [P]
+ * (DEVICE), with respect to the parameters of the last svr_topk_forward
+ * (mean, log_scale, quat, amp, and pose through the left Jacobian of SO(3))
+ * to out, and with respect to sigma to g_sigma [M] (DEVICE, may be NULL).
+ * Pixels with g_p = 0 are skipped.  The lists are held fixed (the gradient
+ * of the selection itself is zero almost everywhere).  Errors: SVR_ERR_STATE
+ * before a build or forward, or for nbr / K other than the build's;
+ * SVR_ERR_ARG for NULL pointers or delta <= 0. */
+int svr_topk_build(svr_ctx* ctx, const float* mean, const float* pose, const float* mask, int K, int32_t* nbr);
+int svr_topk_forward(svr_ctx* ctx, const svr_params* params, const float* sigma, const int32_t* nbr, int K,
+                     float delta, const float* target, const float* mask, float* pred, float* loss,
+                     float* grad_pred);
+int svr_topk_backward(svr_ctx* ctx, const svr_params* params, const int32_t* nbr, int K, const float* grad_pred,
+                      const svr_grads* out, float* g_sigma);
+
 /* AdamW (App. A.1).  lr[6] = learning rates of the groups mean, log_scale,
  * quat, amp, pose rotation omega, pose translation tau.  Updates params,
  * exp_avg and exp_avg_sq in place; step counts from 1 (bias correction).

@@ -7,6 +7,8 @@ baseline leg use it to judge the HIP path.  The product path never imports it.
 * ``brute`` -- NumPy brute force over every (slice, pixel, Gaussian) triple.
 * ``optim`` -- masked-MSE and L1 losses, the scale regulariser and AdamW.
 * ``init``  -- content-adaptive sampling of the initial means (Eq. 6).
+* ``topk``  -- the normalised Top-K model of Eqs. 2 and 5 (PyTorch FP64,
+  gradients by autograd).
 """
 from .core import (build, load, forward, forward_pixels, backward, backward_subset,
                    backward_band, forward_band, backward_subset_band, num_threads,

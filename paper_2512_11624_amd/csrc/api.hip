@@ -26,11 +26,13 @@ using namespace svr;
 namespace {
 enum Stage {
     ST_SLICE_POSE, ST_CULL_COUNT, ST_SCAN, ST_EMIT, ST_SORT, ST_TILE_RANGES, ST_TILE_ORDER, ST_MASK_SUM,
-    ST_FORWARD, ST_LOSS, ST_ZERO, ST_BACKWARD, ST_PROJECT_BACKWARD, ST_POSE_CHAIN, ST_ADAM, ST_COUNT
+    ST_FORWARD, ST_LOSS, ST_ZERO, ST_BACKWARD, ST_PROJECT_BACKWARD, ST_POSE_CHAIN, ST_ADAM, ST_TOPK_KNN,
+    ST_TOPK_INVERSE, ST_TOPK_FORWARD, ST_TOPK_BACKWARD, ST_COUNT
 };
 const char* const kStageNames[ST_COUNT] = {
     "slice_pose", "cull_count", "scan", "emit", "sort", "tile_ranges", "tile_order", "mask_sum",
-    "forward_tile", "loss_reduce", "zero_fill", "backward_tile", "project_backward", "pose_chain", "adam"};
+    "forward_tile", "loss_reduce", "zero_fill", "backward_tile", "project_backward", "pose_chain", "adam",
+    "topk_knn", "topk_inverse", "topk_forward", "topk_backward"};
 
 constexpr int kGaussBlock = 256;
 constexpr int kMaxSubjectSlices = 4096;
@@ -92,6 +94,25 @@ struct svr_ctx {
     DevBuf<int64_t> d_init_subpix, d_init_cdf, d_init_bsum, d_init_base, d_init_total;
     DevBuf<double> d_init_g;
     DevBuf<unsigned long long> d_init_gmax;
+    // normalised Top-K model (allocated on first use)
+    DevBuf<TopkGauss> d_topk_gauss;
+    DevBuf<TopkSlice> d_topk_slices;
+    DevBuf<SlicePose> d_topk_pose;
+    DevBuf<uint32_t> d_topk_bb;
+    DevBuf<TopkGrid> d_topk_grid;
+    DevBuf<int2> d_topk_cells, d_topk_granges;
+    DevBuf<float4> d_topk_smean;
+    DevBuf<uint32_t> d_topk_ck, d_topk_cv, d_topk_ck2, d_topk_cv2;
+    DevBuf<uint32_t> d_topk_pk, d_topk_pv, d_topk_pk2, d_topk_pv2;
+    DevBuf<char> d_topk_sort_tmp;
+    DevBuf<float2> d_topk_state;
+    DevBuf<float> d_topk_partial, d_topk_pose_acc, d_topk_msum;
+    DevBuf<int> d_topk_status;
+    const uint32_t* topk_gpix = nullptr;
+    const int32_t* topk_nbr = nullptr;
+    int32_t topk_K = 0;
+    bool topk_built = false, topk_forwarded = false;
+    int64_t topk_split_tiles = 0;
     DevBuf<unsigned long long> d_incut;
     DevBuf<uint32_t> d_tkeys, d_tvals, d_tkeys2, d_tvals2;
     DevBuf<char> d_tsort_tmp;
@@ -518,6 +539,12 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
         release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
         release(c->d_init_gmax);
+        release(c->d_topk_gauss); release(c->d_topk_slices); release(c->d_topk_pose); release(c->d_topk_bb);
+        release(c->d_topk_grid); release(c->d_topk_cells); release(c->d_topk_granges); release(c->d_topk_smean);
+        release(c->d_topk_ck); release(c->d_topk_cv); release(c->d_topk_ck2); release(c->d_topk_cv2);
+        release(c->d_topk_pk); release(c->d_topk_pv); release(c->d_topk_pk2); release(c->d_topk_pv2);
+        release(c->d_topk_sort_tmp); release(c->d_topk_state); release(c->d_topk_partial);
+        release(c->d_topk_pose_acc); release(c->d_topk_msum); release(c->d_topk_status);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -596,6 +623,8 @@ int svr_set_geometry(svr_ctx* c, const svr_geometry* g) {
     c->max_subject_slices = maxs;
     c->has_geom = true;
     c->binned = false;
+    c->topk_built = false;
+    c->topk_forwarded = false;
     if (!c->host_only && hipSetDevice(c->device) != hipSuccess)
         return fail(c, SVR_ERR_HIP, "hipSetDevice(%d) failed", c->device);
     return build_tables(c);
@@ -873,6 +902,194 @@ int svr_init_means(svr_ctx* c, const float* image, const float* mask, const floa
     HIPCHK(c, launch_init_sample(c->d_geo.p, c->d_init_pose.p, c->d_init_tab.p, c->d_subj.p, c->n_subjects,
                                  c->d_init_subpix.p, c->d_init_cdf.p, c->d_init_total.p, image, u, c->N, mean,
                                  pixel, value, st));
+    return SVR_OK;
+}
+
+namespace {
+int max_slice_pixels(const svr_ctx* c) {
+    int64_t mx = 1;
+    for (int i = 0; i < c->M; ++i) mx = std::max<int64_t>(mx, (int64_t)c->H[i] * c->W[i]);
+    return (int)std::min<int64_t>(mx, 1 << 30);
+}
+
+int key_bits_for(int64_t n) {
+    int kb = 1;
+    while (kb < 32 && (1LL << kb) < n) ++kb;
+    return kb;
+}
+
+int check_params(svr_ctx* c, const svr_params* p) {
+    if (!p || (c->N > 0 && (!p->mean || !p->log_scale || !p->quat || !p->amp)) || (c->M > 0 && !p->pose))
+        return fail(c, SVR_ERR_ARG, "a parameter pointer is NULL");
+    return SVR_OK;
+}
+}  // namespace
+
+int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float* mask, int K, int32_t* nbr) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!mean || !pose || !nbr) return fail(c, SVR_ERR_ARG, "mean, pose or nbr is NULL");
+    if (K < 1 || K > 1024) return fail(c, SVR_ERR_ARG, "K must be in [1, 1024]");
+    if (c->M > 65535) return fail(c, SVR_ERR_CAPACITY, "more than 65535 slices");
+    if ((int64_t)c->P * K > 0x7fffffffLL)
+        return fail(c, SVR_ERR_CAPACITY, "P * K = %lld exceeds 2^31-1", (long long)c->P * K);
+    const int32_t S = c->n_subjects, M = c->M;
+    std::vector<int> has_slices(S, 0);
+    for (int i = 0; i < M; ++i) has_slices[c->slice_subject[i]] = 1;
+    for (int s = 0; s < S; ++s)
+        if (has_slices[s] && c->gauss_off[s + 1] - c->gauss_off[s] < K)
+            return fail(c, SVR_ERR_ARG, "subject %d has fewer than K = %d Gaussians", s, K);
+    c->topk_built = false;
+    c->topk_forwarded = false;
+    hipStream_t st = c->stream;
+    StageScope sc(c, ST_TOPK_KNN);
+    HIPCHK(c, ensure(c->d_topk_pose, (size_t)M));
+    HIPCHK(c, ensure(c->d_topk_slices, (size_t)M));
+    HIPCHK(c, ensure(c->d_topk_bb, (size_t)6 * S));
+    HIPCHK(c, ensure(c->d_topk_grid, (size_t)S));
+    HIPCHK(c, ensure(c->d_topk_status, 2));
+    HIPCHK(c, launch_slice_pose(c->d_geo.p, pose, c->d_topk_pose.p, M, st));
+    HIPCHK(c, launch_topk_prepare(nullptr, nullptr, nullptr, nullptr, 0, c->d_topk_pose.p, c->d_geo.p, nullptr, M,
+                                  nullptr, c->d_topk_slices.p, st));
+    HIPCHK(c, launch_topk_bbox(mean, c->d_blocks.p, c->n_blocks, S, c->d_topk_bb.p, st));
+    std::vector<uint32_t> bb(6 * (size_t)S);
+    HIPCHK(c, hipMemcpyAsync(bb.data(), c->d_topk_bb.p, bb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    // one cell grid per subject: about 8 means per cell on average
+    std::vector<TopkGrid> grid(S);
+    int64_t cells = 0;
+    for (int s = 0; s < S; ++s) {
+        TopkGrid& g = grid[s];
+        memset(&g, 0, sizeof(g));
+        const int64_t ns = c->gauss_off[s + 1] - c->gauss_off[s];
+        double lo[3], ext[3], vol = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = ns > 0 ? topk_order_float(bb[6 * s + d]) : 0.0;
+            const double hi = ns > 0 ? topk_order_float(bb[6 * s + 3 + d]) : 0.0;
+            ext[d] = std::max(hi - lo[d], 1e-3);
+            vol *= ext[d];
+        }
+        double h = ns > 0 ? cbrt(vol / (double)ns * 8.0) : 1.0;
+        h = std::max(h, 1e-3);
+        int64_t dims[3];
+        for (;;) {
+            for (int d = 0; d < 3; ++d) dims[d] = (int64_t)floor(ext[d] / h) + 1;
+            if (dims[0] * dims[1] * dims[2] <= (1LL << 24)) break;
+            h *= 1.25;
+        }
+        for (int d = 0; d < 3; ++d) {
+            g.origin[d] = (float)lo[d];
+            g.dims[d] = (int32_t)dims[d];
+        }
+        g.h = (float)h;
+        g.inv_h = (float)(1.0 / h);
+        // radius holding about K means at the subject's mean density, with margin
+        const double dens = ns > 0 ? (double)ns / vol : 1.0;
+        g.rho0 = (float)(1.3 * cbrt(3.0 * K / (4.0 * M_PI * dens)));
+        g.base = cells;
+        cells += dims[0] * dims[1] * dims[2];
+    }
+    if (cells > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "neighbour grid too large");
+    HIPCHK(c, hipMemcpyAsync(c->d_topk_grid.p, grid.data(), grid.size() * sizeof(TopkGrid), hipMemcpyHostToDevice, st));
+    const int64_t N = c->N;
+    HIPCHK(c, ensure(c->d_topk_cells, (size_t)cells));
+    HIPCHK(c, ensure(c->d_topk_smean, (size_t)N));
+    HIPCHK(c, ensure(c->d_topk_ck, (size_t)N));
+    HIPCHK(c, ensure(c->d_topk_cv, (size_t)N));
+    HIPCHK(c, ensure(c->d_topk_ck2, (size_t)N));
+    HIPCHK(c, ensure(c->d_topk_cv2, (size_t)N));
+    const int64_t n_pairs = c->P * (int64_t)K;
+    HIPCHK(c, ensure(c->d_topk_sort_tmp, std::max(sort_tmp_bytes(N), sort_tmp_bytes(n_pairs))));
+    HIPCHK(c, launch_topk_cells(mean, c->d_blocks.p, c->n_blocks, c->d_topk_grid.p, N, cells, c->d_topk_ck.p,
+                                c->d_topk_cv.p, c->d_topk_ck2.p, c->d_topk_cv2.p, c->d_topk_sort_tmp.p,
+                                key_bits_for(cells), c->d_topk_cells.p, c->d_topk_smean.p, st));
+    int max_tiles = 1;
+    for (int i = 0; i < M; ++i) max_tiles = std::max(max_tiles, ((c->W[i] + 15) / 16) * ((c->H[i] + 15) / 16));
+    HIPCHK(c, launch_fill_zero(c->d_topk_status.p, 2 * sizeof(int), st));
+    HIPCHK(c, launch_topk_knn(c->d_geo.p, c->d_topk_slices.p, c->d_topk_grid.p, c->d_topk_cells.p,
+                              c->d_topk_smean.p, mask, M, max_tiles, K, nbr, c->d_topk_status.p, st));
+    int status[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(status, c->d_topk_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->topk_split_tiles = status[1];
+    if (status[0] > 0)
+        return fail(c, SVR_ERR_CAPACITY, "neighbour search failed for %d pixels (too dense or too far from the means)",
+                    status[0]);
+    {
+        StageScope sc2(c, ST_TOPK_INVERSE);
+        HIPCHK(c, ensure(c->d_topk_pk, (size_t)n_pairs));
+        HIPCHK(c, ensure(c->d_topk_pv, (size_t)n_pairs));
+        HIPCHK(c, ensure(c->d_topk_pk2, (size_t)n_pairs));
+        HIPCHK(c, ensure(c->d_topk_pv2, (size_t)n_pairs));
+        HIPCHK(c, ensure(c->d_topk_granges, (size_t)N));
+        HIPCHK(c, launch_topk_inverse(nbr, n_pairs, K, N, key_bits_for(N + 1), c->d_topk_pk.p, c->d_topk_pv.p,
+                                      c->d_topk_pk2.p, c->d_topk_pv2.p, c->d_topk_sort_tmp.p, c->d_topk_granges.p,
+                                      &c->topk_gpix, st));
+    }
+    c->topk_nbr = nbr;
+    c->topk_K = K;
+    c->topk_built = true;
+    return SVR_OK;
+}
+
+int svr_topk_forward(svr_ctx* c, const svr_params* params, const float* sigma, const int32_t* nbr, int K,
+                     float delta, const float* target, const float* mask, float* pred, float* loss,
+                     float* grad_pred) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!pred) return fail(c, SVR_ERR_ARG, "pred is NULL");
+    if ((rc = check_params(c, params)) != SVR_OK) return rc;
+    const bool want_loss = loss || grad_pred;
+    if (want_loss && (!target || !mask))
+        return fail(c, SVR_ERR_ARG, "loss outputs requested without target and mask");
+    if (!(delta > 0.f) || !isfinite(delta)) return fail(c, SVR_ERR_ARG, "delta must be finite and > 0");
+    if (!c->topk_built || nbr != c->topk_nbr || K != c->topk_K)
+        return fail(c, SVR_ERR_STATE, "nbr / K are not those of the last svr_topk_build");
+    hipStream_t st = c->stream;
+    const int32_t M = c->M;
+    const int mhw = max_slice_pixels(c);
+    HIPCHK(c, ensure(c->d_topk_gauss, (size_t)c->N));
+    HIPCHK(c, ensure(c->d_topk_state, (size_t)c->P));
+    HIPCHK(c, ensure(c->d_topk_partial, std::max(topk_pose_partial_floats(M, mhw), (size_t)1024)));
+    HIPCHK(c, ensure(c->d_topk_msum, 1));
+    HIPCHK(c, ensure(c->d_partial, 1024));
+    StageScope sc(c, ST_TOPK_FORWARD);
+    HIPCHK(c, launch_slice_pose(c->d_geo.p, params->pose, c->d_topk_pose.p, M, st));
+    HIPCHK(c, launch_topk_prepare(params->mean, params->log_scale, params->quat, params->amp, c->N,
+                                  c->d_topk_pose.p, c->d_geo.p, sigma, M, c->d_topk_gauss.p, c->d_topk_slices.p, st));
+    if (want_loss && c->loss_kind == SVR_LOSS_MSE)
+        HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_topk_msum.p, st));
+    HIPCHK(c, launch_topk_forward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, nbr, K, delta, c->loss_kind, M,
+                                  mhw, want_loss ? target : nullptr, mask,
+                                  c->loss_kind == SVR_LOSS_MSE ? c->d_topk_msum.p : nullptr, pred,
+                                  c->d_topk_state.p, grad_pred, c->d_topk_partial.p, loss, st));
+    c->topk_forwarded = true;
+    return SVR_OK;
+}
+
+int svr_topk_backward(svr_ctx* c, const svr_params* params, const int32_t* nbr, int K, const float* grad_pred,
+                      const svr_grads* out, float* g_sigma) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if ((rc = check_params(c, params)) != SVR_OK) return rc;
+    if (!grad_pred) return fail(c, SVR_ERR_ARG, "grad_pred is NULL");
+    if (!out || (c->N > 0 && (!out->mean || !out->log_scale || !out->quat || !out->amp)) ||
+        (c->M > 0 && !out->pose))
+        return fail(c, SVR_ERR_ARG, "a gradient output pointer is NULL");
+    if (!c->topk_built || nbr != c->topk_nbr || K != c->topk_K)
+        return fail(c, SVR_ERR_STATE, "nbr / K are not those of the last svr_topk_build");
+    if (!c->topk_forwarded) return fail(c, SVR_ERR_STATE, "svr_topk_forward has not been called");
+    hipStream_t st = c->stream;
+    const int32_t M = c->M;
+    const int mhw = max_slice_pixels(c);
+    HIPCHK(c, ensure(c->d_topk_pose_acc, (size_t)6 * std::max(M, 1)));
+    StageScope sc(c, ST_TOPK_BACKWARD);
+    HIPCHK(c, launch_topk_backward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, nbr, K, 0.f, M, mhw,
+                                   grad_pred, c->d_topk_state.p, c->d_topk_granges.p, c->topk_gpix,
+                                   params->log_scale, params->quat, c->N, out->mean, out->log_scale, out->quat,
+                                   out->amp, c->d_topk_partial.p, c->d_topk_pose_acc.p, g_sigma, st));
+    HIPCHK(c, launch_pose_chain(params->pose, c->d_topk_pose_acc.p, out->pose, M, st));
     return SVR_OK;
 }
 

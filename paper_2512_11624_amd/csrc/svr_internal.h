@@ -52,6 +52,32 @@ struct InitSlice {
     int32_t pad;
 };
 
+// Normalised Top-K model (Eqs. 2 and 5): activated Gaussian, 48 B:
+//   a = (mu, c), b = (S00, S01, S02, S11), c = (S12, S22, 0, 0) of Sigma_j.
+struct TopkGauss {
+    float4 a, b, c;
+};
+// Slice constants of the Top-K model: pose, P = R Sigma_PSF R^T (00 01 02 11
+// 12 22) and the intensity scalar.
+struct TopkSlice {
+    float R[9];
+    float t[3];
+    float P[6];
+    float sigma;
+    float pad[3];
+};
+// Uniform cell grid of one subject's means for the neighbour search; cell
+// (cx, cy, cz) has global id base + (cz * dims[1] + cy) * dims[0] + cx.
+struct TopkGrid {
+    float origin[3];
+    float inv_h;
+    float h;
+    float rho0;          // first search radius (mm)
+    int32_t dims[3];
+    int32_t pad;
+    int64_t base;
+};
+
 // One record = one (slice, Gaussian) pair that survives culling, 32 bytes.
 //   r0 = (p*_x, p*_y, beta', amp)   centre in slice pixel units, beta' = KZ beta
 //   r1 = (A'_00, A'_01, A'_11, slice id bits)  conic in pixel units times KZ
@@ -187,5 +213,38 @@ hipError_t launch_init_sample(const SliceGeo* geo, const SlicePose* pose, const 
                               const SubjectInfo* subj, int32_t s_n, const int64_t* sub_pix, const int64_t* cdf,
                               const int64_t* total, const float* image, const float* u, int64_t N, float* mean,
                               int64_t* pixel, float* value, hipStream_t st);
+
+// Normalised Top-K model (csrc/topk.hip).
+hipError_t launch_topk_prepare(const float* mean, const float* log_scale, const float* quat, const float* amp,
+                               int64_t n, const SlicePose* pose, const SliceGeo* geo, const float* sigma, int32_t m,
+                               TopkGauss* gauss, TopkSlice* slices, hipStream_t st);
+// bb [6 * n_subjects] order-preserving float keys (min xyz, max xyz)
+hipError_t launch_topk_bbox(const float* mean, const GaussBlock* blocks, int32_t nb, int32_t n_subjects,
+                            uint32_t* bb, hipStream_t st);
+float topk_order_float(uint32_t k);
+hipError_t launch_topk_cells(const float* mean, const GaussBlock* blocks, int32_t nb, const TopkGrid* grid,
+                             int64_t n, int64_t n_cells, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                             uint32_t* vals_alt, void* sort_tmp, int key_bits, int2* cells, float4* smean,
+                             hipStream_t st);
+// status [2] (zeroed by the caller): pixels without K neighbours, sub-tile
+// splits
+hipError_t launch_topk_knn(const SliceGeo* geo, const TopkSlice* slices, const TopkGrid* grid, const int2* cells,
+                           const float4* smean, const float* mask, int32_t m, int32_t max_tiles, int32_t K,
+                           int32_t* nbr, int* status, hipStream_t st);
+hipError_t launch_topk_inverse(const int32_t* nbr, int64_t n_pairs, int32_t K, int64_t n_gauss, int key_bits,
+                               uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                               void* sort_tmp, int2* granges, const uint32_t** gpix, hipStream_t st);
+int32_t topk_blocks_x(int32_t max_hw);
+hipError_t launch_topk_forward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
+                               const int32_t* nbr, int32_t K, float delta, int32_t loss_kind, int32_t m,
+                               int32_t max_hw, const float* target, const float* mask, const float* msum, float* pred,
+                               float2* state, float* grad, float* partial, float* loss, hipStream_t st);
+size_t topk_pose_partial_floats(int32_t m, int32_t max_hw);
+hipError_t launch_topk_backward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
+                                const int32_t* nbr, int32_t K, float delta, int32_t m, int32_t max_hw,
+                                const float* grad_pred, const float2* state, const int2* granges,
+                                const uint32_t* gpix, const float* log_scale, const float* quat, int64_t n_gauss,
+                                float* g_mean, float* g_ls, float* g_quat, float* g_amp, float* partial,
+                                float* pose_acc, float* g_sigma, hipStream_t st);
 
 }  // namespace svr

@@ -109,6 +109,9 @@ _SIGS = {
     "svr_scale_regularizer": ([vp, vp, C.c_int64, C.c_float, C.c_float, vp, vp], C.c_int),
     "svr_init_cdf": ([vp, vp, vp, C.c_float, vp, C.POINTER(C.c_int64)], C.c_int),
     "svr_init_means": ([vp, vp, vp, vp, C.c_float, vp, vp, vp, vp], C.c_int),
+    "svr_topk_build": ([vp, vp, vp, vp, C.c_int, vp], C.c_int),
+    "svr_topk_forward": ([vp, C.POINTER(svr_params), vp, vp, C.c_int, C.c_float, vp, vp, vp, vp, vp], C.c_int),
+    "svr_topk_backward": ([vp, C.POINTER(svr_params), vp, C.c_int, vp, C.POINTER(svr_grads), vp], C.c_int),
     "svr_autotune": ([vp, C.POINTER(svr_params), vp, C.c_int, C.c_char_p, C.POINTER(svr_config),
                       C.POINTER(C.c_float), C.c_int], C.c_int),
 }
@@ -264,6 +267,24 @@ class Context:
     def svr_init_means(self, image, mask, pose, lambda_init, u, mean, pixel=None, value=None):
         self._check(load().svr_init_means(self.h, _ptr(image), _ptr(mask), _ptr(pose), float(lambda_init),
                                           _ptr(u), _ptr(mean), _ptr(pixel), _ptr(value)), "svr_init_means")
+
+    def svr_topk_build(self, mean, pose, K, nbr, mask=None):
+        self._check(load().svr_topk_build(self.h, _ptr(mean), _ptr(pose), _ptr(mask), int(K), _ptr(nbr)),
+                    "svr_topk_build")
+
+    def svr_topk_forward(self, mean, log_scale, quat, amp, pose, nbr, K, delta, pred, target=None, mask=None,
+                         sigma=None, loss=None, grad_pred=None):
+        p = svr_params(*(_ptr(t) for t in (mean, log_scale, quat, amp, pose)))
+        self._check(load().svr_topk_forward(self.h, C.byref(p), _ptr(sigma), _ptr(nbr), int(K), float(delta),
+                                            _ptr(target), _ptr(mask), _ptr(pred), _ptr(loss), _ptr(grad_pred)),
+                    "svr_topk_forward")
+
+    def svr_topk_backward(self, mean, log_scale, quat, amp, pose, nbr, K, grad_pred, g_mean, g_log_scale, g_quat,
+                          g_amp, g_pose, g_sigma=None):
+        p = svr_params(*(_ptr(t) for t in (mean, log_scale, quat, amp, pose)))
+        g = svr_grads(*(_ptr(t) for t in (g_mean, g_log_scale, g_quat, g_amp, g_pose)))
+        self._check(load().svr_topk_backward(self.h, C.byref(p), _ptr(nbr), int(K), _ptr(grad_pred), C.byref(g),
+                                             _ptr(g_sigma)), "svr_topk_backward")
 
     def svr_set_count_pairs(self, enable: bool):
         self._check(load().svr_set_count_pairs(self.h, int(bool(enable))), "svr_set_count_pairs")
