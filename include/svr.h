@@ -304,6 +304,29 @@ int svr_topk_forward(svr_ctx* ctx, const svr_params* params, const float* sigma,
 int svr_topk_backward(svr_ctx* ctx, const svr_params* params, const int32_t* nbr, int K, const float* grad_pred,
                       const svr_grads* out, float* g_sigma);
 
+/* ------------------------------------------------------------------------ */
+/* Per-slice outlier terms (Sec. 2.4) on a prediction pred [P] (DEVICE) from
+ * svr_forward or svr_topk_forward called without target: the learnable
+ * intensity scalar sigma_i (the slice is predicted as sigma_i y) and the
+ * aleatoric weight omega_i = exp(rho_i) that down-weights a slice.  The
+ * paper gives no loss form for omega_i; it is read as a per-slice
+ * likelihood scale, with r = sigma_i y - I, S_i the slice's masked data sum
+ * and n_i its mask sum:
+ *   SVR_LOSS_MSE:  L = (sum_i e^{-2 rho_i} S_i + 2 n_i rho_i) / sum m,
+ *                  S_i = sum m r^2  (Gaussian, standard deviation omega_i);
+ *   SVR_LOSS_L1:   L = sum_i e^{-rho_i} S_i + n_i rho_i,
+ *                  S_i = sum m |r|  (Laplace, scale omega_i);
+ * both equal the plain data terms at sigma = 1, rho = 0.  Inputs: target,
+ * mask [P], sigma [M] and log_omega [M] = rho (DEVICE; sigma / log_omega
+ * NULL = 1 / 0).  Outputs (DEVICE, each may be NULL): loss [1], grad_pred
+ * [P] = dL/dy (pass it to svr_backward / svr_topk_backward), slice_sums [M]
+ * = S_i, g_sigma [M], g_log_omega [M].  Asynchronous.  Errors:
+ * SVR_ERR_STATE without geometry, SVR_ERR_ARG for NULL pred / target /
+ * mask. */
+int svr_slice_loss(svr_ctx* ctx, const float* pred, const float* target, const float* mask, const float* sigma,
+                   const float* log_omega, float* loss, float* grad_pred, float* slice_sums, float* g_sigma,
+                   float* g_log_omega);
+
 /* AdamW (App. A.1).  lr[6] = learning rates of the groups mean, log_scale,
  * quat, amp, pose rotation omega, pose translation tau.  Updates params,
  * exp_avg and exp_avg_sq in place; step counts from 1 (bias correction).
@@ -319,6 +342,13 @@ typedef struct {
 
 int svr_step(svr_ctx* ctx, const svr_grads* params_inout, const svr_grads* grads,
              float* exp_avg, float* exp_avg_sq, const svr_adam* hp, int64_t step);
+
+/* The same AdamW update on one plain vector p [n] with gradient g [n] and
+ * moments exp_avg / exp_avg_sq [n] (all DEVICE), learning rate lr (hp->lr is
+ * not used): for per-slice parameters such as sigma and log_omega.
+ * Errors: SVR_ERR_ARG for null pointers, n < 0, step < 1, bad betas. */
+int svr_adam_vector(svr_ctx* ctx, float* p, const float* g, float* exp_avg, float* exp_avg_sq, int64_t n, float lr,
+                    const svr_adam* hp, int64_t step);
 
 /* Counters of the last svr_project_bin / svr_forward.  Record and instance
  * counts are exact after svr_project_bin.  n_incut (pairs inside the cutoff,

@@ -1,0 +1,59 @@
+"""Per-slice outlier terms of Sec. 2.4 on top of a data term, FP64 NumPy.
+
+TEST INFRASTRUCTURE ONLY: the HIP path never imports it.
+
+The paper names a learnable intensity scalar sigma_i per slice (global
+intensity shifts) and an aleatoric weight omega_i per slice that down-weights
+corrupted slices in the loss, without giving the weighting's form.  Reading
+(a negative log-likelihood with a per-slice scale, as in the uncertainty
+weighting the paper cites NeSVoR for), with rho_i = log omega_i:
+
+* the prediction of slice i is sigma_i y_p; r_p = sigma_i y_p - I_p;
+* masked MSE kind (Gaussian likelihood with standard deviation omega_i):
+      L = ( sum_i e^{-2 rho_i} S_i + 2 n_i rho_i ) / sum_p m_p,
+      S_i = sum_{p in i} m_p r_p^2,  n_i = sum_{p in i} m_p;
+* masked L1 kind (Laplace likelihood with scale omega_i):
+      L = sum_i e^{-rho_i} S_i + n_i rho_i,  S_i = sum_{p in i} m_p |r_p|.
+At sigma = 1 and rho = 0 both reduce to the plain masked MSE and L1 terms.
+Gradients: with respect to y_p, sigma_i and rho_i (the L1 subgradient takes
+sign(0) = 0).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def slice_loss(pred, target, mask, pix_offset, kind, sigma=None, log_omega=None):
+    """(loss, dL/dy [P], per-slice data sums S [M], dL/dsigma [M],
+    dL/drho [M]) for kind 0 (masked MSE) or 1 (masked L1)."""
+    y = np.asarray(pred, np.float64)
+    t = np.asarray(target, np.float64)
+    m = np.asarray(mask, np.float64)
+    po = np.asarray(pix_offset, np.int64)
+    M = len(po) - 1
+    sig = np.ones(M) if sigma is None else np.asarray(sigma, np.float64)
+    rho = np.zeros(M) if log_omega is None else np.asarray(log_omega, np.float64)
+    sl = np.repeat(np.arange(M), np.diff(po))
+    yh = sig[sl] * y
+    r = yh - t
+    n = np.array([m[po[i]:po[i + 1]].sum() for i in range(M)])
+    if kind == 0:
+        phi = m * r * r
+        S = np.array([phi[po[i]:po[i + 1]].sum() for i in range(M)])
+        msum = m.sum()
+        w = np.exp(-2.0 * rho)
+        loss = float((w * S + 2.0 * n * rho).sum() / msum)
+        g_yh = w[sl] * 2.0 * m * r / msum
+        g_rho = (-2.0 * w * S + 2.0 * n) / msum
+    elif kind == 1:
+        phi = m * np.abs(r)
+        S = np.array([phi[po[i]:po[i + 1]].sum() for i in range(M)])
+        w = np.exp(-rho)
+        loss = float((w * S + n * rho).sum())
+        g_yh = w[sl] * m * np.sign(r)
+        g_rho = -w * S + n
+    else:
+        raise ValueError(kind)
+    g_y = g_yh * sig[sl]
+    g_sig = np.array([(g_yh * y)[po[i]:po[i + 1]].sum() for i in range(M)])
+    return loss, g_y, S, g_sig, g_rho

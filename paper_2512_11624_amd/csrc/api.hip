@@ -108,6 +108,7 @@ struct svr_ctx {
     DevBuf<float2> d_topk_state;
     DevBuf<float> d_topk_partial, d_topk_pose_acc, d_topk_msum;
     DevBuf<int> d_topk_status;
+    DevBuf<float> d_sl_scratch, d_sl_msum;   // per-slice outlier terms
     const uint32_t* topk_gpix = nullptr;
     const int32_t* topk_nbr = nullptr;
     int32_t topk_K = 0;
@@ -545,6 +546,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_topk_pk); release(c->d_topk_pv); release(c->d_topk_pk2); release(c->d_topk_pv2);
         release(c->d_topk_sort_tmp); release(c->d_topk_state); release(c->d_topk_partial);
         release(c->d_topk_pose_acc); release(c->d_topk_msum); release(c->d_topk_status);
+        release(c->d_sl_scratch); release(c->d_sl_msum);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -1090,6 +1092,48 @@ int svr_topk_backward(svr_ctx* c, const svr_params* params, const int32_t* nbr, 
                                    params->log_scale, params->quat, c->N, out->mean, out->log_scale, out->quat,
                                    out->amp, c->d_topk_partial.p, c->d_topk_pose_acc.p, g_sigma, st));
     HIPCHK(c, launch_pose_chain(params->pose, c->d_topk_pose_acc.p, out->pose, M, st));
+    return SVR_OK;
+}
+
+int svr_slice_loss(svr_ctx* c, const float* pred, const float* target, const float* mask, const float* sigma,
+                   const float* log_omega, float* loss, float* grad_pred, float* slice_sums, float* g_sigma,
+                   float* g_log_omega) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!pred || !target || !mask) return fail(c, SVR_ERR_ARG, "pred, target or mask is NULL");
+    hipStream_t st = c->stream;
+    const int mhw = max_slice_pixels(c);
+    HIPCHK(c, ensure(c->d_sl_scratch, slice_loss_partial_floats(std::max(c->M, 1), mhw)));
+    HIPCHK(c, ensure(c->d_sl_msum, 1));
+    HIPCHK(c, ensure(c->d_partial, 1024));
+    if (c->loss_kind == SVR_LOSS_MSE) HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_sl_msum.p, st));
+    else HIPCHK(c, launch_fill_zero(c->d_sl_msum.p, sizeof(float), st));
+    HIPCHK(c, launch_slice_loss(c->d_geo.p, c->M, mhw, pred, target, mask, sigma, log_omega, c->d_sl_msum.p,
+                                c->loss_kind, loss, grad_pred, slice_sums, g_sigma, g_log_omega, c->d_sl_scratch.p,
+                                st));
+    return SVR_OK;
+}
+
+int svr_adam_vector(svr_ctx* c, float* p, const float* g, float* exp_avg, float* exp_avg_sq, int64_t n, float lr,
+                    const svr_adam* hp, int64_t step) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (n < 0) return fail(c, SVR_ERR_ARG, "n < 0");
+    if (n == 0) return SVR_OK;
+    if (!p || !g || !exp_avg || !exp_avg_sq || !hp) return fail(c, SVR_ERR_ARG, "NULL argument");
+    if (step < 1) return fail(c, SVR_ERR_ARG, "step must be >= 1");
+    if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0 && hp->beta2 >= 0.0 && hp->beta2 < 1.0 && hp->eps >= 0.0))
+        return fail(c, SVR_ERR_ARG, "invalid Adam hyper-parameters");
+    AdamSeg s;
+    s.p = p;
+    s.g = g;
+    s.n = n;
+    s.state_off = 0;
+    s.lr_a = s.lr_b = lr;
+    s.pose_layout = 0;
+    HIPCHK(c, launch_adam(&s, 1, exp_avg, exp_avg_sq, hp->beta1, hp->beta2, hp->eps, hp->weight_decay, step,
+                          c->stream));
     return SVR_OK;
 }
 

@@ -106,7 +106,8 @@ class FitResult:
 
 
 def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
-        psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum"):
+        psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
+        outliers=False, outlier_lr=1e-2):
     """Runs n_iter fitting iterations of project_bin + forward + backward +
     AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
     covers the iterations only; the PSNR read-out every ``psnr_every``
@@ -115,7 +116,11 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     Eq. 7 (masked L1 sum plus reg_lambda sum ||s - s_target||^2).
     ``reg_reading``: "sum" weighs the sums as written in Eq. 7; "mean" reads
     reg_lambda as weighting the mean L1 per masked pixel against the mean
-    penalty per Gaussian, i.e. applies reg_lambda * sum(mask) / N to the sums."""
+    penalty per Gaussian, i.e. applies reg_lambda * sum(mask) / N to the sums.
+    ``outliers`` adds the per-slice intensity scalar sigma_i and aleatoric
+    weight omega_i = exp(rho_i) of Sec. 2.4 (svr_slice_loss), both learnt
+    with AdamW at ``outlier_lr``; they are returned in the result as
+    ``sigma`` and ``log_omega`` (host arrays)."""
     import torch
     if objective not in ("mse", "l1+reg"):
         raise ValueError(f"unknown objective {objective}")
@@ -134,16 +139,30 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     loss = torch.empty(1, device=dev)
     res = FitResult()
     elapsed = 0.0
+    if outliers:
+        sig = torch.ones(M, device=dev)
+        rho = torch.zeros(M, device=dev)
+        g_sig = torch.empty(M, device=dev)
+        g_rho = torch.empty(M, device=dev)
+        st_o = [torch.zeros(M, device=dev) for _ in range(4)]
     torch.cuda.synchronize()
     for it in range(1, n_iter + 1):
         t0 = time.perf_counter()
         scale = gamma ** ((it - 1) // step_lr)
         ctx.svr_project_bin(*params.views())
-        ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
+        if outliers:
+            ctx.svr_forward(pred)
+            ctx.svr_slice_loss(pred, target, mask, sig, rho, loss=loss, grad_pred=gpred, g_sigma=g_sig,
+                               g_log_omega=g_rho)
+        else:
+            ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
         ctx.svr_backward(gpred, *grad.views())
         if objective == "l1+reg":
             ctx.svr_scale_regularizer(params.views()[1], lam, s_target, grad.views()[1], loss)
         ctx.svr_step(params.views(), grad.views(), m, v, [x * scale for x in lr], it)
+        if outliers:
+            ctx.svr_adam_vector(sig, g_sig, st_o[0], st_o[1], outlier_lr * scale, it)
+            ctx.svr_adam_vector(rho, g_rho, st_o[2], st_o[3], outlier_lr * scale, it)
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
         if probe is not None and (it % psnr_every == 0 or it == n_iter):
@@ -158,6 +177,9 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
                 break
     res.seconds = elapsed
     res.final_psnr = res.psnr[-1] if res.psnr else float("nan")
+    if outliers:
+        res.sigma = sig.cpu().numpy()
+        res.log_omega = rho.cpu().numpy()
     return res
 
 
@@ -218,7 +240,7 @@ def amplitude_lr(lr, kappa):
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
                      known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-                     init="jitter", psf=True):
+                     init="jitter", psf=True, corrupt=0.0, outliers=False):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -232,7 +254,10 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     "adaptive" (Eq. 6 with lambda_init = 0, as in the paper) or "uniform"
     (lambda_init = 1), both from the observed slices via adaptive_init.
     ``psf=False`` fits with a zero PSF (the slices are still acquired with
-    it), the paper's PSF ablation.  Returns the FitResult, with the
+    it), the paper's PSF ablation.  ``corrupt`` is the fraction of slices
+    corrupted after acquisition (half of them with their intensity scaled
+    by 1.5, half replaced by noise of the same mean); ``outliers`` fits the
+    per-slice sigma_i and omega_i of Sec. 2.4 as well.  Returns the FitResult, with the
     PSNR of the generating mixture itself (the representation's ceiling
     against the phantom) in ``gt_psnr``."""
     import torch
@@ -240,6 +265,17 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     prob = synth.config2(seed)
     axes = prob.extra["axes"]
     target = synth.head_observation(prob, seed + 1)
+    bad = np.zeros(0, np.int64)
+    if corrupt > 0:
+        rng_c = np.random.default_rng(seed + 3)
+        bad = np.sort(rng_c.choice(prob.n_slices, max(1, int(round(corrupt * prob.n_slices))), replace=False))
+        po = prob.pix_offset
+        for k, i in enumerate(bad):
+            sl = slice(po[i], po[i + 1])
+            if k % 2 == 0:
+                target[sl] *= 1.5
+            else:
+                target[sl] = rng_c.uniform(0.0, 2.0 * float(target[sl].mean()), po[i + 1] - po[i]).astype(np.float32)
     h = 0.5
     shape = tuple(int(2 * a / h) for a in axes[::-1])   # (nz, ny, nx)
     c = voxel_centres(shape, h)
@@ -286,12 +322,13 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
               lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
-              s_target=s_target, reg_reading=reg_reading,
+              s_target=s_target, reg_reading=reg_reading, outliers=outliers,
               callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
     res.initial_psnr = p0
     res.gt_psnr = gt_psnr
+    res.corrupted = bad.tolist()
     res.pose_err = dict(rot_deg_identity=float(np.degrees(np.abs(true_pose[:, :3]).mean())),
                         rot_deg_fitted=float(np.degrees(np.abs(est[:, :3] - true_pose[:, :3]).mean())),
                         trans_mm_identity=float(np.abs(true_pose[:, 3:]).mean()),
@@ -315,14 +352,26 @@ def main(argv=None):
     ap.add_argument("--reg-reading", choices=("sum", "mean"), default="sum")
     ap.add_argument("--init", choices=("jitter", "adaptive", "uniform"), default="jitter")
     ap.add_argument("--no-psf", action="store_true", help="fit with a zero PSF")
+    ap.add_argument("--corrupt", type=float, default=0.0, help="fraction of corrupted slices")
+    ap.add_argument("--outliers", action="store_true", help="fit the per-slice sigma_i and omega_i")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
                            scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
                            reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading,
-                           init=a.init, psf=not a.no_psf)
-    print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0,
+                           init=a.init, psf=not a.no_psf, corrupt=a.corrupt, outliers=a.outliers)
+    extra = {}
+    if a.outliers:
+        bad = np.asarray(res.corrupted, np.int64)
+        clean = np.setdiff1d(np.arange(len(res.sigma)), bad)
+        om = np.exp(res.log_omega)
+        extra = dict(omega_clean=float(om[clean].mean()), omega_scaled=float(om[bad[0::2]].mean()) if len(bad) else None,
+                     omega_noise=float(om[bad[1::2]].mean()) if len(bad) > 1 else None,
+                     sigma_clean=float(res.sigma[clean].mean()),
+                     sigma_scaled=float(res.sigma[bad[0::2]].mean()) if len(bad) else None)
+    print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0, **extra,
                           known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
-                          reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, corrupt=a.corrupt,
+                          outliers=a.outliers, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),

@@ -109,6 +109,8 @@ _SIGS = {
     "svr_scale_regularizer": ([vp, vp, C.c_int64, C.c_float, C.c_float, vp, vp], C.c_int),
     "svr_init_cdf": ([vp, vp, vp, C.c_float, vp, C.POINTER(C.c_int64)], C.c_int),
     "svr_init_means": ([vp, vp, vp, vp, C.c_float, vp, vp, vp, vp], C.c_int),
+    "svr_slice_loss": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
+    "svr_adam_vector": ([vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.POINTER(svr_adam), C.c_int64], C.c_int),
     "svr_topk_build": ([vp, vp, vp, vp, C.c_int, vp], C.c_int),
     "svr_topk_forward": ([vp, C.POINTER(svr_params), vp, vp, C.c_int, C.c_float, vp, vp, vp, vp, vp], C.c_int),
     "svr_topk_backward": ([vp, C.POINTER(svr_params), vp, C.c_int, vp, C.POINTER(svr_grads), vp], C.c_int),
@@ -267,6 +269,17 @@ class Context:
     def svr_init_means(self, image, mask, pose, lambda_init, u, mean, pixel=None, value=None):
         self._check(load().svr_init_means(self.h, _ptr(image), _ptr(mask), _ptr(pose), float(lambda_init),
                                           _ptr(u), _ptr(mean), _ptr(pixel), _ptr(value)), "svr_init_means")
+
+    def svr_slice_loss(self, pred, target, mask, sigma=None, log_omega=None, loss=None, grad_pred=None,
+                       slice_sums=None, g_sigma=None, g_log_omega=None):
+        self._check(load().svr_slice_loss(self.h, _ptr(pred), _ptr(target), _ptr(mask), _ptr(sigma), _ptr(log_omega),
+                                          _ptr(loss), _ptr(grad_pred), _ptr(slice_sums), _ptr(g_sigma),
+                                          _ptr(g_log_omega)), "svr_slice_loss")
+
+    def svr_adam_vector(self, p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        hp = svr_adam((C.c_float * 6)(*[lr] * 6), beta1, beta2, eps, weight_decay)
+        self._check(load().svr_adam_vector(self.h, _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr),
+                                           C.byref(hp), int(step)), "svr_adam_vector")
 
     def svr_topk_build(self, mean, pose, K, nbr, mask=None):
         self._check(load().svr_topk_build(self.h, _ptr(mean), _ptr(pose), _ptr(mask), int(K), _ptr(nbr)),

@@ -102,6 +102,9 @@ def test_host_only_context_config_and_state_errors():
     assert b"key_bits" in lib.svr_last_error(ctx.h)
     assert lib.svr_init_cdf(ctx.h, dummy, None, 0.5, dummy, None) == svr.SVR_ERR_NODEVICE
     assert lib.svr_init_means(ctx.h, dummy, None, dummy, 0.5, dummy, dummy, None, None) == svr.SVR_ERR_NODEVICE
+    assert lib.svr_slice_loss(ctx.h, dummy, dummy, dummy, None, None, None, None, None, None, None) == \
+        svr.SVR_ERR_NODEVICE
+    assert lib.svr_topk_build(ctx.h, dummy, dummy, None, 8, dummy) == svr.SVR_ERR_NODEVICE
 
 
 def test_capacity_error_on_too_many_subject_slices():
