@@ -316,7 +316,12 @@ int svr_topk_backward(svr_ctx* ctx, const svr_params* params, const int32_t* nbr
  *                  S_i = sum m r^2  (Gaussian, standard deviation omega_i);
  *   SVR_LOSS_L1:   L = sum_i e^{-rho_i} S_i + n_i rho_i,
  *                  S_i = sum m |r|  (Laplace, scale omega_i);
- * both equal the plain data terms at sigma = 1, rho = 0.  Inputs: target,
+ * both equal the plain data terms at sigma = 1, rho = 0.  A common factor on
+ * a subject's sigma_i trades against its amplitudes, and a common shift of
+ * its rho_i rescales its data term against any regulariser; the terms above
+ * therefore use the per-subject centred sigma_i / geomean(sigma) and
+ * rho_i - mean(rho), and the gradients with respect to log sigma and rho sum
+ * to zero over each subject.  Inputs: target,
  * mask [P], sigma [M] and log_omega [M] = rho (DEVICE; sigma / log_omega
  * NULL = 1 / 0).  Outputs (DEVICE, each may be NULL): loss [1], grad_pred
  * [P] = dL/dy (pass it to svr_backward / svr_topk_backward), slice_sums [M]

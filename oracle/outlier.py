@@ -15,6 +15,14 @@ weighting the paper cites NeSVoR for), with rho_i = log omega_i:
 * masked L1 kind (Laplace likelihood with scale omega_i):
       L = sum_i e^{-rho_i} S_i + n_i rho_i,  S_i = sum_{p in i} m_p |r_p|.
 At sigma = 1 and rho = 0 both reduce to the plain masked MSE and L1 terms.
+
+Gauge: a common factor on every sigma_i of a subject trades against its
+amplitudes, and a common shift of its rho_i rescales the whole data term
+against the regulariser, so neither is identifiable.  Reading: the loss
+uses the per-subject centred values sigma'_i = sigma_i / geomean_s(sigma)
+and rho'_i = rho_i - mean_s(rho) (means over the subject's slices); the
+terms then only redistribute intensity and weight between slices, and the
+gradients with respect to log sigma and rho sum to zero per subject.
 Gradients: with respect to y_p, sigma_i and rho_i (the L1 subgradient takes
 sign(0) = 0).
 """
@@ -23,16 +31,26 @@ from __future__ import annotations
 import numpy as np
 
 
-def slice_loss(pred, target, mask, pix_offset, kind, sigma=None, log_omega=None):
+def slice_loss(pred, target, mask, pix_offset, kind, sigma=None, log_omega=None, slice_subject=None):
     """(loss, dL/dy [P], per-slice data sums S [M], dL/dsigma [M],
-    dL/drho [M]) for kind 0 (masked MSE) or 1 (masked L1)."""
+    dL/drho [M]) for kind 0 (masked MSE) or 1 (masked L1); slice_subject
+    [M] groups the slices for the centring (default: one subject)."""
     y = np.asarray(pred, np.float64)
     t = np.asarray(target, np.float64)
     m = np.asarray(mask, np.float64)
     po = np.asarray(pix_offset, np.int64)
     M = len(po) - 1
-    sig = np.ones(M) if sigma is None else np.asarray(sigma, np.float64)
-    rho = np.zeros(M) if log_omega is None else np.asarray(log_omega, np.float64)
+    sig_raw = np.ones(M) if sigma is None else np.asarray(sigma, np.float64)
+    rho_raw = np.zeros(M) if log_omega is None else np.asarray(log_omega, np.float64)
+    subj = np.zeros(M, np.int64) if slice_subject is None else np.asarray(slice_subject, np.int64)
+    ls_mean = np.zeros(M)
+    rho_mean = np.zeros(M)
+    for s in np.unique(subj):
+        k = subj == s
+        ls_mean[k] = np.log(sig_raw[k]).mean()
+        rho_mean[k] = rho_raw[k].mean()
+    sig = sig_raw * np.exp(-ls_mean)
+    rho = rho_raw - rho_mean
     sl = np.repeat(np.arange(M), np.diff(po))
     yh = sig[sl] * y
     r = yh - t
@@ -55,5 +73,12 @@ def slice_loss(pred, target, mask, pix_offset, kind, sigma=None, log_omega=None)
     else:
         raise ValueError(kind)
     g_y = g_yh * sig[sl]
-    g_sig = np.array([(g_yh * y)[po[i]:po[i + 1]].sum() for i in range(M)])
-    return loss, g_y, S, g_sig, g_rho
+    g_sigc = np.array([(g_yh * y)[po[i]:po[i + 1]].sum() for i in range(M)])   # dL/dsigma'_i
+    a = sig * g_sigc                                                            # dL/dlog sigma'_i
+    g_sig = np.zeros(M)
+    g_rho_raw = np.zeros(M)
+    for s in np.unique(subj):
+        k = subj == s
+        g_sig[k] = (a[k] - a[k].mean()) / sig_raw[k]
+        g_rho_raw[k] = g_rho[k] - g_rho[k].mean()
+    return loss, g_y, S, g_sig, g_rho_raw

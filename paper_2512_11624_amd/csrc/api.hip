@@ -1104,14 +1104,14 @@ int svr_slice_loss(svr_ctx* c, const float* pred, const float* target, const flo
     if (!pred || !target || !mask) return fail(c, SVR_ERR_ARG, "pred, target or mask is NULL");
     hipStream_t st = c->stream;
     const int mhw = max_slice_pixels(c);
-    HIPCHK(c, ensure(c->d_sl_scratch, slice_loss_partial_floats(std::max(c->M, 1), mhw)));
+    HIPCHK(c, ensure(c->d_sl_scratch, slice_loss_partial_floats(std::max(c->M, 1), mhw, c->n_subjects)));
     HIPCHK(c, ensure(c->d_sl_msum, 1));
     HIPCHK(c, ensure(c->d_partial, 1024));
     if (c->loss_kind == SVR_LOSS_MSE) HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_sl_msum.p, st));
     else HIPCHK(c, launch_fill_zero(c->d_sl_msum.p, sizeof(float), st));
-    HIPCHK(c, launch_slice_loss(c->d_geo.p, c->M, mhw, pred, target, mask, sigma, log_omega, c->d_sl_msum.p,
-                                c->loss_kind, loss, grad_pred, slice_sums, g_sigma, g_log_omega, c->d_sl_scratch.p,
-                                st));
+    HIPCHK(c, launch_slice_loss(c->d_geo.p, c->d_subj.p, c->n_subjects, c->M, mhw, pred, target, mask, sigma,
+                                log_omega, c->d_sl_msum.p, c->loss_kind, loss, grad_pred, slice_sums, g_sigma,
+                                g_log_omega, c->d_sl_scratch.p, st));
     return SVR_OK;
 }
 

@@ -216,11 +216,11 @@ hipError_t launch_init_sample(const SliceGeo* geo, const SlicePose* pose, const 
 
 // Per-slice outlier terms (csrc/outlier.hip); scratch holds
 // slice_loss_partial_floats(m, max_hw) floats; msum is the mask sum (MSE).
-size_t slice_loss_partial_floats(int32_t m, int32_t max_hw);
-hipError_t launch_slice_loss(const SliceGeo* geo, int32_t m, int32_t max_hw, const float* pred,
-                             const float* target, const float* mask, const float* sigma, const float* log_omega,
-                             const float* msum, int32_t kind, float* loss, float* grad, float* slice_sums,
-                             float* g_sigma, float* g_rho, float* scratch, hipStream_t st);
+size_t slice_loss_partial_floats(int32_t m, int32_t max_hw, int32_t s_n);
+hipError_t launch_slice_loss(const SliceGeo* geo, const SubjectInfo* subj, int32_t s_n, int32_t m, int32_t max_hw,
+                             const float* pred, const float* target, const float* mask, const float* sigma,
+                             const float* log_omega, const float* msum, int32_t kind, float* loss, float* grad,
+                             float* slice_sums, float* g_sigma, float* g_rho, float* scratch, hipStream_t st);
 
 // Normalised Top-K model (csrc/topk.hip).
 hipError_t launch_topk_prepare(const float* mean, const float* log_scale, const float* quat, const float* amp,

@@ -240,7 +240,7 @@ def amplitude_lr(lr, kappa):
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
                      known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-                     init="jitter", psf=True, corrupt=0.0, outliers=False):
+                     init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-2):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -322,7 +322,7 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
               lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
-              s_target=s_target, reg_reading=reg_reading, outliers=outliers,
+              s_target=s_target, reg_reading=reg_reading, outliers=outliers, outlier_lr=outlier_lr,
               callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
@@ -354,16 +354,20 @@ def main(argv=None):
     ap.add_argument("--no-psf", action="store_true", help="fit with a zero PSF")
     ap.add_argument("--corrupt", type=float, default=0.0, help="fraction of corrupted slices")
     ap.add_argument("--outliers", action="store_true", help="fit the per-slice sigma_i and omega_i")
+    ap.add_argument("--outlier-lr", type=float, default=1e-2, help="AdamW rate of sigma_i and log omega_i")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
                            scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
                            reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading,
-                           init=a.init, psf=not a.no_psf, corrupt=a.corrupt, outliers=a.outliers)
+                           init=a.init, psf=not a.no_psf, corrupt=a.corrupt, outliers=a.outliers,
+                           outlier_lr=a.outlier_lr)
     extra = {}
     if a.outliers:
         bad = np.asarray(res.corrupted, np.int64)
         clean = np.setdiff1d(np.arange(len(res.sigma)), bad)
-        om = np.exp(res.log_omega)
+        # the loss uses the centred values (one subject here)
+        om = np.exp(res.log_omega - res.log_omega.mean())
+        res.sigma = res.sigma / np.exp(np.log(res.sigma).mean())
         extra = dict(omega_clean=float(om[clean].mean()), omega_scaled=float(om[bad[0::2]].mean()) if len(bad) else None,
                      omega_noise=float(om[bad[1::2]].mean()) if len(bad) > 1 else None,
                      sigma_clean=float(res.sigma[clean].mean()),
@@ -371,7 +375,7 @@ def main(argv=None):
     print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0, **extra,
                           known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
                           reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, corrupt=a.corrupt,
-                          outliers=a.outliers, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          outliers=a.outliers, outlier_lr=a.outlier_lr, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),

@@ -49,12 +49,17 @@ def test_slice_loss_matches_oracle(ctx, name, kind):
                g_log_omega=torch.empty(M, device="cuda"))
     ctx.svr_slice_loss(to_dev(pred), to_dev(target), to_dev(mask), to_dev(sigma), to_dev(rho), **out)
     torch.cuda.synchronize()
-    loss, g, S, gs, gr = outlier.slice_loss(pred, target, mask, prob.pix_offset, kind, sigma, rho)
+    loss, g, S, gs, gr = outlier.slice_loss(pred, target, mask, prob.pix_offset, kind, sigma, rho,
+                                            prob.slice_subject)
     check_close([out["loss"].item()], [loss], "loss")
     gp = out["grad_pred"].cpu().numpy()
     if kind == svr.SVR_LOSS_L1:
         # the sign of r may differ where |r| is at FP32 rounding level
-        r = sigma[np.repeat(np.arange(M), np.diff(prob.pix_offset))].astype(np.float64) * pred - target
+        sc = sigma.astype(np.float64)
+        for s_ in np.unique(prob.slice_subject):
+            k_ = prob.slice_subject == s_
+            sc[k_] /= np.exp(np.log(sc[k_]).mean())
+        r = sc[np.repeat(np.arange(M), np.diff(prob.pix_offset))] * pred - target
         keep = np.abs(r) > 1e-5
         check_close(gp[keep], g[keep], "grad_pred")
     else:

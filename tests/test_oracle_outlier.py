@@ -30,34 +30,51 @@ def test_gradients_match_autograd(kind):
     y, t, m, po = _data(1)
     rng = np.random.default_rng(2)
     M = len(po) - 1
+    subj = np.array([0, 0, 1, 1])
     sig, rho = rng.uniform(0.7, 1.3, M), rng.normal(0, 0.3, M)
-    loss, g, S, gs, gr = outlier.slice_loss(y, t, m, po, kind, sig, rho)
+    loss, g, S, gs, gr = outlier.slice_loss(y, t, m, po, kind, sig, rho, subj)
     yt = torch.tensor(y, requires_grad=True)
     st = torch.tensor(sig, requires_grad=True)
     rt = torch.tensor(rho, requires_grad=True)
+    sub = torch.as_tensor(subj)
+    cnt = torch.zeros(2, dtype=torch.float64).index_add(0, sub, torch.ones(M, dtype=torch.float64))
+    lsm = torch.zeros(2, dtype=torch.float64).index_add(0, sub, torch.log(st)) / cnt
+    rm = torch.zeros(2, dtype=torch.float64).index_add(0, sub, rt) / cnt
+    sc = st * torch.exp(-lsm[sub])
+    rc = rt - rm[sub]
     sl = torch.as_tensor(np.repeat(np.arange(M), np.diff(po)))
-    r = st[sl] * yt - torch.tensor(t)
+    r = sc[sl] * yt - torch.tensor(t)
     mt = torch.tensor(m)
     n = torch.zeros(M, dtype=torch.float64).index_add(0, sl, mt)
     if kind == 0:
         Sx = torch.zeros(M, dtype=torch.float64).index_add(0, sl, mt * r * r)
-        L = (torch.exp(-2 * rt) * Sx + 2 * n * rt).sum() / mt.sum()
+        L = (torch.exp(-2 * rc) * Sx + 2 * n * rc).sum() / mt.sum()
     else:
         Sx = torch.zeros(M, dtype=torch.float64).index_add(0, sl, mt * r.abs())
-        L = (torch.exp(-rt) * Sx + n * rt).sum()
+        L = (torch.exp(-rc) * Sx + n * rc).sum()
     L.backward()
     assert abs(loss - L.item()) < 1e-12
     assert np.abs(g - yt.grad.numpy()).max() < 1e-13
     assert np.abs(gs - st.grad.numpy()).max() < 1e-12
     assert np.abs(gr - rt.grad.numpy()).max() < 1e-12
+    # gauge: a common factor on a subject's sigma or shift of its rho changes nothing
+    l2 = outlier.slice_loss(y, t, m, po, kind, sig * np.array([2.0, 2.0, 0.5, 0.5]), rho + np.array([1, 1, -3, -3]),
+                            subj)[0]
+    assert abs(l2 - loss) < 1e-12 * max(1.0, abs(loss))
 
 
 @pytest.mark.parametrize("kind", [0, 1])
 def test_weight_optimum_is_the_slice_scale(kind):
-    # dL/drho_i = 0 at omega_i^2 = S_i / n_i (Gaussian) or omega_i = S_i / n_i (Laplace)
-    y, t, m, po = _data(3, sizes=(40, 50, 60))
-    _, _, S, _, _ = outlier.slice_loss(y, t, m, po, kind)
-    n = np.array([m[po[i]:po[i + 1]].sum() for i in range(3)])
-    rho = 0.5 * np.log(S / n) if kind == 0 else np.log(S / n)
-    _, _, _, _, gr = outlier.slice_loss(y, t, m, po, kind, None, rho)
-    assert np.abs(gr).max() < 1e-12
+    # slices of equal mask sums n: the (centred) weights are stationary at
+    # omega_i^2 proportional to S_i / n (Gaussian) or omega_i to S_i / n
+    # (Laplace), the per-slice likelihood scales, whatever the common factor
+    y, t, m, po = _data(3, sizes=(50, 50, 50))
+    m[:] = 1.0
+    S = outlier.slice_loss(y, t, m, po, kind)[2]
+    assert np.ptp(S) > 0.1 * S.mean()          # the slices differ
+    rho = 0.5 * np.log(S / 50.0) if kind == 0 else np.log(S / 50.0)
+    for shift in (0.0, 0.7, -2.0):
+        gr = outlier.slice_loss(y, t, m, po, kind, None, rho + shift)[4]
+        assert np.abs(gr).max() < 1e-12
+    gr = outlier.slice_loss(y, t, m, po, kind, None, np.zeros(3))[4]
+    assert np.abs(gr).max() > 1e-2
