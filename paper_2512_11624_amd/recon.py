@@ -107,7 +107,7 @@ class FitResult:
 
 def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
         psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-        outliers=False, outlier_lr=1e-2):
+        outliers=False, outlier_lr=1e-3):
     """Runs n_iter fitting iterations of project_bin + forward + backward +
     AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
     covers the iterations only; the PSNR read-out every ``psnr_every``
@@ -240,7 +240,7 @@ def amplitude_lr(lr, kappa):
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
                      known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-                     init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-2):
+                     init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-3):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -354,7 +354,7 @@ def main(argv=None):
     ap.add_argument("--no-psf", action="store_true", help="fit with a zero PSF")
     ap.add_argument("--corrupt", type=float, default=0.0, help="fraction of corrupted slices")
     ap.add_argument("--outliers", action="store_true", help="fit the per-slice sigma_i and omega_i")
-    ap.add_argument("--outlier-lr", type=float, default=1e-2, help="AdamW rate of sigma_i and log omega_i")
+    ap.add_argument("--outlier-lr", type=float, default=1e-3, help="AdamW rate of sigma_i and log omega_i")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
                            scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
