@@ -404,8 +404,9 @@ def run_topk(args, ctx, prob, desc, init, target, mask, target_np):
     """One step = svr_topk_forward (masked MSE) + svr_topk_backward + AdamW,
     with the neighbour lists rebuilt every --topk-refresh steps (the paper
     refreshes its index every 50 epochs); the search is timed separately and
-    its cost is spread over the refresh interval.  value = P * K pixel-
-    neighbour pairs per step / amortised seconds per step."""
+    its cost is spread over the refresh interval.  value = pixel-neighbour
+    pairs per step (K per pixel inside the mask, the pixels that have lists)
+    / amortised seconds per step."""
     import torch
     from paper_2512_11624_amd import svr
     N, M, P = prob.n_gauss, prob.n_slices, prob.n_pixels
@@ -450,7 +451,8 @@ def run_topk(args, ctx, prob, desc, init, target, mask, target_np):
     timing = ctx.svr_get_timing()
     ctx.svr_set_timing(False)
     ms_per_step = ms_iter + ms_build / args.topk_refresh
-    pairs = P * K
+    # lists exist for the pixels inside the mask only; the others predict 0
+    pairs = int((prob.mask > 0).sum()) * K
     value = pairs / (ms_per_step / 1e3)
     log(f"topk: build {ms_build:.3f} ms, iteration {ms_iter:.3f} ms, amortised {ms_per_step:.3f} ms/step, "
         f"{value:.4g} pair-evals/s")
@@ -478,6 +480,7 @@ def run_topk(args, ctx, prob, desc, init, target, mask, target_np):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "model": "normalised Top-K (Eqs. 2 and 5)", "K": K, "delta": delta,
                    "refresh_every": args.topk_refresh, "gaussians": N, "slices": M, "pixels": P,
+                   "pixels_with_lists": int((prob.mask > 0).sum()), "pairs_per_step": pairs,
                    "step": "topk_forward(masked MSE)+topk_backward+AdamW, neighbour search amortised"},
         "ms_build": ms_build, "ms_iteration": ms_iter,
         "stages_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},

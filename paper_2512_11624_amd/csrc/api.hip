@@ -108,6 +108,15 @@ struct svr_ctx {
     DevBuf<float2> d_topk_state;
     DevBuf<float> d_topk_partial, d_topk_pose_acc, d_topk_msum;
     DevBuf<int> d_topk_status;
+    DevBuf<int> d_topk_flag, d_topk_aoff;
+    DevBuf<uint8_t> d_topk_active;
+    DevBuf<int32_t> d_topk_act, d_topk_act_off;
+    DevBuf<char> d_topk_scan_tmp;
+    DevBuf<long long> d_topk_tot;
+    int64_t topk_n_act = 0;
+    int32_t topk_max_act = 1;
+    DevBuf<int32_t> d_topk_iperm, d_topk_lint;
+    const uint32_t* topk_perm = nullptr;
     DevBuf<float> d_sl_scratch, d_sl_msum;   // per-slice outlier terms
     const uint32_t* topk_gpix = nullptr;
     const int32_t* topk_nbr = nullptr;
@@ -547,6 +556,9 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_topk_sort_tmp); release(c->d_topk_state); release(c->d_topk_partial);
         release(c->d_topk_pose_acc); release(c->d_topk_msum); release(c->d_topk_status);
         release(c->d_sl_scratch); release(c->d_sl_msum);
+        release(c->d_topk_flag); release(c->d_topk_aoff); release(c->d_topk_active); release(c->d_topk_act);
+        release(c->d_topk_act_off); release(c->d_topk_scan_tmp); release(c->d_topk_tot);
+        release(c->d_topk_iperm); release(c->d_topk_lint);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -952,8 +964,8 @@ int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float
     HIPCHK(c, ensure(c->d_topk_grid, (size_t)S));
     HIPCHK(c, ensure(c->d_topk_status, 2));
     HIPCHK(c, launch_slice_pose(c->d_geo.p, pose, c->d_topk_pose.p, M, st));
-    HIPCHK(c, launch_topk_prepare(nullptr, nullptr, nullptr, nullptr, 0, c->d_topk_pose.p, c->d_geo.p, nullptr, M,
-                                  nullptr, c->d_topk_slices.p, st));
+    HIPCHK(c, launch_topk_prepare(nullptr, nullptr, nullptr, nullptr, 0, nullptr, c->d_topk_pose.p, c->d_geo.p,
+                                  nullptr, M, nullptr, c->d_topk_slices.p, st));
     HIPCHK(c, launch_topk_bbox(mean, c->d_blocks.p, c->n_blocks, S, c->d_topk_bb.p, st));
     std::vector<uint32_t> bb(6 * (size_t)S);
     HIPCHK(c, hipMemcpyAsync(bb.data(), c->d_topk_bb.p, bb.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -1002,10 +1014,10 @@ int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float
     HIPCHK(c, ensure(c->d_topk_ck2, (size_t)N));
     HIPCHK(c, ensure(c->d_topk_cv2, (size_t)N));
     const int64_t n_pairs = c->P * (int64_t)K;
-    HIPCHK(c, ensure(c->d_topk_sort_tmp, std::max(sort_tmp_bytes(N), sort_tmp_bytes(n_pairs))));
+    HIPCHK(c, ensure(c->d_topk_sort_tmp, std::max(sort_tmp_bytes(N), sort_tmp_bytes(n_pairs))));   // n_act*K <= n_pairs
     HIPCHK(c, launch_topk_cells(mean, c->d_blocks.p, c->n_blocks, c->d_topk_grid.p, N, cells, c->d_topk_ck.p,
                                 c->d_topk_cv.p, c->d_topk_ck2.p, c->d_topk_cv2.p, c->d_topk_sort_tmp.p,
-                                key_bits_for(cells), c->d_topk_cells.p, c->d_topk_smean.p, st));
+                                key_bits_for(cells), c->d_topk_cells.p, c->d_topk_smean.p, &c->topk_perm, st));
     int max_tiles = 1;
     for (int i = 0; i < M; ++i) max_tiles = std::max(max_tiles, ((c->W[i] + 15) / 16) * ((c->H[i] + 15) / 16));
     HIPCHK(c, launch_fill_zero(c->d_topk_status.p, 2 * sizeof(int), st));
@@ -1020,12 +1032,37 @@ int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float
                     status[0]);
     {
         StageScope sc2(c, ST_TOPK_INVERSE);
-        HIPCHK(c, ensure(c->d_topk_pk, (size_t)n_pairs));
-        HIPCHK(c, ensure(c->d_topk_pv, (size_t)n_pairs));
-        HIPCHK(c, ensure(c->d_topk_pk2, (size_t)n_pairs));
-        HIPCHK(c, ensure(c->d_topk_pv2, (size_t)n_pairs));
+        // the pixels with a list, per slice
+        const int64_t P = c->P;
+        HIPCHK(c, ensure(c->d_topk_flag, (size_t)P));
+        HIPCHK(c, ensure(c->d_topk_aoff, (size_t)P));
+        HIPCHK(c, ensure(c->d_topk_active, (size_t)P));
+        HIPCHK(c, ensure(c->d_topk_act, (size_t)P));
+        HIPCHK(c, ensure(c->d_topk_act_off, (size_t)M + 1));
+        HIPCHK(c, ensure(c->d_topk_scan_tmp, scan_tmp_bytes(P)));
+        HIPCHK(c, ensure(c->d_topk_tot, 2));
+        HIPCHK(c, launch_topk_active(nbr, P, K, c->d_geo.p, M, c->d_topk_flag.p, c->d_topk_aoff.p,
+                                     c->d_topk_active.p, c->d_topk_act.p, c->d_topk_act_off.p, c->d_topk_tot.p,
+                                     c->d_topk_scan_tmp.p, st));
+        std::vector<int32_t> aoff(M + 1);
+        HIPCHK(c, hipMemcpyAsync(aoff.data(), c->d_topk_act_off.p, aoff.size() * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        c->topk_n_act = aoff[M];
+        c->topk_max_act = 1;
+        for (int i = 0; i < M; ++i) c->topk_max_act = std::max(c->topk_max_act, aoff[i + 1] - aoff[i]);
+        // internal lists (cell-order positions) and their inverse
+        const int64_t n_int = c->topk_n_act * (int64_t)K;
+        HIPCHK(c, ensure(c->d_topk_iperm, (size_t)N));
+        HIPCHK(c, ensure(c->d_topk_lint, (size_t)n_int));
+        HIPCHK(c, launch_topk_internal(nbr, c->d_topk_act.p, c->topk_n_act, K, c->topk_perm, N, c->d_topk_iperm.p,
+                                       c->d_topk_lint.p, st));
+        HIPCHK(c, ensure(c->d_topk_pk, (size_t)n_int));
+        HIPCHK(c, ensure(c->d_topk_pv, (size_t)n_int));
+        HIPCHK(c, ensure(c->d_topk_pk2, (size_t)n_int));
+        HIPCHK(c, ensure(c->d_topk_pv2, (size_t)n_int));
         HIPCHK(c, ensure(c->d_topk_granges, (size_t)N));
-        HIPCHK(c, launch_topk_inverse(nbr, n_pairs, K, N, key_bits_for(N + 1), c->d_topk_pk.p, c->d_topk_pv.p,
+        HIPCHK(c, launch_topk_inverse(c->d_topk_lint.p, n_int, N, key_bits_for(N), c->d_topk_pk.p, c->d_topk_pv.p,
                                       c->d_topk_pk2.p, c->d_topk_pv2.p, c->d_topk_sort_tmp.p, c->d_topk_granges.p,
                                       &c->topk_gpix, st));
     }
@@ -1052,18 +1089,21 @@ int svr_topk_forward(svr_ctx* c, const svr_params* params, const float* sigma, c
     const int32_t M = c->M;
     const int mhw = max_slice_pixels(c);
     HIPCHK(c, ensure(c->d_topk_gauss, (size_t)c->N));
-    HIPCHK(c, ensure(c->d_topk_state, (size_t)c->P));
-    HIPCHK(c, ensure(c->d_topk_partial, std::max(topk_pose_partial_floats(M, mhw), (size_t)1024)));
+    HIPCHK(c, ensure(c->d_topk_state, (size_t)std::max<int64_t>(c->topk_n_act, 1)));
+    HIPCHK(c, ensure(c->d_topk_partial, std::max(std::max(topk_pose_partial_floats(M, c->topk_max_act),
+                                                          topk_loss_partial_floats(M, mhw, c->topk_max_act)),
+                                                 (size_t)1024)));
     HIPCHK(c, ensure(c->d_topk_msum, 1));
     HIPCHK(c, ensure(c->d_partial, 1024));
     StageScope sc(c, ST_TOPK_FORWARD);
     HIPCHK(c, launch_slice_pose(c->d_geo.p, params->pose, c->d_topk_pose.p, M, st));
-    HIPCHK(c, launch_topk_prepare(params->mean, params->log_scale, params->quat, params->amp, c->N,
+    HIPCHK(c, launch_topk_prepare(params->mean, params->log_scale, params->quat, params->amp, c->N, c->topk_perm,
                                   c->d_topk_pose.p, c->d_geo.p, sigma, M, c->d_topk_gauss.p, c->d_topk_slices.p, st));
     if (want_loss && c->loss_kind == SVR_LOSS_MSE)
         HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_topk_msum.p, st));
-    HIPCHK(c, launch_topk_forward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, nbr, K, delta, c->loss_kind, M,
-                                  mhw, want_loss ? target : nullptr, mask,
+    HIPCHK(c, launch_topk_forward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, c->d_topk_lint.p, c->d_topk_act.p,
+                                  c->d_topk_act_off.p, c->d_topk_active.p, K, delta, c->loss_kind, M, mhw,
+                                  c->topk_max_act, want_loss ? target : nullptr, mask,
                                   c->loss_kind == SVR_LOSS_MSE ? c->d_topk_msum.p : nullptr, pred,
                                   c->d_topk_state.p, grad_pred, c->d_topk_partial.p, loss, st));
     c->topk_forwarded = true;
@@ -1086,9 +1126,11 @@ int svr_topk_backward(svr_ctx* c, const svr_params* params, const int32_t* nbr, 
     const int32_t M = c->M;
     const int mhw = max_slice_pixels(c);
     HIPCHK(c, ensure(c->d_topk_pose_acc, (size_t)6 * std::max(M, 1)));
+    (void)mhw;
     StageScope sc(c, ST_TOPK_BACKWARD);
-    HIPCHK(c, launch_topk_backward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, nbr, K, 0.f, M, mhw,
-                                   grad_pred, c->d_topk_state.p, c->d_topk_granges.p, c->topk_gpix,
+    HIPCHK(c, launch_topk_backward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, c->d_topk_lint.p, c->d_topk_act.p,
+                                   c->d_topk_act_off.p, K, M, c->topk_max_act,
+                                   grad_pred, c->d_topk_state.p, c->d_topk_granges.p, c->topk_gpix, c->topk_perm,
                                    params->log_scale, params->quat, c->N, out->mean, out->log_scale, out->quat,
                                    out->amp, c->d_topk_partial.p, c->d_topk_pose_acc.p, g_sigma, st));
     HIPCHK(c, launch_pose_chain(params->pose, c->d_topk_pose_acc.p, out->pose, M, st));

@@ -54,11 +54,14 @@ __device__ inline float order_float(uint32_t k) {
 // --------------------------------------------------------------------------
 // activation and per-slice constants
 // --------------------------------------------------------------------------
+// out[s] for Gaussian perm[s] (perm NULL: identity); the neighbour grid's
+// cell order keeps spatial neighbours close in memory.
 __global__ void k_topk_activate(const float* __restrict__ mean, const float* __restrict__ log_scale,
                                 const float* __restrict__ quat, const float* __restrict__ amp, int64_t n,
-                                TopkGauss* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+                                const uint32_t* __restrict__ perm, TopkGauss* __restrict__ out) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t j = perm ? (int64_t)perm[s] : s;
     float qw = quat[4 * j], qx = quat[4 * j + 1], qy = quat[4 * j + 2], qz = quat[4 * j + 3];
     const float inv = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     qw *= inv; qx *= inv; qy *= inv; qz *= inv;
@@ -78,7 +81,7 @@ __global__ void k_topk_activate(const float* __restrict__ mean, const float* __r
     g.a = make_float4(mean[3 * j], mean[3 * j + 1], mean[3 * j + 2], amp[j]);
     g.b = make_float4(S[0], S[1], S[2], S[3]);
     g.c = make_float4(S[4], S[5], 0.f, 0.f);
-    out[j] = g;
+    out[s] = g;
 }
 
 __global__ void k_topk_slices(const SlicePose* __restrict__ pose, const SliceGeo* __restrict__ geo,
@@ -503,13 +506,51 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
 }
 
 // (Gaussian, pixel) pairs of the neighbour lists
-__global__ void k_pairs(const int32_t* __restrict__ nbr, int64_t n, uint32_t* __restrict__ keys,
-                        uint32_t* __restrict__ vals, int32_t K, uint32_t n_gauss) {
+__global__ void k_pairs(const int32_t* __restrict__ lint, int64_t n, uint32_t* __restrict__ keys,
+                        uint32_t* __restrict__ vals) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int32_t j = nbr[s];
-    keys[s] = j < 0 ? n_gauss : (uint32_t)j;   // no list: sorts after every Gaussian
-    vals[s] = (uint32_t)(s / K);
+    keys[s] = (uint32_t)lint[s];   // cell-order position of the Gaussian
+    vals[s] = (uint32_t)s;         // entry; its active pixel is s / K
+}
+
+__global__ void k_iperm(const uint32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ iperm) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) iperm[perm[s]] = (int32_t)s;
+}
+
+// Internal lists of the active pixels: cell-order positions instead of ids.
+__global__ void k_lists_internal(const int32_t* __restrict__ nbr, const int32_t* __restrict__ act, int64_t n,
+                                 int32_t K, const int32_t* __restrict__ iperm, int32_t* __restrict__ lint) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t a = e / K;
+    lint[e] = iperm[nbr[(int64_t)act[a] * K + (e - a * K)]];
+}
+
+// pixels with a list: flags, compaction (after an exclusive scan of the
+// flags) and each slice's range
+__global__ void k_act_flags(const int32_t* __restrict__ nbr, int64_t P, int32_t K, int* __restrict__ flag,
+                            uint8_t* __restrict__ active) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int f = nbr[p * K] >= 0 ? 1 : 0;
+    flag[p] = f;
+    active[p] = (uint8_t)f;
+}
+
+__global__ void k_act_compact(const int* __restrict__ flag, const int* __restrict__ off, int64_t P,
+                              int32_t* __restrict__ act) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    if (flag[p]) act[off[p]] = (int32_t)p;
+}
+
+__global__ void k_act_offsets(const int* __restrict__ off, const SliceGeo* __restrict__ geo, int32_t m,
+                              const long long* __restrict__ total, int32_t* __restrict__ act_off) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > m) return;
+    act_off[i] = i < m ? off[geo[i].pix_off] : (int32_t)total[0];
 }
 
 // --------------------------------------------------------------------------
@@ -519,33 +560,76 @@ struct TopkFwdArgs {
     const SliceGeo* geo;
     const TopkSlice* slices;
     const TopkGauss* gauss;
-    const int32_t* nbr;
+    const int32_t* nbr;       // internal lists [n_act, K] (cell-order positions)
+    const int32_t* act;       // pixels with a list, increasing
+    const int32_t* act_off;   // [M+1] each slice's range in act
     int32_t K;
     float delta;
     int32_t loss_kind;
 };
 
-__global__ __launch_bounds__(kBlock) void k_topk_forward(TopkFwdArgs a, const float* __restrict__ target,
-                                                         const float* __restrict__ mask,
-                                                         const float* __restrict__ msum, float* __restrict__ pred,
-                                                         float2* __restrict__ state, float* __restrict__ grad,
-                                                         float* __restrict__ partial, int32_t blocks_x) {
+// Pixels without a list: prediction 0 and their data term (pixels of the
+// build's mask all have lists, so with that mask these terms are 0).
+__global__ __launch_bounds__(kBlock) void k_topk_inactive(const SliceGeo* __restrict__ geo,
+                                                          const uint8_t* __restrict__ active, int32_t loss_kind,
+                                                          const float* __restrict__ target,
+                                                          const float* __restrict__ mask,
+                                                          const float* __restrict__ msum, float* __restrict__ pred,
+                                                          float* __restrict__ grad, float* __restrict__ partial,
+                                                          int32_t blocks_x, int32_t stride) {
     __shared__ float s_red[kBlock / 64];
     const int i = blockIdx.y;
-    const SliceGeo& sg = a.geo[i];
-    const TopkSlice& ts = a.slices[i];
+    const SliceGeo& sg = geo[i];
     const int64_t n = (int64_t)sg.H * sg.W;
     const float inv_msum = (msum && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     float acc = 0.f;
     for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)blocks_x * kBlock) {
+        const int64_t p = sg.pix_off + q;
+        if (active[p]) continue;
+        pred[p] = 0.f;
+        if (target) {
+            const float m = mask ? mask[p] : 1.f;
+            const float rr = -target[p];
+            if (loss_kind == 0) {
+                acc = fmaf(m * rr, rr, acc);
+                if (grad) grad[p] = 2.f * m * rr * inv_msum;
+            } else {
+                acc = fmaf(m, fabsf(rr), acc);
+                if (grad) grad[p] = rr > 0.f ? m : (rr < 0.f ? -m : 0.f);
+            }
+        }
+    }
+    if (!partial) return;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[(int64_t)i * stride + blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+// One thread per pixel with a list; act [n_act] holds those pixels in
+// increasing order, act_off [M+1] each slice's range in it.
+__global__ __launch_bounds__(kBlock) void k_topk_forward(TopkFwdArgs a, const float* __restrict__ target,
+                                                         const float* __restrict__ mask,
+                                                         const float* __restrict__ msum, float* __restrict__ pred,
+                                                         float2* __restrict__ state, float* __restrict__ grad,
+                                                         float* __restrict__ partial, int32_t blocks_x,
+                                                         int32_t stride) {
+    __shared__ float s_red[kBlock / 64];
+    const int i = blockIdx.y;
+    const SliceGeo& sg = a.geo[i];
+    const TopkSlice& ts = a.slices[i];
+    const int a0 = a.act_off[i], a1 = a.act_off[i + 1];
+    const float inv_msum = (msum && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
+    float acc = 0.f;
+    for (int qa = a0 + blockIdx.x * kBlock + threadIdx.x; qa < a1; qa += blocks_x * kBlock) {
+        const int64_t p = a.act[qa];
+        const int64_t q = p - sg.pix_off;
         const int r = (int)(q / sg.W), k = (int)(q - (int64_t)r * sg.W);
         float x, y, z, ux, uy;
         pixel_world(sg, ts, r, k, x, y, z, ux, uy);
-        const int64_t p = sg.pix_off + q;
-        const int32_t* nb = a.nbr + p * a.K;
+        const int32_t* nb = a.nbr + (int64_t)qa * a.K;
         float num = 0.f, den = 0.f;
-        const int kk = nb[0] < 0 ? 0 : a.K;   // no list: y = 0
-        for (int t = 0; t < kk; ++t) {
+        for (int t = 0; t < a.K; ++t) {
             const TopkGauss g = a.gauss[nb[t]];
             const float S[6] = {g.b.x + ts.P[0], g.b.y + ts.P[1], g.b.z + ts.P[2],
                                 g.b.w + ts.P[3], g.c.x + ts.P[4], g.c.y + ts.P[5]};
@@ -558,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void k_topk_forward(TopkFwdArgs a, const fl
         const float yn = num / dd;
         const float yv = ts.sigma * yn;
         pred[p] = yv;
-        if (state) state[p] = make_float2(yn, dd);
+        if (state) state[qa] = make_float2(yn, dd);
         if (target) {
             const float m = mask ? mask[p] : 1.f;
             const float rr = yv - target[p];
@@ -575,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_topk_forward(TopkFwdArgs a, const fl
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) partial[(int64_t)i * blocks_x + blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x == 0) partial[(int64_t)i * stride + blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
 }
 
 __global__ __launch_bounds__(kBlock) void k_topk_loss(const float* __restrict__ partial, int64_t n,
@@ -606,20 +690,21 @@ __global__ __launch_bounds__(kBlock) void k_topk_pose_pass(TopkFwdArgs a, const 
     const int i = blockIdx.y;
     const SliceGeo& sg = a.geo[i];
     const TopkSlice& ts = a.slices[i];
-    const int64_t n = (int64_t)sg.H * sg.W;
+    const int a0 = a.act_off[i], a1 = a.act_off[i + 1];
     float acc[kPoseTerms];
     for (int e = 0; e < kPoseTerms; ++e) acc[e] = 0.f;
-    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (int64_t)blocks_x * kBlock) {
-        const int64_t p = sg.pix_off + q;
+    for (int qa = a0 + blockIdx.x * kBlock + threadIdx.x; qa < a1; qa += blocks_x * kBlock) {
+        const int64_t p = a.act[qa];
         const float gy = grad_pred[p];
-        if (gy == 0.f || a.nbr[p * a.K] < 0) continue;
+        if (gy == 0.f) continue;
+        const int64_t q = p - sg.pix_off;
         const int r = (int)(q / sg.W), k = (int)(q - (int64_t)r * sg.W);
         float x, y, z, ux, uy;
         pixel_world(sg, ts, r, k, x, y, z, ux, uy);
-        const float2 st = state[p];
+        const float2 st = state[qa];
         const float yn = st.x, inv_dd = 1.f / st.y;
         const float gs = gy * ts.sigma * inv_dd;
-        const int32_t* nb = a.nbr + p * a.K;
+        const int32_t* nb = a.nbr + (int64_t)qa * a.K;
         float dx0 = 0.f, dx1 = 0.f, dx2 = 0.f;
         float G[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int t = 0; t < a.K; ++t) {
@@ -705,18 +790,21 @@ __device__ inline int slice_of_pixel(const SliceGeo* geo, int32_t m, int64_t p) 
 // One wave per Gaussian over the pixels whose lists hold it.
 __global__ __launch_bounds__(kBlock) void k_topk_gauss_pass(
         TopkFwdArgs a, int32_t m, const int2* __restrict__ granges, const uint32_t* __restrict__ gpix,
-        const float* __restrict__ grad_pred, const float2* __restrict__ state, const float* __restrict__ log_scale,
-        const float* __restrict__ quat, int64_t n_gauss, float* __restrict__ g_mean, float* __restrict__ g_ls,
-        float* __restrict__ g_quat, float* __restrict__ g_amp) {
-    const int64_t j = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+        const uint32_t* __restrict__ perm, const float* __restrict__ grad_pred, const float2* __restrict__ state,
+        const float* __restrict__ log_scale, const float* __restrict__ quat, int64_t n_gauss,
+        float* __restrict__ g_mean, float* __restrict__ g_ls, float* __restrict__ g_quat,
+        float* __restrict__ g_amp) {
+    const int64_t pos = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (j >= n_gauss) return;
-    const TopkGauss g = a.gauss[j];
-    const int2 rg = granges[j];
+    if (pos >= n_gauss) return;
+    const int64_t j = perm[pos];
+    const TopkGauss g = a.gauss[pos];
+    const int2 rg = granges[pos];
     float acc[10];
     for (int e = 0; e < 10; ++e) acc[e] = 0.f;
     for (int s = rg.x + lane; s < rg.y; s += 64) {
-        const int64_t p = gpix[s];
+        const int64_t ai = gpix[s] / (uint32_t)a.K;
+        const int64_t p = a.act[ai];
         const float gy = grad_pred[p];
         if (gy == 0.f) continue;
         const int i = slice_of_pixel(a.geo, m, p);
@@ -730,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_topk_gauss_pass(
                             g.b.w + ts.P[3], g.c.x + ts.P[4], g.c.y + ts.P[5]};
         float wx, wy, wz;
         const float e = pair_eval(S, x - g.a.x, y - g.a.y, z - g.a.z, wx, wy, wz);
-        const float2 st = state[p];
+        const float2 st = state[ai];
         const float gs = gy * ts.sigma / st.y;
         acc[0] += gs * e;                       // d c
         const float ge = gs * (g.a.w - st.x) * e;
@@ -790,11 +878,11 @@ __global__ __launch_bounds__(kBlock) void k_topk_gauss_pass(
 }  // namespace
 
 hipError_t launch_topk_prepare(const float* mean, const float* log_scale, const float* quat, const float* amp,
-                               int64_t n, const SlicePose* pose, const SliceGeo* geo, const float* sigma, int32_t m,
-                               TopkGauss* gauss, TopkSlice* slices, hipStream_t st) {
+                               int64_t n, const uint32_t* perm, const SlicePose* pose, const SliceGeo* geo,
+                               const float* sigma, int32_t m, TopkGauss* gauss, TopkSlice* slices, hipStream_t st) {
     if (n > 0)
         hipLaunchKernelGGL(k_topk_activate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mean, log_scale,
-                           quat, amp, n, gauss);
+                           quat, amp, n, perm, gauss);
     if (m > 0) hipLaunchKernelGGL(k_topk_slices, dim3((m + 127) / 128), dim3(128), 0, st, pose, geo, sigma, m, slices);
     return hipGetLastError();
 }
@@ -819,13 +907,14 @@ float topk_order_float(uint32_t k) {
 hipError_t launch_topk_cells(const float* mean, const GaussBlock* blocks, int32_t nb, const TopkGrid* grid,
                              int64_t n, int64_t n_cells, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, void* sort_tmp, int key_bits, int2* cells, float4* smean,
-                             hipStream_t st) {
+                             const uint32_t** perm, hipStream_t st) {
     if (nb > 0) hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, st, mean, blocks, nb, grid, keys, vals);
     bool alt = false;
     hipError_t e = launch_radix_sort(keys, vals, keys_alt, vals_alt, n, key_bits, sort_tmp, &alt, st);
     if (e != hipSuccess) return e;
     const uint32_t* sk = alt ? keys_alt : keys;
     const uint32_t* sv = alt ? vals_alt : vals;
+    *perm = sv;
     e = launch_fill_zero(cells, sizeof(int2) * (size_t)n_cells, st);
     if (e != hipSuccess) return e;
     if (n > 0) {
@@ -845,12 +934,23 @@ hipError_t launch_topk_knn(const SliceGeo* geo, const TopkSlice* slices, const T
     return hipGetLastError();
 }
 
-hipError_t launch_topk_inverse(const int32_t* nbr, int64_t n_pairs, int32_t K, int64_t n_gauss, int key_bits,
+hipError_t launch_topk_internal(const int32_t* nbr, const int32_t* act, int64_t n_act, int32_t K,
+                                const uint32_t* perm, int64_t n_gauss, int32_t* iperm, int32_t* lint, hipStream_t st) {
+    if (n_gauss > 0)
+        hipLaunchKernelGGL(k_iperm, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, st, perm, n_gauss, iperm);
+    const int64_t n = n_act * K;
+    if (n > 0)
+        hipLaunchKernelGGL(k_lists_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nbr, act, n, K,
+                           (const int32_t*)iperm, lint);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_inverse(const int32_t* lint, int64_t n_pairs, int64_t n_gauss, int key_bits,
                                uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                void* sort_tmp, int2* granges, const uint32_t** gpix, hipStream_t st) {
     if (n_pairs > 0)
-        hipLaunchKernelGGL(k_pairs, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, st, nbr, n_pairs, keys,
-                           vals, K, (uint32_t)n_gauss);
+        hipLaunchKernelGGL(k_pairs, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, st, lint, n_pairs, keys,
+                           vals);
     bool alt = false;
     hipError_t e = launch_radix_sort(keys, vals, keys_alt, vals_alt, n_pairs, key_bits, sort_tmp, &alt, st);
     if (e != hipSuccess) return e;
@@ -866,42 +966,65 @@ hipError_t launch_topk_inverse(const int32_t* nbr, int64_t n_pairs, int32_t K, i
 
 int32_t topk_blocks_x(int32_t max_hw) { return std::max(1, std::min((max_hw + kBlock - 1) / kBlock, 64)); }
 
-hipError_t launch_topk_forward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
-                               const int32_t* nbr, int32_t K, float delta, int32_t loss_kind, int32_t m,
-                               int32_t max_hw, const float* target, const float* mask, const float* msum, float* pred,
-                               float2* state, float* grad, float* partial, float* loss, hipStream_t st) {
-    if (m <= 0) return hipSuccess;
-    TopkFwdArgs a{geo, slices, gauss, nbr, K, delta, loss_kind};
-    const int bx = topk_blocks_x(max_hw);
-    hipLaunchKernelGGL(k_topk_forward, dim3(bx, m), dim3(kBlock), 0, st, a, target, mask, msum, pred, state, grad,
-                       target && loss ? partial : nullptr, bx);
-    if (target && loss)
-        hipLaunchKernelGGL(k_topk_loss, dim3(1), dim3(kBlock), 0, st, (const float*)partial, (int64_t)m * bx, msum,
-                           loss_kind, loss);
+hipError_t launch_topk_active(const int32_t* nbr, int64_t P, int32_t K, const SliceGeo* geo, int32_t m, int* flag,
+                              int* off, uint8_t* active, int32_t* act, int32_t* act_off, long long* total,
+                              void* scan_tmp, hipStream_t st) {
+    if (P <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((P + 255) / 256);
+    hipLaunchKernelGGL(k_act_flags, dim3(nb), dim3(256), 0, st, nbr, P, K, flag, active);
+    hipError_t e = launch_scan_int(flag, off, P, total, scan_tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_act_compact, dim3(nb), dim3(256), 0, st, (const int*)flag, (const int*)off, P, act);
+    hipLaunchKernelGGL(k_act_offsets, dim3((m + 1 + 63) / 64), dim3(64), 0, st, (const int*)off, geo, m,
+                       (const long long*)total, act_off);
     return hipGetLastError();
 }
 
-size_t topk_pose_partial_floats(int32_t m, int32_t max_hw) {
-    return (size_t)m * topk_blocks_x(max_hw) * kPoseTerms;
+size_t topk_loss_partial_floats(int32_t m, int32_t max_hw, int32_t max_act) {
+    return (size_t)m * (topk_blocks_x(max_hw) + topk_blocks_x(max_act));
+}
+
+hipError_t launch_topk_forward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
+                               const int32_t* nbr, const int32_t* act, const int32_t* act_off, const uint8_t* active,
+                               int32_t K, float delta, int32_t loss_kind, int32_t m, int32_t max_hw, int32_t max_act,
+                               const float* target, const float* mask, const float* msum, float* pred, float2* state,
+                               float* grad, float* partial, float* loss, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, K, delta, loss_kind};
+    const int bx = topk_blocks_x(max_hw), ba = topk_blocks_x(max_act);
+    const bool want = target && loss;
+    hipLaunchKernelGGL(k_topk_inactive, dim3(bx, m), dim3(kBlock), 0, st, geo, active, loss_kind, target, mask, msum,
+                       pred, grad, want ? partial : nullptr, bx, bx + ba);
+    hipLaunchKernelGGL(k_topk_forward, dim3(ba, m), dim3(kBlock), 0, st, a, target, mask, msum, pred, state, grad,
+                       want ? partial + bx : nullptr, ba, bx + ba);
+    if (want)
+        hipLaunchKernelGGL(k_topk_loss, dim3(1), dim3(kBlock), 0, st, (const float*)partial,
+                           (int64_t)m * (bx + ba), msum, loss_kind, loss);
+    return hipGetLastError();
+}
+
+size_t topk_pose_partial_floats(int32_t m, int32_t max_act) {
+    return (size_t)m * topk_blocks_x(max_act) * kPoseTerms;
 }
 
 hipError_t launch_topk_backward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
-                                const int32_t* nbr, int32_t K, float delta, int32_t m, int32_t max_hw,
-                                const float* grad_pred, const float2* state, const int2* granges,
-                                const uint32_t* gpix, const float* log_scale, const float* quat, int64_t n_gauss,
+                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, int32_t K, int32_t m,
+                                int32_t max_act, const float* grad_pred, const float2* state, const int2* granges,
+                                const uint32_t* gpix, const uint32_t* perm, const float* log_scale, const float* quat,
+                                int64_t n_gauss,
                                 float* g_mean, float* g_ls, float* g_quat, float* g_amp, float* partial,
                                 float* pose_acc, float* g_sigma, hipStream_t st) {
-    TopkFwdArgs a{geo, slices, gauss, nbr, K, delta, 0};
+    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, K, 0.f, 0};
     if (m > 0) {
-        const int bx = topk_blocks_x(max_hw);
+        const int bx = topk_blocks_x(max_act);
         hipLaunchKernelGGL(k_topk_pose_pass, dim3(bx, m), dim3(kBlock), 0, st, a, grad_pred, state, partial, bx);
         hipLaunchKernelGGL(k_topk_pose_reduce, dim3((m + 63) / 64), dim3(64), 0, st, (const float*)partial, bx,
                            slices, m, pose_acc, g_sigma);
     }
     if (n_gauss > 0)
         hipLaunchKernelGGL(k_topk_gauss_pass, dim3((unsigned)((n_gauss * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           st, a, m, granges, gpix, grad_pred, state, log_scale, quat, n_gauss, g_mean, g_ls, g_quat,
-                           g_amp);
+                           st, a, m, granges, gpix, perm, grad_pred, state, log_scale, quat, n_gauss, g_mean, g_ls,
+                           g_quat, g_amp);
     return hipGetLastError();
 }
 
