@@ -116,6 +116,9 @@ struct svr_ctx {
     int64_t topk_n_act = 0;
     int32_t topk_max_act = 1;
     DevBuf<int32_t> d_topk_iperm, d_topk_lint;
+    DevBuf<int64_t> d_topk_qoff;
+    DevBuf<float4> d_topk_pxw;
+    DevBuf<float2> d_topk_pyd;
     const uint32_t* topk_perm = nullptr;
     DevBuf<float> d_sl_scratch, d_sl_msum;   // per-slice outlier terms
     const uint32_t* topk_gpix = nullptr;
@@ -558,7 +561,8 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_sl_scratch); release(c->d_sl_msum);
         release(c->d_topk_flag); release(c->d_topk_aoff); release(c->d_topk_active); release(c->d_topk_act);
         release(c->d_topk_act_off); release(c->d_topk_scan_tmp); release(c->d_topk_tot);
-        release(c->d_topk_iperm); release(c->d_topk_lint);
+        release(c->d_topk_iperm); release(c->d_topk_lint); release(c->d_topk_qoff); release(c->d_topk_pxw);
+        release(c->d_topk_pyd);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
@@ -1019,7 +1023,7 @@ int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float
                                 c->d_topk_cv.p, c->d_topk_ck2.p, c->d_topk_cv2.p, c->d_topk_sort_tmp.p,
                                 key_bits_for(cells), c->d_topk_cells.p, c->d_topk_smean.p, &c->topk_perm, st));
     int max_tiles = 1;
-    for (int i = 0; i < M; ++i) max_tiles = std::max(max_tiles, ((c->W[i] + 15) / 16) * ((c->H[i] + 15) / 16));
+    for (int i = 0; i < M; ++i) max_tiles = std::max(max_tiles, topk_knn_tiles(c->H[i], c->W[i]));
     HIPCHK(c, launch_fill_zero(c->d_topk_status.p, 2 * sizeof(int), st));
     HIPCHK(c, launch_topk_knn(c->d_geo.p, c->d_topk_slices.p, c->d_topk_grid.p, c->d_topk_cells.p,
                               c->d_topk_smean.p, mask, M, max_tiles, K, nbr, c->d_topk_status.p, st));
@@ -1034,14 +1038,22 @@ int svr_topk_build(svr_ctx* c, const float* mean, const float* pose, const float
         StageScope sc2(c, ST_TOPK_INVERSE);
         // the pixels with a list, per slice
         const int64_t P = c->P;
-        HIPCHK(c, ensure(c->d_topk_flag, (size_t)P));
-        HIPCHK(c, ensure(c->d_topk_aoff, (size_t)P));
+        std::vector<int64_t> qoff(M + 1, 0);
+        for (int i = 0; i < M; ++i)
+            qoff[i + 1] = qoff[i] + (int64_t)((c->H[i] + 7) / 8 * 8) * ((c->W[i] + 7) / 8 * 8);
+        const int64_t Q = qoff[M];
+        if (Q > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "too many pixels for the neighbour lists");
+        HIPCHK(c, ensure(c->d_topk_qoff, (size_t)M + 1));
+        HIPCHK(c, hipMemcpyAsync(c->d_topk_qoff.p, qoff.data(), qoff.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                                 st));
+        HIPCHK(c, ensure(c->d_topk_flag, (size_t)Q));
+        HIPCHK(c, ensure(c->d_topk_aoff, (size_t)Q));
         HIPCHK(c, ensure(c->d_topk_active, (size_t)P));
         HIPCHK(c, ensure(c->d_topk_act, (size_t)P));
         HIPCHK(c, ensure(c->d_topk_act_off, (size_t)M + 1));
-        HIPCHK(c, ensure(c->d_topk_scan_tmp, scan_tmp_bytes(P)));
+        HIPCHK(c, ensure(c->d_topk_scan_tmp, scan_tmp_bytes(Q)));
         HIPCHK(c, ensure(c->d_topk_tot, 2));
-        HIPCHK(c, launch_topk_active(nbr, P, K, c->d_geo.p, M, c->d_topk_flag.p, c->d_topk_aoff.p,
+        HIPCHK(c, launch_topk_active(nbr, K, c->d_geo.p, c->d_topk_qoff.p, M, Q, c->d_topk_flag.p, c->d_topk_aoff.p,
                                      c->d_topk_active.p, c->d_topk_act.p, c->d_topk_act_off.p, c->d_topk_tot.p,
                                      c->d_topk_scan_tmp.p, st));
         std::vector<int32_t> aoff(M + 1);
@@ -1102,7 +1114,7 @@ int svr_topk_forward(svr_ctx* c, const svr_params* params, const float* sigma, c
     if (want_loss && c->loss_kind == SVR_LOSS_MSE)
         HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_topk_msum.p, st));
     HIPCHK(c, launch_topk_forward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, c->d_topk_lint.p, c->d_topk_act.p,
-                                  c->d_topk_act_off.p, c->d_topk_active.p, K, delta, c->loss_kind, M, mhw,
+                                  c->d_topk_act_off.p, c->d_topk_active.p, c->topk_n_act, K, delta, c->loss_kind, M, mhw,
                                   c->topk_max_act, want_loss ? target : nullptr, mask,
                                   c->loss_kind == SVR_LOSS_MSE ? c->d_topk_msum.p : nullptr, pred,
                                   c->d_topk_state.p, grad_pred, c->d_topk_partial.p, loss, st));
@@ -1126,13 +1138,16 @@ int svr_topk_backward(svr_ctx* c, const svr_params* params, const int32_t* nbr, 
     const int32_t M = c->M;
     const int mhw = max_slice_pixels(c);
     HIPCHK(c, ensure(c->d_topk_pose_acc, (size_t)6 * std::max(M, 1)));
+    HIPCHK(c, ensure(c->d_topk_pxw, (size_t)std::max<int64_t>(c->topk_n_act, 1)));
+    HIPCHK(c, ensure(c->d_topk_pyd, (size_t)std::max<int64_t>(c->topk_n_act, 1)));
     (void)mhw;
     StageScope sc(c, ST_TOPK_BACKWARD);
     HIPCHK(c, launch_topk_backward(c->d_geo.p, c->d_topk_slices.p, c->d_topk_gauss.p, c->d_topk_lint.p, c->d_topk_act.p,
-                                   c->d_topk_act_off.p, K, M, c->topk_max_act,
+                                   c->d_topk_act_off.p, c->topk_n_act, K, M, c->topk_max_act,
                                    grad_pred, c->d_topk_state.p, c->d_topk_granges.p, c->topk_gpix, c->topk_perm,
                                    params->log_scale, params->quat, c->N, out->mean, out->log_scale, out->quat,
-                                   out->amp, c->d_topk_partial.p, c->d_topk_pose_acc.p, g_sigma, st));
+                                   out->amp, c->d_topk_partial.p, c->d_topk_pose_acc.p, g_sigma, c->d_topk_pxw.p,
+                                   c->d_topk_pyd.p, st));
     HIPCHK(c, launch_pose_chain(params->pose, c->d_topk_pose_acc.p, out->pose, M, st));
     return SVR_OK;
 }

@@ -239,12 +239,14 @@ hipError_t launch_topk_cells(const float* mean, const GaussBlock* blocks, int32_
                              uint32_t* vals_alt, void* sort_tmp, int key_bits, int2* cells, float4* smean,
                              const uint32_t** perm, hipStream_t st);
 // status [2] (zeroed by the caller): pixels without K neighbours, sub-tile
-// splits
+// splits; max_tiles = the largest topk_knn_tiles over the slices
+int32_t topk_knn_tiles(int32_t H, int32_t W);
 hipError_t launch_topk_knn(const SliceGeo* geo, const TopkSlice* slices, const TopkGrid* grid, const int2* cells,
                            const float4* smean, const float* mask, int32_t m, int32_t max_tiles, int32_t K,
                            int32_t* nbr, int* status, hipStream_t st);
-// Internal lists lint [n_act, K]: the lists of the active pixels with every
-// id replaced by its cell-order position (iperm [N] scratch).
+// Internal lists lint [K, n_act] (entry t of active pixel a at t * n_act +
+// a): the lists of the active pixels with every id replaced by its
+// cell-order position (iperm [N] scratch).
 hipError_t launch_topk_internal(const int32_t* nbr, const int32_t* act, int64_t n_act, int32_t K,
                                 const uint32_t* perm, int64_t n_gauss, int32_t* iperm, int32_t* lint, hipStream_t st);
 // Inverse lists: entries of lint sorted by position; granges [N] per
@@ -252,25 +254,28 @@ hipError_t launch_topk_internal(const int32_t* nbr, const int32_t* act, int64_t 
 hipError_t launch_topk_inverse(const int32_t* lint, int64_t n_pairs, int64_t n_gauss, int key_bits,
                                uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                                void* sort_tmp, int2* granges, const uint32_t** gpix, hipStream_t st);
-// Pixels with a list (nbr[p*K] >= 0): flag [P] and active [P] (0/1), off [P]
-// their exclusive scan (scan_tmp: scan_tmp_bytes(P)), act [n_act] the
-// pixels, act_off [M+1] each slice's range, total [2] with total[0] = n_act.
-hipError_t launch_topk_active(const int32_t* nbr, int64_t P, int32_t K, const SliceGeo* geo, int32_t m, int* flag,
-                              int* off, uint8_t* active, int32_t* act, int32_t* act_off, long long* total,
-                              void* scan_tmp, hipStream_t st);
+// Pixels with a list (nbr[p*K] >= 0) in 8x8-patch order: positions of
+// slice i start at qoff[i] (its pixels padded to whole patches, Q in all);
+// flag, off [Q] (off = exclusive scan, scan_tmp: scan_tmp_bytes(Q)),
+// active [P] (0/1 per pixel), act [n_act] the pixels, act_off [M+1] each
+// slice's range, total [2] with total[0] = n_act.
+hipError_t launch_topk_active(const int32_t* nbr, int32_t K, const SliceGeo* geo, const int64_t* qoff, int32_t m,
+                              int64_t Q, int* flag, int* off, uint8_t* active, int32_t* act, int32_t* act_off,
+                              long long* total, void* scan_tmp, hipStream_t st);
 int32_t topk_blocks_x(int32_t max_hw);
 size_t topk_loss_partial_floats(int32_t m, int32_t max_hw, int32_t max_act);
 hipError_t launch_topk_forward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, const uint8_t* active,
-                               int32_t K, float delta, int32_t loss_kind, int32_t m, int32_t max_hw, int32_t max_act,
+                               int64_t n_act, int32_t K, float delta, int32_t loss_kind, int32_t m, int32_t max_hw, int32_t max_act,
                                const float* target, const float* mask, const float* msum, float* pred, float2* state,
                                float* grad, float* partial, float* loss, hipStream_t st);
 size_t topk_pose_partial_floats(int32_t m, int32_t max_act);
 hipError_t launch_topk_backward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
-                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, int32_t K, int32_t m,
-                                int32_t max_act, const float* grad_pred, const float2* state, const int2* granges,
+                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, int64_t n_act,
+                                int32_t K, int32_t m, int32_t max_act, const float* grad_pred, const float2* state, const int2* granges,
                                 const uint32_t* gpix, const uint32_t* perm, const float* log_scale, const float* quat,
                                 int64_t n_gauss, float* g_mean, float* g_ls, float* g_quat, float* g_amp,
-                                float* partial, float* pose_acc, float* g_sigma, hipStream_t st);
+                                float* partial, float* pose_acc, float* g_sigma, float4* pxw, float2* pyd,
+                                hipStream_t st);
 
 }  // namespace svr

@@ -13,7 +13,7 @@
 //   k_bbox / host      per-subject bounding box and a uniform cell grid;
 //   k_cell_keys, sort  Gaussians sorted by cell (stable, so by id within a
 //                      cell), k_cell_ranges gives each cell's range;
-//   k_knn              one workgroup per 16x16 pixel tile: the means inside
+//   k_knn              one wave per 8x8 pixel tile: the means inside
 //                      the slab box that holds the radius-rho ball of every
 //                      pixel of the tile are compacted into LDS in cell
 //                      order; each lane (pixel) then selects its K nearest
@@ -21,7 +21,7 @@
 //                      exact pick inside the boundary bin.  If some pixel
 //                      has fewer than K means within rho, rho grows by 1.3;
 //                      if the means within reach exceed LDS, the tile is
-//                      split into 4x4 and then single-pixel sub-tiles, and a
+//                      split into 4x4, 2x2 and single-pixel sub-tiles, and a
 //                      single pixel streams its candidates through LDS.
 //   inverse lists      (Gaussian, pixel) pairs sorted by Gaussian, so that
 //                      the adjoint gathers per Gaussian without atomics.
@@ -39,7 +39,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTileSide = 16;
-constexpr int kCandCap = 2560;   // means staged in LDS per (sub-)tile
+constexpr int kKnnSide = 8;      // neighbour search: one wave per 8x8 pixel tile
+constexpr int kKnnThreads = kKnnSide * kKnnSide;
+constexpr int kCandCap = 1024;   // means staged in LDS per (sub-)tile
 constexpr int kBins = 64;
 constexpr int kMaxTries = 20;
 
@@ -157,11 +159,17 @@ __global__ void k_bbox(const float* __restrict__ mean, const GaussBlock* __restr
             hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], o, 64));
         }
     }
-    if ((threadIdx.x & 63) == 0 && gb.g_end > gb.g_begin) {
+    __shared__ uint32_t s_lo[4][3], s_hi[4][3];
+    if ((threadIdx.x & 63) == 0)
         for (int k = 0; k < 3; ++k) {
-            atomicMin(bb + 6 * gb.subject + k, lo[k]);
-            atomicMax(bb + 6 * gb.subject + 3 + k, hi[k]);
+            s_lo[threadIdx.x >> 6][k] = lo[k];
+            s_hi[threadIdx.x >> 6][k] = hi[k];
         }
+    __syncthreads();
+    if (threadIdx.x < 3 && gb.g_end > gb.g_begin) {
+        const int k = threadIdx.x;
+        atomicMin(bb + 6 * gb.subject + k, min(min(s_lo[0][k], s_lo[1][k]), min(s_lo[2][k], s_lo[3][k])));
+        atomicMax(bb + 6 * gb.subject + 3 + k, max(max(s_hi[0][k], s_hi[1][k]), max(s_hi[2][k], s_hi[3][k])));
     }
 }
 
@@ -228,7 +236,7 @@ __device__ inline int block_excl_scan_int(int v, int* s_wave, int& total) {
     __syncthreads();
     int before = 0;
     total = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < kKnnThreads / 64; ++w) {
         if (w < wave) before += s_wave[w];
         total += s_wave[w];
     }
@@ -238,10 +246,10 @@ __device__ inline int block_excl_scan_int(int v, int* s_wave, int& total) {
 
 struct KnnShared {
     float4 cand[kCandCap];
-    uint16_t hist[kBins * kBlock];
-    int cell_off[kBlock + 1];
-    int cell_start[kBlock];
-    int wave[kBlock / 64];
+    uint16_t hist[kBins * kKnnThreads];
+    int cell_off[kKnnThreads + 1];
+    int cell_start[kKnnThreads];
+    int wave[kKnnThreads / 64];
     int n;
     int box[4];
 };
@@ -274,7 +282,7 @@ __device__ int gather_chunk(const KnnArgs& a, const TopkSlice& ts, const TopkGri
     const float r2 = rho * rho;
     if (threadIdx.x == 0) sh.n = 0;
     __syncthreads();
-    for (int64_t cb = 0; cb < ncell; cb += kBlock) {
+    for (int64_t cb = 0; cb < ncell; cb += kKnnThreads) {
         const int64_t c = cb + threadIdx.x;
         int cnt = 0, start = 0;
         if (c < ncell) {
@@ -290,12 +298,12 @@ __device__ int gather_chunk(const KnnArgs& a, const TopkSlice& ts, const TopkGri
         sh.cell_off[threadIdx.x] = off;
         sh.cell_start[threadIdx.x] = start;
         __syncthreads();
-        for (int qb = 0; qb < total; qb += kBlock) {
+        for (int qb = 0; qb < total; qb += kKnnThreads) {
             const int q = qb + threadIdx.x;
             bool keep = false;
             float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
             if (q < total) {
-                int l = 0, h = kBlock - 1;   // last cell whose offset is <= q
+                int l = 0, h = kKnnThreads - 1;   // last cell whose offset is <= q
                 while (l < h) {
                     const int mid = (l + h + 1) >> 1;
                     if (sh.cell_off[mid] <= q) l = mid; else h = mid - 1;
@@ -321,17 +329,17 @@ __device__ int gather_chunk(const KnnArgs& a, const TopkSlice& ts, const TopkGri
     return sh.n;
 }
 
-__global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
+__global__ __launch_bounds__(kKnnThreads) void k_knn(KnnArgs a) {
     __shared__ KnnShared sh;
     const int i = blockIdx.y;
     const SliceGeo& sg = a.geo[i];
-    const int ntx = (sg.W + kTileSide - 1) / kTileSide, nty = (sg.H + kTileSide - 1) / kTileSide;
+    const int ntx = (sg.W + kKnnSide - 1) / kKnnSide, nty = (sg.H + kKnnSide - 1) / kKnnSide;
     if ((int)blockIdx.x >= ntx * nty) return;
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const TopkSlice& ts = a.slices[i];
     const TopkGrid& g = a.grid[sg.subject];
-    const int lr = threadIdx.x / kTileSide, lc = threadIdx.x % kTileSide;
-    const int r = ty * kTileSide + lr, k = tx * kTileSide + lc;
+    const int lr = threadIdx.x / kKnnSide, lc = threadIdx.x % kKnnSide;
+    const int r = ty * kKnnSide + lr, k = tx * kKnnSide + lc;
     const bool valid = r < sg.H && k < sg.W;
     float px, py, pz, ux, uy;
     pixel_world(sg, ts, min(r, sg.H - 1), min(k, sg.W - 1), px, py, pz, ux, uy);
@@ -343,35 +351,39 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
         for (int q = 0; q < K; ++q) out[q] = -1;
     if (!__syncthreads_or(need ? 1 : 0)) return;
 
-    // Sub-tiles of side 16, then 4, then 1 while their candidates exceed LDS
-    // (then they are streamed through LDS in chunks).
-    for (int side = kTileSide; side >= 1; side >>= 2) {
-        const int nsub = kTileSide / side;
+    // Sub-tiles of side 8, 4, 2, then 1 while their candidates exceed LDS
+    // (then they are streamed through LDS in chunks).  Each pixel finishes
+    // as soon as it has K means within the current radius; the radius grows
+    // (and the slab shrinks to the unfinished pixels) for the others only.
+    bool fin = !need;
+    for (int side = kKnnSide; side >= 1; side >>= 1) {
+        const int nsub = kKnnSide / side;
         bool split = false;
         for (int sub = 0; sub < nsub * nsub && !split; ++sub) {
             const int sr = (sub / nsub) * side, sc = (sub % nsub) * side;
-            const bool mine = need && lr >= sr && lr < sr + side && lc >= sc && lc < sc + side;
-            if (threadIdx.x == 0) {
-                sh.box[0] = 1 << 30; sh.box[1] = -1; sh.box[2] = 1 << 30; sh.box[3] = -1;
-            }
-            __syncthreads();
-            if (mine) {
-                atomicMin(&sh.box[0], r);
-                atomicMax(&sh.box[1], r);
-                atomicMin(&sh.box[2], k);
-                atomicMax(&sh.box[3], k);
-            }
-            __syncthreads();
-            const int r0 = sh.box[0], r1 = sh.box[1], c0 = sh.box[2], c1 = sh.box[3];
-            __syncthreads();
-            if (r1 < 0) continue;
-            const float u0 = ((float)c0 - 0.5f * (float)(sg.W - 1)) * sg.dx;
-            const float u1 = ((float)c1 - 0.5f * (float)(sg.W - 1)) * sg.dx;
-            const float v0 = ((float)r0 - 0.5f * (float)(sg.H - 1)) * sg.dy;
-            const float v1 = ((float)r1 - 0.5f * (float)(sg.H - 1)) * sg.dy;
-            float rho = 0.5f * g.rho0;
-            bool done = false;
-            for (int attempt = 0; attempt < kMaxTries && !done; ++attempt, rho *= 1.3f) {
+            const bool in_sub = need && lr >= sr && lr < sr + side && lc >= sc && lc < sc + side;
+            float rho = 0.8f * g.rho0;
+            for (int attempt = 0; attempt < kMaxTries; ++attempt, rho *= 1.3f) {
+                const bool mine = in_sub && !fin;
+                if (!__syncthreads_or(mine ? 1 : 0)) break;
+                // pixel rectangle of the unfinished pixels
+                if (threadIdx.x == 0) {
+                    sh.box[0] = 1 << 30; sh.box[1] = -1; sh.box[2] = 1 << 30; sh.box[3] = -1;
+                }
+                __syncthreads();
+                if (mine) {
+                    atomicMin(&sh.box[0], r);
+                    atomicMax(&sh.box[1], r);
+                    atomicMin(&sh.box[2], k);
+                    atomicMax(&sh.box[3], k);
+                }
+                __syncthreads();
+                const int r0 = sh.box[0], r1 = sh.box[1], c0 = sh.box[2], c1 = sh.box[3];
+                __syncthreads();
+                const float u0 = ((float)c0 - 0.5f * (float)(sg.W - 1)) * sg.dx;
+                const float u1 = ((float)c1 - 0.5f * (float)(sg.W - 1)) * sg.dx;
+                const float v0 = ((float)r0 - 0.5f * (float)(sg.H - 1)) * sg.dy;
+                const float v1 = ((float)r1 - 0.5f * (float)(sg.H - 1)) * sg.dy;
                 const int n = gather_chunk(a, ts, g, u0, u1, v0, v1, rho, 0, sh);
                 if (n > kCandCap && side > 1) {
                     split = true;
@@ -383,14 +395,14 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
                 const float scale1 = (float)kBins / r2;
                 // pass 1: histogram of squared distances over [0, rho^2)
                 if (mine)
-                    for (int b = 0; b < kBins; ++b) sh.hist[b * kBlock + threadIdx.x] = 0;
+                    for (int b = 0; b < kBins; ++b) sh.hist[b * kKnnThreads + threadIdx.x] = 0;
                 for (int chn = 0; chn < nch; ++chn) {
                     if (!resident) gather_chunk(a, ts, g, u0, u1, v0, v1, rho, chn * kCandCap, sh);
                     const int cnt = min(kCandCap, n - chn * kCandCap);
                     if (mine)
                         for (int c = 0; c < cnt; ++c) {
                             const float d2 = dist2(px, py, pz, sh.cand[c]);
-                            if (d2 < r2) sh.hist[min((int)(d2 * scale1), kBins - 1) * kBlock + threadIdx.x] += 1;
+                            if (d2 < r2) sh.hist[min((int)(d2 * scale1), kBins - 1) * kKnnThreads + threadIdx.x] += 1;
                         }
                     __syncthreads();
                 }
@@ -398,35 +410,36 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
                 if (mine) {
                     int cum = 0;
                     for (int b = 0; b < kBins; ++b) {
-                        const int h = sh.hist[b * kBlock + threadIdx.x];
+                        const int h = sh.hist[b * kKnnThreads + threadIdx.x];
                         if (cum + h >= K) { bstar = b; break; }
                         cum += h;
                     }
                     have = cum;
                 }
-                if (__syncthreads_or(mine && bstar < 0 ? 1 : 0)) continue;   // grow rho
+                const bool res = mine && bstar >= 0;   // this pixel completes at this radius
+                if (!__syncthreads_or(res ? 1 : 0)) continue;   // grow rho for all
                 // pass 2: the boundary bin split into kBins sub-bins
-                const float lo_b = mine ? (float)bstar / scale1 : 0.f;
+                const float lo_b = res ? (float)bstar / scale1 : 0.f;
                 const float scale2 = (float)kBins * scale1;
-                if (mine)
-                    for (int b = 0; b < kBins; ++b) sh.hist[b * kBlock + threadIdx.x] = 0;
+                if (res)
+                    for (int b = 0; b < kBins; ++b) sh.hist[b * kKnnThreads + threadIdx.x] = 0;
                 for (int chn = 0; chn < nch; ++chn) {
                     if (!resident) gather_chunk(a, ts, g, u0, u1, v0, v1, rho, chn * kCandCap, sh);
                     const int cnt = min(kCandCap, n - chn * kCandCap);
-                    if (mine)
+                    if (res)
                         for (int c = 0; c < cnt; ++c) {
                             const float d2 = dist2(px, py, pz, sh.cand[c]);
                             if (d2 < r2 && min((int)(d2 * scale1), kBins - 1) == bstar)
-                                sh.hist[min(max((int)((d2 - lo_b) * scale2), 0), kBins - 1) * kBlock + threadIdx.x] +=
+                                sh.hist[min(max((int)((d2 - lo_b) * scale2), 0), kBins - 1) * kKnnThreads + threadIdx.x] +=
                                     1;
                         }
                     __syncthreads();
                 }
                 int b2 = kBins - 1;
-                if (mine) {
+                if (res) {
                     int cum = have;
                     for (int b = 0; b < kBins; ++b) {
-                        const int h = sh.hist[b * kBlock + threadIdx.x];
+                        const int h = sh.hist[b * kKnnThreads + threadIdx.x];
                         if (cum + h >= K) { b2 = b; break; }
                         cum += h;
                     }
@@ -436,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
                 for (int chn = 0; chn < nch; ++chn) {
                     if (!resident) gather_chunk(a, ts, g, u0, u1, v0, v1, rho, chn * kCandCap, sh);
                     const int cnt = min(kCandCap, n - chn * kCandCap);
-                    if (mine)
+                    if (res)
                         for (int c = 0; c < cnt; ++c) {
                             const float d2 = dist2(px, py, pz, sh.cand[c]);
                             if (d2 >= r2) continue;
@@ -451,8 +464,8 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
                 float last_d = -1.f;
                 int last_c = -1;
                 bool stuck = false;
-                while (__syncthreads_or(mine && cnt_out < K && !stuck ? 1 : 0)) {
-                    const bool want = mine && cnt_out < K && !stuck;
+                while (__syncthreads_or(res && cnt_out < K && !stuck ? 1 : 0)) {
+                    const bool want = res && cnt_out < K && !stuck;
                     float best_d = 3.4e38f;
                     int best_c = -1;
                     uint32_t best_id = 0;
@@ -486,16 +499,20 @@ __global__ __launch_bounds__(kBlock) void k_knn(KnnArgs a) {
                         }
                     }
                 }
-                if (mine && cnt_out < K) {
-                    for (int q = 0; q < K; ++q) out[q] = -1;
-                    atomicAdd(a.status, 1);
+                if (res) {
+                    if (cnt_out < K) {
+                        for (int q = 0; q < K; ++q) out[q] = -1;
+                        atomicAdd(a.status, 1);
+                    }
+                    fin = true;
                 }
-                done = true;
             }
             if (split) break;
-            if (!done && mine) {
+            // radius limit reached without K means
+            if (in_sub && !fin) {
                 for (int q = 0; q < K; ++q) out[q] = -1;
                 atomicAdd(a.status, 1);
+                fin = true;
             }
             __syncthreads();
         }
@@ -511,7 +528,7 @@ __global__ void k_pairs(const int32_t* __restrict__ lint, int64_t n, uint32_t* _
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     keys[s] = (uint32_t)lint[s];   // cell-order position of the Gaussian
-    vals[s] = (uint32_t)s;         // entry; its active pixel is s / K
+    vals[s] = (uint32_t)s;         // entry; its active pixel is s % n_act
 }
 
 __global__ void k_iperm(const uint32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ iperm) {
@@ -519,38 +536,63 @@ __global__ void k_iperm(const uint32_t* __restrict__ perm, int64_t n, int32_t* _
     if (s < n) iperm[perm[s]] = (int32_t)s;
 }
 
-// Internal lists of the active pixels: cell-order positions instead of ids.
-__global__ void k_lists_internal(const int32_t* __restrict__ nbr, const int32_t* __restrict__ act, int64_t n,
+// Internal lists of the active pixels, entry t of active pixel a at
+// lint[t * n_act + a] (coalesced over a wave's pixels), holding cell-order
+// positions instead of ids.
+__global__ void k_lists_internal(const int32_t* __restrict__ nbr, const int32_t* __restrict__ act, int64_t n_act,
                                  int32_t K, const int32_t* __restrict__ iperm, int32_t* __restrict__ lint) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const int64_t a = e / K;
-    lint[e] = iperm[nbr[(int64_t)act[a] * K + (e - a * K)]];
+    if (e >= n_act * K) return;
+    const int64_t t = e / n_act, a = e - t * n_act;
+    lint[e] = iperm[nbr[(int64_t)act[a] * K + t]];
 }
 
-// pixels with a list: flags, compaction (after an exclusive scan of the
-// flags) and each slice's range
-__global__ void k_act_flags(const int32_t* __restrict__ nbr, int64_t P, int32_t K, int* __restrict__ flag,
+// Pixels with a list, in 8x8-patch order: position q of slice i enumerates
+// its pixels padded to whole patches (patch row-major, then row-major inside
+// the patch), so that consecutive listed pixels -- the lanes of a wave --
+// form compact patches whose neighbour sets overlap.  qoff [M+1]: first
+// position of each slice.
+__device__ inline int64_t patch_pixel(const SliceGeo* geo, const int64_t* qoff, int32_t m, int64_t q, int& slice) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (qoff[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    slice = lo;
+    const SliceGeo& sg = geo[lo];
+    const int64_t l = q - qoff[lo];
+    const int ntx8 = (sg.W + 7) >> 3;
+    const int64_t pi = l >> 6;
+    const int w = (int)(l & 63);
+    const int y = (int)(pi / ntx8) * 8 + (w >> 3), x = (int)(pi % ntx8) * 8 + (w & 7);
+    return (y < sg.H && x < sg.W) ? sg.pix_off + (int64_t)y * sg.W + x : -1;
+}
+
+__global__ void k_act_flags(const int32_t* __restrict__ nbr, const SliceGeo* __restrict__ geo,
+                            const int64_t* __restrict__ qoff, int32_t m, int64_t Q, int32_t K, int* __restrict__ flag,
                             uint8_t* __restrict__ active) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    const int f = nbr[p * K] >= 0 ? 1 : 0;
-    flag[p] = f;
-    active[p] = (uint8_t)f;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    int slice;
+    const int64_t p = patch_pixel(geo, qoff, m, q, slice);
+    const int f = (p >= 0 && nbr[p * K] >= 0) ? 1 : 0;
+    flag[q] = f;
+    if (p >= 0) active[p] = (uint8_t)f;
 }
 
-__global__ void k_act_compact(const int* __restrict__ flag, const int* __restrict__ off, int64_t P,
-                              int32_t* __restrict__ act) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    if (flag[p]) act[off[p]] = (int32_t)p;
+__global__ void k_act_compact(const int* __restrict__ flag, const int* __restrict__ off, const SliceGeo* __restrict__ geo,
+                              const int64_t* __restrict__ qoff, int32_t m, int64_t Q, int32_t* __restrict__ act) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q || !flag[q]) return;
+    int slice;
+    act[off[q]] = (int32_t)patch_pixel(geo, qoff, m, q, slice);
 }
 
-__global__ void k_act_offsets(const int* __restrict__ off, const SliceGeo* __restrict__ geo, int32_t m,
+__global__ void k_act_offsets(const int* __restrict__ off, const int64_t* __restrict__ qoff, int32_t m,
                               const long long* __restrict__ total, int32_t* __restrict__ act_off) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > m) return;
-    act_off[i] = i < m ? off[geo[i].pix_off] : (int32_t)total[0];
+    act_off[i] = i < m ? off[qoff[i]] : (int32_t)total[0];
 }
 
 // --------------------------------------------------------------------------
@@ -563,6 +605,7 @@ struct TopkFwdArgs {
     const int32_t* nbr;       // internal lists [n_act, K] (cell-order positions)
     const int32_t* act;       // pixels with a list, increasing
     const int32_t* act_off;   // [M+1] each slice's range in act
+    int64_t n_act;
     int32_t K;
     float delta;
     int32_t loss_kind;
@@ -627,10 +670,10 @@ __global__ __launch_bounds__(kBlock) void k_topk_forward(TopkFwdArgs a, const fl
         const int r = (int)(q / sg.W), k = (int)(q - (int64_t)r * sg.W);
         float x, y, z, ux, uy;
         pixel_world(sg, ts, r, k, x, y, z, ux, uy);
-        const int32_t* nb = a.nbr + (int64_t)qa * a.K;
+        const int32_t* nb = a.nbr + qa;
         float num = 0.f, den = 0.f;
         for (int t = 0; t < a.K; ++t) {
-            const TopkGauss g = a.gauss[nb[t]];
+            const TopkGauss g = a.gauss[nb[(int64_t)t * a.n_act]];
             const float S[6] = {g.b.x + ts.P[0], g.b.y + ts.P[1], g.b.z + ts.P[2],
                                 g.b.w + ts.P[3], g.c.x + ts.P[4], g.c.y + ts.P[5]};
             float wx, wy, wz;
@@ -683,9 +726,12 @@ __global__ __launch_bounds__(kBlock) void k_topk_loss(const float* __restrict__ 
 // --------------------------------------------------------------------------
 constexpr int kPoseTerms = 13;   // (R u) x dx (3), dx (3), G_P (6), d sigma (1)
 
+// Also leaves, per listed pixel, what the Gaussian pass needs: pxw = (x, gs)
+// with gs = g sigma / (D + delta) (0: skip), pyd = (N / (D + delta), slice).
 __global__ __launch_bounds__(kBlock) void k_topk_pose_pass(TopkFwdArgs a, const float* __restrict__ grad_pred,
                                                            const float2* __restrict__ state,
-                                                           float* __restrict__ partial, int32_t blocks_x) {
+                                                           float* __restrict__ partial, int32_t blocks_x,
+                                                           float4* __restrict__ pxw, float2* __restrict__ pyd) {
     __shared__ float s_red[kPoseTerms][kBlock / 64];
     const int i = blockIdx.y;
     const SliceGeo& sg = a.geo[i];
@@ -696,7 +742,6 @@ __global__ __launch_bounds__(kBlock) void k_topk_pose_pass(TopkFwdArgs a, const 
     for (int qa = a0 + blockIdx.x * kBlock + threadIdx.x; qa < a1; qa += blocks_x * kBlock) {
         const int64_t p = a.act[qa];
         const float gy = grad_pred[p];
-        if (gy == 0.f) continue;
         const int64_t q = p - sg.pix_off;
         const int r = (int)(q / sg.W), k = (int)(q - (int64_t)r * sg.W);
         float x, y, z, ux, uy;
@@ -704,11 +749,14 @@ __global__ __launch_bounds__(kBlock) void k_topk_pose_pass(TopkFwdArgs a, const 
         const float2 st = state[qa];
         const float yn = st.x, inv_dd = 1.f / st.y;
         const float gs = gy * ts.sigma * inv_dd;
-        const int32_t* nb = a.nbr + (int64_t)qa * a.K;
+        pxw[qa] = make_float4(x, y, z, gs);
+        pyd[qa] = make_float2(yn, __int_as_float(i));
+        if (gy == 0.f) continue;
+        const int32_t* nb = a.nbr + qa;
         float dx0 = 0.f, dx1 = 0.f, dx2 = 0.f;
         float G[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         for (int t = 0; t < a.K; ++t) {
-            const TopkGauss g = a.gauss[nb[t]];
+            const TopkGauss g = a.gauss[nb[(int64_t)t * a.n_act]];
             const float S[6] = {g.b.x + ts.P[0], g.b.y + ts.P[1], g.b.z + ts.P[2],
                                 g.b.w + ts.P[3], g.c.x + ts.P[4], g.c.y + ts.P[5]};
             float wx, wy, wz;
@@ -778,19 +826,10 @@ __global__ void k_topk_pose_reduce(const float* __restrict__ partial, int32_t bl
     if (g_sigma) g_sigma[i] = s[12];
 }
 
-__device__ inline int slice_of_pixel(const SliceGeo* geo, int32_t m, int64_t p) {
-    int lo = 0, hi = m - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (geo[mid].pix_off <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // One wave per Gaussian over the pixels whose lists hold it.
 __global__ __launch_bounds__(kBlock) void k_topk_gauss_pass(
-        TopkFwdArgs a, int32_t m, const int2* __restrict__ granges, const uint32_t* __restrict__ gpix,
-        const uint32_t* __restrict__ perm, const float* __restrict__ grad_pred, const float2* __restrict__ state,
+        TopkFwdArgs a, const int2* __restrict__ granges, const uint32_t* __restrict__ gpix,
+        const uint32_t* __restrict__ perm, const float4* __restrict__ pxw, const float2* __restrict__ pyd,
         const float* __restrict__ log_scale, const float* __restrict__ quat, int64_t n_gauss,
         float* __restrict__ g_mean, float* __restrict__ g_ls, float* __restrict__ g_quat,
         float* __restrict__ g_amp) {
@@ -803,25 +842,17 @@ __global__ __launch_bounds__(kBlock) void k_topk_gauss_pass(
     float acc[10];
     for (int e = 0; e < 10; ++e) acc[e] = 0.f;
     for (int s = rg.x + lane; s < rg.y; s += 64) {
-        const int64_t ai = gpix[s] / (uint32_t)a.K;
-        const int64_t p = a.act[ai];
-        const float gy = grad_pred[p];
-        if (gy == 0.f) continue;
-        const int i = slice_of_pixel(a.geo, m, p);
-        const SliceGeo& sg = a.geo[i];
-        const TopkSlice& ts = a.slices[i];
-        const int64_t q = p - sg.pix_off;
-        const int r = (int)(q / sg.W), k = (int)(q - (int64_t)r * sg.W);
-        float x, y, z, ux, uy;
-        pixel_world(sg, ts, r, k, x, y, z, ux, uy);
-        const float S[6] = {g.b.x + ts.P[0], g.b.y + ts.P[1], g.b.z + ts.P[2],
-                            g.b.w + ts.P[3], g.c.x + ts.P[4], g.c.y + ts.P[5]};
+        const int64_t ai = (int64_t)gpix[s] % a.n_act;
+        const float4 xw = pxw[ai];
+        const float gs = xw.w;
+        if (gs == 0.f) continue;
+        const float2 yd = pyd[ai];
+        const float* P = a.slices[__float_as_int(yd.y)].P;
+        const float S[6] = {g.b.x + P[0], g.b.y + P[1], g.b.z + P[2], g.b.w + P[3], g.c.x + P[4], g.c.y + P[5]};
         float wx, wy, wz;
-        const float e = pair_eval(S, x - g.a.x, y - g.a.y, z - g.a.z, wx, wy, wz);
-        const float2 st = state[ai];
-        const float gs = gy * ts.sigma / st.y;
+        const float e = pair_eval(S, xw.x - g.a.x, xw.y - g.a.y, xw.z - g.a.z, wx, wy, wz);
         acc[0] += gs * e;                       // d c
-        const float ge = gs * (g.a.w - st.x) * e;
+        const float ge = gs * (g.a.w - yd.x) * e;
         acc[1] += ge * wx;                      // d mu
         acc[2] += ge * wy;
         acc[3] += ge * wz;
@@ -925,12 +956,14 @@ hipError_t launch_topk_cells(const float* mean, const GaussBlock* blocks, int32_
     return hipGetLastError();
 }
 
+int32_t topk_knn_tiles(int32_t H, int32_t W) { return ((W + kKnnSide - 1) / kKnnSide) * ((H + kKnnSide - 1) / kKnnSide); }
+
 hipError_t launch_topk_knn(const SliceGeo* geo, const TopkSlice* slices, const TopkGrid* grid, const int2* cells,
                            const float4* smean, const float* mask, int32_t m, int32_t max_tiles, int32_t K,
                            int32_t* nbr, int* status, hipStream_t st) {
     if (m <= 0 || max_tiles <= 0) return hipSuccess;
     KnnArgs a{geo, slices, grid, cells, smean, mask, K, nbr, status};
-    hipLaunchKernelGGL(k_knn, dim3(max_tiles, m), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_knn, dim3(max_tiles, m), dim3(kKnnThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -940,7 +973,7 @@ hipError_t launch_topk_internal(const int32_t* nbr, const int32_t* act, int64_t 
         hipLaunchKernelGGL(k_iperm, dim3((unsigned)((n_gauss + 255) / 256)), dim3(256), 0, st, perm, n_gauss, iperm);
     const int64_t n = n_act * K;
     if (n > 0)
-        hipLaunchKernelGGL(k_lists_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nbr, act, n, K,
+        hipLaunchKernelGGL(k_lists_internal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nbr, act, n_act, K,
                            (const int32_t*)iperm, lint);
     return hipGetLastError();
 }
@@ -966,16 +999,17 @@ hipError_t launch_topk_inverse(const int32_t* lint, int64_t n_pairs, int64_t n_g
 
 int32_t topk_blocks_x(int32_t max_hw) { return std::max(1, std::min((max_hw + kBlock - 1) / kBlock, 64)); }
 
-hipError_t launch_topk_active(const int32_t* nbr, int64_t P, int32_t K, const SliceGeo* geo, int32_t m, int* flag,
-                              int* off, uint8_t* active, int32_t* act, int32_t* act_off, long long* total,
-                              void* scan_tmp, hipStream_t st) {
-    if (P <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((P + 255) / 256);
-    hipLaunchKernelGGL(k_act_flags, dim3(nb), dim3(256), 0, st, nbr, P, K, flag, active);
-    hipError_t e = launch_scan_int(flag, off, P, total, scan_tmp, st);
+hipError_t launch_topk_active(const int32_t* nbr, int32_t K, const SliceGeo* geo, const int64_t* qoff, int32_t m,
+                              int64_t Q, int* flag, int* off, uint8_t* active, int32_t* act, int32_t* act_off,
+                              long long* total, void* scan_tmp, hipStream_t st) {
+    if (Q <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((Q + 255) / 256);
+    hipLaunchKernelGGL(k_act_flags, dim3(nb), dim3(256), 0, st, nbr, geo, qoff, m, Q, K, flag, active);
+    hipError_t e = launch_scan_int(flag, off, Q, total, scan_tmp, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_act_compact, dim3(nb), dim3(256), 0, st, (const int*)flag, (const int*)off, P, act);
-    hipLaunchKernelGGL(k_act_offsets, dim3((m + 1 + 63) / 64), dim3(64), 0, st, (const int*)off, geo, m,
+    hipLaunchKernelGGL(k_act_compact, dim3(nb), dim3(256), 0, st, (const int*)flag, (const int*)off, geo, qoff, m, Q,
+                       act);
+    hipLaunchKernelGGL(k_act_offsets, dim3((m + 1 + 63) / 64), dim3(64), 0, st, (const int*)off, qoff, m,
                        (const long long*)total, act_off);
     return hipGetLastError();
 }
@@ -986,11 +1020,11 @@ size_t topk_loss_partial_floats(int32_t m, int32_t max_hw, int32_t max_act) {
 
 hipError_t launch_topk_forward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, const uint8_t* active,
-                               int32_t K, float delta, int32_t loss_kind, int32_t m, int32_t max_hw, int32_t max_act,
+                               int64_t n_act, int32_t K, float delta, int32_t loss_kind, int32_t m, int32_t max_hw, int32_t max_act,
                                const float* target, const float* mask, const float* msum, float* pred, float2* state,
                                float* grad, float* partial, float* loss, hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, K, delta, loss_kind};
+    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, n_act, K, delta, loss_kind};
     const int bx = topk_blocks_x(max_hw), ba = topk_blocks_x(max_act);
     const bool want = target && loss;
     hipLaunchKernelGGL(k_topk_inactive, dim3(bx, m), dim3(kBlock), 0, st, geo, active, loss_kind, target, mask, msum,
@@ -1008,23 +1042,24 @@ size_t topk_pose_partial_floats(int32_t m, int32_t max_act) {
 }
 
 hipError_t launch_topk_backward(const SliceGeo* geo, const TopkSlice* slices, const TopkGauss* gauss,
-                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, int32_t K, int32_t m,
-                                int32_t max_act, const float* grad_pred, const float2* state, const int2* granges,
+                                const int32_t* nbr, const int32_t* act, const int32_t* act_off, int64_t n_act,
+                                int32_t K, int32_t m, int32_t max_act, const float* grad_pred, const float2* state, const int2* granges,
                                 const uint32_t* gpix, const uint32_t* perm, const float* log_scale, const float* quat,
                                 int64_t n_gauss,
                                 float* g_mean, float* g_ls, float* g_quat, float* g_amp, float* partial,
-                                float* pose_acc, float* g_sigma, hipStream_t st) {
-    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, K, 0.f, 0};
+                                float* pose_acc, float* g_sigma, float4* pxw, float2* pyd, hipStream_t st) {
+    TopkFwdArgs a{geo, slices, gauss, nbr, act, act_off, n_act, K, 0.f, 0};
     if (m > 0) {
         const int bx = topk_blocks_x(max_act);
-        hipLaunchKernelGGL(k_topk_pose_pass, dim3(bx, m), dim3(kBlock), 0, st, a, grad_pred, state, partial, bx);
+        hipLaunchKernelGGL(k_topk_pose_pass, dim3(bx, m), dim3(kBlock), 0, st, a, grad_pred, state, partial, bx, pxw,
+                           pyd);
         hipLaunchKernelGGL(k_topk_pose_reduce, dim3((m + 63) / 64), dim3(64), 0, st, (const float*)partial, bx,
                            slices, m, pose_acc, g_sigma);
     }
     if (n_gauss > 0)
         hipLaunchKernelGGL(k_topk_gauss_pass, dim3((unsigned)((n_gauss * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           st, a, m, granges, gpix, perm, grad_pred, state, log_scale, quat, n_gauss, g_mean, g_ls,
-                           g_quat, g_amp);
+                           st, a, granges, gpix, perm, (const float4*)pxw, (const float2*)pyd, log_scale, quat,
+                           n_gauss, g_mean, g_ls, g_quat, g_amp);
     return hipGetLastError();
 }
 
