@@ -58,9 +58,12 @@ class VolumeProbe:
 
     ``gt`` and ``mask`` are flat arrays over the grid (z-major, then rows,
     then columns).  ``cutoff`` is the footprint radius used for the read-out
-    (the fitted model's own window by default)."""
+    (the fitted model's own window by default).  ``model="topk"`` reads the
+    volume out with the normalised Top-K model instead (K = ``topk_k``
+    nearest means of every voxel inside the mask, rebuilt per read-out)."""
 
-    def __init__(self, n_gauss, shape, spacing, centre, gt, mask, device=0, cutoff=3.0, tile=16):
+    def __init__(self, n_gauss, shape, spacing, centre, gt, mask, device=0, cutoff=3.0, tile=16, model="windowed",
+                 topk_k=50, topk_delta=1e-6):
         import torch
         self.grid = volume_grid(shape, spacing, centre)
         g = self.grid
@@ -78,16 +81,27 @@ class VolumeProbe:
         self.pose = torch.zeros((self.geom.n_slices, 6), dtype=torch.float32, device=dev)
         self.vol = torch.empty(self.P, dtype=torch.float32, device=dev)
         self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self.model, self.topk_k, self.topk_delta = model, topk_k, topk_delta
+        if model == "topk":
+            self.nbr = torch.empty(self.P, topk_k, dtype=torch.int32, device=dev)
+
+    def _forward(self, mean, log_scale, quat, amp, with_loss):
+        tgt = (self.gt, self.mask) if with_loss else (None, None)
+        if self.model == "topk":
+            self.ctx.svr_topk_build(mean, self.pose, self.topk_k, self.nbr, mask=self.mask)
+            self.ctx.svr_topk_forward(mean, log_scale, quat, amp, self.pose, self.nbr, self.topk_k, self.topk_delta,
+                                      self.vol, *tgt, loss=self.loss if with_loss else None)
+        else:
+            self.ctx.svr_project_bin(mean, log_scale, quat, amp, self.pose)
+            self.ctx.svr_forward(self.vol, *tgt, loss=self.loss if with_loss else None)
 
     def render(self, mean, log_scale, quat, amp):
         """The volume at the grid voxels (device tensor, flat)."""
-        self.ctx.svr_project_bin(mean, log_scale, quat, amp, self.pose)
-        self.ctx.svr_forward(self.vol)
+        self._forward(mean, log_scale, quat, amp, False)
         return self.vol
 
     def psnr(self, mean, log_scale, quat, amp):
-        self.ctx.svr_project_bin(mean, log_scale, quat, amp, self.pose)
-        self.ctx.svr_forward(self.vol, self.gt, self.mask, loss=self.loss)
+        self._forward(mean, log_scale, quat, amp, True)
         mse = float(self.loss.item())
         return 10.0 * math.log10(self.max_gt ** 2 / max(mse, 1e-30))
 
@@ -107,7 +121,7 @@ class FitResult:
 
 def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
         psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-        outliers=False, outlier_lr=1e-3):
+        outliers=False, outlier_lr=1e-3, model="windowed", topk_k=50, topk_refresh=50, topk_delta=1e-6):
     """Runs n_iter fitting iterations of project_bin + forward + backward +
     AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
     covers the iterations only; the PSNR read-out every ``psnr_every``
@@ -120,12 +134,18 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     ``outliers`` adds the per-slice intensity scalar sigma_i and aleatoric
     weight omega_i = exp(rho_i) of Sec. 2.4 (svr_slice_loss), both learnt
     with AdamW at ``outlier_lr``; they are returned in the result as
-    ``sigma`` and ``log_omega`` (host arrays)."""
+    ``sigma`` and ``log_omega`` (host arrays).  ``model``: "windowed" (the
+    exact-amplitude model with 3-sigma footprints) or "topk" (the paper's
+    normalised Top-K model, Eqs. 2 and 5, with K = ``topk_k`` neighbour lists
+    rebuilt every ``topk_refresh`` iterations for the masked pixels; the
+    rebuilds are timed with the iterations)."""
     import torch
     if objective not in ("mse", "l1+reg"):
         raise ValueError(f"unknown objective {objective}")
     if reg_reading not in ("sum", "mean"):
         raise ValueError(f"unknown reg_reading {reg_reading}")
+    if model not in ("windowed", "topk"):
+        raise ValueError(f"unknown model {model}")
     ctx.svr_set_loss(svr.SVR_LOSS_L1 if objective == "l1+reg" else svr.SVR_LOSS_MSE)
     N, M = params.N, params.M
     lam = reg_lambda * float(mask.sum().item()) / N if reg_reading == "mean" else reg_lambda
@@ -139,6 +159,8 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     loss = torch.empty(1, device=dev)
     res = FitResult()
     elapsed = 0.0
+    if model == "topk":
+        nbr = torch.empty(P, topk_k, dtype=torch.int32, device=dev)
     if outliers:
         sig = torch.ones(M, device=dev)
         rho = torch.zeros(M, device=dev)
@@ -149,14 +171,27 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     for it in range(1, n_iter + 1):
         t0 = time.perf_counter()
         scale = gamma ** ((it - 1) // step_lr)
-        ctx.svr_project_bin(*params.views())
+        pv = params.views()
+        if model == "topk":
+            if (it - 1) % topk_refresh == 0:
+                ctx.svr_topk_build(pv[0], pv[4], topk_k, nbr, mask=mask)
+            if outliers:
+                ctx.svr_topk_forward(*pv, nbr, topk_k, topk_delta, pred)
+            else:
+                ctx.svr_topk_forward(*pv, nbr, topk_k, topk_delta, pred, target, mask, loss=loss, grad_pred=gpred)
+        else:
+            ctx.svr_project_bin(*pv)
+            if outliers:
+                ctx.svr_forward(pred)
+            else:
+                ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
         if outliers:
-            ctx.svr_forward(pred)
             ctx.svr_slice_loss(pred, target, mask, sig, rho, loss=loss, grad_pred=gpred, g_sigma=g_sig,
                                g_log_omega=g_rho)
+        if model == "topk":
+            ctx.svr_topk_backward(*pv, nbr, topk_k, gpred, *grad.views())
         else:
-            ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
-        ctx.svr_backward(gpred, *grad.views())
+            ctx.svr_backward(gpred, *grad.views())
         if objective == "l1+reg":
             ctx.svr_scale_regularizer(params.views()[1], lam, s_target, grad.views()[1], loss)
         ctx.svr_step(params.views(), grad.views(), m, v, [x * scale for x in lr], it)
@@ -183,7 +218,8 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     return res
 
 
-def adaptive_init(ctx, target, mask, n_gauss, n_slices, lambda_init=0.0, seed=0, scale=1.6, pose=None):
+def adaptive_init(ctx, target, mask, n_gauss, n_slices, lambda_init=0.0, seed=0, scale=1.6, pose=None,
+                  rescale=True):
     """Content-adaptive initialisation (Sec. 2.5, Eq. 6) for the context's
     geometry: means drawn by svr_init_means from the observed slices
     (lambda_init = 0 favours edges only, 1 is uniform over the mask),
@@ -191,8 +227,9 @@ def adaptive_init(ctx, target, mask, n_gauss, n_slices, lambda_init=0.0, seed=0,
     rotations, and amplitudes equal to the sampled intensities times the one
     factor that best fits (least squares over the mask) the slices rendered
     from them to the observed slices; that scalar is computed on the host
-    from one rendered pass.  Returns (svr.Params on the target's device, that
-    factor)."""
+    from one rendered pass (skipped with ``rescale=False``, for the normalised
+    model whose amplitudes are intensities).  Returns (svr.Params on the
+    target's device, that factor)."""
     import torch
     from . import synth
     dev = target.device
@@ -204,6 +241,8 @@ def adaptive_init(ctx, target, mask, n_gauss, n_slices, lambda_init=0.0, seed=0,
     ctx.svr_init_means(target, mask, pz, lambda_init, u, mean, None, amp)
     log_scale.fill_(math.log(scale))
     quat[:, 0] = 1.0
+    if not rescale:
+        return p, 1.0
     pred = torch.empty(ctx.n_pixels, dtype=torch.float32, device=dev)
     ctx.svr_project_bin(*p.views())
     ctx.svr_forward(pred)
@@ -240,7 +279,7 @@ def amplitude_lr(lr, kappa):
 
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
                      known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
-                     init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-3):
+                     init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-3, model="windowed"):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm,
     against slices simulated from the phantom itself (piecewise-constant
@@ -257,7 +296,10 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     it), the paper's PSF ablation.  ``corrupt`` is the fraction of slices
     corrupted after acquisition (half of them with their intensity scaled
     by 1.5, half replaced by noise of the same mean); ``outliers`` fits the
-    per-slice sigma_i and omega_i of Sec. 2.4 as well.  Returns the FitResult, with the
+    per-slice sigma_i and omega_i of Sec. 2.4 as well.  ``model="topk"`` fits
+    and reads out the paper's normalised Top-K model (K = 50, lists rebuilt
+    every 50 iterations); its amplitudes are intensities, so they start at
+    the sampled (or generating) intensities and use the paper's rates.  Returns the FitResult, with the
     PSNR of the generating mixture itself (the representation's ceiling
     against the phantom) in ``gt_psnr``."""
     import torch
@@ -281,7 +323,7 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     c = voxel_centres(shape, h)
     gt = synth.head_intensity(c, axes) * synth.head_bias(c, prob.extra["bias"], axes)
     vmask = (np.linalg.norm(c / axes[None, :], axis=1) <= 1.0).astype(np.float32)
-    probe = VolumeProbe(prob.n_gauss, shape, h, (0, 0, 0), gt, vmask, device=device, tile=tile)
+    probe = VolumeProbe(prob.n_gauss, shape, h, (0, 0, 0), gt, vmask, device=device, tile=tile, model=model)
     ctx = svr.Context(device)
     if init not in ("jitter", "adaptive", "uniform"):
         raise ValueError(f"unknown init {init}")
@@ -294,24 +336,29 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     ctx.svr_set_geometry(fit_geom)
     dev = torch.device("cuda", device)
     pose0 = prob.pose if known_poses else np.zeros((prob.n_slices, 6), np.float32)
+    topk = model == "topk"
+    # intensity at the generating means; the windowed model's amplitude is
+    # intensity x kappa, the normalised model's is the intensity itself
+    inten = (synth.head_intensity(prob.mean.astype(np.float64), axes) *
+             synth.head_bias(prob.mean.astype(np.float64), prob.extra["bias"], axes)).astype(np.float32)
     if init == "jitter":
         rng = np.random.default_rng(seed + 2)
         mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)
-        amp = np.full_like(prob.amp, prob.amp.mean())
+        amp = np.full_like(prob.amp, inten.mean() if topk else prob.amp.mean())
         params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, pose0)
     else:
         params, kappa_init = adaptive_init(ctx, torch.as_tensor(target, device=dev),
                                            torch.as_tensor(prob.mask, device=dev), prob.n_gauss, prob.n_slices,
                                            0.0 if init == "adaptive" else 1.0, seed + 2, s_target,
-                                           torch.as_tensor(pose0, device=dev))
-    # amplitude = intensity x kappa (generating mixture, or the init's factor)
-    inten = synth.head_intensity(prob.mean.astype(np.float64), axes) * \
-        synth.head_bias(prob.mean.astype(np.float64), prob.extra["bias"], axes)
-    kappa = float(np.median(prob.amp / np.maximum(inten, 1e-6))) if init == "jitter" else kappa_init
+                                           torch.as_tensor(pose0, device=dev), rescale=not topk)
+    if topk:
+        kappa = 1.0
+    else:
+        kappa = float(np.median(prob.amp / np.maximum(inten, 1e-6))) if init == "jitter" else kappa_init
     lr = amplitude_lr(PAPER_LR, kappa) if scale_amp_lr else PAPER_LR
     if known_poses:
         lr = lr[:4] + (0.0, 0.0)
-    gt = svr.Params.from_arrays(*prob.params(), prob.pose)
+    gt = svr.Params.from_arrays(prob.mean, prob.log_scale, prob.quat, inten if topk else prob.amp, prob.pose)
     gt_psnr = probe.psnr(*gt.views()[:4])
     del gt
     p0 = probe.psnr(*params.views()[:4])
@@ -322,7 +369,7 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
               lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
-              s_target=s_target, reg_reading=reg_reading, outliers=outliers, outlier_lr=outlier_lr,
+              s_target=s_target, reg_reading=reg_reading, outliers=outliers, outlier_lr=outlier_lr, model=model,
               callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None)
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
@@ -355,12 +402,14 @@ def main(argv=None):
     ap.add_argument("--corrupt", type=float, default=0.0, help="fraction of corrupted slices")
     ap.add_argument("--outliers", action="store_true", help="fit the per-slice sigma_i and omega_i")
     ap.add_argument("--outlier-lr", type=float, default=1e-3, help="AdamW rate of sigma_i and log omega_i")
+    ap.add_argument("--model", choices=("windowed", "topk"), default="windowed",
+                    help="windowed: exact amplitude, 3-sigma footprints; topk: the paper's normalised Top-K model")
     a = ap.parse_args(argv)
     res = head_convergence(a.iters, a.psnr_every, log=lambda s: print(s, flush=True),
                            scale_amp_lr=not a.paper_amp_lr, known_poses=a.known_poses, objective=a.objective,
                            reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading,
                            init=a.init, psf=not a.no_psf, corrupt=a.corrupt, outliers=a.outliers,
-                           outlier_lr=a.outlier_lr)
+                           outlier_lr=a.outlier_lr, model=a.model)
     extra = {}
     if a.outliers:
         bad = np.asarray(res.corrupted, np.int64)
@@ -375,7 +424,7 @@ def main(argv=None):
     print(json.dumps(dict(run="head convergence", iters=res.iters[-1] if res.iters else 0, **extra,
                           known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
                           reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, corrupt=a.corrupt,
-                          outliers=a.outliers, outlier_lr=a.outlier_lr, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
+                          outliers=a.outliers, outlier_lr=a.outlier_lr, model=a.model, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,
                           curve=[[i, round(t, 3), round(p, 3)] for i, t, p in zip(res.iters, res.times, res.psnr)])),
