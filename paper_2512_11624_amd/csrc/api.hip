@@ -136,6 +136,7 @@ struct svr_ctx {
     int64_t n_rec = 0, n_inst = 0, n_cand = 0;
     const uint32_t* sorted_vals = nullptr;
     const uint32_t* sorted_idx = nullptr;
+    const uint32_t* sorted_keys = nullptr;
     svr_params params{};
     bool count_pairs = false;
     bool incut_pending = false;
@@ -373,6 +374,8 @@ RenderArgs render_args(svr_ctx* c) {
     a.ranges = c->d_ranges.p;
     a.inst_rec = c->sorted_vals;
     a.inst_idx = c->sorted_idx;
+    a.inst_key = c->sorted_keys;
+    a.n_inst = c->n_inst;
     a.rec = c->d_rec.p;
     a.tile_order = c->cfg.persistent ? c->tile_order : nullptr;
     a.n_tiles = c->n_tiles;
@@ -468,6 +471,7 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     const uint32_t* sk = alt ? c->d_keys2.p : c->d_keys.p;
     c->sorted_vals = alt ? c->d_vals2.p : c->d_vals.p;
     c->sorted_idx = alt ? c->d_idx2.p : c->d_idx.p;
+    c->sorted_keys = sk;
     {
         StageScope sc(c, ST_TILE_RANGES);
         HIPCHK(c, launch_tile_ranges(sk, ninst, c->d_ranges.p, c->n_tiles, st));
@@ -754,7 +758,7 @@ int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, co
     RenderArgs ra = render_args(c);
     {
         StageScope sc(c, ST_BACKWARD);
-        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_inst_grad.p, c->d_work.p, st));
+        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_inst_grad.p, st));
     }
     ProjectArgs pa = project_args(c);
     {

@@ -14,11 +14,12 @@
 // and walks its record's footprint box inside the tile, accumulating into an
 // LDS pixel tile with ds_add_f32; only box pixels are evaluated.
 //
-// Adjoint (record per lane): the tile's upstream gradients are staged in LDS;
-// each lane owns one instance and walks the pixels of its record's footprint
-// box inside the tile, accumulating the seven moment sums it needs in
-// registers (no cross-lane reduction), and writes them to the instance's
-// emission slot (no atomics).
+// Adjoint (record per lane): a workgroup takes a fixed chunk of 256 instances
+// of the tile-ordered list and stages the upstream gradients of the chunk's
+// tiles in LDS; each lane owns one instance and walks the pixels of its
+// record's footprint box inside its tile, accumulating the seven moment sums
+// it needs in registers (no cross-lane reduction), and writes them to the
+// instance's emission slot (no atomics).
 #include "svr_internal.h"
 
 namespace svr {
@@ -626,149 +627,193 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
     }
 }
 
-// Adjoint, record per lane: the tile's upstream gradient is staged in LDS;
-// every lane walks one instance's box and sums, with t = g e (inside the cut):
+// Adjoint, record per lane, over fixed chunks of the sorted instance list:
+// workgroup b takes instances [256 b, 256 b + 256), which are ordered by tile
+// and may span several tiles, so every workgroup has one full round of work
+// whatever the instance count of a tile, and the grid load stays even (one
+// workgroup per tile left the chip with a long tail of busy tiles).  The
+// upstream gradients of the chunk's tiles are staged in LDS (up to KT tiles at
+// a time; a chunk over more tiles takes further passes); every lane walks one
+// instance's box and sums, with t = g e (inside the cut):
 //   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
 //   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
 // from which the gradient with respect to the stored record fields follows
 // (dz/d field, times amp ln 2).  The result goes to the instance's emission
 // slot, so no atomics are needed.  The walk is rows outer, columns inner,
 // with per-row sums folded in with dy (three accumulations per pixel instead
-// of seven).  A wave runs each loop as long as its largest trip count, so
-// each round of up to 256 instances is first ordered by (box height, box
-// width) with a counting sort in LDS, and lane j walks the j-th box: the
-// lanes of a wave then have boxes of the same shape.  Which lane walks which
-// instance changes no instance's sum, so the result stays deterministic.
+// of seven).  A wave runs each loop as long as its largest trip count, so the
+// pass's instances are first ordered by (box height, box width) with a
+// counting sort in LDS, and lane j walks the j-th box: the lanes of a wave
+// then have boxes of the same shape.  Which lane walks which instance changes
+// no instance's sum, so the result is deterministic and independent of the
+// chunking.
 template <int T, int NT>
 __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
                                                  const float* __restrict__ grad_scale,
-                                                 float4* __restrict__ inst_grad,
-                                                 int* __restrict__ work_counter) {
+                                                 float4* __restrict__ inst_grad) {
     constexpr int kB = (T + 1) * (T + 1);
-    __shared__ float s_g[T * T];
+    constexpr int KT = (1024 / (T * T)) > 0 ? 1024 / (T * T) : 1;  // tiles staged per pass (4 KB)
+    constexpr int NW = NT / 64;
+    __shared__ float s_g[KT * T * T];
     __shared__ float4 s_box[NT][2];
     __shared__ uint32_t s_slot[NT];
+    __shared__ int s_gb[NT];
     __shared__ int s_hist[kB + 1];
     __shared__ int s_perm[NT];
-    __shared__ int s_wsum[NT / 64];
-    __shared__ int s_next;
+    __shared__ int s_wsum[NW];
+    __shared__ int s_tile[NT];        // per lane, then the chunk's distinct tiles in order
+    __shared__ int2 s_org[KT];        // pass tiles: (x0 | y0 << 16, valid W | valid H << 16)
+    __shared__ long long s_base[KT];  // pass tiles: global pixel id of the tile origin
+    __shared__ int s_stride[KT];      // pass tiles: slice width
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
+    if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float scale = grad_scale ? grad_scale[0] : 1.f;
-    int iter = 0;
-    while (true) {
-        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
-        if (tile < 0) break;
-        const TileCoord tc = tile_coord(a, tile);
-        const int2 rg = a.ranges[tile];
-        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
-        __syncthreads();
-        for (int p = tid; p < T * T; p += NT) {
-            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
-            s_g[p] = (px < tc.W && py < tc.H) ? grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale : 0.f;
+
+    // tile of every lane's instance (-1: past the end, or emission padding)
+    const int64_t inst = chunk * NT + tid;
+    int tile = -1;
+    if (inst < a.n_inst) {
+        const uint32_t t = a.inst_key[inst] >> kClassBits;
+        if (t < (uint32_t)a.n_tiles) tile = (int)t;
+    }
+    s_tile[tid] = tile;
+    __syncthreads();
+    // the chunk's distinct tiles: a lane heads a run when its tile differs
+    // from the previous lane's; rslot = index of the lane's run
+    const bool head = tile >= 0 && (tid == 0 || s_tile[tid - 1] != tile);
+    const uint64_t hm = __ballot(head);
+    if (lane == 0) s_wsum[wv] = __popcll(hm);
+    __syncthreads();
+    int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
+    int nd = 0;
+    for (int q = 0; q < NW; ++q) {
+        if (q < wv) rslot += s_wsum[q];
+        nd += s_wsum[q];
+    }
+    __syncthreads();  // every lane has read s_tile[tid - 1] and s_wsum
+    if (head) s_tile[rslot] = tile;
+    for (int p0 = 0; p0 < nd; p0 += KT) {
+        const int np = min(KT, nd - p0);
+        __syncthreads();  // distinct-tile list written / previous pass done with LDS
+        if (tid < np) {
+            const TileCoord tc = tile_coord(a, s_tile[p0 + tid]);
+            s_org[tid] = make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16));
+            s_base[tid] = tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0;
+            s_stride[tid] = tc.W;
         }
-        const int n = rg.y - rg.x;
-        for (int r0 = 0; r0 < n; r0 += NT) {
-            const int cnt = min(NT, n - r0);
-            __syncthreads();
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-            __syncthreads();
-            int bucket = 0, pos = 0;
-            if (tid < cnt) {
-                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
-                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-                const bool empty = w == 0 || h == 0;
-                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-                bucket = empty ? 0 : (h * (T + 1) + w);
-                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                           ((y1 + 1) << 24)));
-                s_slot[tid] = a.inst_idx[rg.x + r0 + tid];
-                pos = atomicAdd(&s_hist[bucket], 1);
+        for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+        __syncthreads();
+        for (int q = tid; q < np * T * T; q += NT) {
+            const int sl = q / (T * T), pix = q - sl * (T * T);
+            const int2 o = s_org[sl];
+            const int px = pix % T, py = pix / T;
+            s_g[q] = (px < (o.y & 0xffff) && py < (o.y >> 16))
+                         ? grad_pred[s_base[sl] + (int64_t)py * s_stride[sl] + px] * scale
+                         : 0.f;
+        }
+        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
+        int bucket = 0, pos = 0;
+        if (act) {
+            const int2 o = s_org[rslot - p0];
+            const Record R = a.rec[a.inst_rec[inst]];
+            const LaneBox b = lane_box(R, o.x & 0xffff, o.x >> 16, (o.y & 0xffff) - 1, (o.y >> 16) - 1, tau2k);
+            const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+            const bool empty = w == 0 || h == 0;
+            const int bx0 = empty ? 0 : b.x0, bx1 = empty ? -1 : b.x1;
+            const int by0 = empty ? 0 : b.y0, by1 = empty ? -1 : b.y1;
+            bucket = empty ? 0 : (h * (T + 1) + w);
+            s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+            s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                        __int_as_float((bx0 + 1) | ((bx1 + 1) << 8) | ((by0 + 1) << 16) |
+                                                       ((by1 + 1) << 24)));
+            s_slot[tid] = a.inst_idx[inst];
+            s_gb[tid] = (rslot - p0) * T * T;
+            pos = atomicAdd(&s_hist[bucket], 1);
+        }
+        __syncthreads();
+        {   // exclusive scan of the bucket counts: thread t takes a run of
+            // ceil(kB / NT); s_hist[kB] receives the total
+            const int per = (kB + NT - 1) / NT;
+            const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+            int local = 0;
+            for (int k = kb; k < ke; ++k) local += s_hist[k];
+            int incl = local;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
             }
+            if (lane == 63) s_wsum[wv] = incl;
             __syncthreads();
-            {   // exclusive scan of the bucket counts: thread t takes a run of ceil(kB / NT)
-                const int per = (kB + NT - 1) / NT;
-                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-                int local = 0;
-                for (int k = kb; k < ke; ++k) local += s_hist[k];
-                int incl = local;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int u = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += u;
-                }
-                if (lane == 63) s_wsum[wv] = incl;
-                __syncthreads();
-                int run = incl - local;
-                for (int q = 0; q < wv; ++q) run += s_wsum[q];
-                for (int k = kb; k < ke; ++k) {
-                    const int c = s_hist[k];
-                    s_hist[k] = run;
-                    run += c;
-                }
+            int acc = incl - local;
+            for (int q = 0; q < wv; ++q) acc += s_wsum[q];
+            for (int k = kb; k < ke; ++k) {
+                const int c = s_hist[k];
+                s_hist[k] = acc;
+                acc += c;
             }
-            __syncthreads();
-            if (tid < cnt) s_perm[s_hist[bucket] + pos] = tid;
-            __syncthreads();
-            if (tid < cnt) {
-                const int q = s_perm[tid];
-                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
-                const int pk = __float_as_int(p1.w);
-                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-                const float pxl = p0.x, pyl = p0.y, bz = p0.z, am = p0.w;
-                const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
-                float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-                const int hh = (w > 0 && h > 0) ? h : 0;
-                const float dx0 = (float)bx0 - pxl;
-                const float b2a01 = 2.f * a01;
-                float dy = (float)by0 - pyl;
-                int gr = by0 * T + bx0;
-                for (int r = 0; r < hh; ++r) {
-                    const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
-                    float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
-                    int gi = gr;
-                    for (int c = 0; c < w; ++c) {
-                        const float g = s_g[gi];
-                        const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
-                        const float v = e - etau;
-                        Sa = fmaf(g, fmaxf(v, 0.f), Sa);
-                        const float t = (v > 0.f) ? g * e : 0.f;
-                        const float tx = t * dx;
-                        R0 += t;
-                        R1 += tx;
-                        R2 = fmaf(tx, dx, R2);
-                        dx += 1.f;
-                        ++gi;
-                    }
-                    S0 += R0;
-                    Sx += R1;
-                    Sxx += R2;
-                    Sy = fmaf(dy, R0, Sy);
-                    Sxy = fmaf(dy, R1, Sxy);
-                    Syy = fmaf(dy * dy, R0, Syy);
-                    dy += 1.f;
-                    gr += T;
+            if (kb < kB && ke == kB) s_hist[kB] = acc;
+        }
+        __syncthreads();
+        if (act) s_perm[s_hist[bucket] + pos] = tid;
+        __syncthreads();
+        if (tid < s_hist[kB]) {
+            const int q = s_perm[tid];
+            const float4 p0v = s_box[q][0], p1 = s_box[q][1];
+            const int pk = __float_as_int(p1.w);
+            const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+            const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+            const float pxl = p0v.x, pyl = p0v.y, bz = p0v.z, am = p0v.w;
+            const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
+            float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
+            const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+            const int hh = (w > 0 && h > 0) ? h : 0;
+            const float dx0 = (float)bx0 - pxl;
+            const float b2a01 = 2.f * a01;
+            float dy = (float)by0 - pyl;
+            int gr = s_gb[q] + by0 * T + bx0;
+            for (int r = 0; r < hh; ++r) {
+                const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
+                float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
+                int gi = gr;
+                for (int c = 0; c < w; ++c) {
+                    const float g = s_g[gi];
+                    const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
+                    const float v = e - etau;
+                    Sa = fmaf(g, fmaxf(v, 0.f), Sa);
+                    const float t = (v > 0.f) ? g * e : 0.f;
+                    const float tx = t * dx;
+                    R0 += t;
+                    R1 += tx;
+                    R2 = fmaf(tx, dx, R2);
+                    dx += 1.f;
+                    ++gi;
                 }
-                const float k2 = am * SVR_LN2;
-                float4 g0, g1;
-                g0.x = Sa;
-                g0.y = k2 * S0;
-                g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
-                g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
-                g1.x = k2 * Sxx;
-                g1.y = 2.f * k2 * Sxy;
-                g1.z = k2 * Syy;
-                g1.w = 0.f;
-                const uint32_t e_slot = s_slot[q];
-                inst_grad[2 * (int64_t)e_slot] = g0;
-                inst_grad[2 * (int64_t)e_slot + 1] = g1;
+                S0 += R0;
+                Sx += R1;
+                Sxx += R2;
+                Sy = fmaf(dy, R0, Sy);
+                Sxy = fmaf(dy, R1, Sxy);
+                Syy = fmaf(dy * dy, R0, Syy);
+                dy += 1.f;
+                gr += T;
             }
+            const float k2 = am * SVR_LN2;
+            float4 g0, g1;
+            g0.x = Sa;
+            g0.y = k2 * S0;
+            g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
+            g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
+            g1.x = k2 * Sxx;
+            g1.y = 2.f * k2 * Sxy;
+            g1.z = k2 * Syy;
+            g1.w = 0.f;
+            const uint32_t e_slot = s_slot[q];
+            inst_grad[2 * (int64_t)e_slot] = g0;
+            inst_grad[2 * (int64_t)e_slot + 1] = g1;
         }
     }
 }
@@ -971,25 +1016,23 @@ hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int3
 }
 
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           float4* inst_grad, int* work_counter, hipStream_t st) {
-    if (a.n_tiles <= 0) return hipSuccess;
-    if (a.persistent) {
-        hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
-        if (e != hipSuccess) return e;
-    }
-    // four waves per tile (one wave per tile measured slower: tiles with many
-    // instances then serialise on a single wave)
+                           float4* inst_grad, hipStream_t st) {
+    if (a.n_tiles <= 0 || a.n_inst <= 0) return hipSuccess;
+    // four waves per chunk of 256 instances (one wave per tile measured
+    // slower: tiles with many instances then serialise on a single wave)
     constexpr int NT = 256;
-    const int grid = grid_for(a, NT);
+    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    if (n_chunks > 0x7fffffffLL - 8) return hipErrorInvalidValue;
+    const int grid = (int)(((n_chunks + 7) >> 3) << 3);  // whole XCD remap
     switch (a.tile) {
         case 8:
-            hipLaunchKernelGGL((k_backward<8, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+            hipLaunchKernelGGL((k_backward<8, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         case 16:
-            hipLaunchKernelGGL((k_backward<16, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+            hipLaunchKernelGGL((k_backward<16, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         case 32:
-            hipLaunchKernelGGL((k_backward<32, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+            hipLaunchKernelGGL((k_backward<32, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         default: return hipErrorInvalidValue;
     }

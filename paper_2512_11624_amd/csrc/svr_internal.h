@@ -157,6 +157,8 @@ struct RenderArgs {
     const int2* ranges;          // [n_tiles] [start, end) into sorted instances
     const uint32_t* inst_rec;    // sorted instance -> record id
     const uint32_t* inst_idx;    // sorted instance -> emission slot
+    const uint32_t* inst_key;    // sorted instance -> key (tile << kClassBits | class)
+    int64_t n_inst;              // sorted instances (emission padding included)
     const Record* rec;
     const int32_t* tile_order;   // persistent mode: tiles by decreasing cost (or NULL)
     int32_t n_tiles;
@@ -186,7 +188,7 @@ hipError_t launch_scale_reg(const float* log_scale, int64_t n, float lambda, flo
 hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m,
                                 const float* msum, float* slice_sse, float* loss, hipStream_t st);
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           float4* inst_grad, int* work_counter, hipStream_t st);
+                           float4* inst_grad, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 struct AdamSeg {
