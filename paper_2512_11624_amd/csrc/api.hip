@@ -87,6 +87,7 @@ struct svr_ctx {
     DevBuf<int> d_work, d_fallback;
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
+    DevBuf<float> d_fwd_part;     // record-per-lane forward: two tile partials per instance chunk
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     // content-adaptive initialisation (allocated on first use)
     DevBuf<InitSlice> d_init_tab;
@@ -552,7 +553,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_fallback);
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
-        release(c->d_regpart); release(c->d_smask);
+        release(c->d_regpart); release(c->d_smask); release(c->d_fwd_part);
         release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
         release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
         release(c->d_init_gmax);
@@ -715,6 +716,8 @@ int svr_forward(svr_ctx* c, const float* target, const float* mask, float* pred,
     HIPCHK(c, ensure(c->d_partial, 1024));
     HIPCHK(c, ensure(c->d_work, 4));
     HIPCHK(c, ensure(c->d_incut, 1));
+    const size_t npart = forward_partial_floats(ra);
+    if (npart) HIPCHK(c, ensure(c->d_fwd_part, npart));
     if (want_loss) {
         StageScope sc(c, ST_MASK_SUM);
         HIPCHK(c, launch_mask_sum(mask, c->P, c->d_partial.p, c->d_msum.p, st));
@@ -727,7 +730,7 @@ int svr_forward(svr_ctx* c, const float* target, const float* mask, float* pred,
     {
         StageScope sc(c, ST_FORWARD);
         HIPCHK(c, launch_forward(ra, want_loss ? target : nullptr, mask, c->d_msum.p, pred, grad_pred,
-                                 c->d_tile_sse.p, incut, c->d_work.p, st));
+                                 c->d_tile_sse.p, incut, c->d_work.p, npart ? c->d_fwd_part.p : nullptr, st));
     }
     if (want_loss) {
         StageScope sc(c, ST_LOSS);

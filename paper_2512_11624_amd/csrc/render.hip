@@ -306,182 +306,267 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
     return b;
 }
 
-// Forward, record per lane with exact integer accumulation.  Per round of up
-// to 256 of the tile's instances: the boxes are counting-sorted by shape in
-// LDS (a wave's lanes then walk boxes of one shape), each lane walks one box
-// rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum) to
-// the pixel's int32 LDS sum with an integer LDS atomic (float LDS atomics are
-// slow on this GPU, integer ones are not).  The quantum is 2^(e - 30) with
-// 2^e above the round's sum of |a|, so no pixel's round sum can overflow and
-// the rounding error per term is below 2^-31 of that sum.  Integer sums do
-// not depend on the order of the adds; each pixel's owner thread then adds
-// the round's total to its float sum in round order, so the result is
+// Epilogue of a tile whose sums are final: pred, and with kLoss the data
+// term's gradient and the tile's loss partial tile_sse[tile].  acc holds the
+// tile's T x T sums (tile-local row major); org = (x0 | y0 << 16, valid
+// width | valid height << 16), base = global pixel id of the tile origin,
+// stride = slice width.  Called by all threads of the workgroup; s_red holds
+// a float per wave.
+template <int T, int NT, bool kLoss>
+__device__ inline void finish_tile(const RenderArgs& a, int tile, const float* acc, int2 org, int64_t base,
+                                   int stride, const float* __restrict__ target, const float* __restrict__ mask,
+                                   float inv_msum, float* __restrict__ pred, float* __restrict__ grad,
+                                   float* __restrict__ tile_sse, float* s_red) {
+    const int tid = threadIdx.x;
+    const int vw = org.y & 0xffff, vh = org.y >> 16;
+    float sq = 0.f;
+    for (int p = tid; p < T * T; p += NT) {
+        const int px = p % T, py = p / T;
+        if (px < vw && py < vh) {
+            const int64_t pi = base + (int64_t)py * stride + px;
+            const float y = acc[p];
+            pred[pi] = y;
+            if (kLoss) loss_term(a.loss_kind, mask[pi], y - target[pi], inv_msum, sq, grad ? grad + pi : nullptr);
+        }
+    }
+    if (kLoss) {
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        if ((tid & 63) == 0) s_red[tid >> 6] = sq;
+        __syncthreads();
+        if (tid == 0) {
+            float t = 0.f;
+            for (int q = 0; q < NT / 64; ++q) t += s_red[q];
+            tile_sse[tile] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Forward, record per lane with exact integer accumulation, over fixed chunks
+// of the tile-ordered instance list (the chunking of the adjoint): workgroup b
+// takes instances [256 b, 256 b + 256), which may span a few tiles.  Per pass
+// (up to KT of the chunk's tiles) the boxes are counting-sorted by shape in
+// LDS (a wave's lanes then walk boxes of one shape), and each lane walks one
+// box rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum)
+// to its tile's int32 LDS sum with an integer LDS atomic (float LDS atomics
+// are slow on this GPU, integer ones are not).  The quantum is 2^(e - 30)
+// with 2^e above the pass's sum of |a|, so no pixel's sum can overflow and
+// the rounding error per term is below 2^-31 of that sum; integer sums do not
+// depend on the order of the adds.  A tile whose instances all lie in the
+// chunk is finished here; the first and the last tile of a chunk may run on
+// into neighbouring chunks, and their sums go to the chunk's two partial
+// slots, which k_forward_finish adds in chunk order.  The result is
 // deterministic.
 template <int T, bool kLoss, bool kCount>
-__global__ __launch_bounds__(256) void k_forward_rpl(RenderArgs a, const float* __restrict__ target,
-                                                     const float* __restrict__ mask,
-                                                     const float* __restrict__ msum,
-                                                     float* __restrict__ pred, float* __restrict__ grad,
-                                                     float* __restrict__ tile_sse,
-                                                     unsigned long long* __restrict__ incut,
-                                                     int* __restrict__ work_counter) {
+__global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float* __restrict__ target,
+                                                       const float* __restrict__ mask,
+                                                       const float* __restrict__ msum,
+                                                       float* __restrict__ pred, float* __restrict__ grad,
+                                                       float* __restrict__ tile_sse,
+                                                       unsigned long long* __restrict__ incut,
+                                                       float* __restrict__ partial) {
     constexpr int NT = 256, NW = 4;
     constexpr int kB = (T + 1) * (T + 1);
-    __shared__ float s_acc[T * T];
-    __shared__ int s_iacc[T * T];
+    constexpr int KT = (1024 / (T * T)) > 0 ? 1024 / (T * T) : 1;
+    __shared__ int s_iacc[KT * T * T];  // fixed-point sums, then (in place) their float values
     __shared__ float4 s_box[NT][2];
-    __shared__ int s_hist[kB];
+    __shared__ int s_gb[NT];
+    __shared__ int s_hist[kB + 1];
     __shared__ int s_perm[NT];
     __shared__ int s_wsum[NW];
     __shared__ float s_fsum[NW];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
-    __shared__ int s_next;
+    __shared__ int s_tile[NT];
+    __shared__ int2 s_org[KT];
+    __shared__ long long s_base[KT];
+    __shared__ int s_stride[KT];
+    __shared__ int s_fin[KT];  // -1: tile finished here, else the partial slot (0 first run, 1 last run)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
+    if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
-    int iter = 0;
-    while (true) {
-        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
-        if (tile < 0) break;
-        const TileCoord tc = tile_coord(a, tile);
-        const int2 rg = a.ranges[tile];
-        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
+    float* s_facc = reinterpret_cast<float*>(s_iacc);
+
+    const int64_t inst = chunk * NT + tid;
+    int tile = -1;
+    if (inst < a.n_inst) {
+        const uint32_t t = a.inst_key[inst] >> kClassBits;
+        if (t < (uint32_t)a.n_tiles) tile = (int)t;
+    }
+    s_tile[tid] = tile;
+    __syncthreads();
+    const bool head = tile >= 0 && (tid == 0 || s_tile[tid - 1] != tile);
+    const uint64_t hm = __ballot(head);
+    if (lane == 0) s_wsum[wv] = __popcll(hm);
+    __syncthreads();
+    int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
+    int nd = 0;
+    for (int q = 0; q < NW; ++q) {
+        if (q < wv) rslot += s_wsum[q];
+        nd += s_wsum[q];
+    }
+    __syncthreads();
+    if (head) s_tile[rslot] = tile;
+    unsigned int cnt = 0;
+    for (int p0 = 0; p0 < nd; p0 += KT) {
+        const int np = min(KT, nd - p0);
         __syncthreads();
-        for (int p = tid; p < T * T; p += NT) {
-            s_acc[p] = 0.f;
-            s_iacc[p] = 0;
+        if (tid < np) {
+            const int rs = p0 + tid, t = s_tile[rs];
+            const TileCoord tc = tile_coord(a, t);
+            s_org[tid] = make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16));
+            s_base[tid] = tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0;
+            s_stride[tid] = tc.W;
+            const int2 rg = a.ranges[t];
+            const bool inside = rg.x >= chunk * NT && rg.y <= chunk * NT + NT;
+            s_fin[tid] = inside ? -1 : (rs == 0 ? 0 : 1);
         }
-        unsigned int cnt = 0;
-        const int n = rg.y - rg.x;
-        for (int r0 = 0; r0 < n; r0 += NT) {
-            const int nb = min(NT, n - r0);
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-            __syncthreads();
-            int bucket = 0, pos = 0;
-            float absa = 0.f;
-            if (tid < nb) {
-                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
-                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-                const bool empty = w == 0 || h == 0;
-                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-                bucket = empty ? 0 : (h * (T + 1) + w);
-                absa = empty ? 0.f : fabsf(b.am);
-                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                           ((y1 + 1) << 24)));
-                pos = atomicAdd(&s_hist[bucket], 1);
+        for (int q = tid; q < np * T * T; q += NT) s_iacc[q] = 0;
+        for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+        __syncthreads();
+        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
+        int bucket = 0, pos = 0;
+        float absa = 0.f;
+        if (act) {
+            const int2 o = s_org[rslot - p0];
+            const Record R = a.rec[a.inst_rec[inst]];
+            const LaneBox b = lane_box(R, o.x & 0xffff, o.x >> 16, (o.y & 0xffff) - 1, (o.y >> 16) - 1, tau2k);
+            const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+            const bool empty = w == 0 || h == 0;
+            const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+            const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+            bucket = empty ? 0 : (h * (T + 1) + w);
+            absa = empty ? 0.f : fabsf(b.am);
+            s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+            s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                        __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                       ((y1 + 1) << 24)));
+            s_gb[tid] = (rslot - p0) * T * T;
+            pos = atomicAdd(&s_hist[bucket], 1);
+        }
+        for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
+        if (lane == 0) s_fsum[wv] = absa;
+        __syncthreads();
+        const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
+        {   // exclusive scan of the bucket counts; s_hist[kB] receives the total
+            const int per = (kB + NT - 1) / NT;
+            const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+            int local = 0;
+            for (int k = kb; k < ke; ++k) local += s_hist[k];
+            int incl = local;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
             }
-            for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
-            if (lane == 0) s_fsum[wv] = absa;
+            if (lane == 63) s_wsum[wv] = incl;
             __syncthreads();
-            const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
-            {
-                const int per = (kB + NT - 1) / NT;
-                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-                int local = 0;
-                for (int k = kb; k < ke; ++k) local += s_hist[k];
-                int incl = local;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int u = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += u;
-                }
-                if (lane == 63) s_wsum[wv] = incl;
-                __syncthreads();
-                int run = incl - local;
-                for (int q = 0; q < wv; ++q) run += s_wsum[q];
-                for (int k = kb; k < ke; ++k) {
-                    const int c = s_hist[k];
-                    s_hist[k] = run;
-                    run += c;
-                }
+            int run = incl - local;
+            for (int q = 0; q < wv; ++q) run += s_wsum[q];
+            for (int k = kb; k < ke; ++k) {
+                const int c = s_hist[k];
+                s_hist[k] = run;
+                run += c;
             }
-            __syncthreads();
-            if (tid < nb) s_perm[s_hist[bucket] + pos] = tid;
-            __syncthreads();
-            // quantum: the round's sum of |a| spans 2^30 quanta
-            const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
-            const float to_q = ldexpf(1.f, 30 - ex);
-            if (tid < nb) {
-                const int q = s_perm[tid];
-                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
-                const int pk = __float_as_int(p1.w);
-                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-                const float amq = p0.w * to_q;
-                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-                const int hh = (w > 0 && h > 0) ? h : 0;
-                const float dx0 = (float)bx0 - p0.x;
-                float dy = (float)by0 - p0.y;
-                int gr = by0 * T + bx0;
-                for (int r = 0; r < hh; ++r) {
-                    const float zy = fmaf(p1.z * dy, dy, p0.z), bxl = 2.f * p1.y * dy;
-                    float dx = dx0;
-                    int gi = gr;
-                    for (int c = 0; c < w; ++c) {
-                        const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
-                        if (v > 0.f) {
-                            atomicAdd(&s_iacc[gi], __float2int_rn(amq * v));
-                            if (kCount) ++cnt;
-                        }
-                        dx += 1.f;
-                        ++gi;
+            if (kb < kB && ke == kB) s_hist[kB] = run;
+        }
+        __syncthreads();
+        if (act) s_perm[s_hist[bucket] + pos] = tid;
+        __syncthreads();
+        // quantum: the pass's sum of |a| spans 2^30 quanta
+        const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
+        const float to_q = ldexpf(1.f, 30 - ex);
+        if (tid < s_hist[kB]) {
+            const int q = s_perm[tid];
+            const float4 p0v = s_box[q][0], p1 = s_box[q][1];
+            const int pk = __float_as_int(p1.w);
+            const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+            const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+            const float amq = p0v.w * to_q;
+            const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+            const int hh = (w > 0 && h > 0) ? h : 0;
+            const float dx0 = (float)bx0 - p0v.x;
+            float dy = (float)by0 - p0v.y;
+            int gr = s_gb[q] + by0 * T + bx0;
+            for (int r = 0; r < hh; ++r) {
+                const float zy = fmaf(p1.z * dy, dy, p0v.z), bxl = 2.f * p1.y * dy;
+                float dx = dx0;
+                int gi = gr;
+                for (int c = 0; c < w; ++c) {
+                    const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
+                    if (v > 0.f) {
+                        atomicAdd(&s_iacc[gi], __float2int_rn(amq * v));
+                        if (kCount) ++cnt;
                     }
-                    dy += 1.f;
-                    gr += T;
+                    dx += 1.f;
+                    ++gi;
                 }
-            }
-            __syncthreads();
-            const float from_q = ldexpf(1.f, ex - 30);
-            for (int p = tid; p < T * T; p += NT) {
-                const int v = s_iacc[p];
-                if (v != 0) {
-                    s_acc[p] += (float)v * from_q;
-                    s_iacc[p] = 0;
-                }
+                dy += 1.f;
+                gr += T;
             }
         }
         __syncthreads();
-        float sq = 0.f;
-        for (int p = tid; p < T * T; p += NT) {
-            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
-            if (px < tc.W && py < tc.H) {
-                const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
-                const float acc = s_acc[p];
-                pred[pi] = acc;
-                if (kLoss) {
-                    const float m = mask[pi];
-                    const float r = acc - target[pi];
-                    loss_term(a.loss_kind, m, r, inv_msum, sq, grad ? grad + pi : nullptr);
-                }
-            }
-        }
-        if (kLoss || kCount) {
-            for (int o = 32; o > 0; o >>= 1) {
-                sq += __shfl_xor(sq, o, 64);
-                if (kCount) cnt += __shfl_xor(cnt, o, 64);
-            }
-            if (lane == 0) {
-                s_red[wv] = sq;
-                s_cnt[wv] = cnt;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                float t = 0.f;
-                unsigned long long c = 0;
-                for (int q = 0; q < NW; ++q) {
-                    t += s_red[q];
-                    c += s_cnt[q];
-                }
-                if (kLoss) tile_sse[tile] = t;
-                if (kCount && c) atomicAdd(incut, c);
+        const float from_q = ldexpf(1.f, ex - 30);
+        for (int q = tid; q < np * T * T; q += NT) s_facc[q] = (float)s_iacc[q] * from_q;
+        __syncthreads();
+        for (int sl = 0; sl < np; ++sl) {
+            const int fin = s_fin[sl];
+            if (fin < 0) {
+                finish_tile<T, NT, kLoss>(a, s_tile[p0 + sl], s_facc + sl * T * T, s_org[sl], s_base[sl],
+                                          s_stride[sl], target, mask, inv_msum, pred, grad, tile_sse, s_red);
+            } else {
+                float* dst = partial + ((size_t)chunk * 2 + fin) * (T * T);
+                for (int p = tid; p < T * T; p += NT) dst[p] = s_facc[sl * T * T + p];
             }
         }
     }
+    if (kCount) {
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) s_cnt[wv] = cnt;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long c = 0;
+            for (int q = 0; q < NW; ++q) c += s_cnt[q];
+            if (c) atomicAdd(incut, c);
+        }
+    }
+}
+
+// Tiles that k_forward_chunk did not finish: those without instances (sums
+// zero) and those whose instances span several chunks (sums = the chunks'
+// partial slots added in chunk order: the tile is the last run of its first
+// chunk unless it starts that chunk, and the first run of every later one).
+template <int T, bool kLoss>
+__global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const float* __restrict__ target,
+                                                        const float* __restrict__ mask,
+                                                        const float* __restrict__ msum,
+                                                        float* __restrict__ pred, float* __restrict__ grad,
+                                                        float* __restrict__ tile_sse,
+                                                        const float* __restrict__ partial) {
+    constexpr int NT = 256;
+    __shared__ float s_acc[T * T];
+    __shared__ float s_red[NT / 64];
+    const int tile = xcd_tile(blockIdx.x, a.n_tiles);
+    if (tile >= a.n_tiles) return;
+    const int2 rg = a.ranges[tile];
+    const int64_t c0 = rg.y > rg.x ? rg.x / NT : 0, c1 = rg.y > rg.x ? (rg.y - 1) / NT : -1;
+    if (rg.y > rg.x && c0 == c1) return;  // finished by its chunk
+    const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
+    for (int p = threadIdx.x; p < T * T; p += NT) {
+        float acc = 0.f;
+        for (int64_t c = c0; c <= c1; ++c) {
+            const int ps = (c == c0 && rg.x != c0 * NT) ? 1 : 0;
+            acc += partial[((size_t)c * 2 + ps) * (T * T) + p];
+        }
+        s_acc[p] = acc;
+    }
+    const TileCoord tc = tile_coord(a, tile);
+    finish_tile<T, NT, kLoss>(a, tile, s_acc, make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16)),
+                              tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0, tc.W, target, mask, inv_msum, pred, grad,
+                              tile_sse, s_red);
 }
 
 // Forward, record on lanes: a batch of the tile's records is staged in LDS
@@ -914,29 +999,49 @@ hipError_t fwd_rol_dispatch(const RenderArgs& a, const float* target, const floa
 }
 
 template <int T>
-hipError_t fwd_rpl_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
-                            float* pred, float* grad, float* tile_sse, unsigned long long* incut,
-                            int* work_counter, int grid, hipStream_t st) {
+hipError_t fwd_chunk_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
+                              float* pred, float* grad, float* tile_sse, unsigned long long* incut,
+                              float* partial, hipStream_t st) {
     const bool loss = target != nullptr;
     const bool count = incut != nullptr;
-    if (loss && count)
-        hipLaunchKernelGGL((k_forward_rpl<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
-                           pred, grad, tile_sse, incut, work_counter);
-    else if (loss)
-        hipLaunchKernelGGL((k_forward_rpl<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
-                           pred, grad, tile_sse, incut, work_counter);
-    else if (count)
-        hipLaunchKernelGGL((k_forward_rpl<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
-                           pred, grad, tile_sse, incut, work_counter);
+    constexpr int NT = 256;
+    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    if (n_chunks > 0x7fffffffLL - 8) return hipErrorInvalidValue;
+    if (n_chunks > 0) {
+        if (!partial) return hipErrorInvalidValue;
+        const int grid = (int)(((n_chunks + 7) >> 3) << 3);  // whole XCD remap
+        if (loss && count)
+            hipLaunchKernelGGL((k_forward_chunk<T, true, true>), dim3(grid), dim3(NT), 0, st, a, target, mask, msum,
+                               pred, grad, tile_sse, incut, partial);
+        else if (loss)
+            hipLaunchKernelGGL((k_forward_chunk<T, true, false>), dim3(grid), dim3(NT), 0, st, a, target, mask, msum,
+                               pred, grad, tile_sse, incut, partial);
+        else if (count)
+            hipLaunchKernelGGL((k_forward_chunk<T, false, true>), dim3(grid), dim3(NT), 0, st, a, target, mask, msum,
+                               pred, grad, tile_sse, incut, partial);
+        else
+            hipLaunchKernelGGL((k_forward_chunk<T, false, false>), dim3(grid), dim3(NT), 0, st, a, target, mask, msum,
+                               pred, grad, tile_sse, incut, partial);
+    }
+    const int tgrid = ((a.n_tiles + 7) >> 3) << 3;
+    if (loss)
+        hipLaunchKernelGGL((k_forward_finish<T, true>), dim3(tgrid), dim3(NT), 0, st, a, target, mask, msum, pred,
+                           grad, tile_sse, (const float*)partial);
     else
-        hipLaunchKernelGGL((k_forward_rpl<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
-                           pred, grad, tile_sse, incut, work_counter);
+        hipLaunchKernelGGL((k_forward_finish<T, false>), dim3(tgrid), dim3(NT), 0, st, a, target, mask, msum, pred,
+                           grad, tile_sse, (const float*)partial);
     return hipGetLastError();
+}
+
+size_t forward_partial_floats(const RenderArgs& a) {
+    if (a.forward_mode != 1 || a.n_inst <= 0) return 0;
+    const int64_t n_chunks = (a.n_inst + 255) / 256;
+    return (size_t)n_chunks * 2 * (size_t)a.tile * (size_t)a.tile;
 }
 
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask, const float* msum,
                           float* pred, float* grad_pred, float* tile_sse, unsigned long long* incut,
-                          int* work_counter, hipStream_t st) {
+                          int* work_counter, float* partial, hipStream_t st) {
     if (a.n_tiles <= 0) return hipSuccess;
     if (a.persistent) {
         hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
@@ -952,11 +1057,10 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
         }
     }
     if (a.forward_mode == 1) {
-        const int grid = grid_for(a, 256);
         switch (a.tile) {
-            case 8: return fwd_rpl_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
-            case 16: return fwd_rpl_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
-            case 32: return fwd_rpl_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 8: return fwd_chunk_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
+            case 16: return fwd_chunk_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
+            case 32: return fwd_chunk_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
             default: return hipErrorInvalidValue;
         }
     }

@@ -177,9 +177,11 @@ hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, int2* ranges, int
                               hipStream_t st);
 hipError_t launch_mask_sum(const float* mask, int64_t n, float* partial, float* out,
                            hipStream_t st);
+// partial: forward_partial_floats(a) floats of scratch (record-per-lane mode).
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask,
                           const float* msum, float* pred, float* grad_pred, float* tile_sse,
-                          unsigned long long* incut, int* work_counter, hipStream_t st);
+                          unsigned long long* incut, int* work_counter, float* partial, hipStream_t st);
+size_t forward_partial_floats(const RenderArgs& a);
 // Scale regulariser (adds to g [n,3] and, if loss != NULL, to loss[0]);
 // partial holds kRegBlocks floats.
 constexpr int kRegBlocks = 512;
