@@ -87,8 +87,8 @@ const char* svr_last_error(const svr_ctx* ctx);
  * slice i is sum_{k<i} height[k]*width[k].
  * Errors: SVR_ERR_ARG for null arrays, nonpositive sizes, unsorted subjects,
  * negative spacing/FWHM, non-monotone Gaussian offsets; SVR_ERR_CAPACITY when
- * the total pixel or tile count exceeds 2^31-1 or a subject has more than
- * 4096 slices. */
+ * the total pixel or tile count exceeds 2^31-1, a slice side exceeds 65535
+ * pixels or a subject has more than 4096 slices. */
 typedef struct {
     int32_t n_subjects;
     const int64_t* gauss_offsets;  /* [n_subjects+1], gauss_offsets[0] = 0 */

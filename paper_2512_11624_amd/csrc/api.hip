@@ -73,6 +73,7 @@ struct svr_ctx {
     DevBuf<SubjectInfo> d_subj;
     DevBuf<GaussBlock> d_blocks;
     DevBuf<int32_t> d_tile_slice;
+    DevBuf<int4> d_tile_org;       // per tile origin, see TileOrg
     DevBuf<int2> d_counts, d_offsets;
     DevBuf<char> d_scan_tmp;
     DevBuf<long long> d_totals;
@@ -250,8 +251,23 @@ int build_tables(svr_ctx* c) {
     if (kb + kClassBits > 32) return fail(c, SVR_ERR_CAPACITY, "tile count %lld too large for the sort key", (long long)tiles);
     c->key_bits = kb + kClassBits;
     std::vector<int32_t> tile_slice((size_t)tiles);
-    for (int i = 0; i < c->M; ++i)
-        for (int t = 0; t < geo[i].ntx * geo[i].nty; ++t) tile_slice[geo[i].tile_base + t] = i;
+    // per tile: global pixel id of its origin (two ints), x0 | y0 << 16 and
+    // slice width | valid width << 16 | valid height << 24 (see TileOrg)
+    std::vector<int4> tile_org((size_t)tiles);
+    for (int i = 0; i < c->M; ++i) {
+        if (geo[i].W > 0xffff || geo[i].H > 0xffff)
+            return fail(c, SVR_ERR_CAPACITY, "slice %d is %d x %d pixels; at most 65535 per side", i, geo[i].H,
+                        geo[i].W);
+        for (int t = 0; t < geo[i].ntx * geo[i].nty; ++t) {
+            tile_slice[geo[i].tile_base + t] = i;
+            const int ty = t / geo[i].ntx, tx = t - ty * geo[i].ntx;
+            const int x0 = tx * T, y0 = ty * T;
+            const int64_t base = geo[i].pix_off + (int64_t)y0 * geo[i].W + x0;
+            const int vw = std::min(T, geo[i].W - x0), vh = std::min(T, geo[i].H - y0);
+            tile_org[geo[i].tile_base + t] = make_int4((int)(uint32_t)(uint64_t)base, (int)((uint64_t)base >> 32),
+                                                       x0 | (y0 << 16), geo[i].W | (vw << 16) | (vh << 24));
+        }
+    }
     std::vector<SubjectInfo> subj(c->n_subjects);
     std::vector<GaussBlock> blocks;
     for (int s = 0; s < c->n_subjects; ++s) {
@@ -285,6 +301,7 @@ int build_tables(svr_ctx* c) {
     HIPCHK(c, ensure(c->d_subj, subj.size()));
     HIPCHK(c, ensure(c->d_blocks, blocks.size()));
     HIPCHK(c, ensure(c->d_tile_slice, tile_slice.size()));
+    HIPCHK(c, ensure(c->d_tile_org, tile_org.size()));
     HIPCHK(c, ensure(c->d_ranges, tile_slice.size()));
     HIPCHK(c, ensure(c->d_tile_sse, tile_slice.size()));
     HIPCHK(c, ensure(c->d_slice_sse, (size_t)c->M));
@@ -299,6 +316,8 @@ int build_tables(svr_ctx* c) {
         HIPCHK(c, hipMemcpyAsync(c->d_blocks.p, blocks.data(), blocks.size() * sizeof(GaussBlock), hipMemcpyHostToDevice, st));
     if (!tile_slice.empty())
         HIPCHK(c, hipMemcpyAsync(c->d_tile_slice.p, tile_slice.data(), tile_slice.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!tile_org.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_tile_org.p, tile_org.data(), tile_org.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
     c->binned = false;
     return SVR_OK;
@@ -372,6 +391,7 @@ RenderArgs render_args(svr_ctx* c) {
     RenderArgs a;
     a.geo = c->d_geo.p;
     a.tile_slice = c->d_tile_slice.p;
+    a.tile_org = c->d_tile_org.p;
     a.ranges = c->d_ranges.p;
     a.inst_rec = c->sorted_vals;
     a.inst_idx = c->sorted_idx;
@@ -544,7 +564,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         release(c->d_geo); release(c->d_pose); release(c->d_subj); release(c->d_blocks);
-        release(c->d_tile_slice); release(c->d_counts); release(c->d_offsets); release(c->d_scan_tmp);
+        release(c->d_tile_slice); release(c->d_tile_org); release(c->d_counts); release(c->d_offsets); release(c->d_scan_tmp);
         release(c->d_totals); release(c->d_rec); release(c->d_rec_inst); release(c->d_inst_grad);
         release(c->d_idx); release(c->d_idx2); release(c->d_keys);
         release(c->d_vals); release(c->d_keys2); release(c->d_vals2); release(c->d_sort_tmp);

@@ -138,6 +138,25 @@ __device__ inline TileCoord tile_coord(const RenderArgs& a, int tile) {
     return c;
 }
 
+// Origin of a tile from the per-tile table (static geometry): global pixel
+// id of its first pixel, tile-local clip (valid width and height) and the
+// slice width.
+struct TileOrg {
+    int64_t base;
+    int x0, y0, stride, vw, vh;
+};
+
+__device__ inline TileOrg tile_org(int4 v) {
+    TileOrg o;
+    o.base = (int64_t)(((uint64_t)(uint32_t)v.y << 32) | (uint64_t)(uint32_t)v.x);
+    o.x0 = v.z & 0xffff;
+    o.y0 = (int)((uint32_t)v.z >> 16);
+    o.stride = v.w & 0xffff;
+    o.vw = (v.w >> 16) & 0xff;
+    o.vh = (int)((uint32_t)v.w >> 24);
+    return o;
+}
+
 // Returns the next tile of this workgroup, or -1.
 template <int NT>
 __device__ inline int next_tile(const RenderArgs& a, int* work_counter, int& it, int* s_next) {
@@ -308,29 +327,26 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
 
 // Epilogue of a tile whose sums are final: pred, and with kLoss the data
 // term's gradient and the tile's loss partial tile_sse[tile].  acc holds the
-// tile's T x T sums (tile-local row major); org = (x0 | y0 << 16, valid
-// width | valid height << 16), base = global pixel id of the tile origin,
-// stride = slice width.  Called by all threads of the workgroup; s_red holds
-// a float per wave.
+// tile's T x T sums (tile-local row major).  Called by all threads of the
+// workgroup; s_red holds a float per wave.
 template <int T, int NT, bool kLoss>
-__device__ inline void finish_tile(const RenderArgs& a, int tile, const float* acc, int2 org, int64_t base,
-                                   int stride, const float* __restrict__ target, const float* __restrict__ mask,
+__device__ inline void finish_tile(const RenderArgs& a, int tile, const float* acc, const TileOrg& o,
+                                   const float* __restrict__ target, const float* __restrict__ mask,
                                    float inv_msum, float* __restrict__ pred, float* __restrict__ grad,
                                    float* __restrict__ tile_sse, float* s_red) {
     const int tid = threadIdx.x;
-    const int vw = org.y & 0xffff, vh = org.y >> 16;
     float sq = 0.f;
     for (int p = tid; p < T * T; p += NT) {
         const int px = p % T, py = p / T;
-        if (px < vw && py < vh) {
-            const int64_t pi = base + (int64_t)py * stride + px;
+        if (px < o.vw && py < o.vh) {
+            const int64_t pi = o.base + (int64_t)py * o.stride + px;
             const float y = acc[p];
             pred[pi] = y;
             if (kLoss) loss_term(a.loss_kind, mask[pi], y - target[pi], inv_msum, sq, grad ? grad + pi : nullptr);
         }
     }
     if (kLoss) {
-        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        for (int o2 = 32; o2 > 0; o2 >>= 1) sq += __shfl_xor(sq, o2, 64);
         if ((tid & 63) == 0) s_red[tid >> 6] = sq;
         __syncthreads();
         if (tid == 0) {
@@ -377,10 +393,8 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     __shared__ float s_fsum[NW];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
-    __shared__ int s_tile[NT];
-    __shared__ int2 s_org[KT];
-    __shared__ long long s_base[KT];
-    __shared__ int s_stride[KT];
+    __shared__ int4 s_org[KT];  // the pass's tiles (TileOrg packing)
+    __shared__ int s_ptile[KT];
     __shared__ int s_fin[KT];  // -1: tile finished here, else the partial slot (0 first run, 1 last run)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
@@ -391,17 +405,45 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     float* s_facc = reinterpret_cast<float*>(s_iacc);
 
+    // every lane's instance: tile, run head, record and box (independent loads)
     const int64_t inst = chunk * NT + tid;
     int tile = -1;
+    bool head = false;
+    int4 org = make_int4(0, 0, 0, 0);
     if (inst < a.n_inst) {
         const uint32_t t = a.inst_key[inst] >> kClassBits;
-        if (t < (uint32_t)a.n_tiles) tile = (int)t;
+        if (t < (uint32_t)a.n_tiles) {
+            tile = (int)t;
+            head = tid == 0 || (a.inst_key[inst - 1] >> kClassBits) != t;
+            org = a.tile_org[tile];
+        }
     }
-    s_tile[tid] = tile;
-    __syncthreads();
-    const bool head = tile >= 0 && (tid == 0 || s_tile[tid - 1] != tile);
+    for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
     const uint64_t hm = __ballot(head);
     if (lane == 0) s_wsum[wv] = __popcll(hm);
+    int bucket = 0;
+    float absa = 0.f;
+    int fin = -1;
+    if (tile >= 0) {
+        const Record R = a.rec[a.inst_rec[inst]];
+        const TileOrg o = tile_org(org);
+        const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+        const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+        const bool empty = w == 0 || h == 0;
+        const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+        const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+        bucket = empty ? 0 : (h * (T + 1) + w);
+        absa = empty ? 0.f : fabsf(b.am);
+        s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+        s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                    __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                   ((y1 + 1) << 24)));
+        if (head) {
+            const int2 rg = a.ranges[tile];
+            const bool inside = rg.x >= chunk * NT && rg.y <= chunk * NT + NT;
+            fin = inside ? -1 : (tid == 0 ? 0 : 1);
+        }
+    }
     __syncthreads();
     int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
     int nd = 0;
@@ -409,49 +451,32 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         if (q < wv) rslot += s_wsum[q];
         nd += s_wsum[q];
     }
-    __syncthreads();
-    if (head) s_tile[rslot] = tile;
     unsigned int cnt = 0;
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
-        __syncthreads();
-        if (tid < np) {
-            const int rs = p0 + tid, t = s_tile[rs];
-            const TileCoord tc = tile_coord(a, t);
-            s_org[tid] = make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16));
-            s_base[tid] = tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0;
-            s_stride[tid] = tc.W;
-            const int2 rg = a.ranges[t];
-            const bool inside = rg.x >= chunk * NT && rg.y <= chunk * NT + NT;
-            s_fin[tid] = inside ? -1 : (rs == 0 ? 0 : 1);
+        if (p0 > 0) {
+            __syncthreads();  // the previous pass is done with LDS
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+        }
+        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
+        if (act && head) {
+            s_org[rslot - p0] = org;
+            s_ptile[rslot - p0] = tile;
+            s_fin[rslot - p0] = fin;
         }
         for (int q = tid; q < np * T * T; q += NT) s_iacc[q] = 0;
-        for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+        // the pass's sum of |a| (its instances only)
+        float pa = act ? absa : 0.f;
+        for (int o = 32; o > 0; o >>= 1) pa += __shfl_xor(pa, o, 64);
+        if (lane == 0) s_fsum[wv] = pa;
         __syncthreads();
-        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
-        int bucket = 0, pos = 0;
-        float absa = 0.f;
+        int pos = 0;
         if (act) {
-            const int2 o = s_org[rslot - p0];
-            const Record R = a.rec[a.inst_rec[inst]];
-            const LaneBox b = lane_box(R, o.x & 0xffff, o.x >> 16, (o.y & 0xffff) - 1, (o.y >> 16) - 1, tau2k);
-            const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-            const bool empty = w == 0 || h == 0;
-            const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-            const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-            bucket = empty ? 0 : (h * (T + 1) + w);
-            absa = empty ? 0.f : fabsf(b.am);
-            s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-            s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                        __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                       ((y1 + 1) << 24)));
             s_gb[tid] = (rslot - p0) * T * T;
             pos = atomicAdd(&s_hist[bucket], 1);
         }
-        for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
-        if (lane == 0) s_fsum[wv] = absa;
-        __syncthreads();
         const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
+        __syncthreads();
         {   // exclusive scan of the bucket counts; s_hist[kB] receives the total
             const int per = (kB + NT - 1) / NT;
             const int kb = min(tid * per, kB), ke = min(kb + per, kB);
@@ -513,12 +538,13 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         for (int q = tid; q < np * T * T; q += NT) s_facc[q] = (float)s_iacc[q] * from_q;
         __syncthreads();
         for (int sl = 0; sl < np; ++sl) {
-            const int fin = s_fin[sl];
-            if (fin < 0) {
-                finish_tile<T, NT, kLoss>(a, s_tile[p0 + sl], s_facc + sl * T * T, s_org[sl], s_base[sl],
-                                          s_stride[sl], target, mask, inv_msum, pred, grad, tile_sse, s_red);
+            const int f = s_fin[sl];
+            if (f < 0) {
+                const TileOrg o = tile_org(s_org[sl]);
+                finish_tile<T, NT, kLoss>(a, s_ptile[sl], s_facc + sl * T * T, o, target, mask, inv_msum, pred,
+                                          grad, tile_sse, s_red);
             } else {
-                float* dst = partial + ((size_t)chunk * 2 + fin) * (T * T);
+                float* dst = partial + ((size_t)chunk * 2 + f) * (T * T);
                 for (int p = tid; p < T * T; p += NT) dst[p] = s_facc[sl * T * T + p];
             }
         }
@@ -563,9 +589,7 @@ __global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const floa
         }
         s_acc[p] = acc;
     }
-    const TileCoord tc = tile_coord(a, tile);
-    finish_tile<T, NT, kLoss>(a, tile, s_acc, make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16)),
-                              tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0, tc.W, target, mask, inv_msum, pred, grad,
+    finish_tile<T, NT, kLoss>(a, tile, s_acc, tile_org(a.tile_org[tile]), target, mask, inv_msum, pred, grad,
                               tile_sse, s_red);
 }
 
@@ -746,78 +770,77 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
     __shared__ int s_hist[kB + 1];
     __shared__ int s_perm[NT];
     __shared__ int s_wsum[NW];
-    __shared__ int s_tile[NT];        // per lane, then the chunk's distinct tiles in order
-    __shared__ int2 s_org[KT];        // pass tiles: (x0 | y0 << 16, valid W | valid H << 16)
-    __shared__ long long s_base[KT];  // pass tiles: global pixel id of the tile origin
-    __shared__ int s_stride[KT];      // pass tiles: slice width
+    __shared__ int4 s_org[KT];  // the pass's tiles (TileOrg packing)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
     if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
-    const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
-    const float scale = grad_scale ? grad_scale[0] : 1.f;
+    const float etau = a.etau;
 
-    // tile of every lane's instance (-1: past the end, or emission padding)
+    // every lane's instance: tile (-1 past the end or for emission padding),
+    // whether it heads a run of its tile in the chunk, its record and box;
+    // the loads are independent so their latencies overlap
     const int64_t inst = chunk * NT + tid;
     int tile = -1;
+    bool head = false;
+    int4 org = make_int4(0, 0, 0, 0);
     if (inst < a.n_inst) {
         const uint32_t t = a.inst_key[inst] >> kClassBits;
-        if (t < (uint32_t)a.n_tiles) tile = (int)t;
+        if (t < (uint32_t)a.n_tiles) {
+            tile = (int)t;
+            head = tid == 0 || (a.inst_key[inst - 1] >> kClassBits) != t;
+            org = a.tile_org[tile];
+        }
     }
-    s_tile[tid] = tile;
-    __syncthreads();
-    // the chunk's distinct tiles: a lane heads a run when its tile differs
-    // from the previous lane's; rslot = index of the lane's run
-    const bool head = tile >= 0 && (tid == 0 || s_tile[tid - 1] != tile);
+    for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
     const uint64_t hm = __ballot(head);
     if (lane == 0) s_wsum[wv] = __popcll(hm);
+    int bucket = 0;
+    if (tile >= 0) {
+        const Record R = a.rec[a.inst_rec[inst]];
+        const TileOrg o = tile_org(org);
+        const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+        const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+        const bool empty = w == 0 || h == 0;
+        const int bx0 = empty ? 0 : b.x0, bx1 = empty ? -1 : b.x1;
+        const int by0 = empty ? 0 : b.y0, by1 = empty ? -1 : b.y1;
+        bucket = empty ? 0 : (h * (T + 1) + w);
+        s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+        s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                    __int_as_float((bx0 + 1) | ((bx1 + 1) << 8) | ((by0 + 1) << 16) |
+                                                   ((by1 + 1) << 24)));
+        s_slot[tid] = a.inst_idx[inst];
+    }
     __syncthreads();
+    // rslot = index of the lane's run (distinct tile) in the chunk
     int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
     int nd = 0;
     for (int q = 0; q < NW; ++q) {
         if (q < wv) rslot += s_wsum[q];
         nd += s_wsum[q];
     }
-    __syncthreads();  // every lane has read s_tile[tid - 1] and s_wsum
-    if (head) s_tile[rslot] = tile;
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
-        __syncthreads();  // distinct-tile list written / previous pass done with LDS
-        if (tid < np) {
-            const TileCoord tc = tile_coord(a, s_tile[p0 + tid]);
-            s_org[tid] = make_int2(tc.x0 | (tc.y0 << 16), min(T, tc.W - tc.x0) | (min(T, tc.H - tc.y0) << 16));
-            s_base[tid] = tc.pix_off + (int64_t)tc.y0 * tc.W + tc.x0;
-            s_stride[tid] = tc.W;
-        }
-        for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-        __syncthreads();
-        for (int q = tid; q < np * T * T; q += NT) {
-            const int sl = q / (T * T), pix = q - sl * (T * T);
-            const int2 o = s_org[sl];
-            const int px = pix % T, py = pix / T;
-            s_g[q] = (px < (o.y & 0xffff) && py < (o.y >> 16))
-                         ? grad_pred[s_base[sl] + (int64_t)py * s_stride[sl] + px] * scale
-                         : 0.f;
+        if (p0 > 0) {
+            __syncthreads();  // the previous pass is done with LDS
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
         }
         const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
-        int bucket = 0, pos = 0;
+        if (act && head) s_org[rslot - p0] = org;
+        __syncthreads();  // s_org and the zeroed histogram are visible
+        int pos = 0;
         if (act) {
-            const int2 o = s_org[rslot - p0];
-            const Record R = a.rec[a.inst_rec[inst]];
-            const LaneBox b = lane_box(R, o.x & 0xffff, o.x >> 16, (o.y & 0xffff) - 1, (o.y >> 16) - 1, tau2k);
-            const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-            const bool empty = w == 0 || h == 0;
-            const int bx0 = empty ? 0 : b.x0, bx1 = empty ? -1 : b.x1;
-            const int by0 = empty ? 0 : b.y0, by1 = empty ? -1 : b.y1;
-            bucket = empty ? 0 : (h * (T + 1) + w);
-            s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-            s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                        __int_as_float((bx0 + 1) | ((bx1 + 1) << 8) | ((by0 + 1) << 16) |
-                                                       ((by1 + 1) << 24)));
-            s_slot[tid] = a.inst_idx[inst];
             s_gb[tid] = (rslot - p0) * T * T;
             pos = atomicAdd(&s_hist[bucket], 1);
+        }
+        for (int q = tid; q < np * T * T; q += NT) {
+            const int sl = q / (T * T), pix = q - sl * (T * T);
+            const TileOrg o = tile_org(s_org[sl]);
+            const int px = pix % T, py = pix / T;
+            float gv = 0.f;
+            if (px < o.vw && py < o.vh) gv = grad_pred[o.base + (int64_t)py * o.stride + px];
+            s_g[q] = gv;
         }
         __syncthreads();
         {   // exclusive scan of the bucket counts: thread t takes a run of
@@ -845,6 +868,7 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
         __syncthreads();
         if (act) s_perm[s_hist[bucket] + pos] = tid;
         __syncthreads();
+        const float scale = grad_scale ? grad_scale[0] : 1.f;
         if (tid < s_hist[kB]) {
             const int q = s_perm[tid];
             const float4 p0v = s_box[q][0], p1 = s_box[q][1];
@@ -886,9 +910,10 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
                 dy += 1.f;
                 gr += T;
             }
-            const float k2 = am * SVR_LN2;
+            // the upstream scale multiplies every sum (it was applied to g)
+            const float k2 = am * SVR_LN2 * scale;
             float4 g0, g1;
-            g0.x = Sa;
+            g0.x = Sa * scale;
             g0.y = k2 * S0;
             g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
             g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);

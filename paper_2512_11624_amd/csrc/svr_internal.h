@@ -154,6 +154,7 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 struct RenderArgs {
     const SliceGeo* geo;
     const int32_t* tile_slice;   // [n_tiles]
+    const int4* tile_org;        // [n_tiles] origin of the tile (TileOrg packing)
     const int2* ranges;          // [n_tiles] [start, end) into sorted instances
     const uint32_t* inst_rec;    // sorted instance -> record id
     const uint32_t* inst_idx;    // sorted instance -> emission slot
