@@ -223,6 +223,19 @@ def sequential_subjects(prob, par, target, mask, cfg, steps, warmup):
     return dict(ms_per_round=ms, subjects=len(runs))
 
 
+def stage_breakdown(ctx, run, n):
+    """Per-stage GPU times over `run` called n times, with every stage
+    bracketed by HIP events.  Event records leave the GPU idle for a few
+    microseconds between kernels, so this runs outside the timed region."""
+    ctx.svr_set_timing_stages(None)
+    ctx.svr_set_timing(True)
+    for _ in range(n):
+        run()
+    t = ctx.svr_get_timing()
+    ctx.svr_set_timing(False)
+    return {k: dict(calls=c, avg_ms=(tt / c if c else 0.0)) for k, (c, tt) in t.items() if c}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +340,16 @@ def main():
     n_incut = int(st["n_incut"])
     log(f"stats: {st}")
 
+    # per-stage breakdown over steps of its own, then the timed region with
+    # events around the dominant stage only
+    n_bk = max(1, min(10, args.steps))
+    stages = stage_breakdown(ctx, step, n_bk)
+    per_step = {k: v["avg_ms"] * v["calls"] / n_bk for k, v in stages.items()}
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"]):
+        log(f"  {k:18s} {v['calls']:5d} calls  {v['avg_ms']:.4f} ms avg")
+    dominant = max(per_step, key=per_step.get)
+
+    ctx.svr_set_timing_stages([dominant])
     ctx.svr_set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -336,24 +359,23 @@ def main():
     t1 = time.perf_counter()
     timing = ctx.svr_get_timing()
     ctx.svr_set_timing(False)
+    ctx.svr_set_timing_stages(None)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_incut / (ms_per_step / 1e3)
     final_loss = float(loss.item())
-    log(f"{ms_per_step:.3f} ms/step, {value:.4g} pair-evals/s, loss {final_loss:.5g}")
+    dom_calls, dom_total = timing[dominant]
+    dom_ms = dom_total / dom_calls
+    log(f"{ms_per_step:.3f} ms/step, {value:.4g} pair-evals/s, loss {final_loss:.5g}; "
+        f"{dominant} {dom_ms:.4f} ms avg in the timed region")
 
-    stages = {k: dict(calls=c, avg_ms=(t / c if c else 0.0)) for k, (c, t) in timing.items() if c}
-    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"]):
-        log(f"  {k:18s} {v['calls']:5d} calls  {v['avg_ms']:.4f} ms avg")
-    per_step = {k: v["avg_ms"] * v["calls"] / args.steps for k, v in stages.items()}
-    dominant = max(per_step, key=per_step.get)
-    rl = stage_roofline(dominant, stages[dominant]["avg_ms"], st, n_incut)
+    rl = stage_roofline(dominant, dom_ms, st, n_incut)
     roofline = None
     if rl:
         bound, achieved, peak, unit, work = rl
         traffic = measured_traffic(dominant, ctx.svr_get_config()["tile"], args.workload)
         roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
                         frac=round(achieved / peak, 6), traffic=traffic, kernel=dominant,
-                        avg_ms=round(stages[dominant]["avg_ms"], 5), work_per_launch=work)
+                        avg_ms=round(dom_ms, 5), work_per_launch=work)
 
     sequential = None
     if args.workload == "batched":
@@ -436,13 +458,30 @@ def run_topk(args, ctx, prob, desc, init, target, mask, target_np):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.svr_set_timing(True)
+    # per-stage breakdown (list build and iterations) over runs of their own,
+    # then the timed region with events around the dominant iteration stage only
+    n_bk = max(1, min(10, args.steps))
+
+    def build_and_steps():
+        build()
+        for _ in range(n_bk):
+            step()
+
+    stages = stage_breakdown(ctx, build_and_steps, 1)
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"]):
+        log(f"  {k:18s} {v['calls']:5d} calls  {v['avg_ms']:.4f} ms avg")
+    per_step = {k: v["avg_ms"] * v["calls"] / n_bk for k, v in stages.items()
+                if k not in ("topk_knn", "topk_inverse")}
+    dominant = max(per_step, key=per_step.get)
     nb = max(1, min(3, args.steps))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(nb):
         build()
     torch.cuda.synchronize()
     ms_build = (time.perf_counter() - t0) * 1e3 / nb
+    ctx.svr_set_timing_stages([dominant])
+    ctx.svr_set_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
@@ -450,25 +489,22 @@ def run_topk(args, ctx, prob, desc, init, target, mask, target_np):
     ms_iter = (time.perf_counter() - t0) * 1e3 / args.steps
     timing = ctx.svr_get_timing()
     ctx.svr_set_timing(False)
+    ctx.svr_set_timing_stages(None)
+    dom_calls, dom_total = timing[dominant]
+    dom_ms = dom_total / dom_calls
     ms_per_step = ms_iter + ms_build / args.topk_refresh
     # lists exist for the pixels inside the mask only; the others predict 0
     pairs = int((prob.mask > 0).sum()) * K
     value = pairs / (ms_per_step / 1e3)
     log(f"topk: build {ms_build:.3f} ms, iteration {ms_iter:.3f} ms, amortised {ms_per_step:.3f} ms/step, "
-        f"{value:.4g} pair-evals/s")
-    stages = {k: dict(calls=c, avg_ms=(t / c if c else 0.0)) for k, (c, t) in timing.items() if c}
-    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["calls"]):
-        log(f"  {k:18s} {v['calls']:5d} calls  {v['avg_ms']:.4f} ms avg")
-    per_step = {k: v["avg_ms"] * v["calls"] / args.steps for k, v in stages.items()
-                if k not in ("topk_knn", "topk_inverse")}
-    dominant = max(per_step, key=per_step.get)
-    rl = stage_roofline(dominant, stages[dominant]["avg_ms"], {}, pairs)
+        f"{value:.4g} pair-evals/s; {dominant} {dom_ms:.4f} ms avg in the timed region")
+    rl = stage_roofline(dominant, dom_ms, {}, pairs)
     roofline = None
     if rl:
         bound, achieved, peak, unit, work = rl
         roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
                         frac=round(achieved / peak, 6), traffic=None, kernel=dominant,
-                        avg_ms=round(stages[dominant]["avg_ms"], 5), work_per_launch=work)
+                        avg_ms=round(dom_ms, 5), work_per_launch=work)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = topk_cpu_baseline(prob, init, target_np, K, delta)

@@ -395,8 +395,11 @@ int svr_sort_pairs(svr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int 
  * up to max_out entries (HOST array) in a fixed stage order, setting *n_out.
  * Stage names: slice_pose, cull_count, scan, emit, sort, tile_ranges,
  * tile_order, mask_sum, forward_tile, loss_reduce, zero_fill, backward_tile,
- * project_backward, pose_chain, adam.  Enabling or disabling clears the
- * totals. */
+ * project_backward, pose_chain, adam, topk_knn, topk_inverse, topk_forward,
+ * topk_backward.  Enabling or disabling clears the totals.  An event record
+ * can leave the GPU idle for several microseconds between kernels, so a
+ * caller timing whole iterations should bracket only the stages it needs
+ * (svr_set_timing_stages). */
 typedef struct {
     char name[32];
     int64_t calls;
@@ -405,6 +408,10 @@ typedef struct {
 
 int svr_set_timing(svr_ctx* ctx, int enable);
 int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
+/* Stages that timing brackets with events: bit s of mask selects stage s in
+ * the order listed above (default: all).  Takes effect for stages launched
+ * afterwards; totals are kept.  Errors: SVR_ERR_ARG for a null context. */
+int svr_set_timing_stages(svr_ctx* ctx, uint32_t mask);
 
 /* ------------------------------------------------------------------------ */
 /* Autotuner (batched launch).  Times the forward and backward tile kernels

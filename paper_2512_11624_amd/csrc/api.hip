@@ -148,6 +148,7 @@ struct svr_ctx {
 
     // stage timing
     bool timing = false;
+    uint32_t timing_mask = 0xffffffffu;  // bit s: stage s is bracketed by events while timing
     std::vector<hipEvent_t> ev_free;
     struct Pending { int stage; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -340,7 +341,7 @@ struct StageScope {
     int stage;
     hipEvent_t a = nullptr;
     StageScope(svr_ctx* ctx, int s) : c(ctx), stage(s) {
-        if (c->timing) {
+        if (c->timing && ((c->timing_mask >> s) & 1u)) {
             a = take_event(c);
             if (a && hipEventRecord(a, c->stream) != hipSuccess) a = nullptr;
         }
@@ -1273,6 +1274,13 @@ int svr_set_timing(svr_ctx* c, int enable) {
         c->t_ms[s] = 0.0;
         c->t_calls[s] = 0;
     }
+    return SVR_OK;
+}
+
+int svr_set_timing_stages(svr_ctx* c, uint32_t mask) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    c->timing_mask = mask;
     return SVR_OK;
 }
 

@@ -90,6 +90,7 @@ _SIGS = {
     "svr_sort_pairs": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
     "svr_set_timing": ([vp, C.c_int], C.c_int),
     "svr_get_timing": ([vp, C.POINTER(svr_timer), C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "svr_set_timing_stages": ([vp, C.c_uint32], C.c_int),
     "svr_posenet_create": ([C.POINTER(vp), C.c_int, vp, C.c_uint64, C.c_int], C.c_int),
     "svr_posenet_destroy": ([vp], C.c_int),
     "svr_posenet_num_params": ([vp], C.c_int64),
@@ -310,6 +311,20 @@ class Context:
 
     def svr_set_timing(self, enable: bool):
         self._check(load().svr_set_timing(self.h, int(bool(enable))), "svr_set_timing")
+
+    def svr_set_timing_stages(self, stages=None):
+        """Bracket only the named stages with events (None: all stages)."""
+        if stages is None:
+            mask = 0xFFFFFFFF
+        else:
+            order = list(self.svr_get_timing().keys())
+            unknown = [s for s in stages if s not in order]
+            if unknown:
+                raise ValueError(f"unknown stages {unknown}")
+            mask = 0
+            for s in stages:
+                mask |= 1 << order.index(s)
+        self._check(load().svr_set_timing_stages(self.h, C.c_uint32(mask)), "svr_set_timing_stages")
 
     def svr_get_timing(self):
         """{stage: (calls, total_ms)}; synchronises the stream."""

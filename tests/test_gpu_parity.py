@@ -213,6 +213,27 @@ def test_incut_pair_count_brackets(ctx):
     assert lo <= st["n_incut"] <= hi, (lo, st["n_incut"], hi)
 
 
+def test_timing_stage_mask(ctx):
+    """With a stage mask only the selected stage is bracketed by events (and
+    counted); the mask does not change any result."""
+    prob = synth.config1(0)
+    params, pose, target = _setup(prob)
+    ref = _run(ctx, prob, params, pose, target, cfg=dict(tile=16, batch=128, persistent=0, cutoff=3.0))
+    ctx.svr_set_timing_stages(["backward_tile"])
+    ctx.svr_set_timing(True)
+    out = _run(ctx, prob, params, pose, target)
+    t = ctx.svr_get_timing()
+    ctx.svr_set_timing(False)
+    ctx.svr_set_timing_stages(None)
+    assert t["backward_tile"][0] == 1 and t["backward_tile"][1] > 0.0, t
+    assert all(c == 0 for k, (c, _) in t.items() if k != "backward_tile"), t
+    assert np.array_equal(out["pred"], ref["pred"])  # the forward is deterministic
+    for k in ("mean", "log_scale", "quat", "amp", "pose"):  # per-Gaussian sums may add in another order
+        assert np.allclose(out[k], ref[k], rtol=1e-5, atol=1e-6 * np.abs(ref[k]).max()), k
+    with pytest.raises(ValueError):
+        ctx.svr_set_timing_stages(["no_such_stage"])
+
+
 def test_radix_sort_matches_stable_argsort(ctx):
     """The binning sort is a stable LSD radix sort: bit-exact against numpy's
     stable argsort, for key widths that take one to four passes of 8- or
