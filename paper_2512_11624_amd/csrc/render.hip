@@ -315,8 +315,11 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
     b.a11 = R.r1.z;
     const float det = b.a00 * b.a11 - b.a01 * b.a01;
     const float rk = tau2k - b.bz;  // KZ (T^2 - beta) <= 0 inside the footprint
-    const float hx = sqrtf(fmaxf(rk * b.a11 / det, 0.f)) + 1e-3f;
-    const float hy = sqrtf(fmaxf(rk * b.a00 / det, 0.f)) + 1e-3f;
+    // hardware reciprocal and square root (about 1 ulp each): the 1e-3 px
+    // slack keeps the box conservative
+    const float rkd = rk * __builtin_amdgcn_rcpf(det);
+    const float hx = __builtin_amdgcn_sqrtf(fmaxf(rkd * b.a11, 0.f)) + 1e-3f;
+    const float hy = __builtin_amdgcn_sqrtf(fmaxf(rkd * b.a00, 0.f)) + 1e-3f;
     // clamp in float before converting (the centre can be far outside the tile)
     b.x0 = (int)fmaxf(ceilf(b.pxl - hx), 0.f);
     b.x1 = (int)fminf(floorf(b.pxl + hx), (float)xmax);
