@@ -480,6 +480,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
 // accumulators.  Finally thread j chains dL/dSigma_j to the log-scales and
 // the quaternion and writes the Gaussian's gradient.
 // ---------------------------------------------------------------------------
+// The projection adjoint runs each Gaussian block as kBlock / kPartGauss
+// workgroups of kPartGauss Gaussians.  Whole blocks of 256 Gaussians, at six
+// resident per CU (LDS), filled the chip about 1.3 times over and left a
+// tail; parts of 128 halve each workgroup's work and LDS (measured 6 %
+// faster; parts of 64 were slower).
+constexpr int kPartGauss = 128;
 constexpr int kGAcc = 11;  // GS (6), gmu (3), gc, glsum
 constexpr int kGAct = 11;  // staged activation: mu (3), Sigma (6), lsum, c
 
@@ -509,6 +515,7 @@ __device__ inline void seg_scan(float (&v)[kN], int key) {
     seg_scan_step<0x143, 0xc>(v, key);
 }
 
+template <int NGS>
 __global__ __launch_bounds__(kBlock) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
     const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
@@ -519,21 +526,27 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     // a multiple of 8 bytes)
     extern __shared__ float s_pose[];
     __shared__ float s_wmax[kBlock / 64];
-    __shared__ int s_roff[kBlock + 1];  // record offsets of the block's Gaussians, relative to the first
-    __shared__ float s_gacc[kGAcc][kBlock];
-    __shared__ float s_act[kGAct][kBlock];
-    const GaussBlock blk = a.blocks[blockIdx.x];
+    __shared__ int s_roff[NGS + 1];  // record offsets of the part's Gaussians, relative to the first
+    __shared__ float s_gacc[kGAcc][NGS];
+    __shared__ float s_act[kGAct][NGS];
+    // workgroup = one NGS-Gaussian part of a Gaussian block
+    constexpr int NS = kBlock / NGS;
+    const GaussBlock blk = a.blocks[blockIdx.x / NS];
+    const int64_t g0 = blk.g_begin + (int64_t)(blockIdx.x % NS) * NGS;
+    if (g0 >= blk.g_end) return;  // empty part (uniform)
+    const int64_t g1 = min(g0 + (int64_t)NGS, blk.g_end);
     const SubjectInfo si = a.subj[blk.subject];
     const int ns = si.s_end - si.s_begin;
     unsigned long long* s_ipose = reinterpret_cast<unsigned long long*>(s_pose + 6 * ns);
     const int tid = threadIdx.x, lane = tid & 63;
-    const int ng = (int)(blk.g_end - blk.g_begin);
-    const int64_t R0 = offsets[blk.g_begin].x;
+    const int ng = (int)(g1 - g0);
+    const int64_t R0 = offsets[g0].x;
     {
-        const int64_t j = blk.g_begin + tid;
+        const int64_t j = g0 + tid;
         if (tid < ng) s_roff[tid] = (int)(offsets[j].x - R0);
         if (tid == ng - 1) s_roff[ng] = (int)(offsets[j].x + counts[j].x - R0);
-        for (int q = 0; q < kGAcc; ++q) s_gacc[q][tid] = 0.f;
+        if (tid < NGS)
+            for (int q = 0; q < kGAcc; ++q) s_gacc[q][tid] = 0.f;
         if (tid < ng) {
             GAct g;
             activate(a, j, g);
@@ -709,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     }
     __syncthreads();
     if (tid < ng) {
-        const int64_t j = blk.g_begin + tid;
+        const int64_t j = g0 + tid;
         GAct g;
         activate(a, j, g);
         float GS[6];
@@ -815,8 +828,10 @@ hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, co
     if (a.n_blocks <= 0) return hipSuccess;
     const int use_lds = (max_subject_slices <= 512) ? 1 : 0;  // dynamic LDS 72 B per slice
     const size_t lds = use_lds ? (sizeof(float) + sizeof(unsigned long long)) * 6 * (size_t)max_subject_slices : 0;
-    hipLaunchKernelGGL(k_project_backward, dim3(a.n_blocks), dim3(kBlock), lds, st, a, offsets, counts,
-                       rec, rec_inst, inst_grad, n_inst, g_mean, g_log_scale, g_quat, g_amp, pose_acc, use_lds);
+    constexpr int NGS = kPartGauss;
+    hipLaunchKernelGGL(k_project_backward<NGS>, dim3(a.n_blocks * (kBlock / NGS)), dim3(kBlock), lds, st, a, offsets,
+                       counts, rec, rec_inst, inst_grad, n_inst, g_mean, g_log_scale, g_quat, g_amp, pose_acc,
+                       use_lds);
     return hipGetLastError();
 }
 
