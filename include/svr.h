@@ -414,18 +414,19 @@ int svr_get_timing(svr_ctx* ctx, svr_timer* out, int max_out, int* n_out);
 int svr_set_timing_stages(svr_ctx* ctx, uint32_t mask);
 
 /* ------------------------------------------------------------------------ */
-/* Autotuner (batched launch).  Times the forward and backward tile kernels
- * on the current bins for every tile size in {8,16,32}, forward mode in
+/* Autotuner (batched launch).  Times binning (svr_project_bin) and the
+ * forward and backward passes for every tile size in {8,16,32}, forward mode in
  * {0,1,2}, LDS batch in {32,64,128,256} (mode 0) and persistent in {0,1}
  * (those allowed by flags), picks the
  * fastest and makes it the context's configuration (re-binning when the tile
  * size changes).  params/grad_pred as in svr_project_bin / svr_backward
  * (grad_pred may be any DEVICE buffer of P floats).  Results are cached in the
- * context per shape bucket (pixels, records, instances rounded to powers of
- * two) and, when cache_path is non-NULL, in a small text file there.
+ * context per shape bucket (pixels and records rounded to powers of two, and
+ * the subject count: none of them depends on the configuration) and, when
+ * cache_path is non-NULL, in a small text file there.
  * out receives the chosen configuration; times_ms (HOST, may be NULL)
- * receives up to max_times measured (forward + backward) times in trial
- * order.  Synchronises the stream. */
+ * receives up to max_times measured (binning + forward + backward) times in
+ * trial order.  Synchronises the stream. */
 #define SVR_TUNE_TILE 1
 #define SVR_TUNE_BATCH 2
 #define SVR_TUNE_PERSISTENT 4

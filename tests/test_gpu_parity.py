@@ -234,6 +234,30 @@ def test_timing_stage_mask(ctx):
         ctx.svr_set_timing_stages(["no_such_stage"])
 
 
+def test_autotune_picks_a_timed_config_and_stays_correct(ctx, tmp_path):
+    """The autotuner times every candidate, installs the fastest, caches it
+    (in the context and in a file: a second call returns the same choice), and
+    the chosen configuration still matches the oracle."""
+    prob = synth.config1(0)
+    params, pose, target = _setup(prob)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
+    ctx.svr_set_geometry(prob)
+    dev = gpu_params(params, pose)
+    gp = torch.ones(prob.n_pixels, device="cuda")
+    cache = str(tmp_path / "tune.txt")
+    flags = svr.SVR_TUNE_TILE | svr.SVR_TUNE_MODE | svr.SVR_TUNE_PERSISTENT
+    cfg, times = ctx.svr_autotune(*dev, gp, flags=flags, cache_path=cache)
+    assert len(times) == 3 * 2 * 3 and all(t > 0 for t in times), times
+    assert cfg["tile"] in (8, 16, 32) and cfg["forward_mode"] in (0, 1, 2) and cfg["persistent"] in (0, 1)
+    assert ctx.svr_get_config()["tile"] == cfg["tile"]
+    cfg2, times2 = ctx.svr_autotune(*dev, gp, flags=flags, cache_path=cache)
+    assert cfg2 == cfg and times2 == []  # answered from the cache
+    out = _run(ctx, prob, params, pose, target)
+    ref = _oracle(prob, params, pose, target)
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1)  # the module's default
+    _compare(out, ref)
+
+
 def test_radix_sort_matches_stable_argsort(ctx):
     """The binning sort is a stable LSD radix sort: bit-exact against numpy's
     stable argsort, for key widths that take one to four passes of 8- or
