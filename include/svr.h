@@ -109,10 +109,13 @@ int64_t svr_num_pixels(const svr_ctx* ctx);
 
 /* Kernel configuration of the tile stages.  tile: 8, 16 or 32 (pixels per
  * tile side); batch: Gaussian records staged in LDS per step of the
- * pixel-per-lane forward, 32..256 and a multiple of 32; persistent (forward
- * only): 0 = one workgroup per tile, 1 = a persistent grid that pulls tiles
- * from a work queue ordered by decreasing instance count (the adjoint always
- * takes fixed chunks of 256 tile-ordered instances per workgroup); cutoff:
+ * pixel-per-lane forward, 32..256 and a multiple of 32; persistent: 0 = the
+ * record-per-lane forward (mode 1) and the adjoint take fixed chunks of 256
+ * tile-ordered instances per workgroup, modes 0 and 2 one workgroup per tile;
+ * 1 = a persistent grid that pulls whole tiles from a work queue ordered by
+ * decreasing instance count (every forward mode and the adjoint).  Chunks
+ * suit workloads whose instances sit in few tiles, the work queue workloads
+ * with many heavy tiles; svr_autotune measures both.  cutoff:
  * footprint radius T in
  * standard deviations, (0, 8]; forward_mode: 0 = pixel per lane (records
  * staged in LDS batches, deterministic summation order), 1 = record per lane

@@ -782,7 +782,7 @@ int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, co
     RenderArgs ra = render_args(c);
     {
         StageScope sc(c, ST_BACKWARD);
-        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_inst_grad.p, st));
+        HIPCHK(c, launch_backward(ra, grad_pred, grad_scale, c->d_inst_grad.p, c->d_work.p, st));
     }
     ProjectArgs pa = project_args(c);
     {

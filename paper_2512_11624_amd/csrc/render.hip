@@ -328,6 +328,187 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
     return b;
 }
 
+// Forward, record per lane, persistent grid (persistent = 1): workgroups pull
+// whole tiles heaviest-first from a work queue, with exact integer
+// accumulation.  Per round of up to 256 of the tile's instances: the boxes
+// are counting-sorted by shape in LDS (a wave's lanes then walk boxes of one
+// shape), each lane walks one box
+// rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum) to
+// the pixel's int32 LDS sum with an integer LDS atomic (float LDS atomics are
+// slow on this GPU, integer ones are not).  The quantum is 2^(e - 30) with
+// 2^e above the round's sum of |a|, so no pixel's round sum can overflow and
+// the rounding error per term is below 2^-31 of that sum.  Integer sums do
+// not depend on the order of the adds; each pixel's owner thread then adds
+// the round's total to its float sum in round order, so the result is
+// deterministic.
+template <int T, bool kLoss, bool kCount>
+__global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const float* __restrict__ target,
+                                                     const float* __restrict__ mask,
+                                                     const float* __restrict__ msum,
+                                                     float* __restrict__ pred, float* __restrict__ grad,
+                                                     float* __restrict__ tile_sse,
+                                                     unsigned long long* __restrict__ incut,
+                                                     int* __restrict__ work_counter) {
+    constexpr int NT = 256, NW = 4;
+    constexpr int kB = (T + 1) * (T + 1);
+    __shared__ float s_acc[T * T];
+    __shared__ int s_iacc[T * T];
+    __shared__ float4 s_box[NT][2];
+    __shared__ int s_hist[kB];
+    __shared__ int s_perm[NT];
+    __shared__ int s_wsum[NW];
+    __shared__ float s_fsum[NW];
+    __shared__ float s_red[NW];
+    __shared__ unsigned int s_cnt[NW];
+    __shared__ int s_next;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const float etau = a.etau;
+    const float tau2k = SVR_KZ * a.tau2;
+    const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
+    int iter = 0;
+    while (true) {
+        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
+        if (tile < 0) break;
+        const TileCoord tc = tile_coord(a, tile);
+        const int2 rg = a.ranges[tile];
+        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
+        __syncthreads();
+        for (int p = tid; p < T * T; p += NT) {
+            s_acc[p] = 0.f;
+            s_iacc[p] = 0;
+        }
+        unsigned int cnt = 0;
+        const int n = rg.y - rg.x;
+        for (int r0 = 0; r0 < n; r0 += NT) {
+            const int nb = min(NT, n - r0);
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+            __syncthreads();
+            int bucket = 0, pos = 0;
+            float absa = 0.f;
+            if (tid < nb) {
+                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
+                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+                const bool empty = w == 0 || h == 0;
+                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+                bucket = empty ? 0 : (h * (T + 1) + w);
+                absa = empty ? 0.f : fabsf(b.am);
+                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                           ((y1 + 1) << 24)));
+                pos = atomicAdd(&s_hist[bucket], 1);
+            }
+            for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
+            if (lane == 0) s_fsum[wv] = absa;
+            __syncthreads();
+            const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
+            {
+                const int per = (kB + NT - 1) / NT;
+                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+                int local = 0;
+                for (int k = kb; k < ke; ++k) local += s_hist[k];
+                int incl = local;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int u = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += u;
+                }
+                if (lane == 63) s_wsum[wv] = incl;
+                __syncthreads();
+                int run = incl - local;
+                for (int q = 0; q < wv; ++q) run += s_wsum[q];
+                for (int k = kb; k < ke; ++k) {
+                    const int c = s_hist[k];
+                    s_hist[k] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            if (tid < nb) s_perm[s_hist[bucket] + pos] = tid;
+            __syncthreads();
+            // quantum: the round's sum of |a| spans 2^30 quanta
+            const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
+            const float to_q = ldexpf(1.f, 30 - ex);
+            if (tid < nb) {
+                const int q = s_perm[tid];
+                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
+                const int pk = __float_as_int(p1.w);
+                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+                const float amq = p0.w * to_q;
+                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+                const int hh = (w > 0 && h > 0) ? h : 0;
+                const float dx0 = (float)bx0 - p0.x;
+                float dy = (float)by0 - p0.y;
+                int gr = by0 * T + bx0;
+                for (int r = 0; r < hh; ++r) {
+                    const float zy = fmaf(p1.z * dy, dy, p0.z), bxl = 2.f * p1.y * dy;
+                    float dx = dx0;
+                    int gi = gr;
+                    for (int c = 0; c < w; ++c) {
+                        const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
+                        if (v > 0.f) {
+                            atomicAdd(&s_iacc[gi], __float2int_rn(amq * v));
+                            if (kCount) ++cnt;
+                        }
+                        dx += 1.f;
+                        ++gi;
+                    }
+                    dy += 1.f;
+                    gr += T;
+                }
+            }
+            __syncthreads();
+            const float from_q = ldexpf(1.f, ex - 30);
+            for (int p = tid; p < T * T; p += NT) {
+                const int v = s_iacc[p];
+                if (v != 0) {
+                    s_acc[p] += (float)v * from_q;
+                    s_iacc[p] = 0;
+                }
+            }
+        }
+        __syncthreads();
+        float sq = 0.f;
+        for (int p = tid; p < T * T; p += NT) {
+            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
+            if (px < tc.W && py < tc.H) {
+                const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
+                const float acc = s_acc[p];
+                pred[pi] = acc;
+                if (kLoss) {
+                    const float m = mask[pi];
+                    const float r = acc - target[pi];
+                    loss_term(a.loss_kind, m, r, inv_msum, sq, grad ? grad + pi : nullptr);
+                }
+            }
+        }
+        if (kLoss || kCount) {
+            for (int o = 32; o > 0; o >>= 1) {
+                sq += __shfl_xor(sq, o, 64);
+                if (kCount) cnt += __shfl_xor(cnt, o, 64);
+            }
+            if (lane == 0) {
+                s_red[wv] = sq;
+                s_cnt[wv] = cnt;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                float t = 0.f;
+                unsigned long long c = 0;
+                for (int q = 0; q < NW; ++q) {
+                    t += s_red[q];
+                    c += s_cnt[q];
+                }
+                if (kLoss) tile_sse[tile] = t;
+                if (kCount && c) atomicAdd(incut, c);
+            }
+        }
+    }
+}
+
+
 // Epilogue of a tile whose sums are final: pred, and with kLoss the data
 // term's gradient and the tile's loss partial tile_sse[tile].  acc holds the
 // tile's T x T sums (tile-local row major).  Called by all threads of the
@@ -762,6 +943,156 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
     }
 }
 
+// Adjoint, record per lane, persistent grid (persistent = 1): workgroups pull
+// whole tiles heaviest-first from a work queue; the tile's upstream gradient
+// is staged in LDS and every lane walks one instance's box and sums, with
+// t = g e (inside the cut):
+//   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
+//   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
+// from which the gradient with respect to the stored record fields follows
+// (dz/d field, times amp ln 2).  The result goes to the instance's emission
+// slot, so no atomics are needed.  The walk is rows outer, columns inner,
+// with per-row sums folded in with dy (three accumulations per pixel instead
+// of seven).  A wave runs each loop as long as its largest trip count, so
+// each round of up to 256 instances is first ordered by (box height, box
+// width) with a counting sort in LDS, and lane j walks the j-th box: the
+// lanes of a wave then have boxes of the same shape.  Which lane walks which
+// instance changes no instance's sum, so the result stays deterministic.
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void k_backward_tiles(RenderArgs a, const float* __restrict__ grad_pred,
+                                                 const float* __restrict__ grad_scale,
+                                                 float4* __restrict__ inst_grad,
+                                                 int* __restrict__ work_counter) {
+    constexpr int kB = (T + 1) * (T + 1);
+    __shared__ float s_g[T * T];
+    __shared__ float4 s_box[NT][2];
+    __shared__ uint32_t s_slot[NT];
+    __shared__ int s_hist[kB + 1];
+    __shared__ int s_perm[NT];
+    __shared__ int s_wsum[NT / 64];
+    __shared__ int s_next;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const float etau = a.etau;
+    const float tau2k = SVR_KZ * a.tau2;
+    const float scale = grad_scale ? grad_scale[0] : 1.f;
+    int iter = 0;
+    while (true) {
+        const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
+        if (tile < 0) break;
+        const TileCoord tc = tile_coord(a, tile);
+        const int2 rg = a.ranges[tile];
+        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
+        __syncthreads();
+        for (int p = tid; p < T * T; p += NT) {
+            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
+            s_g[p] = (px < tc.W && py < tc.H) ? grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale : 0.f;
+        }
+        const int n = rg.y - rg.x;
+        for (int r0 = 0; r0 < n; r0 += NT) {
+            const int cnt = min(NT, n - r0);
+            __syncthreads();
+            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
+            __syncthreads();
+            int bucket = 0, pos = 0;
+            if (tid < cnt) {
+                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
+                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
+                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+                const bool empty = w == 0 || h == 0;
+                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
+                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
+                bucket = empty ? 0 : (h * (T + 1) + w);
+                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
+                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
+                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
+                                                           ((y1 + 1) << 24)));
+                s_slot[tid] = a.inst_idx[rg.x + r0 + tid];
+                pos = atomicAdd(&s_hist[bucket], 1);
+            }
+            __syncthreads();
+            {   // exclusive scan of the bucket counts: thread t takes a run of ceil(kB / NT)
+                const int per = (kB + NT - 1) / NT;
+                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
+                int local = 0;
+                for (int k = kb; k < ke; ++k) local += s_hist[k];
+                int incl = local;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int u = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += u;
+                }
+                if (lane == 63) s_wsum[wv] = incl;
+                __syncthreads();
+                int run = incl - local;
+                for (int q = 0; q < wv; ++q) run += s_wsum[q];
+                for (int k = kb; k < ke; ++k) {
+                    const int c = s_hist[k];
+                    s_hist[k] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+            if (tid < cnt) s_perm[s_hist[bucket] + pos] = tid;
+            __syncthreads();
+            if (tid < cnt) {
+                const int q = s_perm[tid];
+                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
+                const int pk = __float_as_int(p1.w);
+                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
+                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
+                const float pxl = p0.x, pyl = p0.y, bz = p0.z, am = p0.w;
+                const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
+                float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
+                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
+                const int hh = (w > 0 && h > 0) ? h : 0;
+                const float dx0 = (float)bx0 - pxl;
+                const float b2a01 = 2.f * a01;
+                float dy = (float)by0 - pyl;
+                int gr = by0 * T + bx0;
+                for (int r = 0; r < hh; ++r) {
+                    const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
+                    float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
+                    int gi = gr;
+                    for (int c = 0; c < w; ++c) {
+                        const float g = s_g[gi];
+                        const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
+                        const float v = e - etau;
+                        Sa = fmaf(g, fmaxf(v, 0.f), Sa);
+                        const float t = (v > 0.f) ? g * e : 0.f;
+                        const float tx = t * dx;
+                        R0 += t;
+                        R1 += tx;
+                        R2 = fmaf(tx, dx, R2);
+                        dx += 1.f;
+                        ++gi;
+                    }
+                    S0 += R0;
+                    Sx += R1;
+                    Sxx += R2;
+                    Sy = fmaf(dy, R0, Sy);
+                    Sxy = fmaf(dy, R1, Sxy);
+                    Syy = fmaf(dy * dy, R0, Syy);
+                    dy += 1.f;
+                    gr += T;
+                }
+                const float k2 = am * SVR_LN2;
+                float4 g0, g1;
+                g0.x = Sa;
+                g0.y = k2 * S0;
+                g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
+                g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
+                g1.x = k2 * Sxx;
+                g1.y = 2.f * k2 * Sxy;
+                g1.z = k2 * Syy;
+                g1.w = 0.f;
+                const uint32_t e_slot = s_slot[q];
+                inst_grad[2 * (int64_t)e_slot] = g0;
+                inst_grad[2 * (int64_t)e_slot + 1] = g1;
+            }
+        }
+    }
+}
+
+
 // Adjoint, record per lane, over fixed chunks of the sorted instance list:
 // workgroup b takes instances [256 b, 256 b + 256), which are ordered by tile
 // and may span several tiles, so every workgroup has one full round of work
@@ -1050,6 +1381,27 @@ hipError_t fwd_rol_dispatch(const RenderArgs& a, const float* target, const floa
 }
 
 template <int T>
+hipError_t fwd_rpl_tiles_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
+                                  float* pred, float* grad, float* tile_sse, unsigned long long* incut,
+                                  int* work_counter, int grid, hipStream_t st) {
+    const bool loss = target != nullptr;
+    const bool count = incut != nullptr;
+    if (loss && count)
+        hipLaunchKernelGGL((k_forward_rpl_tiles<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask,
+                           msum, pred, grad, tile_sse, incut, work_counter);
+    else if (loss)
+        hipLaunchKernelGGL((k_forward_rpl_tiles<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask,
+                           msum, pred, grad, tile_sse, incut, work_counter);
+    else if (count)
+        hipLaunchKernelGGL((k_forward_rpl_tiles<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask,
+                           msum, pred, grad, tile_sse, incut, work_counter);
+    else
+        hipLaunchKernelGGL((k_forward_rpl_tiles<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask,
+                           msum, pred, grad, tile_sse, incut, work_counter);
+    return hipGetLastError();
+}
+
+template <int T>
 hipError_t fwd_chunk_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
                               float* pred, float* grad, float* tile_sse, unsigned long long* incut,
                               float* partial, hipStream_t st) {
@@ -1085,7 +1437,7 @@ hipError_t fwd_chunk_dispatch(const RenderArgs& a, const float* target, const fl
 }
 
 size_t forward_partial_floats(const RenderArgs& a) {
-    if (a.forward_mode != 1 || a.n_inst <= 0) return 0;
+    if (a.forward_mode != 1 || a.persistent || a.n_inst <= 0) return 0;
     const int64_t n_chunks = (a.n_inst + 255) / 256;
     return (size_t)n_chunks * 2 * (size_t)a.tile * (size_t)a.tile;
 }
@@ -1104,6 +1456,15 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
             case 8: return fwd_rol_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
             case 16: return fwd_rol_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
             case 32: return fwd_rol_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.forward_mode == 1 && a.persistent) {
+        const int grid = grid_for(a, 256);
+        switch (a.tile) {
+            case 8: return fwd_rpl_tiles_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 16: return fwd_rpl_tiles_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 32: return fwd_rpl_tiles_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
             default: return hipErrorInvalidValue;
         }
     }
@@ -1171,11 +1532,30 @@ hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int3
 }
 
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           float4* inst_grad, hipStream_t st) {
+                           float4* inst_grad, int* work_counter, hipStream_t st) {
     if (a.n_tiles <= 0 || a.n_inst <= 0) return hipSuccess;
-    // four waves per chunk of 256 instances (one wave per tile measured
-    // slower: tiles with many instances then serialise on a single wave)
+    // four waves per workgroup (one wave per tile measured slower: tiles with
+    // many instances then serialise on a single wave)
     constexpr int NT = 256;
+    if (a.persistent) {  // whole tiles, heaviest first, from a work queue
+        hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
+        if (e != hipSuccess) return e;
+        const int grid = grid_for(a, NT);
+        switch (a.tile) {
+            case 8:
+                hipLaunchKernelGGL((k_backward_tiles<8, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                break;
+            case 16:
+                hipLaunchKernelGGL((k_backward_tiles<16, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                break;
+            case 32:
+                hipLaunchKernelGGL((k_backward_tiles<32, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    // fixed chunks of 256 instances of the tile-ordered list
     const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
     if (n_chunks > 0x7fffffffLL - 8) return hipErrorInvalidValue;
     const int grid = (int)(((n_chunks + 7) >> 3) << 3);  // whole XCD remap

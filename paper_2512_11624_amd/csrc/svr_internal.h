@@ -191,7 +191,7 @@ hipError_t launch_scale_reg(const float* log_scale, int64_t n, float lambda, flo
 hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int32_t m,
                                 const float* msum, float* slice_sse, float* loss, hipStream_t st);
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
-                           float4* inst_grad, hipStream_t st);
+                           float4* inst_grad, int* work_counter, hipStream_t st);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 struct AdamSeg {
