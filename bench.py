@@ -13,7 +13,7 @@ full fitting iteration; inputs are resident in HBM before timing starts.
 value = Gaussian-pixel pairs inside the 3-sigma footprint per step (counted
 by the forward kernel) / seconds per step.
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: the hot path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -37,7 +37,7 @@ PEAK_FP32 = 157.3e12      # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12         # MI355X HBM3E, B/s
 LR = [2.5e-2, 2.5e-2, 1e-2, 1e-2, 2.5e-3, 1e-1]   # mean, scale, quat, amp, rotation, translation
 
-# Algorithmic work per unit ("Roofline accounting").
+# Algorithmic work per unit: FLOP count a multiply-add as 2 and an exp2 as 1.
 FLOP_FWD_PAIR = 13.0      # 12 FLOP + 1 exp per in-cut pixel-Gaussian pair
 FLOP_BWD_PAIR = 32.0      # 31 FLOP + 1 exp per in-cut pair (recomputation included)
 FLOP_CULL_CAND = 25.0     # plane test per (slice, Gaussian) candidate
@@ -260,8 +260,9 @@ def main():
                     help="only copy 256 MiB device to device three times (calibrates the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the hot path on one GPU only; multi-GPU runs are not supported "
-              "(see DESIGN.md, 'How the path would shard').", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU only; multi-GPU runs are not supported "
+              "(a slice-parallel split with an all-reduce of the parameter gradients is how it would shard).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -443,7 +443,7 @@ int svr_autotune(svr_ctx* ctx, const svr_params* params, const float* grad_pred,
  * slice (its 32x32 centre upsampled x4, bilinear) plus the slice's nominal
  * placement (stack rotation R0, 9 floats, and nominal centre t0 / 16 mm, 3
  * floats) to a 6-DoF pose delta (omega, tau) that initialises the
- * slice's pose; the plain pose optimisation stays the judge (a proposal is
+ * slice's pose; the plain pose optimisation has the last word (a proposal is
  * only kept where it lowers the slice's forward-model error).  Architecture:
  * 6 x [3x3 conv, stride 2, pad 1, ReLU] with 32, 32, 64, 64, 128, 128
  * channels (128^2 -> 2^2), flatten (512) || placement (12), FC 524 -> 256

@@ -1,7 +1,7 @@
 """FP64 CPU oracle for the Gaussian-primitive slice acquisition model.
 
 TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
-baseline leg use it to judge the HIP path.  The product path never imports it.
+baseline leg use it to check the HIP path.  The product path never imports it.
 
 * ``core``  -- ctypes wrapper of the C oracle (world frame, FP64, OpenMP).
 * ``brute`` -- NumPy brute force over every (slice, pixel, Gaussian) triple.

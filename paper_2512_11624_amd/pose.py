@@ -15,7 +15,7 @@ kernels, and the acceptance test uses the forward model's per-slice error.
   output: the 6-DoF motion in scaled units (omega / 0.25 rad, tau / 8 mm).
 * Acceptance: a proposed pose is kept for a slice only where it lowers that
   slice's forward-model error (masked SSE) against the current volume; the
-  plain pose optimisation remains the judge.
+  plain pose optimisation has the last word.
 """
 from __future__ import annotations
 
