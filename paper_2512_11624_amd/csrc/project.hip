@@ -257,6 +257,11 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
             Proj p;
             project(g, sp, sg.sig2, tau2, p);
             const Box bx = pixel_box(p, sg, tau2);
+            if (!kEmit) {  // count pass: no branch around the counters
+                nrec += 1;
+                ninst += bx.nonempty ? (bx.kx1 / T - bx.kx0 / T + 1) * (bx.ky1 / T - bx.ky0 / T + 1) : 0;
+                continue;
+            }
             if (!bx.nonempty) {
                 // the plane crosses the footprint outside the slice: a null record
                 if (kEmit && nrec < cap.x) {
