@@ -1,0 +1,40 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, the roofline
+arithmetic and the matching of committed traffic records."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""  # no JSON line
+
+
+@pytest.mark.parametrize("stage,per_pair", [("backward_tile", bench.FLOP_BWD_PAIR), ("forward_tile", bench.FLOP_FWD_PAIR)])
+def test_stage_roofline_is_work_over_time(stage, per_pair):
+    bound, achieved, peak, unit, work = bench.stage_roofline(stage, 0.5, {}, 1e8)
+    assert bound == "alu" and unit == "TFLOP/s" and peak == pytest.approx(157.3)
+    assert work == pytest.approx(per_pair * 1e8)
+    assert achieved == pytest.approx(per_pair * 1e8 / 0.5e-3 / 1e12)
+
+
+def test_traffic_record_needs_matching_stage_tile_and_workload():
+    assert bench.measured_traffic("backward_tile", 8, "no-such-workload") is None
+    assert bench.measured_traffic("no_such_stage", 32, "head") is None
+    # a committed record, when present, belongs to the current kernel sources
+    for fn in os.listdir(os.path.join(ROOT, "profiles")):
+        with open(os.path.join(ROOT, "profiles", fn)) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                    assert {"stage", "tile", "workload", "source", "bytes_per_launch"} <= set(kv), fn
+                    assert float(kv["bytes_per_launch"]) > 0
