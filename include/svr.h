@@ -29,9 +29,10 @@
  *     by the caller and never freed by the library.  HOST pointers are read
  *     during the call only.
  *   - All device work is enqueued asynchronously on the context's stream.
- *     svr_project_bin is the one call that synchronises that stream (it reads
- *     the record and instance counts back); svr_get_stats with
- *     SVR_STATS_SYNC also does.
+ *     svr_project_bin is the one call of the iteration that synchronises that
+ *     stream (it reads the record and instance counts back), unless the
+ *     context has a fixed capacity (svr_set_capacity); svr_get_stats with
+ *     SVR_STATS_SYNC and svr_check_status also do.
  *   - Argument checks run on the host before any launch.
  *   - A context is not thread safe; use one context per host thread.
  */
@@ -42,7 +43,7 @@
 extern "C" {
 #endif
 
-#define SVR_ABI_VERSION 1
+#define SVR_ABI_VERSION 2
 
 typedef enum {
     SVR_OK = 0,
@@ -50,7 +51,8 @@ typedef enum {
     SVR_ERR_HIP = -2,       /* HIP runtime error or no usable GPU */
     SVR_ERR_CAPACITY = -3,  /* a count exceeds a representable or configured limit */
     SVR_ERR_STATE = -4,     /* calls out of order (e.g. forward before project_bin) */
-    SVR_ERR_NODEVICE = -5   /* compute call on a host-only context */
+    SVR_ERR_NODEVICE = -5,  /* compute call on a host-only context */
+    SVR_ERR_NONFINITE = -6  /* a checked input or output is NaN or infinite (svr_set_checks) */
 } svr_status;
 
 typedef struct svr_ctx svr_ctx;
@@ -230,10 +232,11 @@ typedef struct {
  * the instances by (slice, tile) with a stable LDS radix sort and builds
  * per-tile ranges.  The records stay valid until the next call; svr_forward
  * and svr_backward use them and assume the parameters have not changed.
- * Synchronises the stream once to read the counts.  Errors: SVR_ERR_STATE
- * without geometry, SVR_ERR_ARG for null pointers or N different from the
- * geometry's Gaussian count, SVR_ERR_CAPACITY above 2^31-1 records or
- * instances. */
+ * Synchronises the stream once to read the counts (not in fixed-capacity
+ * mode, see svr_set_capacity).  Errors: SVR_ERR_STATE without geometry,
+ * SVR_ERR_ARG for null pointers or N different from the geometry's Gaussian
+ * count, SVR_ERR_CAPACITY above 2^31-1 records or instances,
+ * SVR_ERR_NONFINITE (with SVR_CHECK_FINITE) for a non-finite parameter. */
 int svr_project_bin(svr_ctx* ctx, const svr_params* params);
 
 /* Forward model and masked-MSE loss (Eq. 5 with the exact amplitude; the
@@ -361,7 +364,10 @@ int svr_adam_vector(svr_ctx* ctx, float* p, const float* g, float* exp_avg, floa
                     const svr_adam* hp, int64_t step);
 
 /* Counters of the last svr_project_bin / svr_forward.  Record and instance
- * counts are exact after svr_project_bin.  n_incut (pairs inside the cutoff,
+ * counts are exact after svr_project_bin (in fixed-capacity mode only after a
+ * call with SVR_STATS_SYNC, which reads them from the device).
+ * n_fallback_blocks is read (synchronising the stream) only with
+ * SVR_STATS_SYNC.  n_incut (pairs inside the cutoff,
  * i.e. Gaussian-pixel terms that contribute) is counted by svr_forward only
  * when flags has SVR_STATS_SYNC set at the *next* svr_get_stats call after a
  * forward run with counting enabled via svr_set_count_pairs(ctx, 1); the
@@ -378,11 +384,51 @@ typedef struct {
     int64_t n_evaluated;    /* pixel-record evaluations the forward tile kernel performs */
     int32_t key_bits;       /* bits of the sort key */
     int32_t sort_passes;
+    int64_t n_fallback_blocks;  /* Gaussian blocks of 256 whose records exceeded the emission
+                                   kernel's LDS list and were emitted per lane; -1 if not read */
 } svr_stats;
 
 #define SVR_STATS_SYNC 1
 int svr_set_count_pairs(svr_ctx* ctx, int enable);
 int svr_get_stats(svr_ctx* ctx, int flags, svr_stats* out);
+
+/* ------------------------------------------------------------------------ */
+/* Fixed-capacity binning (no host synchronisation).  By default
+ * svr_project_bin reads the record and instance counts back to size its
+ * buffers, which synchronises the stream once per call.  svr_set_capacity
+ * with max_records > 0 and max_instances > 0 allocates the binning buffers
+ * for those counts now (this call synchronises) and switches svr_project_bin
+ * to a mode that never reads back, never allocates and never synchronises:
+ * counts stay on the device, the sort and the tile stages always cover
+ * max_instances slots (unused slots carry a padding key that sorts after every
+ * tile and is skipped), so their cost follows the capacity, not the count.
+ * When a call needs more records or instances than the capacity, it writes
+ * nothing out of bounds: the binning is left empty (every prediction and
+ * gradient of that iteration is 0) and the condition is recorded on the
+ * device; svr_check_status then returns SVR_ERR_CAPACITY with the needed
+ * counts.  max_records = max_instances = 0 returns to the default mode.
+ * Errors: SVR_ERR_ARG for negative values or only one of them 0,
+ * SVR_ERR_CAPACITY above 2^31-1, SVR_ERR_HIP if the allocation fails. */
+int svr_set_capacity(svr_ctx* ctx, int64_t max_records, int64_t max_instances);
+
+/* Finite checks.  With flags & SVR_CHECK_FINITE, svr_project_bin checks
+ * every Gaussian parameter and slice pose, svr_forward every predicted
+ * pixel and svr_backward every gradient it writes, on the device.  A
+ * non-finite value is recorded on the device; svr_project_bin in the default
+ * mode returns SVR_ERR_NONFINITE itself (it synchronises anyway, and then
+ * leaves the binning invalid), the other calls report it through
+ * svr_check_status.  Default: no checks (they cost one extra read of the
+ * checked arrays).  Errors: SVR_ERR_ARG for unknown flags. */
+#define SVR_CHECK_FINITE 1
+int svr_set_checks(svr_ctx* ctx, int flags);
+
+/* Synchronises the context's stream and returns the conditions recorded on
+ * the device since the last svr_check_status (or project_bin that reported
+ * one), then clears them: SVR_ERR_CAPACITY (a fixed-capacity binning was too
+ * small; needed_records / needed_instances, HOST, may be NULL, receive the
+ * counts it needed), else SVR_ERR_NONFINITE (a finite check failed), else
+ * SVR_OK. */
+int svr_check_status(svr_ctx* ctx, int64_t* needed_records, int64_t* needed_instances);
 
 /* Stable radix sort used by tile binning, exposed for verification: sorts the
  * n (key, value) pairs in place by the low key_bits bits of the key (1..32),

@@ -133,6 +133,12 @@ struct svr_ctx {
     DevBuf<char> d_tsort_tmp;
     const int32_t* tile_order = nullptr;
 
+    // fixed-capacity binning (cap_rec > 0): no count read-back in project_bin
+    int64_t cap_rec = 0, cap_inst = 0;
+    int check_flags = 0;            // SVR_CHECK_*
+    DevBuf<DevStatus> d_status;     // conditions recorded on the device
+    DevStatus* h_status = nullptr;  // pinned read-back of d_status
+
     // binning state
     bool binned = false;
     int64_t n_rec = 0, n_inst = 0, n_cand = 0;
@@ -432,12 +438,44 @@ int build_tile_order(svr_ctx* c) {
     return SVR_OK;
 }
 
+// Binning buffers for nrec records and ninst instance slots.
+int ensure_bin_buffers(svr_ctx* c, int64_t nrec, int64_t ninst) {
+    HIPCHK(c, ensure(c->d_fallback, (size_t)std::max(c->n_blocks, 1)));
+    HIPCHK(c, ensure(c->d_rec, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_rec_inst, (size_t)nrec));
+    HIPCHK(c, ensure(c->d_inst_grad, 2 * (size_t)ninst));
+    HIPCHK(c, ensure(c->d_keys, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_vals, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_keys2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_vals2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_idx, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_idx2, (size_t)ninst));
+    HIPCHK(c, ensure(c->d_sort_tmp, sort_tmp_bytes(ninst)));
+    return SVR_OK;
+}
+
+// Finite check of the Gaussian parameters and poses (SVR_CHECK_FINITE).
+int check_params_finite(svr_ctx* c, const svr_params* p) {
+    hipStream_t st = c->stream;
+    HIPCHK(c, launch_check_finite(p->mean, 3 * c->N, c->d_status.p, st));
+    HIPCHK(c, launch_check_finite(p->log_scale, 3 * c->N, c->d_status.p, st));
+    HIPCHK(c, launch_check_finite(p->quat, 4 * c->N, c->d_status.p, st));
+    HIPCHK(c, launch_check_finite(p->amp, c->N, c->d_status.p, st));
+    HIPCHK(c, launch_check_finite(p->pose, 6 * (int64_t)c->M, c->d_status.p, st));
+    return SVR_OK;
+}
+
 int project_bin_impl(svr_ctx* c, const svr_params* p) {
     hipStream_t st = c->stream;
+    const bool fixed = c->cap_rec > 0;
     c->params = *p;
     c->binned = false;
     c->incut_pending = false;
     c->n_incut = -1;
+    if (c->check_flags & SVR_CHECK_FINITE) {
+        int rc = check_params_finite(c, p);
+        if (rc != SVR_OK) return rc;
+    }
     {
         StageScope sc(c, ST_SLICE_POSE);
         HIPCHK(c, launch_slice_pose(c->d_geo.p, p->pose, c->d_pose.p, c->M, st));
@@ -454,11 +492,28 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
         StageScope sc(c, ST_SCAN);
         HIPCHK(c, launch_scan_int2(c->d_counts.p, c->d_offsets.p, c->N, c->d_totals.p, c->d_scan_tmp.p, st));
     }
-    HIPCHK(c, hipMemcpyAsync(c->h_totals, c->d_totals.p, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    const long long nrec = c->h_totals[0], ninst = c->h_totals[1];
-    if (nrec > 0x7fffffffLL || ninst > 0x7fffffffLL)
-        return fail(c, SVR_ERR_CAPACITY, "records (%lld) or instances (%lld) exceed 2^31-1", nrec, ninst);
+    int64_t nrec, ninst;
+    if (fixed) {
+        // counts stay on the device; an iteration that needs more than the
+        // capacity bins nothing and records the needed counts
+        HIPCHK(c, launch_fixed_capacity(c->d_totals.p, c->cap_rec, c->cap_inst, c->d_counts.p, c->N, c->d_status.p, st));
+        nrec = c->cap_rec;
+        ninst = c->cap_inst;
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->h_totals, c->d_totals.p, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
+        if (c->check_flags & SVR_CHECK_FINITE)
+            HIPCHK(c, hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if ((c->check_flags & SVR_CHECK_FINITE) && (c->h_status->bits & kStatusNonfinite)) {
+            HIPCHK(c, launch_fill_zero(c->d_status.p, sizeof(DevStatus), st));
+            return fail(c, SVR_ERR_NONFINITE, "a Gaussian parameter or slice pose is NaN or infinite");
+        }
+        nrec = c->h_totals[0];
+        ninst = c->h_totals[1];
+        if (nrec > 0x7fffffffLL || ninst > 0x7fffffffLL)
+            return fail(c, SVR_ERR_CAPACITY, "records (%lld) or instances (%lld) exceed 2^31-1", (long long)nrec,
+                        (long long)ninst);
+    }
     c->n_rec = nrec;
     c->n_inst = ninst;
     int64_t cand = 0;
@@ -468,21 +523,16 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
         cand += (c->gauss_off[s + 1] - c->gauss_off[s]) * (int64_t)ns;
     }
     c->n_cand = cand;
-    HIPCHK(c, ensure(c->d_fallback, (size_t)std::max(c->n_blocks, 1)));
-    HIPCHK(c, ensure(c->d_rec, (size_t)nrec));
-    HIPCHK(c, ensure(c->d_rec_inst, (size_t)nrec));
-    HIPCHK(c, ensure(c->d_inst_grad, 2 * (size_t)ninst));
-    HIPCHK(c, ensure(c->d_keys, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_vals, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_keys2, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_vals2, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_idx, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_idx2, (size_t)ninst));
-    HIPCHK(c, ensure(c->d_sort_tmp, sort_tmp_bytes(ninst)));
+    {
+        int rc = ensure_bin_buffers(c, nrec, ninst);
+        if (rc != SVR_OK) return rc;
+    }
     {
         StageScope sc(c, ST_EMIT);
         HIPCHK(c, launch_emit(pa, c->d_counts.p, c->d_offsets.p, c->d_rec.p, c->d_rec_inst.p, c->d_keys.p,
-                              c->d_vals.p, c->d_fallback.p, st));
+                              c->d_vals.p, c->d_fallback.p, fixed ? &c->d_status.p->overflow : nullptr, st));
+        if (fixed)
+            HIPCHK(c, launch_pad_instances(c->d_keys.p, c->d_vals.p, ninst, c->d_totals.p, c->d_status.p, st));
     }
     bool alt = false;
     {
@@ -521,6 +571,7 @@ const char* svr_status_string(int s) {
         case SVR_ERR_CAPACITY: return "SVR_ERR_CAPACITY";
         case SVR_ERR_STATE: return "SVR_ERR_STATE";
         case SVR_ERR_NODEVICE: return "SVR_ERR_NODEVICE";
+        case SVR_ERR_NONFINITE: return "SVR_ERR_NONFINITE";
         default: return "SVR_ERR_UNKNOWN";
     }
 }
@@ -552,6 +603,16 @@ int svr_ctx_create(svr_ctx** out, int device, void* hip_stream) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->n_cu = cus;
     if (hipHostMalloc((void**)&c->h_totals, 4 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SVR_ERR_HIP;
+    }
+    if (hipHostMalloc((void**)&c->h_status, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess ||
+        ensure(c->d_status, 1) != hipSuccess ||
+        launch_fill_zero(c->d_status.p, sizeof(DevStatus), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (c->h_status) (void)hipHostFree(c->h_status);
+        release(c->d_status);
+        (void)hipHostFree(c->h_totals);
         delete c;
         return SVR_ERR_HIP;
     }
@@ -590,6 +651,8 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_topk_iperm); release(c->d_topk_lint); release(c->d_topk_qoff); release(c->d_topk_pxw);
         release(c->d_topk_pyd);
         if (c->h_totals) (void)hipHostFree(c->h_totals);
+        if (c->h_status) (void)hipHostFree(c->h_status);
+        release(c->d_status);
         for (auto& p : c->pending) {
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
@@ -759,6 +822,7 @@ int svr_forward(svr_ctx* c, const float* target, const float* mask, float* pred,
         HIPCHK(c, launch_loss_finalize(c->d_tile_sse.p, c->d_geo.p, c->M,
                                        c->loss_kind == SVR_LOSS_MSE ? c->d_msum.p : nullptr, sse, loss, st));
     }
+    if (c->check_flags & SVR_CHECK_FINITE) HIPCHK(c, launch_check_finite(pred, c->P, c->d_status.p, st));
     c->incut_pending = c->count_pairs;
     return SVR_OK;
 }
@@ -794,6 +858,13 @@ int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, co
     {
         StageScope sc(c, ST_POSE_CHAIN);
         HIPCHK(c, launch_pose_chain(c->params.pose, c->d_pose_acc.p, out->pose, c->M, st));
+    }
+    if (c->check_flags & SVR_CHECK_FINITE) {
+        HIPCHK(c, launch_check_finite(out->mean, 3 * c->N, c->d_status.p, st));
+        HIPCHK(c, launch_check_finite(out->log_scale, 3 * c->N, c->d_status.p, st));
+        HIPCHK(c, launch_check_finite(out->quat, 4 * c->N, c->d_status.p, st));
+        HIPCHK(c, launch_check_finite(out->amp, c->N, c->d_status.p, st));
+        HIPCHK(c, launch_check_finite(out->pose, 6 * (int64_t)c->M, c->d_status.p, st));
     }
     return SVR_OK;
 }
@@ -1248,17 +1319,97 @@ int svr_get_stats(svr_ctx* c, int flags, svr_stats* out) {
         // full tile of pixels (before per-wave row culling)
         out->n_evaluated = c->n_inst * (int64_t)c->cfg.tile * c->cfg.tile;
     }
-    if ((flags & SVR_STATS_SYNC) && c->incut_pending && !c->host_only) {
+    out->n_fallback_blocks = -1;
+    const bool fixed = c->cap_rec > 0;
+    if (fixed && c->binned) {  // the host holds only the capacity
+        out->n_records = -1;
+        out->n_instances = -1;
+        out->n_evaluated = -1;
+    }
+    if ((flags & SVR_STATS_SYNC) && !c->host_only) {
         int rc = enter(c);
         if (rc != SVR_OK) return rc;
-        unsigned long long h = 0;
-        HIPCHK(c, hipMemcpyAsync(&h, c->d_incut.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        c->n_incut = (int64_t)h;
-        c->incut_pending = false;
+        if (c->incut_pending) {
+            unsigned long long h = 0;
+            HIPCHK(c, hipMemcpyAsync(&h, c->d_incut.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            c->n_incut = (int64_t)h;
+            c->incut_pending = false;
+        }
+        if (c->binned) {
+            std::vector<int> fb((size_t)std::max(c->n_blocks, 0));
+            if (!fb.empty())
+                HIPCHK(c, hipMemcpyAsync(fb.data(), c->d_fallback.p, fb.size() * sizeof(int), hipMemcpyDeviceToHost,
+                                         c->stream));
+            long long tot[2] = {0, 0};
+            if (fixed) HIPCHK(c, hipMemcpyAsync(tot, c->d_totals.p, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            int64_t nf = 0;
+            for (int v : fb) nf += v != 0;
+            out->n_fallback_blocks = nf;
+            if (fixed) {
+                out->n_records = tot[0];
+                out->n_instances = tot[1];
+                out->n_evaluated = tot[1] * (int64_t)c->cfg.tile * c->cfg.tile;
+            }
+        }
     }
     out->n_incut = c->n_incut;
     return SVR_OK;
+}
+
+int svr_set_capacity(svr_ctx* c, int64_t max_records, int64_t max_instances) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (max_records < 0 || max_instances < 0 || ((max_records == 0) != (max_instances == 0)))
+        return fail(c, SVR_ERR_ARG, "capacities must both be positive, or both 0 (got %lld, %lld)",
+                    (long long)max_records, (long long)max_instances);
+    if (max_records > 0x7fffffffLL || max_instances > 0x7fffffffLL)
+        return fail(c, SVR_ERR_CAPACITY, "capacities above 2^31-1");
+    c->binned = false;
+    c->cap_rec = max_records;
+    c->cap_inst = max_instances;
+    if (max_records == 0 || c->host_only) return SVR_OK;
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    rc = ensure_bin_buffers(c, max_records, max_instances);
+    if (rc != SVR_OK) {
+        c->cap_rec = c->cap_inst = 0;
+        return rc;
+    }
+    return SVR_OK;
+}
+
+int svr_set_checks(svr_ctx* c, int flags) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (flags & ~SVR_CHECK_FINITE) return fail(c, SVR_ERR_ARG, "unknown check flags 0x%x", flags);
+    c->check_flags = flags;
+    return SVR_OK;
+}
+
+int svr_check_status(svr_ctx* c, int64_t* needed_records, int64_t* needed_instances) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (needed_records) *needed_records = 0;
+    if (needed_instances) *needed_instances = 0;
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->h_status, c->d_status.p, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const DevStatus h = *c->h_status;
+    if (h.bits == 0) return SVR_OK;
+    // clear the recorded conditions (the overflow flag of the last binning stays)
+    HIPCHK(c, launch_fill_zero(&c->d_status.p->bits, sizeof(unsigned int), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h.bits & kStatusCapacity) {
+        if (needed_records) *needed_records = h.need_rec;
+        if (needed_instances) *needed_instances = h.need_inst;
+        return fail(c, SVR_ERR_CAPACITY, "a fixed-capacity binning needed %lld records and %lld instances",
+                    (long long)h.need_rec, (long long)h.need_inst);
+    }
+    return fail(c, SVR_ERR_NONFINITE, "a checked parameter, prediction or gradient was NaN or infinite");
 }
 
 int svr_set_timing(svr_ctx* c, int enable) {

@@ -228,9 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
                                                  const int2* __restrict__ offsets,
                                                  Record* __restrict__ rec, int2* __restrict__ rec_inst,
                                                  uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals, const int* __restrict__ only) {
+                                                 uint32_t* __restrict__ vals, const int* __restrict__ only,
+                                                 const int* __restrict__ overflow) {
     __shared__ uint16_t s_list[kList][kBlock];
     if (kEmit && only && only[blockIdx.x] == 0) return;  // emitted by the coalesced path
+    if (kEmit && overflow && *overflow) return;          // fixed capacity exceeded: nothing is written
     const GaussBlock blk = a.blocks[blockIdx.x];
     const SubjectInfo si = a.subj[blk.subject];
     const int64_t j = blk.g_begin + threadIdx.x;
@@ -345,7 +347,8 @@ constexpr int kEmitCap = 6144;  // list entries per block
 __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __restrict__ counts,
                                                  const int2* __restrict__ offsets, Record* __restrict__ rec,
                                                  int2* __restrict__ rec_inst, uint32_t* __restrict__ keys,
-                                                 uint32_t* __restrict__ vals, int* __restrict__ fallback) {
+                                                 uint32_t* __restrict__ vals, int* __restrict__ fallback,
+                                                 const int* __restrict__ overflow) {
     __shared__ uint32_t s_list[kEmitCap];
     __shared__ float s_act[11][kBlock];
     __shared__ int s_wsum[kBlock / 64];
@@ -358,6 +361,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
     const int64_t R1 = offsets[blk.g_end - 1].x + counts[blk.g_end - 1].x;
     const int64_t I1 = offsets[blk.g_end - 1].y + counts[blk.g_end - 1].y;
     const int nrec_blk = (int)(R1 - R0);
+    if (overflow && *overflow) {  // fixed capacity exceeded: nothing is written
+        if (tid == 0) fallback[blockIdx.x] = 0;
+        return;
+    }
     if (nrec_blk > kEmitCap) {
         if (tid == 0) fallback[blockIdx.x] = 1;
         return;
@@ -811,17 +818,18 @@ hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st)
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cull<false>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts,
                        (const int2*)nullptr, (Record*)nullptr, (int2*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                       (const int*)nullptr);
+                       (const int*)nullptr, (const int*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, hipStream_t st) {
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, const int* overflow,
+                       hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(a.n_blocks), dim3(kBlock), 0, st, a, counts, offsets, rec, rec_inst, keys, vals,
-                       fallback);
+                       fallback, overflow);
     hipLaunchKernelGGL(k_cull<true>, dim3(a.n_blocks), dim3(kBlock), 0, st, a, const_cast<int2*>(counts),
-                       offsets, rec, rec_inst, keys, vals, (const int*)fallback);
+                       offsets, rec, rec_inst, keys, vals, (const int*)fallback, overflow);
     return hipGetLastError();
 }
 

@@ -427,8 +427,10 @@ __global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const f
             __syncthreads();
             if (tid < nb) s_perm[s_hist[bucket] + pos] = tid;
             __syncthreads();
-            // quantum: the round's sum of |a| spans 2^30 quanta
-            const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
+            // quantum: the round's sum of |a| spans 2^30 quanta.  A non-finite
+            // amplitude has no quantum: the round's pixels become NaN below.
+            const bool bad = !(suma <= 3.4028235e38f);
+            const int ex = (suma > 0.f && !bad) ? ilogbf(suma) + 1 : 0;
             const float to_q = ldexpf(1.f, 30 - ex);
             if (tid < nb) {
                 const int q = s_perm[tid];
@@ -463,8 +465,9 @@ __global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const f
             const float from_q = ldexpf(1.f, ex - 30);
             for (int p = tid; p < T * T; p += NT) {
                 const int v = s_iacc[p];
+                if (bad) s_acc[p] = __builtin_nanf("");
                 if (v != 0) {
-                    s_acc[p] += (float)v * from_q;
+                    if (!bad) s_acc[p] += (float)v * from_q;
                     s_iacc[p] = 0;
                 }
             }
@@ -688,8 +691,10 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         __syncthreads();
         if (act) s_perm[s_hist[bucket] + pos] = tid;
         __syncthreads();
-        // quantum: the pass's sum of |a| spans 2^30 quanta
-        const int ex = suma > 0.f ? ilogbf(suma) + 1 : 0;
+        // quantum: the pass's sum of |a| spans 2^30 quanta.  A non-finite
+        // amplitude has no quantum: the pass's pixels become NaN below.
+        const bool bad = !(suma <= 3.4028235e38f);
+        const int ex = (suma > 0.f && !bad) ? ilogbf(suma) + 1 : 0;
         const float to_q = ldexpf(1.f, 30 - ex);
         if (tid < s_hist[kB]) {
             const int q = s_perm[tid];
@@ -722,7 +727,7 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         }
         __syncthreads();
         const float from_q = ldexpf(1.f, ex - 30);
-        for (int q = tid; q < np * T * T; q += NT) s_facc[q] = (float)s_iacc[q] * from_q;
+        for (int q = tid; q < np * T * T; q += NT) s_facc[q] = bad ? __builtin_nanf("") : (float)s_iacc[q] * from_q;
         __syncthreads();
         for (int sl = 0; sl < np; ++sl) {
             const int f = s_fin[sl];

@@ -94,10 +94,32 @@ struct Record {
 //   (d amp, d beta', d p*_x, d p*_y | d A'_00, d A'_01, d A'_11, unused)
 // A record's instances occupy the contiguous slots rec_inst[r] = (first, count).
 
+// Conditions recorded on the device by the library's calls, read and cleared
+// by svr_check_status.
+constexpr unsigned int kStatusCapacity = 1u;   // a fixed-capacity binning did not fit
+constexpr unsigned int kStatusNonfinite = 2u;  // a finite check failed
+struct DevStatus {
+    unsigned int bits;
+    int overflow;          // the last fixed-capacity binning did not fit (its binning is empty)
+    long long need_rec;    // counts that binning needed
+    long long need_inst;
+};
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (one per translation unit), all asynchronous on stream.
 // ---------------------------------------------------------------------------
 namespace svr {
+
+// csrc/status.hip: any element of x [n] non-finite -> st->bits |= kStatusNonfinite.
+hipError_t launch_check_finite(const float* x, int64_t n, DevStatus* st, hipStream_t s);
+// Fixed-capacity binning: when totals [2] (records, instances) exceed the
+// capacity, zero every Gaussian's counts [n] and record the needed counts.
+hipError_t launch_fixed_capacity(const long long* totals, int64_t cap_rec, int64_t cap_inst, int2* counts,
+                                 int64_t n, DevStatus* st, hipStream_t s);
+// Padding keys for instance slots [valid, cap), valid = 0 after an overflow
+// else totals[1].
+hipError_t launch_pad_instances(uint32_t* keys, uint32_t* vals, int64_t cap, const long long* totals,
+                                const DevStatus* st, hipStream_t s);
 
 struct ProjectArgs {
     const float* mean;
@@ -121,8 +143,10 @@ hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* 
                              hipStream_t st);
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st);
 // fallback: int per Gaussian block (scratch, written by the first kernel)
+// overflow (may be NULL): when *overflow != 0 the emission writes nothing.
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
-                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, hipStream_t st);
+                       int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, const int* overflow,
+                       hipStream_t st);
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
                                    const Record* rec, const int2* rec_inst, const float4* inst_grad,
                                    int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,

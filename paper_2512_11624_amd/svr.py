@@ -20,6 +20,8 @@ _lib = None
 _lock = threading.Lock()
 
 SVR_OK, SVR_ERR_ARG, SVR_ERR_HIP, SVR_ERR_CAPACITY, SVR_ERR_STATE, SVR_ERR_NODEVICE = 0, -1, -2, -3, -4, -5
+SVR_ERR_NONFINITE = -6
+SVR_CHECK_FINITE = 1
 SVR_STATS_SYNC = 1
 SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_MODE, SVR_TUNE_ALL = 1, 2, 4, 8, 15
 SVR_LOSS_MSE, SVR_LOSS_L1 = 0, 1
@@ -63,7 +65,7 @@ class svr_stats(C.Structure):
     _fields_ = [("n_gauss", C.c_int64), ("n_slices", C.c_int64), ("n_pixels", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_candidates", C.c_int64), ("n_records", C.c_int64),
                 ("n_instances", C.c_int64), ("n_incut", C.c_int64), ("n_evaluated", C.c_int64),
-                ("key_bits", C.c_int32), ("sort_passes", C.c_int32)]
+                ("key_bits", C.c_int32), ("sort_passes", C.c_int32), ("n_fallback_blocks", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,6 +90,9 @@ _SIGS = {
     "svr_set_count_pairs": ([vp, C.c_int], C.c_int),
     "svr_get_stats": ([vp, C.c_int, C.POINTER(svr_stats)], C.c_int),
     "svr_sort_pairs": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
+    "svr_set_capacity": ([vp, C.c_int64, C.c_int64], C.c_int),
+    "svr_set_checks": ([vp, C.c_int], C.c_int),
+    "svr_check_status": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "svr_set_timing": ([vp, C.c_int], C.c_int),
     "svr_get_timing": ([vp, C.POINTER(svr_timer), C.c_int, C.POINTER(C.c_int)], C.c_int),
     "svr_set_timing_stages": ([vp, C.c_uint32], C.c_int),
@@ -177,6 +182,7 @@ class Context:
         self.n_slices = 0
         self.n_subjects = 0
         self.n_pixels = 0
+        self.bin_generation = 0   # svr_project_bin calls made through this object
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -229,6 +235,7 @@ class Context:
     # -- hot path ------------------------------------------------------------
     def svr_project_bin(self, mean, log_scale, quat, amp, pose):
         p = svr_params(_ptr(mean), _ptr(log_scale), _ptr(quat), _ptr(amp), _ptr(pose))
+        self.bin_generation += 1
         self._check(load().svr_project_bin(self.h, C.byref(p)), "svr_project_bin")
 
     def svr_forward(self, pred, target=None, mask=None, loss=None, slice_sse=None, grad_pred=None):
@@ -309,6 +316,22 @@ class Context:
                     "svr_get_stats")
         return s.as_dict()
 
+    def svr_set_capacity(self, max_records: int, max_instances: int):
+        """Fixed-capacity binning (0, 0: back to the default, synchronising mode)."""
+        self._check(load().svr_set_capacity(self.h, int(max_records), int(max_instances)), "svr_set_capacity")
+
+    def svr_set_checks(self, flags: int):
+        self._check(load().svr_set_checks(self.h, int(flags)), "svr_set_checks")
+
+    def svr_check_status(self):
+        """(status, needed_records, needed_instances); the status is returned,
+        not raised (SVR_OK, SVR_ERR_CAPACITY or SVR_ERR_NONFINITE)."""
+        nr, ni = C.c_int64(0), C.c_int64(0)
+        rc = load().svr_check_status(self.h, C.byref(nr), C.byref(ni))
+        if rc not in (SVR_OK, SVR_ERR_CAPACITY, SVR_ERR_NONFINITE):
+            self._check(rc, "svr_check_status")
+        return rc, int(nr.value), int(ni.value)
+
     def svr_set_timing(self, enable: bool):
         self._check(load().svr_set_timing(self.h, int(bool(enable))), "svr_set_timing")
 
@@ -386,7 +409,11 @@ def _grad_fn():
 
         Forward: svr_project_bin + svr_forward (prediction, masked-MSE loss and
         dL/dpred).  Backward: svr_backward scaled by the upstream loss gradient.
-        ``pred`` is not differentiable (gradients flow through the loss)."""
+        ``pred`` is not differentiable (gradients flow through the loss).
+
+        svr_backward uses the context's last binning; when the context has
+        binned other parameters since this forward (another render_loss on the
+        same context), backward first bins the saved parameters again."""
 
         @staticmethod
         def forward(fctx, sctx, mean, log_scale, quat, amp, pose, target, mask):
@@ -397,6 +424,7 @@ def _grad_fn():
             gpred = torch.empty_like(pred)
             sctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
             fctx.sctx = sctx
+            fctx.generation = sctx.bin_generation
             fctx.save_for_backward(gpred, mean, log_scale, quat, amp, pose)
             fctx.mark_non_differentiable(pred)
             return loss[0], pred
@@ -404,6 +432,9 @@ def _grad_fn():
         @staticmethod
         def backward(fctx, g_loss, g_pred):
             gpred, mean, log_scale, quat, amp, pose = fctx.saved_tensors
+            if fctx.sctx.bin_generation != fctx.generation:
+                fctx.sctx.svr_project_bin(mean, log_scale, quat, amp, pose)
+                fctx.generation = fctx.sctx.bin_generation
             grads = [torch.empty_like(t) for t in (mean, log_scale, quat, amp, pose)]
             scale = g_loss.reshape(1).to(torch.float32).contiguous()
             fctx.sctx.svr_backward(gpred, *grads, grad_scale=scale)

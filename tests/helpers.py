@@ -46,6 +46,17 @@ def gpu_params(params, pose):
             to_dev(c, torch.float32), to_dev(pose, torch.float32))
 
 
+# Launch configurations the benchmark and the full-size parity tests use.  The
+# first is bench.py's default (tile 32, record-per-lane forward over fixed
+# chunks of the tile-ordered instance list); tests/test_bench_host.py checks
+# that bench.py's defaults stay in this list.
+BENCH_CONFIGS = [dict(tile=32, batch=128, persistent=0, cutoff=3.0, forward_mode=1),
+                 dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1),
+                 dict(tile=32, batch=128, persistent=1, cutoff=3.0, forward_mode=2),
+                 dict(tile=16, batch=128, persistent=1, cutoff=3.0, forward_mode=0)]
+BENCH_CONFIG_IDS = ["tile32-rpl-chunked", "tile16-rpl-chunked", "tile32-rol-persistent", "tile16-pixel-persistent"]
+
+
 BAND = 1e-4  # relative half-width of q around the cut treated as undecided
 
 

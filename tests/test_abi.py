@@ -33,9 +33,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_status_strings():
     lib = svr.load()
-    assert lib.svr_abi_version() == 1
+    assert lib.svr_abi_version() == 2
     for code, name in [(0, b"SVR_OK"), (-1, b"SVR_ERR_ARG"), (-2, b"SVR_ERR_HIP"), (-3, b"SVR_ERR_CAPACITY"),
-                       (-4, b"SVR_ERR_STATE"), (-5, b"SVR_ERR_NODEVICE"), (99, b"SVR_ERR_UNKNOWN")]:
+                       (-4, b"SVR_ERR_STATE"), (-5, b"SVR_ERR_NODEVICE"), (-6, b"SVR_ERR_NONFINITE"),
+                       (99, b"SVR_ERR_UNKNOWN")]:
         assert lib.svr_status_string(code) == name
 
 
@@ -124,3 +125,23 @@ def test_capacity_error_on_too_many_subject_slices():
 def test_library_is_loaded_from_the_package_tree():
     lib = svr.load()
     assert os.path.dirname(svr.LIB_PATH) == os.path.join(ROOT, "paper_2512_11624_amd")
+
+
+def test_capacity_and_check_argument_errors():
+    """Fixed-capacity binning and finite checks: host-side argument checks."""
+    ctx = svr.Context(device=-1)
+    lib = svr.load()
+    for rec, inst in ((-1, 10), (10, -1), (0, 10), (10, 0)):
+        assert lib.svr_set_capacity(ctx.h, rec, inst) == svr.SVR_ERR_ARG
+        assert b"capacities" in lib.svr_last_error(ctx.h)
+    assert lib.svr_set_capacity(ctx.h, 2 ** 31, 10) == svr.SVR_ERR_CAPACITY
+    assert lib.svr_set_capacity(ctx.h, 1000, 5000) == svr.SVR_OK   # host-only: nothing to allocate
+    assert lib.svr_set_capacity(ctx.h, 0, 0) == svr.SVR_OK
+    assert lib.svr_set_checks(ctx.h, 4) == svr.SVR_ERR_ARG
+    assert lib.svr_set_checks(ctx.h, svr.SVR_CHECK_FINITE) == svr.SVR_OK
+    assert lib.svr_set_checks(ctx.h, 0) == svr.SVR_OK
+    nr, ni = C.c_int64(7), C.c_int64(7)
+    assert lib.svr_check_status(ctx.h, C.byref(nr), C.byref(ni)) == svr.SVR_ERR_NODEVICE
+    assert nr.value == 0 and ni.value == 0
+    assert lib.svr_set_capacity(None, 1, 1) == svr.SVR_ERR_ARG
+    assert lib.svr_check_status(None, None, None) == svr.SVR_ERR_ARG

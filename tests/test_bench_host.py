@@ -38,3 +38,13 @@ def test_traffic_record_needs_matching_stage_tile_and_workload():
                     kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                     assert {"stage", "tile", "workload", "source", "bytes_per_launch"} <= set(kv), fn
                     assert float(kv["bytes_per_launch"]) > 0
+
+
+def test_bench_default_launch_config_is_parity_tested():
+    """The launch configuration bench.py times by default must be one the
+    full-size GPU parity tests run (tests/helpers.BENCH_CONFIGS)."""
+    from helpers import BENCH_CONFIGS
+    a = bench.build_parser().parse_args([])
+    cfg = dict(tile=a.tile, batch=a.batch, persistent=a.persistent, cutoff=3.0, forward_mode=a.forward_mode)
+    assert cfg in BENCH_CONFIGS, cfg
+    assert cfg == BENCH_CONFIGS[0]  # the stress test and the first head case run it

@@ -8,7 +8,7 @@ residuals and gradients are non-trivial.
 import numpy as np
 import pytest
 
-from helpers import BAND, check_band, check_close, gpu_params, to_dev
+from helpers import BAND, BENCH_CONFIG_IDS, BENCH_CONFIGS, check_band, check_close, gpu_params, to_dev
 from paper_2512_11624_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -334,10 +334,6 @@ def test_autograd_function(ctx):
 # oracle (FP64, OpenMP) is fast enough to evaluate every pixel and every
 # gradient at these sizes, so every output block is compared in full.
 
-BENCH_CONFIGS = [dict(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1),
-                 dict(tile=32, batch=128, persistent=1, cutoff=3.0, forward_mode=2),
-                 dict(tile=16, batch=128, persistent=1, cutoff=3.0, forward_mode=0)]
-
 
 @pytest.fixture(scope="module")
 def head_full():
@@ -349,7 +345,7 @@ def head_full():
     return prob, params, pose, target, ref
 
 
-@pytest.mark.parametrize("cfg", BENCH_CONFIGS, ids=["tile16-rpl", "tile32-rol-persistent", "tile16-pixel-persistent"])
+@pytest.mark.parametrize("cfg", BENCH_CONFIGS, ids=BENCH_CONFIG_IDS)
 def test_head_full_size_parity(ctx, head_full, cfg):
     """Head phantom at full size: 500k Gaussians, 128 slices of 256x256."""
     prob, params, pose, target, ref = head_full
@@ -357,15 +353,22 @@ def test_head_full_size_parity(ctx, head_full, cfg):
     _compare(out, ref)
 
 
-def test_stress_full_size_parity(ctx):
-    """Differentiation stress at full size: 1.2M Gaussians, 240 slices of
-    320x320 with interleaved motion segments; all 240 six-DoF pose gradients."""
+@pytest.fixture(scope="module")
+def stress_full():
     prob = synth.config3(0)
     params = synth.perturb_params(prob, 3, d_mu=0.1, d_ls=0.03, d_q=0.03, d_c=0.01)
     pose = prob.pose + np.random.default_rng(4).normal(0, 0.002, prob.pose.shape).astype(np.float32)
     target = (0.6 * prob.mask + synth.gaussian_noise(8, prob.n_pixels, 0.05)).astype(np.float32)
-    out = _run(ctx, prob, params, pose, target, cfg=BENCH_CONFIGS[0])
     ref = _oracle(prob, params, pose, target)
+    return prob, params, pose, target, ref
+
+
+@pytest.mark.parametrize("cfg", BENCH_CONFIGS[:2], ids=BENCH_CONFIG_IDS[:2])
+def test_stress_full_size_parity(ctx, stress_full, cfg):
+    """Differentiation stress at full size: 1.2M Gaussians, 240 slices of
+    320x320 with interleaved motion segments; all 240 six-DoF pose gradients."""
+    prob, params, pose, target, ref = stress_full
+    out = _run(ctx, prob, params, pose, target, cfg=cfg)
     _compare(out, ref)
 
 
