@@ -496,7 +496,8 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     if (fixed) {
         // counts stay on the device; an iteration that needs more than the
         // capacity bins nothing and records the needed counts
-        HIPCHK(c, launch_fixed_capacity(c->d_totals.p, c->cap_rec, c->cap_inst, c->d_counts.p, c->N, c->d_status.p, st));
+        HIPCHK(c, launch_fixed_capacity(c->d_totals.p, c->cap_rec, c->cap_inst, c->d_counts.p, c->d_offsets.p, c->N,
+                                         c->d_status.p, st));
         nrec = c->cap_rec;
         ninst = c->cap_inst;
     } else {

@@ -15,11 +15,13 @@ __global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ 
 }
 
 // One thread per Gaussian: when the counts of this binning exceed the
-// capacity, every Gaussian's record and instance counts become 0 (no later
-// stage then reads a record or instance slot) and the needed counts are
-// recorded.
+// capacity, every Gaussian's record and instance counts and offsets become 0
+// (no later stage then reads a record or instance slot: the per-Gaussian
+// kernels find a Gaussian's records from its offset and the next one's) and
+// the needed counts are recorded.
 __global__ __launch_bounds__(256) void k_fixed_capacity(const long long* __restrict__ totals, int64_t cap_rec,
-                                                        int64_t cap_inst, int2* __restrict__ counts, int64_t n,
+                                                        int64_t cap_inst, int2* __restrict__ counts,
+                                                        int2* __restrict__ offsets, int64_t n,
                                                         DevStatus* __restrict__ st) {
     const long long nr = totals[0], ni = totals[1];
     const bool over = nr > cap_rec || ni > cap_inst;
@@ -32,7 +34,10 @@ __global__ __launch_bounds__(256) void k_fixed_capacity(const long long* __restr
             st->need_inst = ni;
         }
     }
-    if (over && j < n) counts[j] = make_int2(0, 0);
+    if (over && j < n) {
+        counts[j] = make_int2(0, 0);
+        offsets[j] = make_int2(0, 0);
+    }
 }
 
 // Instance slots the binning did not fill get the padding key (above every
@@ -58,10 +63,10 @@ hipError_t launch_check_finite(const float* x, int64_t n, DevStatus* st, hipStre
 }
 
 hipError_t launch_fixed_capacity(const long long* totals, int64_t cap_rec, int64_t cap_inst, int2* counts,
-                                 int64_t n, DevStatus* st, hipStream_t s) {
+                                 int2* offsets, int64_t n, DevStatus* st, hipStream_t s) {
     const int64_t blocks = std::max<int64_t>((n + 255) / 256, 1);
     hipLaunchKernelGGL(k_fixed_capacity, dim3((unsigned)blocks), dim3(256), 0, s, totals, cap_rec, cap_inst, counts,
-                       n, st);
+                       offsets, n, st);
     return hipGetLastError();
 }
 

@@ -113,9 +113,10 @@ namespace svr {
 // csrc/status.hip: any element of x [n] non-finite -> st->bits |= kStatusNonfinite.
 hipError_t launch_check_finite(const float* x, int64_t n, DevStatus* st, hipStream_t s);
 // Fixed-capacity binning: when totals [2] (records, instances) exceed the
-// capacity, zero every Gaussian's counts [n] and record the needed counts.
+// capacity, zero every Gaussian's counts and offsets [n] and record the
+// needed counts.
 hipError_t launch_fixed_capacity(const long long* totals, int64_t cap_rec, int64_t cap_inst, int2* counts,
-                                 int64_t n, DevStatus* st, hipStream_t s);
+                                 int2* offsets, int64_t n, DevStatus* st, hipStream_t s);
 // Padding keys for instance slots [valid, cap), valid = 0 after an overflow
 // else totals[1].
 hipError_t launch_pad_instances(uint32_t* keys, uint32_t* vals, int64_t cap, const long long* totals,
