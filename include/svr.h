@@ -438,6 +438,24 @@ int svr_check_status(svr_ctx* ctx, int64_t* needed_records, int64_t* needed_inst
  * n < 0 or key_bits outside 1..32. */
 int svr_sort_pairs(svr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits);
 
+/* Allocation-free variant of svr_sort_pairs, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and result as svr_sort_pairs (the
+ * same kernels: bit-identical output), with these differences:
+ *   - n <= SVR_SORT_NOALLOC_MAX, else SVR_ERR_CAPACITY (checked on the host);
+ *   - nothing is allocated or freed and the stream is not synchronised: the
+ *     sort is enqueued on the context's stream and has finished when that
+ *     stream has;
+ *   - its scratch (ping-pong keys and values and the pass histograms, 11 MiB)
+ *     is one fixed device array per GPU, held from the library's first
+ *     context on that GPU until the process ends.  Every call on a GPU uses
+ *     that GPU's array, so calls that overlap on one GPU (several streams,
+ *     contexts or host threads) race: the caller must order them.  Nothing in
+ *     the array needs to start at zero.
+ * Errors: as svr_sort_pairs; SVR_ERR_NODEVICE on a host-only context. */
+#define SVR_SORT_NOALLOC_MAX (1 << 20)
+int svr_sort_pairs_noalloc(svr_ctx* ctx, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits);
+
 /* Per-stage GPU timing.  When enabled, every stage the library launches is
  * bracketed by HIP events on the context stream; svr_get_timing synchronises
  * the stream, folds the completed intervals into per-stage totals and copies

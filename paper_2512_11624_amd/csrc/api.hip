@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -560,6 +561,40 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Allocation-free sort (svr_sort_pairs_noalloc).  Its scratch -- ping-pong
+// keys and values and the pass histograms for up to SVR_SORT_NOALLOC_MAX
+// pairs -- is the file-scope device array below, which every GPU the library
+// runs on holds until the process ends.  In host code the array's name is a
+// host-side stand-in, not a device address: kernels and copies get the
+// address hipGetSymbolAddress returns on each device, looked up once per
+// device when the first context on it is created (noalloc_setup).
+namespace {
+constexpr int64_t kNoallocMax = SVR_SORT_NOALLOC_MAX;
+constexpr size_t kNoallocKV = (size_t)kNoallocMax * sizeof(uint32_t);  // keys or values
+constexpr size_t kNoallocTmp = (size_t)3 << 20;                        // pass histograms and scan partials
+constexpr size_t kNoallocBytes = 2 * kNoallocKV + kNoallocTmp;
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocDevices] = {};
+hipError_t g_noalloc_err[kNoallocDevices] = {};
+bool g_noalloc_done[kNoallocDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// Looks up this device's copy of the scratch array; `device` must be current.
+static void noalloc_setup(int device) {
+    if (device < 0 || device >= kNoallocDevices) return;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_done[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    g_noalloc_err[device] = e;
+    g_noalloc_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_noalloc_done[device] = true;
+}
+
+// ---------------------------------------------------------------------------
 extern "C" {
 
 int svr_abi_version(void) { return SVR_ABI_VERSION; }
@@ -600,6 +635,7 @@ int svr_ctx_create(svr_ctx** out, int device, void* hip_stream) {
     c->device = device;
     c->host_only = false;
     c->stream = (hipStream_t)hip_stream;
+    noalloc_setup(device);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->n_cu = cus;
@@ -1484,6 +1520,42 @@ int svr_sort_pairs(svr_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n, int ke
     if (e2 != hipSuccess) return fail(c, SVR_ERR_HIP, "radix sort sync: %s", hipGetErrorString(e2));
     return SVR_OK;
 }
+
+int svr_sort_pairs_noalloc(svr_ctx* c, uint32_t* keys, uint32_t* vals, int64_t n, int key_bits) {
+    if (!c) return SVR_ERR_ARG;
+    c->err.clear();
+    if (n < 0 || key_bits < 1 || key_bits > 32) return fail(c, SVR_ERR_ARG, "n < 0 or key_bits out of range");
+    if (n > 0 && (!keys || !vals)) return fail(c, SVR_ERR_ARG, "keys/vals NULL");
+    if (n > kNoallocMax)
+        return fail(c, SVR_ERR_CAPACITY, "n = %lld exceeds the allocation-free maximum %lld", (long long)n,
+                    (long long)kNoallocMax);
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (n <= 1) return SVR_OK;
+    if (sort_tmp_bytes(n) > kNoallocTmp) return fail(c, SVR_ERR_CAPACITY, "sort scratch exceeds its reserve");
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu);
+        if (c->device >= kNoallocDevices || !g_noalloc_done[c->device])
+            return fail(c, SVR_ERR_STATE, "no scratch address for device %d", c->device);
+        if (g_noalloc_err[c->device] != hipSuccess)
+            return fail(c, SVR_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(g_noalloc_err[c->device]));
+        base = g_noalloc_ptr[c->device];
+    }
+    uint32_t* k2 = (uint32_t*)base;
+    uint32_t* v2 = k2 + kNoallocMax;
+    void* tmp = (char*)base + 2 * kNoallocKV;
+    hipStream_t st = c->stream;
+    bool alt = false;
+    hipError_t e = launch_radix_sort(keys, vals, k2, v2, n, key_bits, tmp, &alt, st);
+    if (e == hipSuccess && alt) {
+        e = hipMemcpyAsync(keys, k2, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(vals, v2, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) return fail(c, SVR_ERR_HIP, "radix sort: %s", hipGetErrorString(e));
+    return SVR_OK;
+}
+
 
 static std::string tune_key(const svr_ctx* c) {
     auto lg = [](int64_t v) {

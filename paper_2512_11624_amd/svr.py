@@ -23,6 +23,7 @@ SVR_OK, SVR_ERR_ARG, SVR_ERR_HIP, SVR_ERR_CAPACITY, SVR_ERR_STATE, SVR_ERR_NODEV
 SVR_ERR_NONFINITE = -6
 SVR_CHECK_FINITE = 1
 SVR_STATS_SYNC = 1
+SVR_SORT_NOALLOC_MAX = 1 << 20
 SVR_TUNE_TILE, SVR_TUNE_BATCH, SVR_TUNE_PERSISTENT, SVR_TUNE_MODE, SVR_TUNE_ALL = 1, 2, 4, 8, 15
 SVR_LOSS_MSE, SVR_LOSS_L1 = 0, 1
 
@@ -90,6 +91,7 @@ _SIGS = {
     "svr_set_count_pairs": ([vp, C.c_int], C.c_int),
     "svr_get_stats": ([vp, C.c_int, C.POINTER(svr_stats)], C.c_int),
     "svr_sort_pairs": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
+    "svr_sort_pairs_noalloc": ([vp, vp, vp, C.c_int64, C.c_int], C.c_int),
     "svr_set_capacity": ([vp, C.c_int64, C.c_int64], C.c_int),
     "svr_set_checks": ([vp, C.c_int], C.c_int),
     "svr_check_status": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
@@ -359,6 +361,11 @@ class Context:
     def svr_sort_pairs(self, keys, vals, key_bits):
         self._check(load().svr_sort_pairs(self.h, _ptr(keys), _ptr(vals), int(keys.numel()), int(key_bits)),
                     "svr_sort_pairs")
+
+    def svr_sort_pairs_noalloc(self, keys, vals, key_bits):
+        """Asynchronous on the context's stream; allocates nothing."""
+        self._check(load().svr_sort_pairs_noalloc(self.h, _ptr(keys), _ptr(vals), int(keys.numel()),
+                                                  int(key_bits)), "svr_sort_pairs_noalloc")
 
     def svr_autotune(self, mean, log_scale, quat, amp, pose, grad_pred, flags=SVR_TUNE_ALL,
                      cache_path=None, max_times=64):

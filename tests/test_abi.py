@@ -145,3 +145,18 @@ def test_capacity_and_check_argument_errors():
     assert nr.value == 0 and ni.value == 0
     assert lib.svr_set_capacity(None, 1, 1) == svr.SVR_ERR_ARG
     assert lib.svr_check_status(None, None, None) == svr.SVR_ERR_ARG
+
+
+def test_noalloc_sort_argument_errors():
+    """svr_sort_pairs_noalloc: host-side checks before any device work."""
+    ctx = svr.Context(device=-1)
+    lib = svr.load()
+    dummy = C.c_void_p(16)
+    assert lib.svr_sort_pairs_noalloc(None, dummy, dummy, 10, 8) == svr.SVR_ERR_ARG
+    assert lib.svr_sort_pairs_noalloc(ctx.h, dummy, dummy, -1, 8) == svr.SVR_ERR_ARG
+    assert lib.svr_sort_pairs_noalloc(ctx.h, dummy, dummy, 10, 0) == svr.SVR_ERR_ARG
+    assert lib.svr_sort_pairs_noalloc(ctx.h, dummy, dummy, 10, 33) == svr.SVR_ERR_ARG
+    assert lib.svr_sort_pairs_noalloc(ctx.h, None, dummy, 10, 8) == svr.SVR_ERR_ARG
+    assert lib.svr_sort_pairs_noalloc(ctx.h, dummy, dummy, svr.SVR_SORT_NOALLOC_MAX + 1, 8) == svr.SVR_ERR_CAPACITY
+    assert b"allocation-free maximum" in lib.svr_last_error(ctx.h)
+    assert lib.svr_sort_pairs_noalloc(ctx.h, dummy, dummy, svr.SVR_SORT_NOALLOC_MAX, 8) == svr.SVR_ERR_NODEVICE
