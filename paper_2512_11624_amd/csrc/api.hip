@@ -28,12 +28,12 @@ namespace {
 enum Stage {
     ST_SLICE_POSE, ST_CULL_COUNT, ST_SCAN, ST_EMIT, ST_SORT, ST_TILE_RANGES, ST_TILE_ORDER, ST_MASK_SUM,
     ST_FORWARD, ST_LOSS, ST_ZERO, ST_BACKWARD, ST_PROJECT_BACKWARD, ST_POSE_CHAIN, ST_ADAM, ST_TOPK_KNN,
-    ST_TOPK_INVERSE, ST_TOPK_FORWARD, ST_TOPK_BACKWARD, ST_COUNT
+    ST_TOPK_INVERSE, ST_TOPK_FORWARD, ST_TOPK_BACKWARD, ST_CLASS_ORDER, ST_COUNT
 };
 const char* const kStageNames[ST_COUNT] = {
     "slice_pose", "cull_count", "scan", "emit", "sort", "tile_ranges", "tile_order", "mask_sum",
     "forward_tile", "loss_reduce", "zero_fill", "backward_tile", "project_backward", "pose_chain", "adam",
-    "topk_knn", "topk_inverse", "topk_forward", "topk_backward"};
+    "topk_knn", "topk_inverse", "topk_forward", "topk_backward", "class_order"};
 
 constexpr int kGaussBlock = 256;
 constexpr int kMaxSubjectSlices = 4096;
@@ -89,7 +89,7 @@ struct svr_ctx {
     DevBuf<int> d_work, d_fallback;
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
-    DevBuf<float> d_fwd_part;     // record-per-lane forward: two tile partials per instance chunk
+    DevBuf<float> d_fwd_part;     // chunked record-per-lane forward: two tile partials per instance chunk
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     // content-adaptive initialisation (allocated on first use)
     DevBuf<InitSlice> d_init_tab;
@@ -539,16 +539,26 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     bool alt = false;
     {
         StageScope sc(c, ST_SORT);
+        // tile bits only: the shape class (low bits) is ordered per tile by the tile kernels
         HIPCHK(c, launch_radix_sort(c->d_keys.p, c->d_vals.p, c->d_keys2.p, c->d_vals2.p, ninst, c->key_bits,
-                                    c->d_sort_tmp.p, &alt, st, c->d_idx.p, c->d_idx2.p));
+                                    c->d_sort_tmp.p, &alt, st, c->d_idx.p, c->d_idx2.p, kClassBits));
     }
     const uint32_t* sk = alt ? c->d_keys2.p : c->d_keys.p;
-    c->sorted_vals = alt ? c->d_vals2.p : c->d_vals.p;
-    c->sorted_idx = alt ? c->d_idx2.p : c->d_idx.p;
-    c->sorted_keys = sk;
+    // each tile's instances then go in shape-class order into the other buffers
+    uint32_t* ko = alt ? c->d_keys.p : c->d_keys2.p;
+    uint32_t* vo = alt ? c->d_vals.p : c->d_vals2.p;
+    uint32_t* xo = alt ? c->d_idx.p : c->d_idx2.p;
     {
         StageScope sc(c, ST_TILE_RANGES);
-        HIPCHK(c, launch_tile_ranges(sk, ninst, c->d_ranges.p, c->n_tiles, st));
+        HIPCHK(c, launch_tile_ranges(sk, ninst, c->d_ranges.p, c->n_tiles, ko, st));
+    }
+    {
+        StageScope sc(c, ST_CLASS_ORDER);
+        HIPCHK(c, launch_class_order(sk, alt ? c->d_vals2.p : c->d_vals.p, alt ? c->d_idx2.p : c->d_idx.p,
+                                     c->d_ranges.p, c->n_tiles, ko, vo, xo, st));
+        c->sorted_keys = ko;
+        c->sorted_vals = vo;
+        c->sorted_idx = xo;
     }
     if (c->cfg.persistent) {
         int rc = build_tile_order(c);
@@ -1345,7 +1355,10 @@ int svr_get_stats(svr_ctx* c, int flags, svr_stats* out) {
     out->n_pixels = c->P;
     out->n_tiles = c->n_tiles;
     out->key_bits = c->key_bits;
-    out->sort_passes = (c->key_bits + radix_digit_bits(c->key_bits) - 1) / radix_digit_bits(c->key_bits);
+    {
+        const int sb = c->key_bits - kClassBits, dw = radix_digit_bits(sb);
+        out->sort_passes = (sb + dw - 1) / dw;
+    }
     out->n_candidates = c->binned ? c->n_cand : 0;
     out->n_records = c->binned ? c->n_rec : 0;
     out->n_instances = c->binned ? c->n_inst : 0;

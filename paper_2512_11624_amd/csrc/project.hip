@@ -135,13 +135,13 @@ struct Box {
     bool nonempty;
 };
 
-// Size class of an instance's clipped footprint box (0: <= 16 px, 1: <= 64,
-// 2: <= 256, 3: larger).  It forms the low bits of the sort key, so that each
-// tile's instances come out grouped by size and the record-per-lane tile
-// kernels see waves of similar per-lane work.
-__device__ inline uint32_t area_class(int a) {
-    const int lg = 32 - __clz((unsigned)max(a - 1, 1));  // ceil(log2(a)) for a >= 2
-    return (uint32_t)min(max((lg - 3) >> 1, 0), (1 << kClassBits) - 1);
+// Shape class of an instance's clipped footprint box (h rows, w columns,
+// each capped at 8): (min(h, 8) - 1) * 8 + min(w, 8) - 1.  It forms the low
+// bits of the sort key, so that each tile's instances come out grouped by box
+// shape and a wave of the record-per-lane tile kernels, whose lanes take
+// consecutive instances, walks boxes of one shape.
+__device__ inline uint32_t shape_class(int w, int h) {
+    return (uint32_t)((min(h, 8) - 1) * 8 + (min(w, 8) - 1));
 }
 
 // Pixel bounding box of the footprint ellipse on slice `sg`.
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
                     for (int tx = tx0; tx <= tx1; ++tx) {
                         const int cw = min(bx.kx1, tx * T + T - 1) - max(bx.kx0, tx * T) + 1;
                         keys[o] = ((uint32_t)(sg.tile_base + ty * sg.ntx + tx) << kClassBits) |
-                                  area_class(cw * ch);
+                                  shape_class(cw, ch);
                         vals[o] = (uint32_t)r;
                         ++o;
                     }
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
                 const int ch = min(bx.ky1, ty * T + T - 1) - max(bx.ky0, ty * T) + 1;
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const int cw = min(bx.kx1, tx * T + T - 1) - max(bx.kx0, tx * T) + 1;
-                    keys[o] = ((uint32_t)(sgp->tile_base + ty * sgp->ntx + tx) << kClassBits) | area_class(cw * ch);
+                    keys[o] = ((uint32_t)(sgp->tile_base + ty * sgp->ntx + tx) << kClassBits) | shape_class(cw, ch);
                     vals[o] = (uint32_t)(R0 + t);
                     ++o;
                 }

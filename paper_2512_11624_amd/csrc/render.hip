@@ -1,25 +1,25 @@
-// Tile stages: per-tile instance ranges, the forward accumulation with the
-// masked-MSE epilogue, and the adjoint.  gfx950, wave64, FP32.
+// Tile stages: per-tile instance ranges and the shape-class order of each
+// tile's instances (the end of the binning), the forward accumulation with
+// the masked-MSE epilogue, and the adjoint.  gfx950, wave64, FP32.
 //
-// Forward (pixel per lane): a workgroup owns one T x T pixel tile of one
-// slice.  Records of the tile are staged in LDS in batches; each wave owns a
-// band of rows and skips records whose footprint rows miss its band.  The
+// Forward, pixel per lane (mode 0): a workgroup owns one T x T pixel tile of
+// one slice.  Records of the tile are staged in LDS in batches; each wave owns
+// a band of rows and skips records whose footprint rows miss its band.  The
 // exponent of a record at tile-local pixel (X, Y) (relative to the tile
 // centre) is the quadratic c0 + c1 X + c2 Y + c3 X^2 + c4 XY + c5 Y^2 whose
 // coefficients are formed once per record at staging, so a pixel-record term
 // costs 5 FMA, one exp2 and the window max(e - e_T, 0).  Every pixel sums its
 // records in the sorted (deterministic) order.
 //
-// Forward, record per lane (the alternative mode): each lane owns one instance
-// and walks its record's footprint box inside the tile, accumulating into an
-// LDS pixel tile with ds_add_f32; only box pixels are evaluated.
-//
-// Adjoint (record per lane): a workgroup takes a fixed chunk of 256 instances
-// of the tile-ordered list and stages the upstream gradients of the chunk's
-// tiles in LDS; each lane owns one instance and walks the pixels of its
-// record's footprint box inside its tile, accumulating the seven moment sums
-// it needs in registers (no cross-lane reduction), and writes them to the
-// instance's emission slot (no atomics).
+// Forward, record per lane (mode 1, the default) and the adjoint: each lane
+// owns one instance and walks its record's footprint box inside the tile.
+// The binning orders every tile's instances by box shape, so the consecutive
+// instances on a wave's lanes walk boxes of (nearly) one shape.  The forward
+// adds fixed-point terms into an LDS pixel tile with integer atomics; the
+// adjoint accumulates the seven moment sums it needs in registers (no
+// cross-lane reduction) and writes them to the instance's emission slot (no
+// atomics).  Both take fixed chunks of 256 instances of the tile-ordered list
+// per workgroup, or (persistent) whole tiles from a work queue.
 #include "svr_internal.h"
 
 namespace svr {
@@ -33,12 +33,18 @@ __device__ inline int xcd_tile(int b, int n_tiles) {
     return (b & 7) * per + (b >> 3);
 }
 
+// [start, end) of every tile's instances in the sorted list.  Slots outside
+// every tile (padding keys, sorted last) are copied to pad_out, the buffer
+// the class order then fills, so that they keep their padding key there.
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, int2* __restrict__ ranges,
-                              uint32_t n_tiles) {
+                              uint32_t n_tiles, uint32_t* __restrict__ pad_out) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const uint32_t k = keys[s] >> kClassBits;  // tile id
-    if (k >= n_tiles) return;
+    if (k >= n_tiles) {
+        if (pad_out) pad_out[s] = keys[s];
+        return;
+    }
     if (s == 0 || (keys[s - 1] >> kClassBits) != k) ranges[k].x = (int)s;
     if (s == n - 1 || (keys[s + 1] >> kClassBits) != k) ranges[k].y = (int)(s + 1);
 }
@@ -328,36 +334,246 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
     return b;
 }
 
-// Forward, record per lane, persistent grid (persistent = 1): workgroups pull
-// whole tiles heaviest-first from a work queue, with exact integer
-// accumulation.  Per round of up to 256 of the tile's instances: the boxes
-// are counting-sorted by shape in LDS (a wave's lanes then walk boxes of one
-// shape), each lane walks one box
-// rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum) to
-// the pixel's int32 LDS sum with an integer LDS atomic (float LDS atomics are
-// slow on this GPU, integer ones are not).  The quantum is 2^(e - 30) with
-// 2^e above the round's sum of |a|, so no pixel's round sum can overflow and
-// the rounding error per term is below 2^-31 of that sum.  Integer sums do
-// not depend on the order of the adds; each pixel's owner thread then adds
-// the round's total to its float sum in round order, so the result is
-// deterministic.
+// Forward walk of one instance's box inside its tile, rows outer and columns
+// inner: adds round(amq max(e - e_T, 0)) to acc[y * T + x] (tile-local pixel)
+// with an integer LDS atomic; pixels outside the cut add an integer zero
+// (branch-free).  Returns the number of in-cut pixels when kCount.
+template <int T, bool kCount>
+__device__ inline unsigned int forward_walk(const LaneBox& b, float amq, int* acc, float etau) {
+    const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+    const int hh = w > 0 ? h : 0;
+    const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
+    float dy = (float)b.y0 - b.pyl;
+    int gr = b.y0 * T + b.x0;
+    unsigned int cnt = 0;
+    for (int r = 0; r < hh; ++r) {
+        const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
+        float dx = dx0;
+        int gi = gr;
+        for (int c = 0; c < w; ++c) {
+            const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy)) - etau;
+            atomicAdd(&acc[gi], __float2int_rn(amq * fmaxf(v, 0.f)));
+            if (kCount) cnt += v > 0.f ? 1u : 0u;
+            dx += 1.f;
+            ++gi;
+        }
+        dy += 1.f;
+        gr += T;
+    }
+    return cnt;
+}
+
+// The seven sums of one instance's adjoint, with t = g e inside the cut:
+//   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
+//   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2.
+struct AdjointSums {
+    float Sa, S0, Sx, Sy, Sxx, Sxy, Syy;
+};
+
+// Adjoint walk of one instance's box over the tile's upstream gradients g
+// (T x T in LDS), rows outer and columns inner, with the per-row sums folded
+// in with dy (three accumulations per pixel).
+template <int T>
+__device__ inline AdjointSums adjoint_walk(const LaneBox& b, const float* g, float etau) {
+    const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+    const int hh = w > 0 ? h : 0;
+    AdjointSums S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
+    float dy = (float)b.y0 - b.pyl;
+    int gr = b.y0 * T + b.x0;
+    for (int r = 0; r < hh; ++r) {
+        const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
+        float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
+        int gi = gr;
+        for (int c = 0; c < w; ++c) {
+            const float gv = g[gi];
+            const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy));
+            const float v = e - etau;
+            S.Sa = fmaf(gv, fmaxf(v, 0.f), S.Sa);
+            const float t = (v > 0.f) ? gv * e : 0.f;
+            const float tx = t * dx;
+            R0 += t;
+            R1 += tx;
+            R2 = fmaf(tx, dx, R2);
+            dx += 1.f;
+            ++gi;
+        }
+        S.S0 += R0;
+        S.Sx += R1;
+        S.Sxx += R2;
+        S.Sy = fmaf(dy, R0, S.Sy);
+        S.Sxy = fmaf(dy, R1, S.Sxy);
+        S.Syy = fmaf(dy * dy, R0, S.Syy);
+        dy += 1.f;
+        gr += T;
+    }
+    return S;
+}
+
+// Gradient with respect to the stored record fields (dz/d field, times
+// amp ln 2) from the seven sums, to the instance's emission slot.  The
+// upstream scale multiplies every sum (it was not applied to g).
+__device__ inline void store_adjoint(const AdjointSums& S, const LaneBox& b, float scale, float4* inst_grad,
+                                     uint32_t e_slot) {
+    const float k2 = b.am * SVR_LN2 * scale;
+    float4 g0, g1;
+    g0.x = S.Sa * scale;
+    g0.y = k2 * S.S0;
+    g0.z = -2.f * k2 * (b.a00 * S.Sx + b.a01 * S.Sy);
+    g0.w = -2.f * k2 * (b.a01 * S.Sx + b.a11 * S.Sy);
+    g1.x = k2 * S.Sxx;
+    g1.y = 2.f * k2 * S.Sxy;
+    g1.z = k2 * S.Syy;
+    g1.w = 0.f;
+    inst_grad[2 * (int64_t)e_slot] = g0;
+    inst_grad[2 * (int64_t)e_slot + 1] = g1;
+}
+
+// Upstream gradients of one tile into LDS, T x T floats, zero outside the
+// slice; 16-byte loads where a row's four pixels are inside the slice and
+// aligned.
+template <int T, int NT>
+__device__ inline void stage_tile(const float* __restrict__ src, const TileOrg& o, float* dst) {
+    constexpr int Q = T * T / 4;
+    for (int q = threadIdx.x; q < Q; q += NT) {
+        const int px = (q % (T / 4)) * 4, py = q / (T / 4);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (py < o.vh) {
+            const int64_t gi = o.base + (int64_t)py * o.stride + px;
+            if (px + 3 < o.vw && (gi & 3) == 0) {
+                v = *reinterpret_cast<const float4*>(src + gi);
+            } else {
+                if (px < o.vw) v.x = src[gi];
+                if (px + 1 < o.vw) v.y = src[gi + 1];
+                if (px + 2 < o.vw) v.z = src[gi + 2];
+                if (px + 3 < o.vw) v.w = src[gi + 3];
+            }
+        }
+        *reinterpret_cast<float4*>(dst + py * T + px) = v;
+    }
+}
+
+// Binning, last step: every tile's instances (sorted by tile, in emission
+// order) are put in order of shape class, the low kClassBits of the key,
+// stably, in segments of kSeg: one workgroup per tile ranks each instance
+// within its class with ballot masks (lanes holding the same class) in input
+// order, with per-wave class counters in LDS, places it in LDS and writes the
+// segment out in order (coalesced).
+// The record-per-lane tile kernels take consecutive instances on a wave's
+// lanes, which then walk boxes of (nearly) one shape.
+constexpr int kSeg = 2048;
+static_assert(kClasses == 64, "one lane per class in the class scan");
+__global__ __launch_bounds__(256) void k_class_order(const uint32_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ vals,
+                                                     const uint32_t* __restrict__ idx,
+                                                     const int2* __restrict__ ranges, int32_t n_tiles,
+                                                     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                     uint32_t* __restrict__ idx_out) {
+    constexpr int NT = 256, NW = 4, PER = kSeg / NT;  // wave w ranks [w PER 64, (w + 1) PER 64)
+    __shared__ int s_cnt[NW][kClasses];
+    __shared__ int s_start[kClasses];
+    __shared__ uint32_t s_k[kSeg], s_v[kSeg], s_x[kSeg];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tile = xcd_tile(blockIdx.x, n_tiles);
+    if (tile >= n_tiles) return;
+    const int2 rg = ranges[tile];
+    const int n = rg.y - rg.x;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int s0 = 0; s0 < n; s0 += kSeg) {
+        const int sn = min(kSeg, n - s0);
+        const int64_t base = (int64_t)rg.x + s0;
+        __syncthreads();  // the previous segment's counters are consumed
+        s_cnt[wv][lane] = 0;
+        __syncthreads();
+        uint32_t kk[PER], vv[PER], xx[PER];
+        int rk[PER];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int j = wv * PER * 64 + it * 64 + lane;
+            const bool valid = j < sn;
+            kk[it] = valid ? keys[base + j] : 0u;
+            vv[it] = valid ? vals[base + j] : 0u;
+            xx[it] = valid ? idx[base + j] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int j = wv * PER * 64 + it * 64 + lane;
+            const bool valid = j < sn;
+            const int c = (int)(kk[it] & (uint32_t)(kClasses - 1));
+            uint64_t peers = __ballot(valid);
+            for (int bit = 0; bit < kClassBits; ++bit) {
+                const bool on = (c >> bit) & 1;
+                const uint64_t bb = __ballot(on);
+                peers &= on ? bb : ~bb;
+            }
+            if (!valid) peers = 0ull;
+            const int leader = valid ? (__ffsll((long long)peers) - 1) : lane;
+            int basec = 0;
+            if (valid && lane == leader) {
+                basec = s_cnt[wv][c];
+                s_cnt[wv][c] = basec + __popcll(peers);
+            }
+            basec = __shfl(basec, leader, 64);
+            rk[it] = valid ? basec + __popcll(peers & lt_mask) : -1;
+        }
+        __syncthreads();
+        if (tid < 64) {  // class tid: prefix over waves, then the class starts
+            int tot = 0;
+            for (int q = 0; q < NW; ++q) {
+                const int c = s_cnt[q][tid];
+                s_cnt[q][tid] = tot;
+                tot += c;
+            }
+            int incl = tot;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += u;
+            }
+            s_start[tid] = incl - tot;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            if (rk[it] >= 0) {
+                const int c = (int)(kk[it] & (uint32_t)(kClasses - 1));
+                const int d = s_start[c] + s_cnt[wv][c] + rk[it];
+                s_k[d] = kk[it];
+                s_v[d] = vv[it];
+                s_x[d] = xx[it];
+            }
+        }
+        __syncthreads();
+        for (int j = tid; j < sn; j += NT) {
+            keys_out[base + j] = s_k[j];
+            vals_out[base + j] = s_v[j];
+            idx_out[base + j] = s_x[j];
+        }
+    }
+}
+
+// Forward, record per lane, one tile per workgroup (persistent: tiles from
+// the work queue, heaviest first), with exact integer accumulation.  Lane i
+// takes the tile's instances i, i + 256, ... (in shape-class order from the
+// binning) and walks each box (forward_walk).  The quantum comes from the
+// tile alone: with 2^emax <= |a| < 2^(emax + 1) for the tile's largest
+// amplitude and n instances, no pixel sum reaches 2^ex,
+// ex = emax + 1 + ceil(log2 n), and 2^ex spans 2^30 quanta, so the int32 sums
+// cannot overflow and a term's rounding error is below 2^-31 of n times the
+// largest amplitude.  Integer sums do not depend on the order of the adds, so
+// the result is deterministic.  A non-finite amplitude makes the tile's
+// pixels NaN.
 template <int T, bool kLoss, bool kCount>
-__global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const float* __restrict__ target,
-                                                     const float* __restrict__ mask,
-                                                     const float* __restrict__ msum,
-                                                     float* __restrict__ pred, float* __restrict__ grad,
-                                                     float* __restrict__ tile_sse,
-                                                     unsigned long long* __restrict__ incut,
-                                                     int* __restrict__ work_counter) {
+__global__ __launch_bounds__(256) void k_forward_tiles(RenderArgs a, const float* __restrict__ target,
+                                                      const float* __restrict__ mask,
+                                                      const float* __restrict__ msum,
+                                                      float* __restrict__ pred, float* __restrict__ grad,
+                                                      float* __restrict__ tile_sse,
+                                                      unsigned long long* __restrict__ incut,
+                                                      int* __restrict__ work_counter) {
     constexpr int NT = 256, NW = 4;
-    constexpr int kB = (T + 1) * (T + 1);
-    __shared__ float s_acc[T * T];
-    __shared__ int s_iacc[T * T];
-    __shared__ float4 s_box[NT][2];
-    __shared__ int s_hist[kB];
-    __shared__ int s_perm[NT];
-    __shared__ int s_wsum[NW];
-    __shared__ float s_fsum[NW];
+    constexpr int kNoAmp = -100000;  // exponent sentinel: no nonzero amplitude
+    __shared__ int s_acc[T * T];
+    __shared__ int s_emax[NW];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
     __shared__ int s_next;
@@ -369,128 +585,55 @@ __global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const f
     while (true) {
         const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
         if (tile < 0) break;
-        const TileCoord tc = tile_coord(a, tile);
         const int2 rg = a.ranges[tile];
-        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
-        __syncthreads();
-        for (int p = tid; p < T * T; p += NT) {
-            s_acc[p] = 0.f;
-            s_iacc[p] = 0;
+        const int n = max(rg.y - rg.x, 0);
+        const TileOrg o = tile_org(a.tile_org[tile]);
+        __syncthreads();  // the previous tile is done with LDS
+        for (int p = tid; p < T * T; p += NT) s_acc[p] = 0;
+        // the tile's largest amplitude exponent (a max: order-independent)
+        int emax = kNoAmp;
+        bool bad = false;
+        for (int j = tid; j < n; j += NT) {
+            const float aa = fabsf(a.rec[a.inst_rec[rg.x + j]].r0.w);
+            if (!(aa <= 3.4028235e38f)) bad = true;
+            else if (aa > 0.f) emax = max(emax, ilogbf(aa));
         }
+        for (int off = 32; off > 0; off >>= 1) emax = max(emax, __shfl_xor(emax, off, 64));
+        const bool wbad = __ballot(bad) != 0ull;
+        if (lane == 0) s_emax[wv] = wbad ? INT_MAX : emax;
+        __syncthreads();
+        int em = kNoAmp;
+        bool tbad = false;
+        for (int q = 0; q < NW; ++q) {
+            const int v = s_emax[q];
+            if (v == INT_MAX) tbad = true;
+            else em = max(em, v);
+        }
+        const int lgn = n > 1 ? 32 - __clz((unsigned)(n - 1)) : 0;
+        const int ex = em > kNoAmp ? em + 1 + lgn : 0;
+        const int sh = min(max(30 - ex, -126), 126);
+        const float to_q = ldexpf(1.f, sh), from_q = ldexpf(1.f, -sh);
         unsigned int cnt = 0;
-        const int n = rg.y - rg.x;
-        for (int r0 = 0; r0 < n; r0 += NT) {
-            const int nb = min(NT, n - r0);
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-            __syncthreads();
-            int bucket = 0, pos = 0;
-            float absa = 0.f;
-            if (tid < nb) {
-                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
-                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-                const bool empty = w == 0 || h == 0;
-                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-                bucket = empty ? 0 : (h * (T + 1) + w);
-                absa = empty ? 0.f : fabsf(b.am);
-                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                           ((y1 + 1) << 24)));
-                pos = atomicAdd(&s_hist[bucket], 1);
-            }
-            for (int o = 32; o > 0; o >>= 1) absa += __shfl_xor(absa, o, 64);
-            if (lane == 0) s_fsum[wv] = absa;
-            __syncthreads();
-            const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
-            {
-                const int per = (kB + NT - 1) / NT;
-                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-                int local = 0;
-                for (int k = kb; k < ke; ++k) local += s_hist[k];
-                int incl = local;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int u = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += u;
-                }
-                if (lane == 63) s_wsum[wv] = incl;
-                __syncthreads();
-                int run = incl - local;
-                for (int q = 0; q < wv; ++q) run += s_wsum[q];
-                for (int k = kb; k < ke; ++k) {
-                    const int c = s_hist[k];
-                    s_hist[k] = run;
-                    run += c;
-                }
-            }
-            __syncthreads();
-            if (tid < nb) s_perm[s_hist[bucket] + pos] = tid;
-            __syncthreads();
-            // quantum: the round's sum of |a| spans 2^30 quanta.  A non-finite
-            // amplitude has no quantum: the round's pixels become NaN below.
-            const bool bad = !(suma <= 3.4028235e38f);
-            const int ex = (suma > 0.f && !bad) ? ilogbf(suma) + 1 : 0;
-            const float to_q = ldexpf(1.f, 30 - ex);
-            if (tid < nb) {
-                const int q = s_perm[tid];
-                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
-                const int pk = __float_as_int(p1.w);
-                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-                const float amq = p0.w * to_q;
-                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-                const int hh = (w > 0 && h > 0) ? h : 0;
-                const float dx0 = (float)bx0 - p0.x;
-                float dy = (float)by0 - p0.y;
-                int gr = by0 * T + bx0;
-                for (int r = 0; r < hh; ++r) {
-                    const float zy = fmaf(p1.z * dy, dy, p0.z), bxl = 2.f * p1.y * dy;
-                    float dx = dx0;
-                    int gi = gr;
-                    for (int c = 0; c < w; ++c) {
-                        const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
-                        // branch-free: pixels outside the cut add an integer zero (measured
-                        // faster than skipping them; the sums are the same)
-                        atomicAdd(&s_iacc[gi], __float2int_rn(amq * fmaxf(v, 0.f)));
-                        if (kCount) cnt += v > 0.f ? 1u : 0u;
-                        dx += 1.f;
-                        ++gi;
-                    }
-                    dy += 1.f;
-                    gr += T;
-                }
-            }
-            __syncthreads();
-            const float from_q = ldexpf(1.f, ex - 30);
-            for (int p = tid; p < T * T; p += NT) {
-                const int v = s_iacc[p];
-                if (bad) s_acc[p] = __builtin_nanf("");
-                if (v != 0) {
-                    if (!bad) s_acc[p] += (float)v * from_q;
-                    s_iacc[p] = 0;
-                }
-            }
+        for (int j = tid; j < n; j += NT) {
+            const Record R = a.rec[a.inst_rec[rg.x + j]];
+            const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+            cnt += forward_walk<T, kCount>(b, b.am * to_q, s_acc, etau);
         }
         __syncthreads();
         float sq = 0.f;
         for (int p = tid; p < T * T; p += NT) {
-            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
-            if (px < tc.W && py < tc.H) {
-                const int64_t pi = tc.pix_off + (int64_t)py * tc.W + px;
-                const float acc = s_acc[p];
-                pred[pi] = acc;
-                if (kLoss) {
-                    const float m = mask[pi];
-                    const float r = acc - target[pi];
-                    loss_term(a.loss_kind, m, r, inv_msum, sq, grad ? grad + pi : nullptr);
-                }
+            const int px = p % T, py = p / T;
+            if (px < o.vw && py < o.vh) {
+                const int64_t pi = o.base + (int64_t)py * o.stride + px;
+                const float y = tbad ? __builtin_nanf("") : (float)s_acc[p] * from_q;
+                pred[pi] = y;
+                if (kLoss) loss_term(a.loss_kind, mask[pi], y - target[pi], inv_msum, sq, grad ? grad + pi : nullptr);
             }
         }
         if (kLoss || kCount) {
-            for (int o = 32; o > 0; o >>= 1) {
-                sq += __shfl_xor(sq, o, 64);
-                if (kCount) cnt += __shfl_xor(cnt, o, 64);
+            for (int off = 32; off > 0; off >>= 1) {
+                sq += __shfl_xor(sq, off, 64);
+                if (kCount) cnt += __shfl_xor(cnt, off, 64);
             }
             if (lane == 0) {
                 s_red[wv] = sq;
@@ -510,7 +653,6 @@ __global__ __launch_bounds__(256) void k_forward_rpl_tiles(RenderArgs a, const f
         }
     }
 }
-
 
 // Epilogue of a tile whose sums are final: pred, and with kLoss the data
 // term's gradient and the tile's loss partial tile_sse[tile].  acc holds the
@@ -546,20 +688,21 @@ __device__ inline void finish_tile(const RenderArgs& a, int tile, const float* a
 }
 
 // Forward, record per lane with exact integer accumulation, over fixed chunks
-// of the tile-ordered instance list (the chunking of the adjoint): workgroup b
-// takes instances [256 b, 256 b + 256), which may span a few tiles.  Per pass
-// (up to KT of the chunk's tiles) the boxes are counting-sorted by shape in
-// LDS (a wave's lanes then walk boxes of one shape), and each lane walks one
-// box rows outer / columns inner and adds round(a max(e - e_T, 0) / quantum)
-// to its tile's int32 LDS sum with an integer LDS atomic (float LDS atomics
-// are slow on this GPU, integer ones are not).  The quantum is 2^(e - 30)
-// with 2^e above the pass's sum of |a|, so no pixel's sum can overflow and
-// the rounding error per term is below 2^-31 of that sum; integer sums do not
-// depend on the order of the adds.  A tile whose instances all lie in the
-// chunk is finished here; the first and the last tile of a chunk may run on
-// into neighbouring chunks, and their sums go to the chunk's two partial
-// slots, which k_forward_finish adds in chunk order.  The result is
-// deterministic.
+// of the tile-ordered instance list (the chunking of the adjoint): workgroup
+// b takes instances [256 b, 256 b + 256), which may span a few tiles, and lane
+// i owns instance 256 b + i.  The binning orders each tile's instances by
+// footprint box shape, so the lanes of a wave walk boxes of (nearly) one
+// shape.  Per pass (up to KT of the chunk's tiles) each lane walks its box,
+// rows outer and columns inner, and adds round(a max(e - e_T, 0) / quantum) to
+// its tile's int32 LDS sum with an integer LDS atomic (float LDS atomics are
+// slow on this GPU, integer ones are not); pixels outside the cut add an
+// integer zero (branch-free).  The quantum is 2^(e - 30) with 2^e above the
+// pass's sum of |a|, so no pixel's sum can overflow and the rounding error per
+// term is below 2^-31 of that sum; integer sums do not depend on the order of
+// the adds.  A tile whose instances all lie in the chunk is finished here; the
+// first and the last tile of a chunk may run on into neighbouring chunks, and
+// their sums go to the chunk's two partial slots, which k_forward_finish adds
+// in chunk order.  The result is deterministic.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float* __restrict__ target,
                                                        const float* __restrict__ mask,
@@ -569,16 +712,8 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
                                                        unsigned long long* __restrict__ incut,
                                                        float* __restrict__ partial) {
     constexpr int NT = 256, NW = 4;
-    // shape buckets: box sides above 16 share the last bucket (a smaller
-    // histogram to scan; measured faster at T = 32)
-    constexpr int kS = T < 16 ? T : 16;
-    constexpr int kB = (kS + 1) * (kS + 1);
     constexpr int KT = (1024 / (T * T)) > 0 ? 1024 / (T * T) : 1;
     __shared__ int s_iacc[KT * T * T];  // fixed-point sums, then (in place) their float values
-    __shared__ float4 s_box[NT][2];
-    __shared__ int s_gb[NT];
-    __shared__ int s_hist[kB + 1];
-    __shared__ int s_perm[NT];
     __shared__ int s_wsum[NW];
     __shared__ float s_fsum[NW];
     __shared__ float s_red[NW];
@@ -595,7 +730,7 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     float* s_facc = reinterpret_cast<float*>(s_iacc);
 
-    // every lane's instance: tile, run head, record and box (independent loads)
+    // the lane's instance: tile, run head, record and box (independent loads)
     const int64_t inst = chunk * NT + tid;
     int tile = -1;
     bool head = false;
@@ -608,32 +743,23 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
             org = a.tile_org[tile];
         }
     }
-    for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
     const uint64_t hm = __ballot(head);
     if (lane == 0) s_wsum[wv] = __popcll(hm);
-    int bucket = 0;
-    float absa = 0.f;
+    LaneBox b = {};
     int fin = -1;
     if (tile >= 0) {
         const Record R = a.rec[a.inst_rec[inst]];
         const TileOrg o = tile_org(org);
-        const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
-        const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-        const bool empty = w == 0 || h == 0;
-        const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-        const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-        bucket = empty ? 0 : (min(h, kS) * (kS + 1) + min(w, kS));
-        absa = empty ? 0.f : fabsf(b.am);
-        s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-        s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                    __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                   ((y1 + 1) << 24)));
+        b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
         if (head) {
             const int2 rg = a.ranges[tile];
             const bool inside = rg.x >= chunk * NT && rg.y <= chunk * NT + NT;
             fin = inside ? -1 : (tid == 0 ? 0 : 1);
         }
     }
+    const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
+    const int hh = w > 0 ? h : 0;
+    const float absa = hh > 0 ? fabsf(b.am) : 0.f;
     __syncthreads();
     int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
     int nd = 0;
@@ -644,10 +770,7 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     unsigned int cnt = 0;
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
-        if (p0 > 0) {
-            __syncthreads();  // the previous pass is done with LDS
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-        }
+        if (p0 > 0) __syncthreads();  // the previous pass is done with LDS
         const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
         if (act && head) {
             s_org[rslot - p0] = org;
@@ -657,65 +780,26 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         for (int q = tid; q < np * T * T; q += NT) s_iacc[q] = 0;
         // the pass's sum of |a| (its instances only)
         float pa = act ? absa : 0.f;
-        for (int o = 32; o > 0; o >>= 1) pa += __shfl_xor(pa, o, 64);
+        for (int off = 32; off > 0; off >>= 1) pa += __shfl_xor(pa, off, 64);
         if (lane == 0) s_fsum[wv] = pa;
         __syncthreads();
-        int pos = 0;
-        if (act) {
-            s_gb[tid] = (rslot - p0) * T * T;
-            pos = atomicAdd(&s_hist[bucket], 1);
-        }
         const float suma = (s_fsum[0] + s_fsum[1]) + (s_fsum[2] + s_fsum[3]);
-        __syncthreads();
-        {   // exclusive scan of the bucket counts; s_hist[kB] receives the total
-            const int per = (kB + NT - 1) / NT;
-            const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-            int local = 0;
-            for (int k = kb; k < ke; ++k) local += s_hist[k];
-            int incl = local;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += u;
-            }
-            if (lane == 63) s_wsum[wv] = incl;
-            __syncthreads();
-            int run = incl - local;
-            for (int q = 0; q < wv; ++q) run += s_wsum[q];
-            for (int k = kb; k < ke; ++k) {
-                const int c = s_hist[k];
-                s_hist[k] = run;
-                run += c;
-            }
-            if (kb < kB && ke == kB) s_hist[kB] = run;
-        }
-        __syncthreads();
-        if (act) s_perm[s_hist[bucket] + pos] = tid;
-        __syncthreads();
         // quantum: the pass's sum of |a| spans 2^30 quanta.  A non-finite
         // amplitude has no quantum: the pass's pixels become NaN below.
         const bool bad = !(suma <= 3.4028235e38f);
         const int ex = (suma > 0.f && !bad) ? ilogbf(suma) + 1 : 0;
         const float to_q = ldexpf(1.f, 30 - ex);
-        if (tid < s_hist[kB]) {
-            const int q = s_perm[tid];
-            const float4 p0v = s_box[q][0], p1 = s_box[q][1];
-            const int pk = __float_as_int(p1.w);
-            const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-            const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-            const float amq = p0v.w * to_q;
-            const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-            const int hh = (w > 0 && h > 0) ? h : 0;
-            const float dx0 = (float)bx0 - p0v.x;
-            float dy = (float)by0 - p0v.y;
-            int gr = s_gb[q] + by0 * T + bx0;
+        if (act) {
+            const float amq = b.am * to_q;
+            const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
+            float dy = (float)b.y0 - b.pyl;
+            int gr = (rslot - p0) * T * T + b.y0 * T + b.x0;
             for (int r = 0; r < hh; ++r) {
-                const float zy = fmaf(p1.z * dy, dy, p0v.z), bxl = 2.f * p1.y * dy;
+                const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
                 float dx = dx0;
                 int gi = gr;
                 for (int c = 0; c < w; ++c) {
-                    const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(p1.x, dx, bxl), zy)) - etau;
-                    // branch-free: pixels outside the cut add an integer zero (measured
-                    // faster than skipping them; the sums are the same)
+                    const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy)) - etau;
                     atomicAdd(&s_iacc[gi], __float2int_rn(amq * fmaxf(v, 0.f)));
                     if (kCount) cnt += v > 0.f ? 1u : 0u;
                     dx += 1.f;
@@ -742,7 +826,7 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         }
     }
     if (kCount) {
-        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
         if (lane == 0) s_cnt[wv] = cnt;
         __syncthreads();
         if (tid == 0) {
@@ -818,7 +902,7 @@ __global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const floa
 // no atomics and is deterministic.  Footprints are small (tens of pixels),
 // so 16-lane groups waste fewer lanes on a box's last pass than half-waves
 // and spread the per-instance set-up over four instances per instruction.
-// Instances are grouped by footprint size in the sort, so the four groups of
+// The binning orders a tile's instances by box shape, so the four groups of
 // a wave see similar boxes.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* __restrict__ target,
@@ -948,189 +1032,61 @@ __global__ __launch_bounds__(256) void k_forward_rol(RenderArgs a, const float* 
     }
 }
 
-// Adjoint, record per lane, persistent grid (persistent = 1): workgroups pull
-// whole tiles heaviest-first from a work queue; the tile's upstream gradient
-// is staged in LDS and every lane walks one instance's box and sums, with
-// t = g e (inside the cut):
-//   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
-//   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
-// from which the gradient with respect to the stored record fields follows
-// (dz/d field, times amp ln 2).  The result goes to the instance's emission
-// slot, so no atomics are needed.  The walk is rows outer, columns inner,
-// with per-row sums folded in with dy (three accumulations per pixel instead
-// of seven).  A wave runs each loop as long as its largest trip count, so
-// each round of up to 256 instances is first ordered by (box height, box
-// width) with a counting sort in LDS, and lane j walks the j-th box: the
-// lanes of a wave then have boxes of the same shape.  Which lane walks which
-// instance changes no instance's sum, so the result stays deterministic.
-template <int T, int NT>
-__global__ __launch_bounds__(NT) void k_backward_tiles(RenderArgs a, const float* __restrict__ grad_pred,
-                                                 const float* __restrict__ grad_scale,
-                                                 float4* __restrict__ inst_grad,
-                                                 int* __restrict__ work_counter) {
-    constexpr int kB = (T + 1) * (T + 1);
-    __shared__ float s_g[T * T];
-    __shared__ float4 s_box[NT][2];
-    __shared__ uint32_t s_slot[NT];
-    __shared__ int s_hist[kB + 1];
-    __shared__ int s_perm[NT];
-    __shared__ int s_wsum[NT / 64];
+// Adjoint, record per lane, one tile per workgroup (persistent: tiles from
+// the work queue, heaviest first).  The tile's upstream gradients are staged
+// in LDS once; lane i takes the tile's instances i, i + 256, ... (in
+// shape-class order from the binning), walks each box (adjoint_walk) and
+// writes the gradient to the instance's emission slot: no cross-lane
+// reduction and no atomics, so the result is deterministic.
+template <int T>
+__global__ __launch_bounds__(256) void k_backward_tiles(RenderArgs a, const float* __restrict__ grad_pred,
+                                                       const float* __restrict__ grad_scale,
+                                                       float4* __restrict__ inst_grad,
+                                                       int* __restrict__ work_counter) {
+    constexpr int NT = 256;
+    __shared__ __align__(16) float s_g[T * T];
     __shared__ int s_next;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const float etau = a.etau;
+    const int tid = threadIdx.x;
     const float tau2k = SVR_KZ * a.tau2;
     const float scale = grad_scale ? grad_scale[0] : 1.f;
     int iter = 0;
     while (true) {
         const int tile = next_tile<NT>(a, work_counter, iter, &s_next);
         if (tile < 0) break;
-        const TileCoord tc = tile_coord(a, tile);
         const int2 rg = a.ranges[tile];
-        const int xmax = min(T, tc.W - tc.x0) - 1, ymax = min(T, tc.H - tc.y0) - 1;
-        __syncthreads();
-        for (int p = tid; p < T * T; p += NT) {
-            const int px = tc.x0 + p % T, py = tc.y0 + p / T;
-            s_g[p] = (px < tc.W && py < tc.H) ? grad_pred[tc.pix_off + (int64_t)py * tc.W + px] * scale : 0.f;
-        }
         const int n = rg.y - rg.x;
-        for (int r0 = 0; r0 < n; r0 += NT) {
-            const int cnt = min(NT, n - r0);
-            __syncthreads();
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-            __syncthreads();
-            int bucket = 0, pos = 0;
-            if (tid < cnt) {
-                const Record R = a.rec[a.inst_rec[rg.x + r0 + tid]];
-                const LaneBox b = lane_box(R, tc.x0, tc.y0, xmax, ymax, tau2k);
-                const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-                const bool empty = w == 0 || h == 0;
-                const int x0 = empty ? 0 : b.x0, x1 = empty ? -1 : b.x1;
-                const int y0 = empty ? 0 : b.y0, y1 = empty ? -1 : b.y1;
-                bucket = empty ? 0 : (h * (T + 1) + w);
-                s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-                s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                            __int_as_float((x0 + 1) | ((x1 + 1) << 8) | ((y0 + 1) << 16) |
-                                                           ((y1 + 1) << 24)));
-                s_slot[tid] = a.inst_idx[rg.x + r0 + tid];
-                pos = atomicAdd(&s_hist[bucket], 1);
-            }
-            __syncthreads();
-            {   // exclusive scan of the bucket counts: thread t takes a run of ceil(kB / NT)
-                const int per = (kB + NT - 1) / NT;
-                const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-                int local = 0;
-                for (int k = kb; k < ke; ++k) local += s_hist[k];
-                int incl = local;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int u = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += u;
-                }
-                if (lane == 63) s_wsum[wv] = incl;
-                __syncthreads();
-                int run = incl - local;
-                for (int q = 0; q < wv; ++q) run += s_wsum[q];
-                for (int k = kb; k < ke; ++k) {
-                    const int c = s_hist[k];
-                    s_hist[k] = run;
-                    run += c;
-                }
-            }
-            __syncthreads();
-            if (tid < cnt) s_perm[s_hist[bucket] + pos] = tid;
-            __syncthreads();
-            if (tid < cnt) {
-                const int q = s_perm[tid];
-                const float4 p0 = s_box[q][0], p1 = s_box[q][1];
-                const int pk = __float_as_int(p1.w);
-                const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-                const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-                const float pxl = p0.x, pyl = p0.y, bz = p0.z, am = p0.w;
-                const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
-                float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-                const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-                const int hh = (w > 0 && h > 0) ? h : 0;
-                const float dx0 = (float)bx0 - pxl;
-                const float b2a01 = 2.f * a01;
-                float dy = (float)by0 - pyl;
-                int gr = by0 * T + bx0;
-                for (int r = 0; r < hh; ++r) {
-                    const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
-                    float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
-                    int gi = gr;
-                    for (int c = 0; c < w; ++c) {
-                        const float g = s_g[gi];
-                        const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
-                        const float v = e - etau;
-                        Sa = fmaf(g, fmaxf(v, 0.f), Sa);
-                        const float t = (v > 0.f) ? g * e : 0.f;
-                        const float tx = t * dx;
-                        R0 += t;
-                        R1 += tx;
-                        R2 = fmaf(tx, dx, R2);
-                        dx += 1.f;
-                        ++gi;
-                    }
-                    S0 += R0;
-                    Sx += R1;
-                    Sxx += R2;
-                    Sy = fmaf(dy, R0, Sy);
-                    Sxy = fmaf(dy, R1, Sxy);
-                    Syy = fmaf(dy * dy, R0, Syy);
-                    dy += 1.f;
-                    gr += T;
-                }
-                const float k2 = am * SVR_LN2;
-                float4 g0, g1;
-                g0.x = Sa;
-                g0.y = k2 * S0;
-                g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
-                g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
-                g1.x = k2 * Sxx;
-                g1.y = 2.f * k2 * Sxy;
-                g1.z = k2 * Syy;
-                g1.w = 0.f;
-                const uint32_t e_slot = s_slot[q];
-                inst_grad[2 * (int64_t)e_slot] = g0;
-                inst_grad[2 * (int64_t)e_slot + 1] = g1;
-            }
+        if (n <= 0) continue;
+        const TileOrg o = tile_org(a.tile_org[tile]);
+        __syncthreads();  // the previous tile is done with s_g
+        stage_tile<T, NT>(grad_pred, o, s_g);
+        __syncthreads();
+        for (int j = tid; j < n; j += NT) {
+            const int64_t i = rg.x + j;
+            const Record R = a.rec[a.inst_rec[i]];
+            const uint32_t e_slot = a.inst_idx[i];
+            const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+            store_adjoint(adjoint_walk<T>(b, s_g, a.etau), b, scale, inst_grad, e_slot);
         }
     }
 }
 
-
-// Adjoint, record per lane, over fixed chunks of the sorted instance list:
-// workgroup b takes instances [256 b, 256 b + 256), which are ordered by tile
-// and may span several tiles, so every workgroup has one full round of work
-// whatever the instance count of a tile, and the grid load stays even (one
-// workgroup per tile left the chip with a long tail of busy tiles).  The
-// upstream gradients of the chunk's tiles are staged in LDS (up to KT tiles at
-// a time; a chunk over more tiles takes further passes); every lane walks one
-// instance's box and sums, with t = g e (inside the cut):
-//   Sa = sum g max(e - e_T, 0), S0 = sum t, Sx = sum t dx, Sy = sum t dy,
-//   Sxx = sum t dx^2, Sxy = sum t dx dy, Syy = sum t dy^2,
-// from which the gradient with respect to the stored record fields follows
-// (dz/d field, times amp ln 2).  The result goes to the instance's emission
-// slot, so no atomics are needed.  The walk is rows outer, columns inner,
-// with per-row sums folded in with dy (three accumulations per pixel instead
-// of seven).  A wave runs each loop as long as its largest trip count, so the
-// pass's instances are first ordered by (box height, box width) with a
-// counting sort in LDS, and lane j walks the j-th box: the lanes of a wave
-// then have boxes of the same shape.  Which lane walks which instance changes
-// no instance's sum, so the result is deterministic and independent of the
-// chunking.
-template <int T, int NT>
-__global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
+// Adjoint, record per lane, over fixed chunks of the tile-ordered instance
+// list: workgroup b takes instances [256 b, 256 b + 256), which may span a few
+// tiles, and lane i owns instance 256 b + i.  The binning orders each tile's
+// instances by footprint box shape, so the 64 consecutive instances of a wave
+// walk boxes of (nearly) one shape and no lane waits long on another.  The
+// upstream gradients of up to KT of the chunk's tiles are staged in LDS per
+// pass; each lane walks its record's box inside its tile (adjoint_walk) and
+// writes the seven sums' gradient to the instance's emission slot: no
+// cross-lane reduction and no atomics, so the result is deterministic and
+// independent of the chunking.
+template <int T>
+__global__ __launch_bounds__(256) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
                                                  const float* __restrict__ grad_scale,
                                                  float4* __restrict__ inst_grad) {
-    constexpr int kB = (T + 1) * (T + 1);
-    constexpr int KT = (1024 / (T * T)) > 0 ? 1024 / (T * T) : 1;  // tiles staged per pass (4 KB)
-    constexpr int NW = NT / 64;
-    __shared__ float s_g[KT * T * T];
-    __shared__ float4 s_box[NT][2];
-    __shared__ uint32_t s_slot[NT];
-    __shared__ int s_gb[NT];
-    __shared__ int s_hist[kB + 1];
-    __shared__ int s_perm[NT];
+    constexpr int NT = 256, NW = 4;
+    constexpr int KT = (2048 / (T * T)) > 0 ? 2048 / (T * T) : 1;  // tiles staged per pass (8 KB)
+    __shared__ __align__(16) float s_g[KT * T * T];
     __shared__ int s_wsum[NW];
     __shared__ int4 s_org[KT];  // the pass's tiles (TileOrg packing)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1138,11 +1094,9 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
     if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
     const float tau2k = SVR_KZ * a.tau2;
-    const float etau = a.etau;
 
-    // every lane's instance: tile (-1 past the end or for emission padding),
-    // whether it heads a run of its tile in the chunk, its record and box;
-    // the loads are independent so their latencies overlap
+    // the lane's instance: tile (-1 past the end or for emission padding),
+    // whether it heads a run of its tile in the chunk, its record and box
     const int64_t inst = chunk * NT + tid;
     int tile = -1;
     bool head = false;
@@ -1155,24 +1109,15 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
             org = a.tile_org[tile];
         }
     }
-    for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
     const uint64_t hm = __ballot(head);
     if (lane == 0) s_wsum[wv] = __popcll(hm);
-    int bucket = 0;
+    LaneBox b = {};
+    uint32_t e_slot = 0;
     if (tile >= 0) {
         const Record R = a.rec[a.inst_rec[inst]];
+        e_slot = a.inst_idx[inst];
         const TileOrg o = tile_org(org);
-        const LaneBox b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
-        const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-        const bool empty = w == 0 || h == 0;
-        const int bx0 = empty ? 0 : b.x0, bx1 = empty ? -1 : b.x1;
-        const int by0 = empty ? 0 : b.y0, by1 = empty ? -1 : b.y1;
-        bucket = empty ? 0 : (h * (T + 1) + w);
-        s_box[tid][0] = make_float4(b.pxl, b.pyl, b.bz, b.am);
-        s_box[tid][1] = make_float4(b.a00, b.a01, b.a11,
-                                    __int_as_float((bx0 + 1) | ((bx1 + 1) << 8) | ((by0 + 1) << 16) |
-                                                   ((by1 + 1) << 24)));
-        s_slot[tid] = a.inst_idx[inst];
+        b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
     }
     __syncthreads();
     // rslot = index of the lane's run (distinct tile) in the chunk
@@ -1182,110 +1127,18 @@ __global__ __launch_bounds__(NT) void k_backward(RenderArgs a, const float* __re
         if (q < wv) rslot += s_wsum[q];
         nd += s_wsum[q];
     }
+    const float scale = grad_scale ? grad_scale[0] : 1.f;
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
-        if (p0 > 0) {
-            __syncthreads();  // the previous pass is done with LDS
-            for (int k = tid; k < kB; k += NT) s_hist[k] = 0;
-        }
+        if (p0 > 0) __syncthreads();  // the previous pass is done with LDS
         const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
         if (act && head) s_org[rslot - p0] = org;
-        __syncthreads();  // s_org and the zeroed histogram are visible
-        int pos = 0;
+        __syncthreads();
+        for (int sl = 0; sl < np; ++sl) stage_tile<T, NT>(grad_pred, tile_org(s_org[sl]), s_g + sl * T * T);
+        __syncthreads();
         if (act) {
-            s_gb[tid] = (rslot - p0) * T * T;
-            pos = atomicAdd(&s_hist[bucket], 1);
-        }
-        for (int q = tid; q < np * T * T; q += NT) {
-            const int sl = q / (T * T), pix = q - sl * (T * T);
-            const TileOrg o = tile_org(s_org[sl]);
-            const int px = pix % T, py = pix / T;
-            float gv = 0.f;
-            if (px < o.vw && py < o.vh) gv = grad_pred[o.base + (int64_t)py * o.stride + px];
-            s_g[q] = gv;
-        }
-        __syncthreads();
-        {   // exclusive scan of the bucket counts: thread t takes a run of
-            // ceil(kB / NT); s_hist[kB] receives the total
-            const int per = (kB + NT - 1) / NT;
-            const int kb = min(tid * per, kB), ke = min(kb + per, kB);
-            int local = 0;
-            for (int k = kb; k < ke; ++k) local += s_hist[k];
-            int incl = local;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += u;
-            }
-            if (lane == 63) s_wsum[wv] = incl;
-            __syncthreads();
-            int acc = incl - local;
-            for (int q = 0; q < wv; ++q) acc += s_wsum[q];
-            for (int k = kb; k < ke; ++k) {
-                const int c = s_hist[k];
-                s_hist[k] = acc;
-                acc += c;
-            }
-            if (kb < kB && ke == kB) s_hist[kB] = acc;
-        }
-        __syncthreads();
-        if (act) s_perm[s_hist[bucket] + pos] = tid;
-        __syncthreads();
-        const float scale = grad_scale ? grad_scale[0] : 1.f;
-        if (tid < s_hist[kB]) {
-            const int q = s_perm[tid];
-            const float4 p0v = s_box[q][0], p1 = s_box[q][1];
-            const int pk = __float_as_int(p1.w);
-            const int bx0 = (pk & 0xff) - 1, bx1 = ((pk >> 8) & 0xff) - 1;
-            const int by0 = ((pk >> 16) & 0xff) - 1, by1 = ((pk >> 24) & 0xff) - 1;
-            const float pxl = p0v.x, pyl = p0v.y, bz = p0v.z, am = p0v.w;
-            const float a00 = p1.x, a01 = p1.y, a11 = p1.z;
-            float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f, Sa = 0.f;
-            const int w = bx1 - bx0 + 1, h = by1 - by0 + 1;
-            const int hh = (w > 0 && h > 0) ? h : 0;
-            const float dx0 = (float)bx0 - pxl;
-            const float b2a01 = 2.f * a01;
-            float dy = (float)by0 - pyl;
-            int gr = s_gb[q] + by0 * T + bx0;
-            for (int r = 0; r < hh; ++r) {
-                const float zy = fmaf(a11 * dy, dy, bz), bxl = b2a01 * dy;
-                float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
-                int gi = gr;
-                for (int c = 0; c < w; ++c) {
-                    const float g = s_g[gi];
-                    const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(a00, dx, bxl), zy));
-                    const float v = e - etau;
-                    Sa = fmaf(g, fmaxf(v, 0.f), Sa);
-                    const float t = (v > 0.f) ? g * e : 0.f;
-                    const float tx = t * dx;
-                    R0 += t;
-                    R1 += tx;
-                    R2 = fmaf(tx, dx, R2);
-                    dx += 1.f;
-                    ++gi;
-                }
-                S0 += R0;
-                Sx += R1;
-                Sxx += R2;
-                Sy = fmaf(dy, R0, Sy);
-                Sxy = fmaf(dy, R1, Sxy);
-                Syy = fmaf(dy * dy, R0, Syy);
-                dy += 1.f;
-                gr += T;
-            }
-            // the upstream scale multiplies every sum (it was applied to g)
-            const float k2 = am * SVR_LN2 * scale;
-            float4 g0, g1;
-            g0.x = Sa * scale;
-            g0.y = k2 * S0;
-            g0.z = -2.f * k2 * (a00 * Sx + a01 * Sy);
-            g0.w = -2.f * k2 * (a01 * Sx + a11 * Sy);
-            g1.x = k2 * Sxx;
-            g1.y = 2.f * k2 * Sxy;
-            g1.z = k2 * Syy;
-            g1.w = 0.f;
-            const uint32_t e_slot = s_slot[q];
-            inst_grad[2 * (int64_t)e_slot] = g0;
-            inst_grad[2 * (int64_t)e_slot + 1] = g1;
+            const AdjointSums S = adjoint_walk<T>(b, s_g + (rslot - p0) * T * T, a.etau);
+            store_adjoint(S, b, scale, inst_grad, e_slot);
         }
     }
 }
@@ -1349,11 +1202,11 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, int2* ranges, int32_t n_tiles,
-                              hipStream_t st) {
+                              uint32_t* pad_out, hipStream_t st) {
     hipError_t e = launch_fill_zero(ranges, sizeof(int2) * (size_t)n_tiles, st);
     if (e != hipSuccess || n <= 0) return e;
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, n, ranges,
-                       (uint32_t)n_tiles);
+                       (uint32_t)n_tiles, pad_out);
     return hipGetLastError();
 }
 
@@ -1386,23 +1239,23 @@ hipError_t fwd_rol_dispatch(const RenderArgs& a, const float* target, const floa
 }
 
 template <int T>
-hipError_t fwd_rpl_tiles_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
-                                  float* pred, float* grad, float* tile_sse, unsigned long long* incut,
-                                  int* work_counter, int grid, hipStream_t st) {
+hipError_t fwd_tiles_dispatch(const RenderArgs& a, const float* target, const float* mask, const float* msum,
+                              float* pred, float* grad, float* tile_sse, unsigned long long* incut,
+                              int* work_counter, int grid, hipStream_t st) {
     const bool loss = target != nullptr;
     const bool count = incut != nullptr;
     if (loss && count)
-        hipLaunchKernelGGL((k_forward_rpl_tiles<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask,
-                           msum, pred, grad, tile_sse, incut, work_counter);
+        hipLaunchKernelGGL((k_forward_tiles<T, true, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
     else if (loss)
-        hipLaunchKernelGGL((k_forward_rpl_tiles<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask,
-                           msum, pred, grad, tile_sse, incut, work_counter);
+        hipLaunchKernelGGL((k_forward_tiles<T, true, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
     else if (count)
-        hipLaunchKernelGGL((k_forward_rpl_tiles<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask,
-                           msum, pred, grad, tile_sse, incut, work_counter);
+        hipLaunchKernelGGL((k_forward_tiles<T, false, true>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
     else
-        hipLaunchKernelGGL((k_forward_rpl_tiles<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask,
-                           msum, pred, grad, tile_sse, incut, work_counter);
+        hipLaunchKernelGGL((k_forward_tiles<T, false, false>), dim3(grid), dim3(256), 0, st, a, target, mask, msum,
+                           pred, grad, tile_sse, incut, work_counter);
     return hipGetLastError();
 }
 
@@ -1447,6 +1300,16 @@ size_t forward_partial_floats(const RenderArgs& a) {
     return (size_t)n_chunks * 2 * (size_t)a.tile * (size_t)a.tile;
 }
 
+hipError_t launch_class_order(const uint32_t* keys, const uint32_t* vals, const uint32_t* idx, const int2* ranges,
+                              int32_t n_tiles, uint32_t* keys_out, uint32_t* vals_out, uint32_t* idx_out,
+                              hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    const int grid = ((n_tiles + 7) >> 3) << 3;  // whole XCD remap
+    hipLaunchKernelGGL(k_class_order, dim3(grid), dim3(256), 0, st, keys, vals, idx, ranges, n_tiles, keys_out,
+                       vals_out, idx_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask, const float* msum,
                           float* pred, float* grad_pred, float* tile_sse, unsigned long long* incut,
                           int* work_counter, float* partial, hipStream_t st) {
@@ -1464,20 +1327,20 @@ hipError_t launch_forward(const RenderArgs& a, const float* target, const float*
             default: return hipErrorInvalidValue;
         }
     }
-    if (a.forward_mode == 1 && a.persistent) {
-        const int grid = grid_for(a, 256);
-        switch (a.tile) {
-            case 8: return fwd_rpl_tiles_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
-            case 16: return fwd_rpl_tiles_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
-            case 32: return fwd_rpl_tiles_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    if (a.forward_mode == 1) {
+    if (a.forward_mode == 1 && !a.persistent) {
         switch (a.tile) {
             case 8: return fwd_chunk_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
             case 16: return fwd_chunk_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
             case 32: return fwd_chunk_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, partial, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (a.forward_mode == 1) {
+        const int grid = grid_for(a, 256);
+        switch (a.tile) {
+            case 8: return fwd_tiles_dispatch<8>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 16: return fwd_tiles_dispatch<16>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
+            case 32: return fwd_tiles_dispatch<32>(a, target, mask, msum, pred, grad_pred, tile_sse, incut, work_counter, grid, st);
             default: return hipErrorInvalidValue;
         }
     }
@@ -1539,8 +1402,6 @@ hipError_t launch_loss_finalize(const float* tile_sse, const SliceGeo* geo, int3
 hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const float* grad_scale,
                            float4* inst_grad, int* work_counter, hipStream_t st) {
     if (a.n_tiles <= 0 || a.n_inst <= 0) return hipSuccess;
-    // four waves per workgroup (one wave per tile measured slower: tiles with
-    // many instances then serialise on a single wave)
     constexpr int NT = 256;
     if (a.persistent) {  // whole tiles, heaviest first, from a work queue
         hipError_t e = launch_fill_zero(work_counter, sizeof(int), st);
@@ -1548,13 +1409,13 @@ hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const fl
         const int grid = grid_for(a, NT);
         switch (a.tile) {
             case 8:
-                hipLaunchKernelGGL((k_backward_tiles<8, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                hipLaunchKernelGGL((k_backward_tiles<8>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
                 break;
             case 16:
-                hipLaunchKernelGGL((k_backward_tiles<16, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                hipLaunchKernelGGL((k_backward_tiles<16>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
                 break;
             case 32:
-                hipLaunchKernelGGL((k_backward_tiles<32, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
+                hipLaunchKernelGGL((k_backward_tiles<32>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad, work_counter);
                 break;
             default: return hipErrorInvalidValue;
         }
@@ -1566,13 +1427,13 @@ hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const fl
     const int grid = (int)(((n_chunks + 7) >> 3) << 3);  // whole XCD remap
     switch (a.tile) {
         case 8:
-            hipLaunchKernelGGL((k_backward<8, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
+            hipLaunchKernelGGL((k_backward<8>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         case 16:
-            hipLaunchKernelGGL((k_backward<16, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
+            hipLaunchKernelGGL((k_backward<16>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         case 32:
-            hipLaunchKernelGGL((k_backward<32, NT>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
+            hipLaunchKernelGGL((k_backward<32>), dim3(grid), dim3(NT), 0, st, a, grad_pred, grad_scale, inst_grad);
             break;
         default: return hipErrorInvalidValue;
     }

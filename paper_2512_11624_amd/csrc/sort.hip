@@ -209,9 +209,9 @@ size_t sort_tmp_bytes(int64_t n) {
 
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                              int64_t n, int key_bits, void* tmp, bool* result_in_alt,
-                             hipStream_t st, uint32_t* idx, uint32_t* idx_alt) {
+                             hipStream_t st, uint32_t* idx, uint32_t* idx_alt, int first_bit) {
     *result_in_alt = false;
-    if (n <= 0 || key_bits <= 0) return hipSuccess;
+    if (n <= 0 || key_bits <= first_bit || first_bit < 0) return hipSuccess;
     const int64_t nb = (n + kItems - 1) / kItems;
     const int64_t nh = nb << kMaxDigitBits;
     int* hist = (int*)tmp;
@@ -219,12 +219,12 @@ hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
     size_t a = sizeof(int) * (size_t)nh * 2;
     a = (a + 255) & ~(size_t)255;
     void* stmp = (char*)tmp + a;
-    const int width = radix_digit_bits(key_bits);
+    const int width = radix_digit_bits(key_bits - first_bit);
     uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
     uint32_t *xi = idx, *xo = idx_alt;
     bool alt = false;
     bool first = true;
-    for (int shift = 0; shift < key_bits; shift += width) {
+    for (int shift = first_bit; shift < key_bits; shift += width) {
         const int nbits = (key_bits - shift) < width ? (key_bits - shift) : width;
         const int mode = !idx ? 0 : (first ? 2 : 1);
         hipError_t e;

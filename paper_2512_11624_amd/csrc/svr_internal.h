@@ -8,8 +8,11 @@
 // exp(-x/2) = exp2(KZ * x)
 #define SVR_KZ (-0.5f * SVR_LOG2E)
 
-// Instance sort key = (global tile id << kClassBits) | footprint size class.
-constexpr int kClassBits = 2;
+// Instance sort key = (global tile id << kClassBits) | footprint shape class.
+// The binning sorts the tile bits only (a tile's instances stay in emission
+// order); the tile kernels order a tile's instances by class in LDS.
+constexpr int kClassBits = 6;
+constexpr int kClasses = 1 << kClassBits;
 
 // Static per-slice geometry (depends on the tile size through the tile table).
 struct SliceGeo {
@@ -163,8 +166,8 @@ hipError_t launch_scan_int(const int* in, int* out, int64_t n, long long* totals
 hipError_t launch_scan_int2(const int2* in, int2* out, int64_t n, long long* totals, void* tmp,
                             hipStream_t st);
 
-// Stable LSD radix sort of (key, value) pairs on the low key_bits bits
-// (higher bits are ignored).
+// Stable LSD radix sort of (key, value) pairs on bits [first_bit, key_bits)
+// of the key (the other bits are ignored and travel with the key).
 // Buffers are ping-ponged; *result_in_alt tells where the result ended.  When
 // idx/idx_alt are given, the input position of every pair travels with it
 // (ending in the same buffer parity as keys).
@@ -174,7 +177,7 @@ int radix_digit_bits(int key_bits);
 hipError_t launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                              uint32_t* vals_alt, int64_t n, int key_bits, void* tmp,
                              bool* result_in_alt, hipStream_t st, uint32_t* idx = nullptr,
-                             uint32_t* idx_alt = nullptr);
+                             uint32_t* idx_alt = nullptr, int first_bit = 0);
 
 struct RenderArgs {
     const SliceGeo* geo;
@@ -198,16 +201,22 @@ struct RenderArgs {
     int32_t n_cu;                // compute units (persistent grid size)
 };
 
-// keys >= n_tiles (emission padding) are ignored.
+// keys >= n_tiles (emission padding) are in no range; they are copied to
+// pad_out (if not NULL) at their positions.
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, int2* ranges, int32_t n_tiles,
-                              hipStream_t st);
+                              uint32_t* pad_out, hipStream_t st);
 hipError_t launch_mask_sum(const float* mask, int64_t n, float* partial, float* out,
                            hipStream_t st);
-// partial: forward_partial_floats(a) floats of scratch (record-per-lane mode).
+// partial: forward_partial_floats(a) floats of scratch (chunked record-per-lane mode).
 hipError_t launch_forward(const RenderArgs& a, const float* target, const float* mask,
                           const float* msum, float* pred, float* grad_pred, float* tile_sse,
                           unsigned long long* incut, int* work_counter, float* partial, hipStream_t st);
 size_t forward_partial_floats(const RenderArgs& a);
+// Stable order of each tile's instances by shape class (keys, values and
+// emission slots from the tile sort -> the _out arrays; ranges unchanged).
+hipError_t launch_class_order(const uint32_t* keys, const uint32_t* vals, const uint32_t* idx, const int2* ranges,
+                              int32_t n_tiles, uint32_t* keys_out, uint32_t* vals_out, uint32_t* idx_out,
+                              hipStream_t st);
 // Scale regulariser (adds to g [n,3] and, if loss != NULL, to loss[0]);
 // partial holds kRegBlocks floats.
 constexpr int kRegBlocks = 512;

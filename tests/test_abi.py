@@ -54,7 +54,7 @@ def test_host_only_context_validates_geometry():
     ctx.svr_set_geometry(p)
     assert ctx.n_pixels == p.n_pixels
     st = ctx.svr_get_stats()
-    assert st["n_tiles"] == 48 * 4 and st["key_bits"] == 8 + 2
+    assert st["n_tiles"] == 48 * 4 and st["key_bits"] == 8 + 6
     ctx.svr_set_config(tile=8)
     assert ctx.svr_get_stats()["n_tiles"] == 48 * 16
     ctx.svr_set_config(tile=32)
