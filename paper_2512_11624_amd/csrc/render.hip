@@ -33,20 +33,34 @@ __device__ inline int xcd_tile(int b, int n_tiles) {
     return (b & 7) * per + (b >> 3);
 }
 
-// [start, end) of every tile's instances in the sorted list.  Slots outside
-// every tile (padding keys, sorted last) are copied to pad_out, the buffer
-// the class order then fills, so that they keep their padding key there.
+// [start, end) of every tile's instances in the tile-sorted list; each
+// thread looks at four consecutive keys.  Slots outside every tile (padding
+// keys, sorted last) are copied to pad_out, the buffer the class order then
+// fills, so that they keep their padding key there.
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, int2* __restrict__ ranges,
                               uint32_t n_tiles, uint32_t* __restrict__ pad_out) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint32_t k = keys[s] >> kClassBits;  // tile id
-    if (k >= n_tiles) {
-        if (pad_out) pad_out[s] = keys[s];
-        return;
+    const int64_t s0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (s0 >= n) return;
+    uint32_t key[4];
+    uint32_t k[6];  // tile ids of keys s0 - 1 .. s0 + 4 (n_tiles outside the list)
+    k[0] = s0 > 0 ? keys[s0 - 1] >> kClassBits : n_tiles;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const uint32_t v = s0 + j < n ? keys[s0 + j] : 0xffffffffu;
+        if (j < 4) key[j] = v;
+        k[j + 1] = s0 + j < n ? min(v >> kClassBits, n_tiles) : n_tiles;
     }
-    if (s == 0 || (keys[s - 1] >> kClassBits) != k) ranges[k].x = (int)s;
-    if (s == n - 1 || (keys[s + 1] >> kClassBits) != k) ranges[k].y = (int)(s + 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t t = k[j + 1];
+        if (s0 + j >= n) break;
+        if (t >= n_tiles) {
+            if (pad_out) pad_out[s0 + j] = key[j];
+            continue;
+        }
+        if (k[j] != t) ranges[t].x = (int)(s0 + j);
+        if (k[j + 2] != t) ranges[t].y = (int)(s0 + j + 1);
+    }
 }
 
 __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
@@ -54,12 +68,23 @@ __global__ void k_fill_zero(uint32_t* __restrict__ p, int64_t n) {
     if (i < n) p[i] = 0u;
 }
 
+// Block partial sums of x [n]: 16-byte loads for the aligned body.
 __global__ __launch_bounds__(256) void k_partial_sum(const float* __restrict__ x, int64_t n,
                                                       float* __restrict__ partial) {
     __shared__ float s[4];
     float acc = 0.f;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc += x[i];
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int head = (int)(((16 - ((uintptr_t)x & 15)) & 15) >> 2);  // scalars before the first 16-byte boundary
+    const int64_t nh = head < n ? head : n;
+    const int64_t n4 = (n - nh) >> 2;
+    const float4* x4 = reinterpret_cast<const float4*>(x + nh);
+    for (int64_t i = t0; i < n4; i += stride) {
+        const float4 v = x4[i];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    if (t0 < nh) acc += x[t0];
+    for (int64_t i = nh + 4 * n4 + t0; i < n; i += stride) acc += x[i];
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -461,7 +486,7 @@ __device__ inline void stage_tile(const float* __restrict__ src, const TileOrg& 
 // segment out in order (coalesced).
 // The record-per-lane tile kernels take consecutive instances on a wave's
 // lanes, which then walk boxes of (nearly) one shape.
-constexpr int kSeg = 2048;
+constexpr int kSeg = 4096;
 static_assert(kClasses == 64, "one lane per class in the class scan");
 __global__ __launch_bounds__(256) void k_class_order(const uint32_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ vals,
@@ -687,22 +712,51 @@ __device__ inline void finish_tile(const RenderArgs& a, int tile, const float* a
     }
 }
 
+// The chunked tile kernels give each workgroup 256 NI consecutive instances
+// of the tile-ordered list; lane i takes instances i, i + 256, ...  The loads
+// of a lane's NI instances are issued together, so their latency is paid once
+// per NI instances (measured best: NI = 2 for the forward, 1 for the adjoint,
+// whose walk holds more registers).
+constexpr int kFwdPer = 2;
+constexpr int kBwdPer = 1;
+
+// Runs (distinct tiles) of a chunk: rslot[k] is the index of the run of the
+// lane's k-th instance (chunk order: k, then wave, then lane), or -1 if it
+// has none; returns the number of runs.  hm[k] are the wave's ballots of
+// run heads.  Called by all threads; s_wsum [NI][4] scratch; ends with a
+// barrier.
+template <int NI>
+__device__ inline int chunk_runs(const uint64_t* hm, const int* tile, const bool* head, int (*s_wsum)[4],
+                                 int* rslot) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = 0; k < NI; ++k)
+        if (lane == 0) s_wsum[k][wv] = __popcll(hm[k]);
+    __syncthreads();
+    int run = 0, pre[NI];
+    for (int k = 0; k < NI; ++k)
+        for (int q = 0; q < 4; ++q) {
+            if (q == wv) pre[k] = run;
+            run += s_wsum[k][q];
+        }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int k = 0; k < NI; ++k)
+        rslot[k] = tile[k] >= 0 ? pre[k] + __popcll(hm[k] & lt) + (head[k] ? 1 : 0) - 1 : -1;
+    return run;
+}
+
 // Forward, record per lane with exact integer accumulation, over fixed chunks
-// of the tile-ordered instance list (the chunking of the adjoint): workgroup
-// b takes instances [256 b, 256 b + 256), which may span a few tiles, and lane
-// i owns instance 256 b + i.  The binning orders each tile's instances by
-// footprint box shape, so the lanes of a wave walk boxes of (nearly) one
-// shape.  Per pass (up to KT of the chunk's tiles) each lane walks its box,
-// rows outer and columns inner, and adds round(a max(e - e_T, 0) / quantum) to
-// its tile's int32 LDS sum with an integer LDS atomic (float LDS atomics are
-// slow on this GPU, integer ones are not); pixels outside the cut add an
-// integer zero (branch-free).  The quantum is 2^(e - 30) with 2^e above the
-// pass's sum of |a|, so no pixel's sum can overflow and the rounding error per
-// term is below 2^-31 of that sum; integer sums do not depend on the order of
-// the adds.  A tile whose instances all lie in the chunk is finished here; the
-// first and the last tile of a chunk may run on into neighbouring chunks, and
-// their sums go to the chunk's two partial slots, which k_forward_finish adds
-// in chunk order.  The result is deterministic.
+// of the tile-ordered instance list (the chunking of the adjoint): a chunk may
+// span a few tiles.  The binning orders each tile's instances by footprint
+// box shape, so the lanes of a wave walk boxes of (nearly) one shape.  Per
+// pass (up to KT of the chunk's tiles) each lane walks its boxes
+// (forward_walk) into its tile's int32 LDS sums.  The quantum is 2^(e - 30)
+// with 2^e above the pass's sum of |a|, so no pixel's sum can overflow and the
+// rounding error per term is below 2^-31 of that sum; integer sums do not
+// depend on the order of the adds.  A tile whose instances all lie in the
+// chunk is finished here; the first and the last tile of a chunk may run on
+// into neighbouring chunks, and their sums go to the chunk's two partial
+// slots, which k_forward_finish adds in chunk order.  The result is
+// deterministic.
 template <int T, bool kLoss, bool kCount>
 __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float* __restrict__ target,
                                                        const float* __restrict__ mask,
@@ -711,10 +765,10 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
                                                        float* __restrict__ tile_sse,
                                                        unsigned long long* __restrict__ incut,
                                                        float* __restrict__ partial) {
-    constexpr int NT = 256, NW = 4;
-    constexpr int KT = (1024 / (T * T)) > 0 ? 1024 / (T * T) : 1;
+    constexpr int NT = 256, NW = 4, NI = kFwdPer, kChunk = NT * NI;
+    constexpr int KT = (2048 * NI / (T * T)) > 0 ? 2048 * NI / (T * T) : 1;  // 8 NI KB of sums per pass
     __shared__ int s_iacc[KT * T * T];  // fixed-point sums, then (in place) their float values
-    __shared__ int s_wsum[NW];
+    __shared__ int s_wsum[NI][NW];
     __shared__ float s_fsum[NW];
     __shared__ float s_red[NW];
     __shared__ unsigned int s_cnt[NW];
@@ -722,64 +776,71 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     __shared__ int s_ptile[KT];
     __shared__ int s_fin[KT];  // -1: tile finished here, else the partial slot (0 first run, 1 last run)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    const int64_t n_chunks = (a.n_inst + kChunk - 1) / kChunk;
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
     if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
+    const int64_t c0 = chunk * kChunk;
     const float etau = a.etau;
     const float tau2k = SVR_KZ * a.tau2;
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     float* s_facc = reinterpret_cast<float*>(s_iacc);
 
-    // the lane's instance: tile, run head, record and box (independent loads)
-    const int64_t inst = chunk * NT + tid;
-    int tile = -1;
-    bool head = false;
-    int4 org = make_int4(0, 0, 0, 0);
-    if (inst < a.n_inst) {
-        const uint32_t t = a.inst_key[inst] >> kClassBits;
-        if (t < (uint32_t)a.n_tiles) {
-            tile = (int)t;
-            head = tid == 0 || (a.inst_key[inst - 1] >> kClassBits) != t;
-            org = a.tile_org[tile];
+    // the lane's instances: tile, run head, record and box (independent loads)
+    int tile[NI], fin[NI], rslot[NI];
+    bool head[NI];
+    int4 org[NI];
+    uint64_t hm[NI];
+    LaneBox b[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int64_t inst = c0 + k * NT + tid;
+        tile[k] = -1;
+        head[k] = false;
+        org[k] = make_int4(0, 0, 0, 0);
+        if (inst < a.n_inst) {
+            const uint32_t t = a.inst_key[inst] >> kClassBits;
+            if (t < (uint32_t)a.n_tiles) {
+                tile[k] = (int)t;
+                head[k] = inst == c0 || (a.inst_key[inst - 1] >> kClassBits) != t;
+                org[k] = a.tile_org[t];
+            }
         }
     }
-    const uint64_t hm = __ballot(head);
-    if (lane == 0) s_wsum[wv] = __popcll(hm);
-    LaneBox b = {};
-    int fin = -1;
-    if (tile >= 0) {
-        const Record R = a.rec[a.inst_rec[inst]];
-        const TileOrg o = tile_org(org);
-        b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
-        if (head) {
-            const int2 rg = a.ranges[tile];
-            const bool inside = rg.x >= chunk * NT && rg.y <= chunk * NT + NT;
-            fin = inside ? -1 : (tid == 0 ? 0 : 1);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        b[k] = LaneBox{};
+        fin[k] = -1;
+        if (tile[k] >= 0) {
+            const int64_t inst = c0 + k * NT + tid;
+            const Record R = a.rec[a.inst_rec[inst]];
+            const TileOrg o = tile_org(org[k]);
+            b[k] = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+            if (head[k]) {
+                const int2 rg = a.ranges[tile[k]];
+                const bool inside = rg.x >= c0 && rg.y <= c0 + kChunk;
+                fin[k] = inside ? -1 : (inst == c0 ? 0 : 1);
+            }
         }
+        hm[k] = __ballot(head[k]);
     }
-    const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
-    const int hh = w > 0 ? h : 0;
-    const float absa = hh > 0 ? fabsf(b.am) : 0.f;
-    __syncthreads();
-    int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
-    int nd = 0;
-    for (int q = 0; q < NW; ++q) {
-        if (q < wv) rslot += s_wsum[q];
-        nd += s_wsum[q];
-    }
+    const int nd = chunk_runs<NI>(hm, tile, head, s_wsum, rslot);
     unsigned int cnt = 0;
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
         if (p0 > 0) __syncthreads();  // the previous pass is done with LDS
-        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
-        if (act && head) {
-            s_org[rslot - p0] = org;
-            s_ptile[rslot - p0] = tile;
-            s_fin[rslot - p0] = fin;
+        float pa = 0.f;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const bool act = rslot[k] >= p0 && rslot[k] < p0 + np;
+            if (act && head[k]) {
+                s_org[rslot[k] - p0] = org[k];
+                s_ptile[rslot[k] - p0] = tile[k];
+                s_fin[rslot[k] - p0] = fin[k];
+            }
+            if (act && b[k].x1 >= b[k].x0 && b[k].y1 >= b[k].y0) pa += fabsf(b[k].am);
         }
         for (int q = tid; q < np * T * T; q += NT) s_iacc[q] = 0;
         // the pass's sum of |a| (its instances only)
-        float pa = act ? absa : 0.f;
         for (int off = 32; off > 0; off >>= 1) pa += __shfl_xor(pa, off, 64);
         if (lane == 0) s_fsum[wv] = pa;
         __syncthreads();
@@ -789,26 +850,10 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
         const bool bad = !(suma <= 3.4028235e38f);
         const int ex = (suma > 0.f && !bad) ? ilogbf(suma) + 1 : 0;
         const float to_q = ldexpf(1.f, 30 - ex);
-        if (act) {
-            const float amq = b.am * to_q;
-            const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
-            float dy = (float)b.y0 - b.pyl;
-            int gr = (rslot - p0) * T * T + b.y0 * T + b.x0;
-            for (int r = 0; r < hh; ++r) {
-                const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
-                float dx = dx0;
-                int gi = gr;
-                for (int c = 0; c < w; ++c) {
-                    const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy)) - etau;
-                    atomicAdd(&s_iacc[gi], __float2int_rn(amq * fmaxf(v, 0.f)));
-                    if (kCount) cnt += v > 0.f ? 1u : 0u;
-                    dx += 1.f;
-                    ++gi;
-                }
-                dy += 1.f;
-                gr += T;
-            }
-        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k)
+            if (rslot[k] >= p0 && rslot[k] < p0 + np)
+                cnt += forward_walk<T, kCount>(b[k], b[k].am * to_q, s_iacc + (rslot[k] - p0) * T * T, etau);
         __syncthreads();
         const float from_q = ldexpf(1.f, ex - 30);
         for (int q = tid; q < np * T * T; q += NT) s_facc[q] = bad ? __builtin_nanf("") : (float)s_iacc[q] * from_q;
@@ -848,17 +893,17 @@ __global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const floa
                                                         float* __restrict__ pred, float* __restrict__ grad,
                                                         float* __restrict__ tile_sse,
                                                         const float* __restrict__ partial) {
-    constexpr int NT = 256;
+    constexpr int NT = 256, kChunk = NT * kFwdPer;
     __shared__ float s_acc[T * T];
     __shared__ float s_red[NT / 64];
     const int tile = xcd_tile(blockIdx.x, a.n_tiles);
     if (tile >= a.n_tiles) return;
     const int2 rg = a.ranges[tile];
-    const int64_t c0 = rg.y > rg.x ? rg.x / NT : 0, c1 = rg.y > rg.x ? (rg.y - 1) / NT : -1;
+    const int64_t c0 = rg.y > rg.x ? rg.x / kChunk : 0, c1 = rg.y > rg.x ? (rg.y - 1) / kChunk : -1;
     if (rg.y > rg.x && c0 == c1) return;  // finished by its chunk
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     // every thread's pixels, summed over the chunks in chunk order; the loads
-    // of eight chunks are issued together (a tile spans tens of chunks)
+    // of eight chunks are issued together
     constexpr int PPT = (T * T + NT - 1) / NT;
     constexpr int U = 8;
     float acc[PPT];
@@ -868,7 +913,7 @@ __global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const floa
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t c = cb + u;
-            const int ps = (c == c0 && rg.x != c0 * NT) ? 1 : 0;
+            const int ps = (c == c0 && rg.x != c0 * kChunk) ? 1 : 0;
             const float* src = partial + ((size_t)c * 2 + ps) * (T * T);
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
@@ -1071,75 +1116,99 @@ __global__ __launch_bounds__(256) void k_backward_tiles(RenderArgs a, const floa
 }
 
 // Adjoint, record per lane, over fixed chunks of the tile-ordered instance
-// list: workgroup b takes instances [256 b, 256 b + 256), which may span a few
-// tiles, and lane i owns instance 256 b + i.  The binning orders each tile's
-// instances by footprint box shape, so the 64 consecutive instances of a wave
-// walk boxes of (nearly) one shape and no lane waits long on another.  The
-// upstream gradients of up to KT of the chunk's tiles are staged in LDS per
-// pass; each lane walks its record's box inside its tile (adjoint_walk) and
-// writes the seven sums' gradient to the instance's emission slot: no
-// cross-lane reduction and no atomics, so the result is deterministic and
-// independent of the chunking.
+// list (256 kBwdPer instances, kBwdPer per lane, which may span a few tiles).
+// The binning orders each tile's instances by footprint box shape, so the 64
+// consecutive instances a wave takes walk boxes of (nearly) one shape.  When
+// the chunk's instances lie in at most KT consecutive tiles (the usual case)
+// their upstream gradients are staged in LDS at once, while the lanes'
+// record loads are in flight; otherwise in passes of up to KT of the chunk's
+// tiles.  Each lane walks its records' boxes (adjoint_walk) and writes each
+// instance's gradient to its emission slot: no cross-lane reduction and no
+// atomics, so the result is deterministic and independent of the chunking.
 template <int T>
 __global__ __launch_bounds__(256) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
                                                  const float* __restrict__ grad_scale,
                                                  float4* __restrict__ inst_grad) {
-    constexpr int NT = 256, NW = 4;
-    constexpr int KT = (2048 / (T * T)) > 0 ? 2048 / (T * T) : 1;  // tiles staged per pass (8 KB)
+    constexpr int NT = 256, NW = 4, NI = kBwdPer, kChunk = NT * NI;
+    constexpr int KT = (2048 * NI / (T * T)) > 0 ? 2048 * NI / (T * T) : 1;  // tiles staged per pass (8 NI KB)
     __shared__ __align__(16) float s_g[KT * T * T];
-    __shared__ int s_wsum[NW];
+    __shared__ int s_wsum[NI][NW];
     __shared__ int4 s_org[KT];  // the pass's tiles (TileOrg packing)
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int64_t n_chunks = (a.n_inst + kChunk - 1) / kChunk;
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
     if (chunk >= n_chunks) return;  // idle workgroup of the XCD remap (uniform)
+    const int64_t c0 = chunk * kChunk;
     const float tau2k = SVR_KZ * a.tau2;
+    const float scale = grad_scale ? grad_scale[0] : 1.f;
+    const uint32_t tf = a.inst_key[c0] >> kClassBits;
+    const uint32_t tl = a.inst_key[min(c0 + kChunk, a.n_inst) - 1] >> kClassBits;
+    const bool fast = tf < (uint32_t)a.n_tiles && tl < (uint32_t)a.n_tiles && tl - tf < (uint32_t)KT;
+    if (fast)
+        for (uint32_t t = tf; t <= tl; ++t)
+            stage_tile<T, NT>(grad_pred, tile_org(a.tile_org[t]), s_g + (t - tf) * T * T);
 
-    // the lane's instance: tile (-1 past the end or for emission padding),
-    // whether it heads a run of its tile in the chunk, its record and box
-    const int64_t inst = chunk * NT + tid;
-    int tile = -1;
-    bool head = false;
-    int4 org = make_int4(0, 0, 0, 0);
-    if (inst < a.n_inst) {
-        const uint32_t t = a.inst_key[inst] >> kClassBits;
-        if (t < (uint32_t)a.n_tiles) {
-            tile = (int)t;
-            head = tid == 0 || (a.inst_key[inst - 1] >> kClassBits) != t;
-            org = a.tile_org[tile];
+    // the lane's instances: tile (-1 past the end or for emission padding),
+    // whether each heads a run of its tile in the chunk, record and box
+    int tile[NI], rslot[NI];
+    bool head[NI];
+    int4 org[NI];
+    uint64_t hm[NI];
+    uint32_t e_slot[NI];
+    LaneBox b[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int64_t inst = c0 + k * NT + tid;
+        tile[k] = -1;
+        head[k] = false;
+        org[k] = make_int4(0, 0, 0, 0);
+        if (inst < a.n_inst) {
+            const uint32_t t = a.inst_key[inst] >> kClassBits;
+            if (t < (uint32_t)a.n_tiles) {
+                tile[k] = (int)t;
+                head[k] = inst == c0 || (a.inst_key[inst - 1] >> kClassBits) != t;
+                org[k] = a.tile_org[t];
+            }
         }
     }
-    const uint64_t hm = __ballot(head);
-    if (lane == 0) s_wsum[wv] = __popcll(hm);
-    LaneBox b = {};
-    uint32_t e_slot = 0;
-    if (tile >= 0) {
-        const Record R = a.rec[a.inst_rec[inst]];
-        e_slot = a.inst_idx[inst];
-        const TileOrg o = tile_org(org);
-        b = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        b[k] = LaneBox{};
+        e_slot[k] = 0;
+        if (tile[k] >= 0) {
+            const int64_t inst = c0 + k * NT + tid;
+            const Record R = a.rec[a.inst_rec[inst]];
+            e_slot[k] = a.inst_idx[inst];
+            const TileOrg o = tile_org(org[k]);
+            b[k] = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+        }
     }
-    __syncthreads();
-    // rslot = index of the lane's run (distinct tile) in the chunk
-    int rslot = __popcll(hm & ((1ull << lane) - 1ull)) + (head ? 1 : 0) - 1;
-    int nd = 0;
-    for (int q = 0; q < NW; ++q) {
-        if (q < wv) rslot += s_wsum[q];
-        nd += s_wsum[q];
+    if (fast) {
+        __syncthreads();  // the staged gradients are visible
+#pragma unroll
+        for (int k = 0; k < NI; ++k)
+            if (tile[k] >= 0)
+                store_adjoint(adjoint_walk<T>(b[k], s_g + (tile[k] - (int)tf) * T * T, a.etau), b[k], scale,
+                              inst_grad, e_slot[k]);
+        return;
     }
-    const float scale = grad_scale ? grad_scale[0] : 1.f;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) hm[k] = __ballot(head[k]);
+    const int nd = chunk_runs<NI>(hm, tile, head, s_wsum, rslot);
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
         if (p0 > 0) __syncthreads();  // the previous pass is done with LDS
-        const bool act = tile >= 0 && rslot >= p0 && rslot < p0 + np;
-        if (act && head) s_org[rslot - p0] = org;
+#pragma unroll
+        for (int k = 0; k < NI; ++k)
+            if (head[k] && rslot[k] >= p0 && rslot[k] < p0 + np) s_org[rslot[k] - p0] = org[k];
         __syncthreads();
         for (int sl = 0; sl < np; ++sl) stage_tile<T, NT>(grad_pred, tile_org(s_org[sl]), s_g + sl * T * T);
         __syncthreads();
-        if (act) {
-            const AdjointSums S = adjoint_walk<T>(b, s_g + (rslot - p0) * T * T, a.etau);
-            store_adjoint(S, b, scale, inst_grad, e_slot);
-        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k)
+            if (rslot[k] >= p0 && rslot[k] < p0 + np)
+                store_adjoint(adjoint_walk<T>(b[k], s_g + (rslot[k] - p0) * T * T, a.etau), b[k], scale, inst_grad,
+                              e_slot[k]);
     }
 }
 
@@ -1205,7 +1274,7 @@ hipError_t launch_tile_ranges(const uint32_t* keys, int64_t n, int2* ranges, int
                               uint32_t* pad_out, hipStream_t st) {
     hipError_t e = launch_fill_zero(ranges, sizeof(int2) * (size_t)n_tiles, st);
     if (e != hipSuccess || n <= 0) return e;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, keys, n, ranges,
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((n + 1023) / 1024)), dim3(256), 0, st, keys, n, ranges,
                        (uint32_t)n_tiles, pad_out);
     return hipGetLastError();
 }
@@ -1265,8 +1334,8 @@ hipError_t fwd_chunk_dispatch(const RenderArgs& a, const float* target, const fl
                               float* partial, hipStream_t st) {
     const bool loss = target != nullptr;
     const bool count = incut != nullptr;
-    constexpr int NT = 256;
-    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    constexpr int NT = 256, kChunk = NT * kFwdPer;
+    const int64_t n_chunks = (a.n_inst + kChunk - 1) / kChunk;
     if (n_chunks > 0x7fffffffLL - 8) return hipErrorInvalidValue;
     if (n_chunks > 0) {
         if (!partial) return hipErrorInvalidValue;
@@ -1296,7 +1365,7 @@ hipError_t fwd_chunk_dispatch(const RenderArgs& a, const float* target, const fl
 
 size_t forward_partial_floats(const RenderArgs& a) {
     if (a.forward_mode != 1 || a.persistent || a.n_inst <= 0) return 0;
-    const int64_t n_chunks = (a.n_inst + 255) / 256;
+    const int64_t n_chunks = (a.n_inst + 256 * kFwdPer - 1) / (256 * kFwdPer);
     return (size_t)n_chunks * 2 * (size_t)a.tile * (size_t)a.tile;
 }
 
@@ -1421,8 +1490,8 @@ hipError_t launch_backward(const RenderArgs& a, const float* grad_pred, const fl
         }
         return hipGetLastError();
     }
-    // fixed chunks of 256 instances of the tile-ordered list
-    const int64_t n_chunks = (a.n_inst + NT - 1) / NT;
+    // fixed chunks of 256 kBwdPer instances of the tile-ordered list
+    const int64_t n_chunks = (a.n_inst + NT * kBwdPer - 1) / (NT * kBwdPer);
     if (n_chunks > 0x7fffffffLL - 8) return hipErrorInvalidValue;
     const int grid = (int)(((n_chunks + 7) >> 3) << 3);  // whole XCD remap
     switch (a.tile) {
