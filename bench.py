@@ -267,6 +267,9 @@ def build_parser():
                          "topk: the paper's normalised Top-K model (Eqs. 2 and 5)")
     ap.add_argument("--topk-k", type=int, default=50, help="neighbours per pixel (the paper's K)")
     ap.add_argument("--topk-refresh", type=int, default=50, help="iterations between neighbour searches")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-pose leg (train the pose network, then batched fits of 16 cube "
+                         "subjects from identity and from accepted proposals)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB device to device three times (calibrates the HBM traffic counters)")
     return ap
@@ -418,6 +421,16 @@ def main():
         sequential["batched_speedup"] = sequential["ms_per_round"] / ms_per_step
         log(f"sequential: {sequential}")
 
+    cfg = ctx.svr_get_config()
+    learned = None
+    if not args.no_learned and args.workload == "head":
+        ctx.close()
+        ctx = None
+        from paper_2512_11624_amd import pose
+        learned = pose.run_learned_vs_plain(log=log)
+        log(f"learned vs plain: median {learned['median_t_learned']:.4f} s vs {learned['median_t_plain']:.4f} s, "
+            f"learned faster on {learned['learned_faster']} of {learned['subjects']}")
+
     cpu = None
     if not args.no_cpu_baseline and args.workload != "batched":
         try:
@@ -440,9 +453,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "gaussians": N, "slices": M, "pixels": P,
-                   "tile": ctx.svr_get_config()["tile"], "batch": ctx.svr_get_config()["batch"],
-                   "persistent": ctx.svr_get_config()["persistent"], "cutoff_sigma": 3.0,
-                   "forward_mode": ctx.svr_get_config()["forward_mode"],
+                   "tile": cfg["tile"], "batch": cfg["batch"],
+                   "persistent": cfg["persistent"], "cutoff_sigma": 3.0,
+                   "forward_mode": cfg["forward_mode"],
                    "step": "project_bin+forward(masked MSE)+backward+AdamW", "autotuned": tuned is not None,
                    "observations": OBSERVATIONS[args.workload],
                    "pair_count": "in-cut pairs of every timed step, counted by replaying the timed steps "
@@ -457,8 +470,11 @@ def main():
     }
     if sequential is not None:
         out["sequential_16_runs"] = sequential
+    if learned is not None:
+        out["learned_vs_plain"] = learned
     print(json.dumps(out), flush=True)
-    ctx.close()
+    if ctx is not None:
+        ctx.close()
 
 
 def run_topk(args, ctx, prob, desc, init, target, mask, target_np):

@@ -1,6 +1,6 @@
 """Learned pose proposal end to end on the GPU: simulated training data from
 the library's own forward, training on the BF16-MFMA network, and the
-acceptance rule (a proposal is kept for a slice only where it lowers that
+acceptance rule (a candidate pose is kept for a slice only where it lowers that
 slice's forward-model error)."""
 import numpy as np
 import pytest
@@ -58,20 +58,22 @@ def test_training_learns_and_acceptance_never_worsens():
     prop = pose.propose(net, obs, torch.as_tensor(pose.placement(geo)).cuda())
     assert torch.isfinite(prop).all()
     zero = params.views()[4].clone()
-    chosen, keep = pose.accept(ctx, params.views()[:4], zero, prop, target, mask)
-    # per-slice errors of the three pose sets, recomputed
+    chosen, choice = pose.accept(ctx, params.views()[:4], zero, prop, target, mask)
+    tonly = torch.cat([zero[:, :3], prop[:, 3:]], 1).contiguous()
+    # per-slice errors of the candidate pose sets and of the chosen one, recomputed
     pred = torch.empty(geo.n_pixels, device="cuda")
     loss = torch.empty(1, device="cuda")
     sse = {}
-    for name, p in (("zero", zero), ("prop", prop), ("chosen", chosen)):
+    for name, p in (("zero", zero), ("prop", prop), ("tonly", tonly), ("chosen", chosen)):
         s = torch.empty(geo.n_slices, device="cuda")
         ctx.svr_project_bin(*params.views()[:4], p)
         ctx.svr_forward(pred, target, mask, loss=loss, slice_sse=s)
         sse[name] = s.cpu().numpy()
-    k = keep.cpu().numpy()
-    assert np.array_equal(sse["chosen"][k], sse["prop"][k])
-    assert np.array_equal(sse["chosen"][~k], sse["zero"][~k])
+    c = choice.cpu().numpy()
+    cand = np.stack([sse["zero"], sse["prop"], sse["tonly"]])
+    assert np.array_equal(sse["chosen"], cand[c, np.arange(geo.n_slices)])
+    assert np.array_equal(sse["chosen"], cand.min(0))  # the lowest error wins; the current pose on ties
     assert np.all(sse["chosen"] <= sse["zero"])
-    print("accepted", int(k.sum()), "of", geo.n_slices)
+    print("kept: proposal", int((c == 1).sum()), "translation only", int((c == 2).sum()), "of", geo.n_slices)
     ctx.close()
     net.close()
