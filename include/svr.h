@@ -340,6 +340,41 @@ int svr_slice_loss(svr_ctx* ctx, const float* pred, const float* target, const f
                    const float* log_omega, float* loss, float* grad_pred, float* slice_sums, float* g_sigma,
                    float* g_log_omega);
 
+/* Multiplicative low-frequency bias field per subject, a reading of the
+ * paper's bias-field Gaussians (Sec. 4, "Bias Correction & Robustness"; the
+ * paper gives no form): subject s has K fixed broad basis Gaussians with
+ * centres m_{s,k} and one width w, and coefficients beta_{s,k};
+ *   b(x) = exp(sum_k beta_{s,k} exp(-|x - m_{s,k}|^2 / (2 w^2)))
+ * at every pixel's world position x_p = R_i u_p + t_i under the poses of the
+ * last svr_project_bin (the field moves with the subject; the context keeps
+ * its own copy of the slice frames, so the caller's pose array may change
+ * after that call).  beta = 0 gives
+ * b = 1.
+ *
+ * svr_bias_apply: pred [P] <- b(x_p) pred[p] in place (call it after
+ * svr_forward without target and before the loss, e.g. svr_slice_loss);
+ * bias [P] (may be NULL) receives b.  centres [S*K*3], beta [S*K], pred and
+ * bias are DEVICE pointers; 1 <= K <= SVR_BIAS_MAX_K, width > 0.
+ * Asynchronous.  Errors: SVR_ERR_STATE before svr_project_bin, SVR_ERR_ARG
+ * for NULL centres / beta / pred or K / width out of range. */
+#define SVR_BIAS_MAX_K 64
+int svr_bias_apply(svr_ctx* ctx, const float* centres, float width, const float* beta, int32_t K, float* pred,
+                   float* bias);
+
+/* Adjoint of svr_bias_apply for the loss L(y'), y' = b y: grad_pred [P]
+ * holds dL/dy' on entry and dL/dy = b dL/dy' on return (pass it on to
+ * svr_backward); g_beta [S*K] receives dL/dbeta = sum_p dL/dy'_p y'_p phi_k;
+ * g_pose [M*6] (may be NULL) has the field's pose terms ADDED to it (through
+ * x_p: dL/dtau = sum dL/dx_p, dL/domega = J_l(omega)^T sum (R_i u_p) x
+ * dL/dx_p, the convention of svr_backward's pose gradient), so call it
+ * after svr_backward when both are wanted.  pred_biased [P] = y' and bias
+ * [P] = b from svr_bias_apply with the same arguments.  All DEVICE pointers.
+ * Sums have a fixed order (deterministic).  Asynchronous.  Errors as
+ * svr_bias_apply, plus SVR_ERR_ARG for NULL pred_biased / bias / grad_pred /
+ * g_beta. */
+int svr_bias_backward(svr_ctx* ctx, const float* centres, float width, const float* beta, int32_t K,
+                      const float* pred_biased, const float* bias, float* grad_pred, float* g_beta, float* g_pose);
+
 /* AdamW (App. A.1).  lr[6] = learning rates of the groups mean, log_scale,
  * quat, amp, pose rotation omega, pose translation tau.  Updates params,
  * exp_avg and exp_avg_sq in place; step counts from 1 (bias correction).

@@ -89,6 +89,7 @@ struct svr_ctx {
     DevBuf<int> d_work, d_fallback;
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
+    DevBuf<float> d_bias_scratch; // bias-field adjoint partials
     DevBuf<float> d_fwd_part;     // chunked record-per-lane forward: two tile partials per instance chunk
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     // content-adaptive initialisation (allocated on first use)
@@ -682,7 +683,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_fallback);
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
-        release(c->d_regpart); release(c->d_smask); release(c->d_fwd_part);
+        release(c->d_regpart); release(c->d_bias_scratch); release(c->d_smask); release(c->d_fwd_part);
         release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
         release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
         release(c->d_init_gmax);
@@ -1315,6 +1316,38 @@ int svr_slice_loss(svr_ctx* c, const float* pred, const float* target, const flo
     HIPCHK(c, launch_slice_loss(c->d_geo.p, c->d_subj.p, c->n_subjects, c->M, mhw, pred, target, mask, sigma,
                                 log_omega, c->d_sl_msum.p, c->loss_kind, loss, grad_pred, slice_sums, g_sigma,
                                 g_log_omega, c->d_sl_scratch.p, st));
+    return SVR_OK;
+}
+
+int svr_bias_apply(svr_ctx* c, const float* centres, float width, const float* beta, int32_t K, float* pred,
+                   float* bias) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!c->binned) return fail(c, SVR_ERR_STATE, "svr_project_bin has not been called");
+    if (!centres || !beta || !pred) return fail(c, SVR_ERR_ARG, "centres, beta or pred is NULL");
+    if (K < 1 || K > SVR_BIAS_MAX_K) return fail(c, SVR_ERR_ARG, "K = %d outside [1, %d]", K, SVR_BIAS_MAX_K);
+    if (!(width > 0.f) || !(width < 3.0e38f)) return fail(c, SVR_ERR_ARG, "width must be positive and finite");
+    HIPCHK(c, launch_bias_apply(c->d_geo.p, c->d_pose.p, c->M, max_slice_pixels(c), centres, width, beta, K, pred,
+                                bias, c->stream));
+    return SVR_OK;
+}
+
+int svr_bias_backward(svr_ctx* c, const float* centres, float width, const float* beta, int32_t K,
+                      const float* pred_biased, const float* bias, float* grad_pred, float* g_beta, float* g_pose) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!c->binned) return fail(c, SVR_ERR_STATE, "svr_project_bin has not been called");
+    if (!centres || !beta || !pred_biased || !bias || !grad_pred || !g_beta)
+        return fail(c, SVR_ERR_ARG, "NULL argument");
+    if (K < 1 || K > SVR_BIAS_MAX_K) return fail(c, SVR_ERR_ARG, "K = %d outside [1, %d]", K, SVR_BIAS_MAX_K);
+    if (!(width > 0.f) || !(width < 3.0e38f)) return fail(c, SVR_ERR_ARG, "width must be positive and finite");
+    const int mhw = max_slice_pixels(c);
+    HIPCHK(c, ensure(c->d_bias_scratch, bias_scratch_floats(std::max(c->M, 1), mhw, K)));
+    HIPCHK(c, launch_bias_backward(c->d_geo.p, c->d_pose.p, c->d_subj.p, c->n_subjects, c->M, mhw, centres, width,
+                                   beta, K, pred_biased, bias, grad_pred, g_beta, g_pose,
+                                   c->d_bias_scratch.p, c->stream));
     return SVR_OK;
 }
 

@@ -213,7 +213,10 @@ __global__ void k_slice_pose(const SliceGeo* __restrict__ geo, const float* __re
         for (int b = 0; b < 3; ++b)
             sp.R[3 * a + b] = E[3 * a] * g.R0[b] + E[3 * a + 1] * g.R0[3 + b] + E[3 * a + 2] * g.R0[6 + b];
     for (int k = 0; k < 3; ++k) sp.t[k] = g.t0[k] + pose[6 * i + 3 + k];
-    sp.pad[0] = sp.pad[1] = sp.pad[2] = sp.pad[3] = 0.f;
+    sp.w[0] = wx;
+    sp.w[1] = wy;
+    sp.w[2] = wz;
+    sp.pad = 0.f;
     out[i] = sp;
 }
 

@@ -31,7 +31,8 @@ struct SliceGeo {
 struct SlicePose {
     float R[9];
     float t[3];
-    float pad[4];
+    float w[3];  // the rotation vector omega the frame was built from
+    float pad;
 };
 
 struct SubjectInfo {
@@ -261,6 +262,19 @@ hipError_t launch_slice_loss(const SliceGeo* geo, const SubjectInfo* subj, int32
                              const float* pred, const float* target, const float* mask, const float* sigma,
                              const float* log_omega, const float* msum, int32_t kind, float* loss, float* grad,
                              float* slice_sums, float* g_sigma, float* g_rho, float* scratch, hipStream_t st);
+
+// Multiplicative bias field per subject (csrc/bias.hip): K <= kBiasMaxK basis
+// Gaussians per subject, centres [S, K, 3], coefficients [S, K].
+constexpr int kBiasMaxK = 64;
+size_t bias_scratch_floats(int32_t m, int32_t max_hw, int32_t K);
+hipError_t launch_bias_apply(const SliceGeo* geo, const SlicePose* pose, int32_t m, int32_t max_hw,
+                             const float* centres, float width, const float* beta, int32_t K, float* pred,
+                             float* bias, hipStream_t st);
+// grad: dL/dy' in, dL/dy out; g_beta [S, K] overwritten; g_pose [M, 6] added to
+hipError_t launch_bias_backward(const SliceGeo* geo, const SlicePose* pose, const SubjectInfo* subj, int32_t s_n,
+                                int32_t m, int32_t max_hw, const float* centres, float width, const float* beta,
+                                int32_t K, const float* pred_biased, const float* bias, float* grad,
+                                float* g_beta, float* g_pose, float* scratch, hipStream_t st);
 
 // Normalised Top-K model (csrc/topk.hip).
 // gauss[s] is Gaussian perm[s] (cell order of the neighbour grid; NULL =

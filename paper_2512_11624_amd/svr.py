@@ -119,6 +119,8 @@ _SIGS = {
     "svr_init_means": ([vp, vp, vp, vp, C.c_float, vp, vp, vp, vp], C.c_int),
     "svr_slice_loss": ([vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], C.c_int),
     "svr_adam_vector": ([vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.POINTER(svr_adam), C.c_int64], C.c_int),
+    "svr_bias_apply": ([vp, vp, C.c_float, vp, C.c_int32, vp, vp], C.c_int),
+    "svr_bias_backward": ([vp, vp, C.c_float, vp, C.c_int32, vp, vp, vp, vp, vp], C.c_int),
     "svr_topk_build": ([vp, vp, vp, vp, C.c_int, vp], C.c_int),
     "svr_topk_forward": ([vp, C.POINTER(svr_params), vp, vp, C.c_int, C.c_float, vp, vp, vp, vp, vp], C.c_int),
     "svr_topk_backward": ([vp, C.POINTER(svr_params), vp, C.c_int, vp, C.POINTER(svr_grads), vp], C.c_int),
@@ -285,6 +287,15 @@ class Context:
         self._check(load().svr_slice_loss(self.h, _ptr(pred), _ptr(target), _ptr(mask), _ptr(sigma), _ptr(log_omega),
                                           _ptr(loss), _ptr(grad_pred), _ptr(slice_sums), _ptr(g_sigma),
                                           _ptr(g_log_omega)), "svr_slice_loss")
+
+    def svr_bias_apply(self, centres, width, beta, K, pred, bias=None):
+        self._check(load().svr_bias_apply(self.h, _ptr(centres), float(width), _ptr(beta), int(K), _ptr(pred),
+                                          _ptr(bias)), "svr_bias_apply")
+
+    def svr_bias_backward(self, centres, width, beta, K, pred_biased, bias, grad_pred, g_beta, g_pose=None):
+        self._check(load().svr_bias_backward(self.h, _ptr(centres), float(width), _ptr(beta), int(K),
+                                             _ptr(pred_biased), _ptr(bias), _ptr(grad_pred), _ptr(g_beta),
+                                             _ptr(g_pose)), "svr_bias_backward")
 
     def svr_adam_vector(self, p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         hp = svr_adam((C.c_float * 6)(*[lr] * 6), beta1, beta2, eps, weight_decay)
