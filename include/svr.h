@@ -375,6 +375,56 @@ int svr_bias_apply(svr_ctx* ctx, const float* centres, float width, const float*
 int svr_bias_backward(svr_ctx* ctx, const float* centres, float width, const float* beta, int32_t K,
                       const float* pred_biased, const float* bias, float* grad_pred, float* g_beta, float* g_pose);
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive densification, a reading of the paper's coarse-to-fine future
+ * work (Sec. 4, "Coarse-to-Fine Optimization": progressive densification
+ * after 3D Gaussian Splatting, starting from few large primitives); the
+ * paper gives no rule, so the clone/split scheme of 3DGS is taken with its
+ * statistic in this model's world frame.
+ *
+ * svr_densify_accumulate: after svr_backward, A_j += ||dL/dmu_j|| and
+ * n_j += 1 where dL/dmu_j is not zero.  g_mean [N*3], grad_acc [N] (float),
+ * count [N] (int32), all DEVICE; the caller zeroes A and n when it starts a
+ * new statistic.  Asynchronous.  Errors: SVR_ERR_STATE without geometry,
+ * SVR_ERR_ARG for NULL arrays. */
+int svr_densify_accumulate(svr_ctx* ctx, const float* g_mean, float* grad_acc, int32_t* count);
+
+typedef struct {
+    float grad_threshold;       /* densify j when n_j > 0 and A_j > fl(grad_threshold * n_j) (FP32), >= 0 */
+    float log_scale_threshold;  /* a densified j splits when max_k log s_jk > this, else it is cloned */
+    float split_offset;         /* a in (0, 1): split children at mu -+ a s_a e, s_a *= sqrt(1 - a^2),
+                                   c *= 1 / (2 sqrt(1 - a^2)); sqrt(3)/2 halves s_a and keeps c */
+    float clone_offset;         /* b >= 0: clone children at mu -+ b s_a e, same shape, c / 2 */
+    float prune_amp;            /* drop j when |c_j| < prune_amp (0: never); pruning wins over densifying */
+} svr_densify_cfg;
+
+/* svr_densify: the densified mixture of the current one.  e is the principal
+ * axis of Sigma_j (the column of R(q_j) of the largest scale s_a, the first
+ * on ties); a split keeps the parent's integral and first two moments, a
+ * clone its integral and mean.  in: the current mean [N*3], log_scale
+ * [N*3], quat [N*4], amp [N] (in->pose unused); grad_acc, count: the
+ * statistic above.  out: mean, log_scale, quat, amp arrays with room for
+ * `capacity` Gaussians (out->pose unused).  Outputs stay grouped by subject
+ * and in parent order; a densified parent is replaced by its two children
+ * ("-" first).  src [capacity] (may be NULL) receives j for a kept Gaussian
+ * and -(j + 1) for a child of j.  exp_avg_in / exp_avg_sq_in [11 N + 6 M]
+ * and exp_avg_out / exp_avg_sq_out [11 K + 6 M] (the svr_step layout; all
+ * four or none; not in place): the moments of kept Gaussians are carried
+ * over, children start from zero, the pose part is copied.  new_offsets
+ * (HOST, [S + 1]) always receives the new per-subject Gaussian offsets; K =
+ * new_offsets[S].  All other pointers are DEVICE.  Synchronous (the new
+ * offsets are read back).  On success the context takes the new offsets
+ * (as svr_set_geometry would with the same slices): the next
+ * svr_project_bin expects the new arrays, and the binning and Top-K state
+ * are invalidated.  Errors: SVR_ERR_CAPACITY when K > capacity (only
+ * new_offsets is written, the context is unchanged) or 2 N > 2^31 - 1;
+ * SVR_ERR_ARG for NULL arrays or out-of-range parameters; SVR_ERR_STATE
+ * without geometry. */
+int svr_densify(svr_ctx* ctx, const svr_params* in, const float* grad_acc, const int32_t* count,
+                const svr_densify_cfg* cfg, const svr_grads* out, int64_t capacity, int32_t* src,
+                const float* exp_avg_in, const float* exp_avg_sq_in, float* exp_avg_out, float* exp_avg_sq_out,
+                int64_t* new_offsets);
+
 /* AdamW (App. A.1).  lr[6] = learning rates of the groups mean, log_scale,
  * quat, amp, pose rotation omega, pose translation tau.  Updates params,
  * exp_avg and exp_avg_sq in place; step counts from 1 (bias correction).

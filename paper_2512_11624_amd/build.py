@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsvr.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "project.hip", "scan.hip", "sort.hip", "render.hip", "adam.hip", "cnn.hip", "init.hip",
-           "topk.hip", "outlier.hip", "status.hip", "bias.hip"]
+           "topk.hip", "outlier.hip", "status.hip", "bias.hip", "densify.hip"]
 ARCH = "gfx950"
 
 

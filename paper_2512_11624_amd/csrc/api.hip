@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <map>
 #include <mutex>
@@ -90,6 +91,9 @@ struct svr_ctx {
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
     DevBuf<float> d_bias_scratch; // bias-field adjoint partials
+    DevBuf<int32_t> d_dens_n, d_dens_pos;   // densification: outputs per Gaussian and their scan
+    DevBuf<int64_t> d_dens_off;             // densification: new per-subject offsets
+    DevBuf<long long> d_dens_tot;
     DevBuf<float> d_fwd_part;     // chunked record-per-lane forward: two tile partials per instance chunk
     DevBuf<uint32_t> d_smask;  // plane-test survivor bits per Gaussian
     // content-adaptive initialisation (allocated on first use)
@@ -683,6 +687,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_fallback);
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
+        release(c->d_dens_n); release(c->d_dens_pos); release(c->d_dens_off); release(c->d_dens_tot);
         release(c->d_regpart); release(c->d_bias_scratch); release(c->d_smask); release(c->d_fwd_part);
         release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
         release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
@@ -1349,6 +1354,87 @@ int svr_bias_backward(svr_ctx* c, const float* centres, float width, const float
                                    beta, K, pred_biased, bias, grad_pred, g_beta, g_pose,
                                    c->d_bias_scratch.p, c->stream));
     return SVR_OK;
+}
+
+int svr_densify_accumulate(svr_ctx* c, const float* g_mean, float* grad_acc, int32_t* count) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (c->N == 0) return SVR_OK;
+    if (!g_mean || !grad_acc || !count) return fail(c, SVR_ERR_ARG, "g_mean, grad_acc or count is NULL");
+    HIPCHK(c, launch_densify_accumulate(g_mean, grad_acc, count, c->N, c->stream));
+    return SVR_OK;
+}
+
+int svr_densify(svr_ctx* c, const svr_params* in, const float* grad_acc, const int32_t* count,
+                const svr_densify_cfg* cfg, const svr_grads* out, int64_t capacity, int32_t* src,
+                const float* exp_avg_in, const float* exp_avg_sq_in, float* exp_avg_out, float* exp_avg_sq_out,
+                int64_t* new_offsets) {
+    int rc = enter(c);
+    if (rc != SVR_OK) return rc;
+    if (!c->has_geom) return fail(c, SVR_ERR_STATE, "no geometry set");
+    if (!in || !cfg || !out || !new_offsets) return fail(c, SVR_ERR_ARG, "in, cfg, out or new_offsets is NULL");
+    const int64_t N = c->N;
+    if (N > 0 && (!in->mean || !in->log_scale || !in->quat || !in->amp || !grad_acc || !count))
+        return fail(c, SVR_ERR_ARG, "an input array is NULL");
+    if (!(cfg->split_offset > 0.f && cfg->split_offset < 1.f))
+        return fail(c, SVR_ERR_ARG, "split_offset must lie in (0, 1)");
+    if (!(cfg->clone_offset >= 0.f) || !isfinite(cfg->clone_offset))
+        return fail(c, SVR_ERR_ARG, "clone_offset must be >= 0 and finite");
+    if (!(cfg->grad_threshold >= 0.f) || isnan(cfg->log_scale_threshold) || isnan(cfg->prune_amp))
+        return fail(c, SVR_ERR_ARG, "grad_threshold must be >= 0; thresholds must not be NaN");
+    const bool moments = exp_avg_in || exp_avg_sq_in || exp_avg_out || exp_avg_sq_out;
+    if (moments && !(exp_avg_in && exp_avg_sq_in && exp_avg_out && exp_avg_sq_out))
+        return fail(c, SVR_ERR_ARG, "the four moment arrays are given together or not at all");
+    if (moments && (exp_avg_out == exp_avg_in || exp_avg_sq_out == exp_avg_sq_in))
+        return fail(c, SVR_ERR_ARG, "moments cannot be remapped in place");
+    if (2 * N > 0x7fffffffLL) return fail(c, SVR_ERR_CAPACITY, "2 N exceeds 2^31-1");
+    hipStream_t st = c->stream;
+    const int S = c->n_subjects;
+    HIPCHK(c, ensure(c->d_dens_n, (size_t)N));
+    HIPCHK(c, ensure(c->d_dens_pos, (size_t)N));
+    HIPCHK(c, ensure(c->d_dens_off, (size_t)S + 1));
+    HIPCHK(c, ensure(c->d_dens_tot, 2));
+    HIPCHK(c, ensure(c->d_scan_tmp, scan_tmp_bytes(N) + 64));
+    HIPCHK(c, launch_densify_plan(grad_acc, count, in->amp, N, cfg->grad_threshold, cfg->prune_amp, c->d_subj.p, S,
+                                  c->d_dens_n.p, c->d_dens_pos.p, c->d_dens_tot.p, c->d_scan_tmp.p, c->d_dens_off.p,
+                                  st));
+    std::vector<int64_t> off((size_t)S + 1);
+    HIPCHK(c, hipMemcpyAsync(off.data(), c->d_dens_off.p, sizeof(int64_t) * (S + 1), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int s = 0; s <= S; ++s) new_offsets[s] = off[s];
+    const int64_t K = off[S];
+    if (K > capacity)
+        return fail(c, SVR_ERR_CAPACITY, "densified mixture has %lld Gaussians, capacity %lld", (long long)K,
+                    (long long)capacity);
+    if (K > 0 && (!out->mean || !out->log_scale || !out->quat || !out->amp))
+        return fail(c, SVR_ERR_ARG, "an output array is NULL");
+    const double a = cfg->split_offset;
+    DensifyArgs d;
+    d.mean = in->mean; d.log_scale = in->log_scale; d.quat = in->quat; d.amp = in->amp;
+    d.n_out = c->d_dens_n.p; d.pos = c->d_dens_pos.p;
+    d.n = N; d.n_new = K;
+    d.o_mean = out->mean; d.o_log_scale = out->log_scale; d.o_quat = out->quat; d.o_amp = out->amp;
+    d.src = src;
+    d.m1_in = exp_avg_in; d.m2_in = exp_avg_sq_in; d.m1_out = exp_avg_out; d.m2_out = exp_avg_sq_out;
+    d.log_scale_thr = cfg->log_scale_threshold;
+    d.split_offset = cfg->split_offset;
+    d.clone_offset = cfg->clone_offset;
+    d.split_dlog = (float)(0.5 * std::log1p(-a * a));
+    d.split_amp = (float)(0.5 / std::sqrt(1.0 - a * a));
+    HIPCHK(c, launch_densify_emit(d, st));
+    if (moments && c->M > 0) {
+        HIPCHK(c, hipMemcpyAsync(exp_avg_out + 11 * K, exp_avg_in + 11 * N, sizeof(float) * 6 * (size_t)c->M,
+                                 hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(exp_avg_sq_out + 11 * K, exp_avg_sq_in + 11 * N, sizeof(float) * 6 * (size_t)c->M,
+                                 hipMemcpyDeviceToDevice, st));
+    }
+    // the context now describes the densified mixture
+    c->gauss_off.assign(off.begin(), off.end());
+    c->N = K;
+    c->topk_built = false;
+    c->topk_forwarded = false;
+    return build_tables(c);
 }
 
 int svr_adam_vector(svr_ctx* c, float* p, const float* g, float* exp_avg, float* exp_avg_sq, int64_t n, float lr,

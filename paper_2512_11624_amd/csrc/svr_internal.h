@@ -276,6 +276,26 @@ hipError_t launch_bias_backward(const SliceGeo* geo, const SlicePose* pose, cons
                                 int32_t K, const float* pred_biased, const float* bias, float* grad,
                                 float* g_beta, float* g_pose, float* scratch, hipStream_t st);
 
+// Adaptive densification (csrc/densify.hip).
+struct DensifyArgs {
+    const float *mean, *log_scale, *quat, *amp;      // [n] parents
+    const int32_t *n_out, *pos;                       // outputs per parent and their exclusive scan
+    int64_t n, n_new;
+    float *o_mean, *o_log_scale, *o_quat, *o_amp;    // [n_new]
+    int32_t* src;                                     // [n_new]: j (kept) or -(j + 1) (child of j); may be NULL
+    const float *m1_in, *m2_in;                       // Adam moments [11 n (+ pose)] or NULL
+    float *m1_out, *m2_out;                           // [11 n_new (+ pose)]
+    float log_scale_thr, split_offset, clone_offset;
+    float split_dlog, split_amp;                      // 1/2 log(1 - a^2), 1 / (2 sqrt(1 - a^2))
+};
+hipError_t launch_densify_accumulate(const float* g_mean, float* acc, int32_t* cnt, int64_t n, hipStream_t st);
+// n_out [n], pos [n] (exclusive scan), total (2 long long), new_off [S + 1];
+// scan_tmp: scan_tmp_bytes(n)
+hipError_t launch_densify_plan(const float* acc, const int32_t* cnt, const float* amp, int64_t n, float grad_thr,
+                               float prune_amp, const SubjectInfo* subj, int32_t S, int32_t* n_out, int32_t* pos,
+                               long long* total, void* scan_tmp, int64_t* new_off, hipStream_t st);
+hipError_t launch_densify_emit(const DensifyArgs& a, hipStream_t st);
+
 // Normalised Top-K model (csrc/topk.hip).
 // gauss[s] is Gaussian perm[s] (cell order of the neighbour grid; NULL =
 // identity).

@@ -58,6 +58,11 @@ class svr_adam(C.Structure):
                 ("eps", C.c_double), ("weight_decay", C.c_double)]
 
 
+class svr_densify_cfg(C.Structure):
+    _fields_ = [("grad_threshold", C.c_float), ("log_scale_threshold", C.c_float), ("split_offset", C.c_float),
+                ("clone_offset", C.c_float), ("prune_amp", C.c_float)]
+
+
 class svr_timer(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("calls", C.c_int64), ("total_ms", C.c_double)]
 
@@ -121,6 +126,9 @@ _SIGS = {
     "svr_adam_vector": ([vp, vp, vp, vp, vp, C.c_int64, C.c_float, C.POINTER(svr_adam), C.c_int64], C.c_int),
     "svr_bias_apply": ([vp, vp, C.c_float, vp, C.c_int32, vp, vp], C.c_int),
     "svr_bias_backward": ([vp, vp, C.c_float, vp, C.c_int32, vp, vp, vp, vp, vp], C.c_int),
+    "svr_densify_accumulate": ([vp, vp, vp, vp], C.c_int),
+    "svr_densify": ([vp, C.POINTER(svr_params), vp, vp, C.POINTER(svr_densify_cfg), C.POINTER(svr_grads), C.c_int64,
+                     vp, vp, vp, vp, vp, vp], C.c_int),
     "svr_topk_build": ([vp, vp, vp, vp, C.c_int, vp], C.c_int),
     "svr_topk_forward": ([vp, C.POINTER(svr_params), vp, vp, C.c_int, C.c_float, vp, vp, vp, vp, vp], C.c_int),
     "svr_topk_backward": ([vp, C.POINTER(svr_params), vp, C.c_int, vp, C.POINTER(svr_grads), vp], C.c_int),
@@ -296,6 +304,31 @@ class Context:
         self._check(load().svr_bias_backward(self.h, _ptr(centres), float(width), _ptr(beta), int(K),
                                              _ptr(pred_biased), _ptr(bias), _ptr(grad_pred), _ptr(g_beta),
                                              _ptr(g_pose)), "svr_bias_backward")
+
+    def svr_densify_accumulate(self, g_mean, grad_acc, count):
+        self._check(load().svr_densify_accumulate(self.h, _ptr(g_mean), _ptr(grad_acc), _ptr(count)),
+                    "svr_densify_accumulate")
+
+    def svr_densify(self, params, grad_acc, count, cfg, out, capacity, src=None, moments_in=None, moments_out=None):
+        """params: (mean, log_scale, quat, amp) tensors; cfg: dict of svr_densify_cfg fields; out: four
+        tensors with room for ``capacity`` Gaussians; moments_in / moments_out: (exp_avg, exp_avg_sq)
+        pairs or None.  Returns the new per-subject offsets (int64 [S + 1]); raises SvrError with
+        ``offsets`` set when they need more than ``capacity``."""
+        P = svr_params(*[_ptr(t) for t in params[:4]], None)
+        O = svr_grads(*[_ptr(t) for t in out[:4]], None)
+        c = svr_densify_cfg(**{k: float(v) for k, v in cfg.items()})
+        mi = moments_in or (None, None)
+        mo = moments_out or (None, None)
+        off = np.zeros(self.n_subjects + 1, np.int64)
+        rc = load().svr_densify(self.h, C.byref(P), _ptr(grad_acc), _ptr(count), C.byref(c), C.byref(O),
+                                int(capacity), _ptr(src), _ptr(mi[0]), _ptr(mi[1]), _ptr(mo[0]), _ptr(mo[1]),
+                                off.ctypes.data)
+        if rc != SVR_OK:
+            err = SvrError(rc, f"svr_densify: {load().svr_last_error(self.h).decode()}")
+            err.offsets = off
+            raise err
+        self.n_gauss = int(off[-1])
+        return off
 
     def svr_adam_vector(self, p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         hp = svr_adam((C.c_float * 6)(*[lr] * 6), beta1, beta2, eps, weight_decay)
