@@ -82,10 +82,15 @@ class VolumeProbe:
         self.vol = torch.empty(self.P, dtype=torch.float32, device=dev)
         self.loss = torch.empty(1, dtype=torch.float32, device=dev)
         self.model, self.topk_k, self.topk_delta = model, topk_k, topk_delta
+        self.n = int(n_gauss)
         if model == "topk":
             self.nbr = torch.empty(self.P, topk_k, dtype=torch.int32, device=dev)
 
     def _forward(self, mean, log_scale, quat, amp, with_loss):
+        if mean.shape[0] != self.n:          # the mixture was densified since the last read-out
+            self.n = int(mean.shape[0])
+            self.geom.gauss_offsets = np.array([0, self.n], np.int64)
+            self.ctx.svr_set_geometry(self.geom)
         tgt = (self.gt, self.mask) if with_loss else (None, None)
         if self.model == "topk":
             self.ctx.svr_topk_build(mean, self.pose, self.topk_k, self.nbr, mask=self.mask)
@@ -102,6 +107,22 @@ class VolumeProbe:
 
     def psnr(self, mean, log_scale, quat, amp):
         self._forward(mean, log_scale, quat, amp, True)
+        mse = float(self.loss.item())
+        return 10.0 * math.log10(self.max_gt ** 2 / max(mse, 1e-30))
+
+    def field(self, centres, width, beta, K):
+        """The bias field b at the grid voxels (device tensor, flat); needs a
+        read-out (render / psnr) first for the grid's frames."""
+        import torch
+        b = torch.ones_like(self.vol)
+        self.ctx.svr_bias_apply(centres, width, beta, K, b)
+        return b
+
+    def psnr_biased(self, mean, log_scale, quat, amp, centres, width, beta, K):
+        """PSNR of the volume times the bias field (what the slices see)."""
+        self._forward(mean, log_scale, quat, amp, False)
+        self.ctx.svr_bias_apply(centres, width, beta, K, self.vol)
+        self.ctx.svr_slice_loss(self.vol, self.gt, self.mask, loss=self.loss)
         mse = float(self.loss.item())
         return 10.0 * math.log10(self.max_gt ** 2 / max(mse, 1e-30))
 
@@ -122,7 +143,7 @@ class FitResult:
 def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=25, step_lr=200, gamma=0.5,
         psnr_target=None, callback=None, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
         outliers=False, outlier_lr=1e-3, model="windowed", topk_k=50, topk_refresh=50, topk_delta=1e-6,
-        pose_start=0):
+        pose_start=0, densify=None, bias=None):
     """Runs n_iter fitting iterations of project_bin + forward + backward +
     AdamW on ``params`` (an svr.Params, updated in place).  The wall clock
     covers the iterations only; the PSNR read-out every ``psnr_every``
@@ -141,7 +162,24 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
     rebuilt every ``topk_refresh`` iterations for the masked pixels; the
     rebuilds are timed with the iterations).  The poses stay where they are
     for the first ``pose_start`` iterations (their rates are 0 there; the
-    volume fits the slices first)."""
+    volume fits the slices first).
+
+    ``densify`` (windowed model): dict(at=[iterations], fraction=f or
+    grad_threshold=t, log_scale_threshold, split_offset, clone_offset,
+    prune_amp, max_gauss).  Every step accumulates the mean-gradient
+    statistic (svr_densify_accumulate); after the step of each listed
+    iteration the mixture is densified (svr_densify) with the threshold t,
+    or with the one that selects the fraction f of the Gaussians seen since
+    the last densification with the largest mean gradient norm, unless the
+    mixture already holds max_gauss; the Adam moments follow the new layout
+    and the statistic restarts.  ``params`` then holds the new mixture.
+    The sizes are recorded in ``res.n_gauss`` as (iteration, N).
+
+    ``bias`` (windowed model): dict(centres [S, K, 3], width, beta [S*K]
+    device tensors / floats, lr): the multiplicative bias field
+    b = exp(sum_k beta_k phi_k) on the predicted pixels (svr_bias_apply),
+    its coefficients learnt with AdamW at ``lr`` (updated in place in
+    ``beta``), its pose terms added to the slices' pose gradients."""
     import torch
     if objective not in ("mse", "l1+reg"):
         raise ValueError(f"unknown objective {objective}")
@@ -149,6 +187,8 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
         raise ValueError(f"unknown reg_reading {reg_reading}")
     if model not in ("windowed", "topk"):
         raise ValueError(f"unknown model {model}")
+    if model == "topk" and (densify or bias):
+        raise ValueError("densification and the bias field run with the windowed model")
     ctx.svr_set_loss(svr.SVR_LOSS_L1 if objective == "l1+reg" else svr.SVR_LOSS_MSE)
     N, M = params.N, params.M
     lam = reg_lambda * float(mask.sum().item()) / N if reg_reading == "mean" else reg_lambda
@@ -170,6 +210,22 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
         g_sig = torch.empty(M, device=dev)
         g_rho = torch.empty(M, device=dev)
         st_o = [torch.zeros(M, device=dev) for _ in range(4)]
+    if densify:
+        d_at = set(int(x) for x in densify["at"])
+        acc = torch.zeros(N, device=dev)
+        cnt = torch.zeros(N, dtype=torch.int32, device=dev)
+        res.n_gauss = [(0, N)]
+        d_cfg = dict(log_scale_threshold=float(densify.get("log_scale_threshold", 0.0)),
+                     split_offset=float(densify.get("split_offset", math.sqrt(3.0) / 2.0)),
+                     clone_offset=float(densify.get("clone_offset", 0.5)),
+                     prune_amp=float(densify.get("prune_amp", 0.0)))
+    if bias:
+        bK, bw, bc, beta = int(bias["K"]), float(bias["width"]), bias["centres"], bias["beta"]
+        g_beta = torch.empty_like(beta)
+        st_b = [torch.zeros_like(beta) for _ in range(2)]
+        bvals = torch.empty(P, device=dev)
+        b_pose = torch.zeros(M, 6, device=dev)
+    sep_loss = outliers or bool(bias)
     torch.cuda.synchronize()
     for it in range(1, n_iter + 1):
         t0 = time.perf_counter()
@@ -184,17 +240,27 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
                 ctx.svr_topk_forward(*pv, nbr, topk_k, topk_delta, pred, target, mask, loss=loss, grad_pred=gpred)
         else:
             ctx.svr_project_bin(*pv)
-            if outliers:
+            if sep_loss:
                 ctx.svr_forward(pred)
             else:
                 ctx.svr_forward(pred, target, mask, loss=loss, grad_pred=gpred)
-        if outliers:
-            ctx.svr_slice_loss(pred, target, mask, sig, rho, loss=loss, grad_pred=gpred, g_sigma=g_sig,
-                               g_log_omega=g_rho)
+        if bias:
+            ctx.svr_bias_apply(bc, bw, beta, bK, pred, bvals)
+        if sep_loss:
+            ctx.svr_slice_loss(pred, target, mask, sig if outliers else None, rho if outliers else None, loss=loss,
+                               grad_pred=gpred, g_sigma=g_sig if outliers else None,
+                               g_log_omega=g_rho if outliers else None)
+        if bias:
+            b_pose.zero_()
+            ctx.svr_bias_backward(bc, bw, beta, bK, pred, bvals, gpred, g_beta, b_pose)
         if model == "topk":
             ctx.svr_topk_backward(*pv, nbr, topk_k, gpred, *grad.views())
         else:
             ctx.svr_backward(gpred, *grad.views())
+        if bias:
+            grad.views()[4].add_(b_pose)
+        if densify:
+            ctx.svr_densify_accumulate(grad.views()[0], acc, cnt)
         if objective == "l1+reg":
             ctx.svr_scale_regularizer(params.views()[1], lam, s_target, grad.views()[1], loss)
         rates = [x * scale for x in lr]
@@ -204,6 +270,27 @@ def fit(ctx, params, target, mask, n_iter, lr=PAPER_LR, probe=None, psnr_every=2
         if outliers:
             ctx.svr_adam_vector(sig, g_sig, st_o[0], st_o[1], outlier_lr * scale, it)
             ctx.svr_adam_vector(rho, g_rho, st_o[2], st_o[3], outlier_lr * scale, it)
+        if bias:
+            ctx.svr_adam_vector(beta, g_beta, st_b[0], st_b[1], float(bias["lr"]) * scale, it)
+        if densify and it in d_at and params.N < int(densify.get("max_gauss", 1 << 30)):
+            cfg = dict(d_cfg)
+            if "fraction" in densify:
+                a_h, c_h = acc.cpu().numpy(), cnt.cpu().numpy()
+                seen = c_h > 0
+                mg = a_h[seen] / c_h[seen]
+                k = int(round(float(densify["fraction"]) * len(mg)))
+                k = min(k, int(densify.get("max_gauss", 1 << 30)) - params.N, len(mg))
+                cfg["grad_threshold"] = float(np.sort(mg)[::-1][k - 1] * (1 - 1e-6)) if k > 0 else float("inf")
+            else:
+                cfg["grad_threshold"] = float(densify["grad_threshold"])
+            if np.isfinite(cfg["grad_threshold"]):
+                new, m, v, _ = ctx.densify_params(params, acc, cnt, cfg, m, v)
+                params.N, params.flat = new.N, new.flat
+                N = new.N
+                grad = svr.Params(N, M, device=dev)
+                acc = torch.zeros(N, device=dev)
+                cnt = torch.zeros(N, dtype=torch.int32, device=dev)
+                res.n_gauss.append((it, N))
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
         if probe is not None and (it % psnr_every == 0 or it == n_iter):
@@ -268,6 +355,44 @@ def time_to_target(res: FitResult, target):
     return float("inf")
 
 
+def bias_basis(axes, kb, device=0):
+    """kb^3 basis centres on a grid over the box [-axes, axes] (one subject,
+    [1, kb^3, 3] device tensor) and their common width, the grid step
+    averaged over the axes."""
+    import torch
+    ax = [np.linspace(-a, a, kb) for a in axes]
+    g = np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(1, -1, 3).astype(np.float32)
+    width = float(np.mean([2 * a / max(kb - 1, 1) for a in axes]))
+    return torch.as_tensor(g, device=torch.device("cuda", device)), width
+
+
+class _BiasedProbe:
+    """fit's read-out with the bias field applied (the beta tensor is read at
+    every call, so it follows the fit)."""
+
+    def __init__(self, probe, centres, width, beta, K):
+        self.probe, self.args = probe, (centres, width, beta, K)
+
+    def psnr(self, *params):
+        return self.probe.psnr_biased(*params, *self.args)
+
+
+def field_error(b_fit, b_true, mask, centred=False):
+    """rms and max of |log b_fit - log b_true| over the mask (with the mean
+    difference ``offset`` removed when ``centred``: a global factor trades
+    against the amplitudes and against the window's lost mass), and the
+    fraction of the true field's log-variance that the fitted field
+    explains."""
+    m = np.asarray(mask) > 0
+    d = np.log(np.asarray(b_fit, np.float64)[m]) - np.log(np.asarray(b_true, np.float64)[m])
+    lt = np.log(np.asarray(b_true, np.float64)[m])
+    off = float(d.mean())
+    if centred:
+        d = d - off
+    return dict(rms_log=float(np.sqrt(np.mean(d * d))), max_log=float(np.abs(d).max()), offset=off,
+                true_rms_log=float(np.std(lt)), explained=float(1.0 - np.mean(d * d) / max(np.var(lt), 1e-30)))
+
+
 # ---------------------------------------------------------------------------
 # Fetal-scale convergence run: the head phantom fitted from its slices
 # ---------------------------------------------------------------------------
@@ -286,7 +411,8 @@ def amplitude_lr(lr, kappa):
 def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=None, scale_amp_lr=True,
                      known_poses=False, objective="mse", reg_lambda=2.5e-3, s_target=1.6, reg_reading="sum",
                      init="jitter", psf=True, corrupt=0.0, outliers=False, outlier_lr=1e-3, model="windowed",
-                     pose_lr_scale=1.0, pose_start=0, observations="mixture"):
+                     pose_lr_scale=1.0, pose_start=0, observations="mixture", coarse=1, densify_at=(),
+                     bias_grid=0, bias_lr=1e-2, motion=(4.0, 2.0)):
     """Fits the 500k-Gaussian head for ``n_iter`` iterations from identity
     poses, amplitudes reset to their mean and means jittered by 0.3 mm.
     ``observations="mixture"`` (the head workload's recipe): the slices are
@@ -313,12 +439,24 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     iterations first (see fit).  ``model="topk"`` fits
     and reads out the paper's normalised Top-K model (K = 50, lists rebuilt
     every 50 iterations); its amplitudes are intensities, so they start at
-    the sampled (or generating) intensities and use the paper's rates.  Returns the FitResult, with the
+    the sampled (or generating) intensities and use the paper's rates.
+    ``coarse`` > 1 starts from N / coarse Gaussians with their scales times
+    coarse^(1/3) (the same density normalisation, so the same amplitudes)
+    and densifies after each iteration in ``densify_at`` (svr_densify; each
+    time the fraction of Gaussians with the largest mean gradient that
+    brings the mixture back to N in that many steps; Gaussians larger than
+    1.5 h, h the generating spacing, split, the others clone).
+    ``bias_grid`` = kb > 0 fits the multiplicative bias field on a kb^3 grid
+    of basis Gaussians over the head's box along (rate ``bias_lr``); PSNR is
+    then that of the volume times the field, and ``res.field`` holds the
+    field's error against the phantom's bias inside the head (a global
+    factor removed).  ``motion`` = (sd deg, sd mm) of the acquisition
+    motion (the workload's N(0, 4 deg), N(0, 2 mm) by default).  Returns the FitResult, with the
     PSNR of the generating mixture itself (the representation's ceiling
     against the phantom) in ``gt_psnr``."""
     import torch
     from . import synth
-    prob = synth.config2(seed)
+    prob = synth.config2(seed, sd_deg=float(motion[0]), sd_mm=float(motion[1]))
     axes = prob.extra["axes"]
     if observations not in ("mixture", "phantom"):
         raise ValueError(f"unknown observations {observations}")
@@ -361,10 +499,11 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
     if init not in ("jitter", "adaptive", "uniform"):
         raise ValueError(f"unknown init {init}")
     ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
-    fit_geom = prob
+    import copy
+    n0 = prob.n_gauss // max(int(coarse), 1)
+    fit_geom = copy.copy(prob)
+    fit_geom.gauss_offsets = np.array([0, n0], np.int64)
     if not psf:
-        import copy
-        fit_geom = copy.copy(prob)
         fit_geom.psf_fwhm = np.zeros_like(prob.psf_fwhm)
     ctx.svr_set_geometry(fit_geom)
     dev = torch.device("cuda", device)
@@ -378,11 +517,13 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
         rng = np.random.default_rng(seed + 2)
         mean = prob.mean + rng.normal(0.0, 0.3, prob.mean.shape).astype(np.float32)
         amp = np.full_like(prob.amp, inten.mean() if topk else prob.amp.mean())
-        params = svr.Params.from_arrays(mean, prob.log_scale, prob.quat, amp, pose0)
+        grow = np.float32(math.log(prob.n_gauss / n0) / 3.0)
+        params = svr.Params.from_arrays(mean[:n0], prob.log_scale[:n0] + grow, prob.quat[:n0], amp[:n0], pose0)
     else:
         params, kappa_init = adaptive_init(ctx, torch.as_tensor(target, device=dev),
-                                           torch.as_tensor(prob.mask, device=dev), prob.n_gauss, prob.n_slices,
-                                           0.0 if init == "adaptive" else 1.0, seed + 2, s_target,
+                                           torch.as_tensor(prob.mask, device=dev), n0, prob.n_slices,
+                                           0.0 if init == "adaptive" else 1.0, seed + 2,
+                                           s_target * (prob.n_gauss / n0) ** (1.0 / 3.0),
                                            torch.as_tensor(pose0, device=dev), rescale=not topk)
     if topk:
         kappa = 1.0
@@ -402,11 +543,30 @@ def head_convergence(n_iter=2000, psnr_every=50, seed=0, device=0, tile=16, log=
             f"generating mixture {gt_psnr:.2f} dB")
     if log:
         log(f"learning rates {lr} (amplitude scale kappa = {kappa:.4g})")
+    densify = None
+    if n0 < prob.n_gauss and len(densify_at):
+        g = (prob.n_gauss / n0) ** (1.0 / len(densify_at))
+        densify = dict(at=list(densify_at), fraction=min(g - 1.0, 1.0), max_gauss=prob.n_gauss,
+                       log_scale_threshold=math.log(1.5 * prob.extra["h"]))
+    bias = None
+    fit_probe = probe
+    if bias_grid:
+        bc, bw = bias_basis(axes, int(bias_grid), device)
+        bias = dict(centres=bc, width=bw, K=int(bias_grid) ** 3, lr=bias_lr,
+                    beta=torch.zeros(int(bias_grid) ** 3, device=dev))
+        fit_probe = _BiasedProbe(probe, bc, bw, bias["beta"], bias["K"])
     res = fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
-              lr=lr, probe=probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
+              lr=lr, probe=fit_probe, psnr_every=psnr_every, objective=objective, reg_lambda=reg_lambda,
               s_target=s_target, reg_reading=reg_reading, outliers=outliers, outlier_lr=outlier_lr, model=model,
-              callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}")) if log else None,
-              pose_start=pose_start)
+              callback=(lambda it, t, p, l: log(f"iter {it}: {t:.2f} s, PSNR {p:.2f} dB, loss {l:.5g}"
+                                                f"{'' if not densify else f', N {params.N}'}")) if log else None,
+              pose_start=pose_start, densify=densify, bias=bias)
+    if bias:
+        probe.render(*params.views()[:4])
+        b_fit = probe.field(bias["centres"], bias["width"], bias["beta"], bias["K"]).cpu().numpy()
+        b_true = synth.head_bias(c, prob.extra["bias"], axes)
+        res.field = field_error(b_fit, b_true, vmask, centred=True)
+        res.plain_psnr = probe.psnr(*params.views()[:4])
     true_pose = prob.pose.astype(np.float64)
     est = params.views()[4].cpu().numpy().astype(np.float64)
     po = prob.pix_offset
@@ -499,6 +659,81 @@ def pose_recovery(n_iter=400, observations="mixture", seed=0, device=0, tile=32,
                       seen=int(seen.sum()))
 
 
+def bias_recovery(n_iter=400, observations="mixture", kb=4, lr=1e-2, seed=0, device=0, tile=32, every=25,
+                  log=None, cutoff=None):
+    """The bias field alone on the head workload: the Gaussians are held at
+    the tissue-only mixture (the generating amplitudes divided by the
+    phantom's bias at their means) and the poses at the truth; only the
+    field's kb^3 coefficients are fitted, from 0 (b = 1), by fit's
+    iteration (masked MSE, AdamW at ``lr``, StepLR).  ``observations``:
+    "mixture", the library's forward of the tissue-only mixture at the true
+    poses (6-sigma window) times the phantom's bias at every pixel centre,
+    Rician noise at SNR 20 (the field model can explain that up to its
+    basis), or "phantom", the phantom's own slices (synth.head_observation).
+    The fit's window is ``cutoff`` (default: the generating 6 sigma for
+    mixture observations, so that the model matches them exactly, else the
+    fitted model's 3 sigma).  Returns rows (iteration, seconds, rms
+    |log b - log b_true| with the mean difference removed, its max, the
+    mean difference (a global factor), the fraction of the true log-field
+    variance explained) over the voxels of the 0.5 mm grid inside the head,
+    and the final error dict."""
+    import torch
+    from . import synth
+    prob = synth.config2(seed)
+    axes, bp = prob.extra["axes"], prob.extra["bias"]
+    dev = torch.device("cuda", device)
+    tissue = (prob.amp / synth.head_bias(prob.mean.astype(np.float64), bp, axes)).astype(np.float32)
+    ctx = svr.Context(device)
+    ctx.svr_set_geometry(prob)
+    if observations == "mixture":
+        ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=6.0, forward_mode=1)
+        tp = svr.Params.from_arrays(prob.mean, prob.log_scale, prob.quat, tissue, prob.pose)
+        ctx.svr_project_bin(*tp.views())
+        clean = torch.empty(prob.n_pixels, device=dev)
+        ctx.svr_forward(clean)
+        bpix = np.concatenate([synth.head_bias(x, bp, axes) for x in synth.pixel_world_positions(
+            prob.rot0, prob.trans0, prob.pose, prob.height, prob.width, prob.spacing)])
+        c = clean.cpu().numpy() * bpix
+        target = synth.rician(c, seed + 1, float(c[prob.mask > 0].mean()) / 20.0)
+        del tp
+    elif observations == "phantom":
+        target = synth.head_observation(prob, seed + 1)
+    else:
+        raise ValueError(f"unknown observations {observations}")
+    cut = (6.0 if observations == "mixture" else 3.0) if cutoff is None else float(cutoff)
+    ctx.svr_set_config(tile=tile, batch=128, persistent=0, cutoff=cut, forward_mode=1)
+    params = svr.Params.from_arrays(prob.mean, prob.log_scale, prob.quat, tissue, prob.pose)
+    h = 0.5
+    shape = tuple(int(2 * a / h) for a in axes[::-1])
+    vc = voxel_centres(shape, h)
+    vmask = (np.linalg.norm(vc / axes[None, :], axis=1) <= 1.0).astype(np.float32)
+    b_true = synth.head_bias(vc, bp, axes)
+    probe = VolumeProbe(prob.n_gauss, shape, h, (0, 0, 0), np.zeros(len(vc), np.float32), vmask, device=device,
+                        tile=tile)
+    probe.render(*params.views()[:4])
+    bc, bw = bias_basis(axes, kb, device)
+    K = kb ** 3
+    beta = torch.zeros(K, device=dev)
+    rows = []
+
+    def err(it, t):
+        e = field_error(probe.field(bc, bw, beta, K).cpu().numpy(), b_true, vmask, centred=True)
+        rows.append((it, t, e["rms_log"], e["max_log"], e["offset"], e["explained"]))
+        if log:
+            log(f"iter {it}: rms |log b - log b_true| {e['rms_log']:.4f} (max {e['max_log']:.3f}, mean offset "
+                f"{e['offset']:+.4f}), explained {e['explained']:.4f} of the true log-variance "
+                f"{e['true_rms_log'] ** 2:.3e}")
+
+    err(0, 0.0)
+    fit(ctx, params, torch.as_tensor(target, device=dev), torch.as_tensor(prob.mask, device=dev), n_iter,
+        lr=(0.0,) * 6, probe=_NoProbe(), psnr_every=every, callback=lambda it, t, p, l: err(it, t),
+        bias=dict(centres=bc, width=bw, K=K, beta=beta, lr=lr))
+    final = field_error(probe.field(bc, bw, beta, K).cpu().numpy(), b_true, vmask, centred=True)
+    probe.close()
+    ctx.close()
+    return rows, final
+
+
 def main(argv=None):
     import argparse
     import json
@@ -520,6 +755,11 @@ def main(argv=None):
                     help="windowed: exact amplitude, 3-sigma footprints; topk: the paper's normalised Top-K model")
     ap.add_argument("--pose-lr-scale", type=float, default=1.0, help="factor on the paper's pose rates")
     ap.add_argument("--pose-start", type=int, default=0, help="iterations with the poses held first")
+    ap.add_argument("--coarse", type=int, default=1, help="start from N / coarse Gaussians and densify")
+    ap.add_argument("--densify-at", default="", help="comma-separated iterations after which to densify")
+    ap.add_argument("--bias-grid", type=int, default=0, help="fit a bias field on a kb^3 basis grid (0: none)")
+    ap.add_argument("--bias-lr", type=float, default=1e-2, help="AdamW rate of the bias coefficients")
+    ap.add_argument("--motion", default="4,2", help="sd of the acquisition motion: degrees,mm")
     ap.add_argument("--observations", choices=("mixture", "phantom"), default="mixture",
                     help="mixture: the forward model of the generating mixture (PSNR against its volume); "
                          "phantom: slices of the phantom itself (PSNR against the phantom)")
@@ -529,15 +769,21 @@ def main(argv=None):
                            reg_lambda=a.reg_lambda, s_target=a.s_target, reg_reading=a.reg_reading,
                            init=a.init, psf=not a.no_psf, corrupt=a.corrupt, outliers=a.outliers,
                            outlier_lr=a.outlier_lr, model=a.model, pose_lr_scale=a.pose_lr_scale,
-                           pose_start=a.pose_start, observations=a.observations)
+                           pose_start=a.pose_start, observations=a.observations, coarse=a.coarse,
+                           densify_at=[int(x) for x in a.densify_at.split(",") if x], bias_grid=a.bias_grid,
+                           bias_lr=a.bias_lr, motion=[float(x) for x in a.motion.split(",")])
     extra = {}
+    if a.coarse > 1:
+        extra["n_gauss"] = getattr(res, "n_gauss", None)
+    if a.bias_grid:
+        extra.update(bias_grid=a.bias_grid, bias_lr=a.bias_lr, field=res.field, psnr_without_field=res.plain_psnr)
     if a.outliers:
         bad = np.asarray(res.corrupted, np.int64)
         clean = np.setdiff1d(np.arange(len(res.sigma)), bad)
         # the loss uses the centred values (one subject here)
         om = np.exp(res.log_omega - res.log_omega.mean())
         res.sigma = res.sigma / np.exp(np.log(res.sigma).mean())
-        extra = dict(omega_clean=float(om[clean].mean()), omega_scaled=float(om[bad[0::2]].mean()) if len(bad) else None,
+        extra.update(omega_clean=float(om[clean].mean()), omega_scaled=float(om[bad[0::2]].mean()) if len(bad) else None,
                      omega_noise=float(om[bad[1::2]].mean()) if len(bad) > 1 else None,
                      sigma_clean=float(res.sigma[clean].mean()),
                      sigma_scaled=float(res.sigma[bad[0::2]].mean()) if len(bad) else None)
@@ -545,7 +791,7 @@ def main(argv=None):
                           known_poses=a.known_poses, objective=a.objective, reg_lambda=a.reg_lambda,
                           reg_reading=a.reg_reading, init=a.init, psf=not a.no_psf, corrupt=a.corrupt,
                           outliers=a.outliers, outlier_lr=a.outlier_lr, model=a.model, observations=a.observations,
-                          pose_lr_scale=a.pose_lr_scale,
+                          pose_lr_scale=a.pose_lr_scale, coarse=a.coarse, motion=a.motion,
                           pose_start=a.pose_start, fit_seconds=res.seconds, initial_psnr=res.initial_psnr,
                           generating_mixture_psnr=res.gt_psnr, final_psnr=res.final_psnr,
                           best_psnr=max(res.psnr) if res.psnr else None, pose_err=res.pose_err,

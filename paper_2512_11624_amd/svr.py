@@ -330,6 +330,29 @@ class Context:
         self.n_gauss = int(off[-1])
         return off
 
+    def densify_params(self, params, grad_acc, count, cfg, exp_avg=None, exp_avg_sq=None):
+        """svr_densify on an svr.Params (and its Adam moments, same layout):
+        returns (new Params, new exp_avg, new exp_avg_sq, src); the output
+        buffers are sized for the worst case 2N."""
+        import torch
+        N, M, dev = params.N, params.M, params.flat.device
+        cap = 2 * N
+        out = [torch.empty(max(cap * w, 1), dtype=torch.float32, device=dev) for w in (3, 3, 4, 1)]
+        src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        mom = exp_avg is not None
+        m_out = [torch.empty(11 * cap + 6 * M, dtype=torch.float32, device=dev) for _ in range(2)] if mom else None
+        off = self.svr_densify(params.views()[:4], grad_acc, count, cfg, out, cap, src,
+                               (exp_avg, exp_avg_sq) if mom else None, m_out)
+        K = int(off[-1])
+        new = Params(K, M, device=dev)
+        v = new.views()
+        for t, o, w in zip(v[:4], out, (3, 3, 4, 1)):
+            t.copy_(o[:w * K].view(t.shape))
+        v[4].copy_(params.views()[4])
+        if mom:
+            m_out = [t[:11 * K + 6 * M].clone() for t in m_out]
+        return new, (m_out[0] if mom else None), (m_out[1] if mom else None), src[:K]
+
     def svr_adam_vector(self, p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         hp = svr_adam((C.c_float * 6)(*[lr] * 6), beta1, beta2, eps, weight_decay)
         self._check(load().svr_adam_vector(self.h, _ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr),
