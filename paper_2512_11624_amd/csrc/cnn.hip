@@ -3,10 +3,12 @@
 // FC 524 -> 256 (ReLU) -> 6 on the flattened 128x2x2 features concatenated
 // with the slice's nominal placement (stack rotation R0, 9 floats, and the
 // nominal centre t0 / 16 mm, 3 floats).  Every convolution and linear layer
-// -- forward, input gradient and weight gradient -- is one implicit GEMM on
-// v_mfma_f32_16x16x32_bf16: operands are rounded to BF16 (round to nearest
-// even) when staged into LDS, products accumulate in FP32, master weights and
-// activations stay FP32.
+// -- forward, input gradient and weight gradient -- is an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16 (the input gradient of the large layers is four:
+// one per parity class of the input pixel, which drops the stride's zero
+// taps): operands are rounded to BF16 (round to nearest even) when staged
+// into LDS, products accumulate in FP32, master weights and activations stay
+// FP32.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -25,24 +27,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
-// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
-__device__ inline unsigned short f2bf(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
 constexpr int BM = 64, BN = 64, BK = 32;
 
-// C[M][N] = sum_k A[M][K] B[K][N]; loaders return 0 outside their operand.
-// blockIdx.z selects the K range [z kz, (z+1) kz) (kz a multiple of BK): with
-// several ranges (split K) the epilogue stores partial sums and a second
-// kernel adds them in a fixed order.
+// C[M][N] = sum_k A[M][K] B[K][N].  Each thread stages 8 consecutive k of
+// one row of A and one column of B per K step: a loader's prep(r) decodes
+// that row (column) once, and load8(state, k0, v) fetches k0 .. k0 + 7 with
+// the index walked incrementally (0 outside the operand).  The K loop is
+// double-buffered: the next step's operands are fetched into registers
+// while the current step's MFMAs run on the other LDS buffer, one barrier
+// per step.  blockIdx.z selects the K range [z kz, (z+1) kz) (kz a multiple
+// of BK): with several ranges (split K) the epilogue stores partial sums and
+// a second kernel adds them in a fixed order.
 template <class LA, class LB, class EP>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N, int K, int kz) {
-    __shared__ __attribute__((aligned(16))) unsigned short sA[BM][BK];
-    __shared__ __attribute__((aligned(16))) unsigned short sB[BN][BK];  // transposed: [n][k]
+    __shared__ __attribute__((aligned(16))) unsigned short sA[2][BM][BK];
+    __shared__ __attribute__((aligned(16))) unsigned short sB[2][BN][BK];  // transposed: [n][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -51,22 +50,32 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EP ep, int M, int N,
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column lr, k offset lk
     const int kb = blockIdx.z * kz, ke = min(K, kb + kz);
-    for (int k0 = kb; k0 < ke; k0 += BK) {
-        us8 va, vb;
+    const auto sa = la.prep(m0 + lr);
+    const auto sb = lb.prep(n0 + lr);
+    float va[8], vb[8];
+    if (kb < ke) {
+        la.load8(sa, kb + lk, va);
+        lb.load8(sb, kb + lk, vb);
+    }
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += BK, buf ^= 1) {
+        bf16x8 ua, ub;  // round to nearest even (v_cvt_pk_bf16_f32)
         for (int e = 0; e < 8; ++e) {
-            const int k = k0 + lk + e;
-            va[e] = f2bf(la(m0 + lr, k));
-            vb[e] = f2bf(lb(k, n0 + lr));
+            ua[e] = (__bf16)va[e];
+            ub[e] = (__bf16)vb[e];
         }
+        *reinterpret_cast<bf16x8*>(&sA[buf][lr][lk]) = ua;
+        *reinterpret_cast<bf16x8*>(&sB[buf][lr][lk]) = ub;
         __syncthreads();
-        *reinterpret_cast<us8*>(&sA[lr][lk]) = va;
-        *reinterpret_cast<us8*>(&sB[lr][lk]) = vb;
-        __syncthreads();
+        if (k0 + BK < ke) {  // next step's operands, in flight during this step's MFMAs
+            la.load8(sa, k0 + BK + lk, va);
+            lb.load8(sb, k0 + BK + lk, vb);
+        }
         const int ko = 8 * (lane >> 4);
         for (int i = 0; i < 2; ++i) {
-            const us8 a = *reinterpret_cast<const us8*>(&sA[wm * 32 + i * 16 + (lane & 15)][ko]);
+            const us8 a = *reinterpret_cast<const us8*>(&sA[buf][wm * 32 + i * 16 + (lane & 15)][ko]);
             for (int j = 0; j < 2; ++j) {
-                const us8 b = *reinterpret_cast<const us8*>(&sB[wn * 32 + j * 16 + (lane & 15)][ko]);
+                const us8 b = *reinterpret_cast<const us8*>(&sB[buf][wn * 32 + j * 16 + (lane & 15)][ko]);
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                                     __builtin_bit_cast(bf16x8, b), acc[i][j], 0, 0, 0);
             }
@@ -86,23 +95,88 @@ struct ConvShape {
     int B, Ci, H, W, Co, OH, OW;
 };
 
+// (c, kh, kw) of k = (c * 3 + kh) * 3 + kw, and the step to k + 1
+struct Tap {
+    int c, kh, kw;
+};
+__device__ inline Tap tap_of(int k) {
+    const int t = k / 3;
+    return Tap{t / 3, t - 3 * (t / 3), k - 3 * t};
+}
+__device__ inline void tap_next(Tap& t) {
+    if (++t.kw == 3) {
+        t.kw = 0;
+        if (++t.kh == 3) {
+            t.kh = 0;
+            ++t.c;
+        }
+    }
+}
+// (n, y, x) of a raster index m = (n * Y + y) * X + x, and the step to m + 1
+struct Pix {
+    int n, y, x;
+};
+__device__ inline Pix pix_of(int m, int Y, int X) {
+    const int t = m / X;
+    return Pix{t / Y, t - Y * (t / Y), m - X * t};
+}
+__device__ inline void pix_next(Pix& p, int Y, int X) {
+    if (++p.x == X) {
+        p.x = 0;
+        if (++p.y == Y) {
+            p.y = 0;
+            ++p.n;
+        }
+    }
+}
+
+// upstream gradient through the ReLU (mask = output > 0; out NULL = identity)
+__device__ inline float dmask(const float* dy, const float* out, int64_t idx) {
+    const float g = dy[idx];
+    return (out && !(out[idx] > 0.f)) ? 0.f : g;
+}
+
 // forward: A = im2col(in) [B*OH*OW][Ci*9], B = W^T
 struct LConvIn {
     const float* x;
     ConvShape s;
-    __device__ float operator()(int m, int k) const {
-        if (m >= s.B * s.OH * s.OW || k >= s.Ci * 9) return 0.f;
-        const int ow = m % s.OW, t = m / s.OW, oh = t % s.OH, n = t / s.OH;
-        const int kw = k % 3, t2 = k / 3, kh = t2 % 3, ci = t2 / 3;
-        const int ih = 2 * oh + kh - 1, iw = 2 * ow + kw - 1;
-        if (ih < 0 || ih >= s.H || iw < 0 || iw >= s.W) return 0.f;
-        return x[(((int64_t)n * s.Ci + ci) * s.H + ih) * s.W + iw];
+    struct St {
+        const float* img;  // the row's image, channel 0
+        int ih0, iw0;      // top-left input pixel of the 3x3 window
+        bool ok;
+    };
+    __device__ St prep(int m) const {
+        St r{x, 0, 0, m < s.B * s.OH * s.OW};
+        if (r.ok) {
+            const Pix p = pix_of(m, s.OH, s.OW);
+            r.img = x + (int64_t)p.n * s.Ci * s.H * s.W;
+            r.ih0 = 2 * p.y - 1;
+            r.iw0 = 2 * p.x - 1;
+        }
+        return r;
+    }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        Tap t = tap_of(k0);
+        const int kc = s.Ci * 9;
+        for (int e = 0; e < 8; ++e) {
+            const int ih = r.ih0 + t.kh, iw = r.iw0 + t.kw;
+            const bool in = r.ok && k0 + e < kc && ih >= 0 && ih < s.H && iw >= 0 && iw < s.W;
+            v[e] = in ? r.img[((int64_t)t.c * s.H + ih) * s.W + iw] : 0.f;
+            tap_next(t);
+        }
     }
 };
 struct LConvW {  // B[k][co] = W[co][k]
     const float* w;
     int Co, Kc;
-    __device__ float operator()(int k, int co) const { return (k < Kc && co < Co) ? w[(int64_t)co * Kc + k] : 0.f; }
+    struct St {
+        const float* p;
+        bool ok;
+    };
+    __device__ St prep(int co) const { return St{w + (int64_t)min(co, Co - 1) * Kc, co < Co}; }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = (r.ok && k0 + e < Kc) ? r.p[k0 + e] : 0.f;
+    }
 };
 struct EConvOut {
     float* y;
@@ -117,35 +191,57 @@ struct EConvOut {
     }
 };
 
-// upstream gradient through the ReLU (mask = output > 0; out NULL = identity)
-__device__ inline float dmask(const float* dy, const float* out, int64_t idx) {
-    const float g = dy[idx];
-    return (out && !(out[idx] > 0.f)) ? 0.f : g;
-}
-
 // input gradient: A[m=(n,ih,iw)][k=(co,kh,kw)] = dOut at oh = (ih+1-kh)/2 when integral
 struct LConvDOut {
     const float* dy;
     const float* out;
     ConvShape s;
-    __device__ float operator()(int m, int k) const {
-        if (m >= s.B * s.H * s.W || k >= s.Co * 9) return 0.f;
-        const int iw = m % s.W, t = m / s.W, ih = t % s.H, n = t / s.H;
-        const int kw = k % 3, t2 = k / 3, kh = t2 % 3, co = t2 / 3;
-        const int ph = ih + 1 - kh, pw = iw + 1 - kw;
-        if (ph < 0 || pw < 0 || (ph & 1) || (pw & 1)) return 0.f;
-        const int oh = ph >> 1, ow = pw >> 1;
-        if (oh >= s.OH || ow >= s.OW) return 0.f;
-        return dmask(dy, out, (((int64_t)n * s.Co + co) * s.OH + oh) * s.OW + ow);
+    struct St {
+        int64_t base;  // offset of the row's sample, channel 0
+        int ph0, pw0;  // ih + 1, iw + 1
+        bool ok;
+    };
+    __device__ St prep(int m) const {
+        St r{0, 0, 0, m < s.B * s.H * s.W};
+        if (r.ok) {
+            const Pix p = pix_of(m, s.H, s.W);
+            r.base = (int64_t)p.n * s.Co * s.OH * s.OW;
+            r.ph0 = p.y + 1;
+            r.pw0 = p.x + 1;
+        }
+        return r;
+    }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        Tap t = tap_of(k0);
+        const int kc = s.Co * 9;
+        for (int e = 0; e < 8; ++e) {
+            const int ph = r.ph0 - t.kh, pw = r.pw0 - t.kw;
+            const int oh = ph >> 1, ow = pw >> 1;
+            const bool in = r.ok && k0 + e < kc && ph >= 0 && pw >= 0 && !(ph & 1) && !(pw & 1) && oh < s.OH &&
+                            ow < s.OW;
+            v[e] = in ? dmask(dy, out, r.base + ((int64_t)t.c * s.OH + oh) * s.OW + ow) : 0.f;
+            tap_next(t);
+        }
     }
 };
 struct LConvWT {  // B[k=(co,kh,kw)][ci] = W[co][ci][kh][kw]
     const float* w;
     ConvShape s;
-    __device__ float operator()(int k, int ci) const {
-        if (k >= s.Co * 9 || ci >= s.Ci) return 0.f;
-        const int kk = k % 9, co = k / 9;
-        return w[((int64_t)co * s.Ci + ci) * 9 + kk];
+    struct St {
+        const float* p;  // W[0][ci]
+        bool ok;
+    };
+    __device__ St prep(int ci) const { return St{w + (int64_t)min(ci, s.Ci - 1) * 9, ci < s.Ci}; }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        int co = k0 / 9, kk = k0 - 9 * co;
+        const int kc = s.Co * 9;
+        for (int e = 0; e < 8; ++e) {
+            v[e] = (r.ok && k0 + e < kc) ? r.p[(int64_t)co * s.Ci * 9 + kk] : 0.f;
+            if (++kk == 9) {
+                kk = 0;
+                ++co;
+            }
+        }
     }
 };
 struct EConvDIn {
@@ -157,22 +253,131 @@ struct EConvDIn {
     }
 };
 
-// weight gradient: M = Co, N = Ci*9 (+1 bias column), K = B*OH*OW
-struct LConvDOutT {  // A[co][m] = masked dOut
+// Input gradient split by the parity (py, px) of the input pixel: with
+// stride 2, pixel ih = 2 y + py receives only from kernel rows kh with
+// ih + 1 - kh even -- kh = 1 (oh = y) when py = 0, kh = 0 (oh = y + 1) and
+// kh = 2 (oh = y) when py = 1 -- and likewise for columns.  The four classes
+// are dense GEMMs over 1, 2, 2 and 4 taps per output channel (9 in all,
+// against 9 per pixel for the plain implicit GEMM, whose other taps are
+// zero).  Rows m = (n, y, x) of the class, k = (co, th, tw).
+struct DgradClass {
+    int py, px, nth, ntw, Hc, Wc;
+};
+__device__ inline int class_kh(int p, int t) { return p ? (t ? 2 : 0) : 1; }
+struct LConvDOutP {
     const float* dy;
     const float* out;
     ConvShape s;
-    __device__ float operator()(int co, int m) const {
-        if (co >= s.Co || m >= s.B * s.OH * s.OW) return 0.f;
-        const int ow = m % s.OW, t = m / s.OW, oh = t % s.OH, n = t / s.OH;
-        return dmask(dy, out, (((int64_t)n * s.Co + co) * s.OH + oh) * s.OW + ow);
+    DgradClass c;
+    struct St {
+        int64_t base;
+        int y, x;
+        bool ok;
+    };
+    __device__ St prep(int m) const {
+        St r{0, 0, 0, m < s.B * c.Hc * c.Wc};
+        if (r.ok) {
+            const Pix p = pix_of(m, c.Hc, c.Wc);
+            r.base = (int64_t)p.n * s.Co * s.OH * s.OW;
+            r.y = p.y;
+            r.x = p.x;
+        }
+        return r;
+    }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        const int nt = c.nth * c.ntw, kc = s.Co * nt;
+        int co = k0 / nt, t = k0 - co * nt;
+        int th = t / c.ntw, tw = t - th * c.ntw;
+        for (int e = 0; e < 8; ++e) {
+            const int oh = r.y + ((c.py && th == 0) ? 1 : 0), ow = r.x + ((c.px && tw == 0) ? 1 : 0);
+            const bool in = r.ok && k0 + e < kc && oh < s.OH && ow < s.OW;
+            v[e] = in ? dmask(dy, out, r.base + ((int64_t)co * s.OH + oh) * s.OW + ow) : 0.f;
+            if (++tw == c.ntw) {
+                tw = 0;
+                if (++th == c.nth) {
+                    th = 0;
+                    ++co;
+                }
+            }
+        }
+    }
+};
+struct LConvWTP {  // B[k=(co,th,tw)][ci] = W[co][ci][kh(th)][kw(tw)]
+    const float* w;
+    ConvShape s;
+    DgradClass c;
+    struct St {
+        const float* p;  // W[0][ci]
+        bool ok;
+    };
+    __device__ St prep(int ci) const { return St{w + (int64_t)min(ci, s.Ci - 1) * 9, ci < s.Ci}; }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        const int nt = c.nth * c.ntw, kc = s.Co * nt;
+        int co = k0 / nt, t = k0 - co * nt;
+        int th = t / c.ntw, tw = t - th * c.ntw;
+        for (int e = 0; e < 8; ++e) {
+            v[e] = (r.ok && k0 + e < kc) ? r.p[(int64_t)co * s.Ci * 9 + class_kh(c.py, th) * 3 + class_kh(c.px, tw)]
+                                         : 0.f;
+            if (++tw == c.ntw) {
+                tw = 0;
+                if (++th == c.nth) {
+                    th = 0;
+                    ++co;
+                }
+            }
+        }
+    }
+};
+struct EConvDInP {
+    float* dx;
+    ConvShape s;
+    DgradClass c;
+    __device__ void operator()(int m, int ci, float v) const {
+        const Pix p = pix_of(m, c.Hc, c.Wc);
+        const int ih = 2 * p.y + c.py, iw = 2 * p.x + c.px;
+        dx[(((int64_t)p.n * s.Ci + ci) * s.H + ih) * s.W + iw] = v;
+    }
+};
+
+// weight gradient: M = Co, N = Ci*9 (+1 bias column), K = B*OH*OW
+struct LConvDOutT {  // A[co][m] = masked dOut, m = (n, oh, ow)
+    const float* dy;
+    const float* out;
+    ConvShape s;
+    struct St {
+        int co;
+        bool ok;
+    };
+    __device__ St prep(int co) const { return St{co, co < s.Co}; }
+    __device__ void load8(const St& r, int m0, float* v) const {
+        Pix p = pix_of(m0, s.OH, s.OW);
+        const int mk = s.B * s.OH * s.OW;
+        for (int e = 0; e < 8; ++e) {
+            const bool in = r.ok && m0 + e < mk;
+            v[e] = in ? dmask(dy, out, (((int64_t)p.n * s.Co + r.co) * s.OH + p.y) * s.OW + p.x) : 0.f;
+            pix_next(p, s.OH, s.OW);
+        }
     }
 };
 struct LConvInB {  // B[m][k] = im2col(in)[m][k], column Ci*9 = 1 (bias)
-    LConvIn c;
-    __device__ float operator()(int m, int k) const {
-        if (k == c.s.Ci * 9) return m < c.s.B * c.s.OH * c.s.OW ? 1.f : 0.f;
-        return c(m, k);
+    const float* x;
+    ConvShape s;
+    struct St {
+        Tap t;
+        bool ok, bias;
+    };
+    __device__ St prep(int k) const { return St{tap_of(k), k <= s.Ci * 9, k == s.Ci * 9}; }
+    __device__ void load8(const St& r, int m0, float* v) const {
+        Pix p = pix_of(m0, s.OH, s.OW);
+        const int mk = s.B * s.OH * s.OW;
+        for (int e = 0; e < 8; ++e) {
+            const int ih = 2 * p.y - 1 + r.t.kh, iw = 2 * p.x - 1 + r.t.kw;
+            const bool valid = r.ok && m0 + e < mk;
+            const bool in = valid && !r.bias && ih >= 0 && ih < s.H && iw >= 0 && iw < s.W;
+            v[e] = r.bias ? (valid ? 1.f : 0.f)
+                          : (in ? x[(((int64_t)p.n * s.Ci + r.t.c) * s.H + ih) * s.W + iw] : 0.f);
+            pix_next(p, s.OH, s.OW);
+        }
     }
 };
 struct EWGrad {
@@ -186,13 +391,17 @@ struct EWGrad {
 };
 
 // ---- linear layers: x [B][Fin], W [Fout][Fin] ----------------------------------
-struct LMat {  // row-major [R][C], optional second block for columns >= C1 (concatenation)
+struct LMat {  // A[r][c]: row-major [R][C], optional second block for columns >= C1 (concatenation)
     const float* a;
     int R, C;
     const float* a2;
     int C1, C2;
-    __device__ float operator()(int r, int c) const {
-        if (r >= R) return 0.f;
+    struct St {
+        int r;
+        bool ok;
+    };
+    __device__ St prep(int r) const { return St{r, r < R}; }
+    __device__ float at(int r, int c) const {
         if (a2) {
             if (c < C1) return a[(int64_t)r * C1 + c];
             if (c < C1 + C2) return a2[(int64_t)r * C2 + (c - C1)];
@@ -200,34 +409,73 @@ struct LMat {  // row-major [R][C], optional second block for columns >= C1 (con
         }
         return c < C ? a[(int64_t)r * C + c] : 0.f;
     }
+    __device__ void load8(const St& st, int c0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = st.ok ? at(st.r, c0 + e) : 0.f;
+    }
 };
 struct LMatT {  // B[k][n] = W[n][k]
     const float* w;
     int N, K;
-    __device__ float operator()(int k, int n) const { return (k < K && n < N) ? w[(int64_t)n * K + k] : 0.f; }
+    struct St {
+        const float* p;
+        bool ok;
+    };
+    __device__ St prep(int n) const { return St{w + (int64_t)min(n, N - 1) * K, n < N}; }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = (r.ok && k0 + e < K) ? r.p[k0 + e] : 0.f;
+    }
+};
+struct LMatN {  // B[k][n] = W[k][n] (row-major [K][N])
+    const float* w;
+    int K, N;
+    struct St {
+        int n;
+        bool ok;
+    };
+    __device__ St prep(int n) const { return St{n, n < N}; }
+    __device__ void load8(const St& r, int k0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = (r.ok && k0 + e < K) ? w[(int64_t)(k0 + e) * N + r.n] : 0.f;
+    }
 };
 struct LMasked {  // A[r][c] = masked dy[r][c]
     const float* dy;
     const float* out;
     int R, C;
-    __device__ float operator()(int r, int c) const {
-        return (r < R && c < C) ? dmask(dy, out, (int64_t)r * C + c) : 0.f;
+    struct St {
+        int64_t base;
+        bool ok;
+    };
+    __device__ St prep(int r) const { return St{(int64_t)r * C, r < R}; }
+    __device__ void load8(const St& st, int c0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = (st.ok && c0 + e < C) ? dmask(dy, out, st.base + c0 + e) : 0.f;
     }
 };
 struct LMaskedT {  // A[o][b] = masked dy[b][o]
     const float* dy;
     const float* out;
     int Bn, F;
-    __device__ float operator()(int o, int b) const {
-        return (o < F && b < Bn) ? dmask(dy, out, (int64_t)b * F + o) : 0.f;
+    struct St {
+        int o;
+        bool ok;
+    };
+    __device__ St prep(int o) const { return St{o, o < F}; }
+    __device__ void load8(const St& st, int b0, float* v) const {
+        for (int e = 0; e < 8; ++e) v[e] = (st.ok && b0 + e < Bn) ? dmask(dy, out, (int64_t)(b0 + e) * F + st.o) : 0.f;
     }
 };
 struct LMatB {  // B[b][i] = x[b][i] (with concatenation), column Fin = 1 (bias)
     LMat x;
     int Fin;
-    __device__ float operator()(int b, int i) const {
-        if (i == Fin) return b < x.R ? 1.f : 0.f;
-        return x(b, i);
+    struct St {
+        int i;
+        bool ok;
+    };
+    __device__ St prep(int i) const { return St{i, i <= Fin}; }
+    __device__ void load8(const St& st, int b0, float* v) const {
+        for (int e = 0; e < 8; ++e) {
+            const int b = b0 + e;
+            v[e] = (!st.ok || b >= x.R) ? 0.f : (st.i == Fin ? 1.f : x.at(b, st.i));
+        }
     }
 };
 struct EStore {
@@ -250,14 +498,21 @@ struct EPartial {
     }
 };
 
+// Sum of the split-K partials in a fixed order: a workgroup takes 64
+// consecutive outputs; wave q adds splits q, q + 4, ... in order, and the four
+// wave sums are added in wave order.
 template <class EP>
-__global__ void k_splitk_sum(const float* __restrict__ ws, int splits, int M, int N, EP ep) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_splitk_sum(const float* __restrict__ ws, int splits, int M, int N, EP ep) {
+    __shared__ float s_part[4][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int64_t mn = (int64_t)M * N;
-    if (idx >= mn) return;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
     float v = 0.f;
-    for (int z = 0; z < splits; ++z) v += ws[z * mn + idx];
-    ep((int)(idx / N), (int)(idx % N), v);
+    if (idx < mn)
+        for (int z = q; z < splits; z += 4) v += ws[z * mn + idx];
+    s_part[q][lane] = v;
+    __syncthreads();
+    if (q == 0 && idx < mn) ep((int)(idx / N), (int)(idx % N), ((s_part[0][lane] + s_part[1][lane]) + s_part[2][lane]) + s_part[3][lane]);
 }
 
 // Splits K when the output has too few 64x64 tiles to fill the chip and
@@ -282,7 +537,7 @@ hipError_t gemm(LA la, LB lb, EP ep, int M, int N, int K, hipStream_t st, float*
     hipLaunchKernelGGL((k_gemm<LA, LB, EPartial>), dim3(gx, gy, splits), dim3(256), 0, st, la, lb,
                        EPartial{ws, M, N}, M, N, K, kz);
     const int64_t mn = (int64_t)M * N;
-    hipLaunchKernelGGL((k_splitk_sum<EP>), dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, (const float*)ws,
+    hipLaunchKernelGGL((k_splitk_sum<EP>), dim3((unsigned)((mn + 63) / 64)), dim3(256), 0, st, (const float*)ws,
                        splits, M, N, ep);
     return hipGetLastError();
 }
@@ -300,11 +555,23 @@ hipError_t conv_fwd(const float* x, const float* w, const float* b, float* y, Co
     return gemm(LConvIn{x, s}, LConvW{w, s.Co, s.Ci * 9}, EConvOut{y, b, s, relu}, s.B * s.OH * s.OW, s.Co, s.Ci * 9, st);
 }
 hipError_t conv_dgrad(const float* dy, const float* out, const float* w, float* dx, ConvShape s, hipStream_t st) {
-    return gemm(LConvDOut{dy, out, s}, LConvWT{w, s}, EConvDIn{dx, s}, s.B * s.H * s.W, s.Ci, s.Co * 9, st);
+    // small layers: one plain implicit GEMM fills the chip better than four
+    // class GEMMs of a quarter of the rows each
+    if ((int64_t)s.B * s.H * s.W < (1 << 18))
+        return gemm(LConvDOut{dy, out, s}, LConvWT{w, s}, EConvDIn{dx, s}, s.B * s.H * s.W, s.Ci, s.Co * 9, st);
+    for (int py = 0; py < 2; ++py)
+        for (int px = 0; px < 2; ++px) {
+            const DgradClass c{py, px, py ? 2 : 1, px ? 2 : 1, (s.H - py + 1) / 2, (s.W - px + 1) / 2};
+            if (c.Hc <= 0 || c.Wc <= 0) continue;
+            hipError_t e = gemm(LConvDOutP{dy, out, s, c}, LConvWTP{w, s, c}, EConvDInP{dx, s, c},
+                                s.B * c.Hc * c.Wc, s.Ci, s.Co * c.nth * c.ntw, st);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 hipError_t conv_wgrad(const float* dy, const float* out, const float* x, float* dw, float* db, ConvShape s,
                       hipStream_t st, float* ws, size_t ws_floats) {
-    return gemm(LConvDOutT{dy, out, s}, LConvInB{LConvIn{x, s}}, EWGrad{dw, db, s.Ci * 9}, s.Co, s.Ci * 9 + 1,
+    return gemm(LConvDOutT{dy, out, s}, LConvInB{x, s}, EWGrad{dw, db, s.Ci * 9}, s.Co, s.Ci * 9 + 1,
                 s.B * s.OH * s.OW, st, ws, ws_floats);
 }
 hipError_t lin_fwd(LMat x, const float* w, const float* b, float* y, int Bn, int Fin, int Fout, int relu,
@@ -314,7 +581,7 @@ hipError_t lin_fwd(LMat x, const float* w, const float* b, float* y, int Bn, int
 hipError_t lin_dgrad(const float* dy, const float* out, const float* w, float* dx, int Bn, int Fin, int Fout,
                      hipStream_t st) {
     // dX[b][i] = sum_o dYm[b][o] W[o][i]
-    return gemm(LMasked{dy, out, Bn, Fout}, LMat{w, Fout, Fin, nullptr, 0, 0}, EStore{dx, nullptr, Fin, 0}, Bn, Fin,
+    return gemm(LMasked{dy, out, Bn, Fout}, LMatN{w, Fout, Fin}, EStore{dx, nullptr, Fin, 0}, Bn, Fin,
                 Fout, st);
 }
 hipError_t lin_wgrad(const float* dy, const float* out, LMat x, float* dw, float* db, int Bn, int Fin, int Fout,
@@ -324,6 +591,18 @@ hipError_t lin_wgrad(const float* dy, const float* out, LMat x, float* dw, float
 }
 
 // ---- small element-wise kernels --------------------------------------------------
+// dy <- dy where out > 0, else 0 (the ReLU's adjoint, applied once so that
+// the layer's weight and input gradients read dy alone)
+__global__ void k_relu_mask(float* __restrict__ dy, const float* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(out[i] > 0.f)) dy[i] = 0.f;
+}
+hipError_t relu_mask(float* dy, const float* out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dy, out, n);
+    return hipGetLastError();
+}
+
 // Bilinear x4 upsampling of an H x W slice to a (4H) x (4W) crop, optionally
 // centre-cropped / padded to 128 x 128, scaled by 1/scale.
 __global__ void k_prepare(const float* __restrict__ slices, int B, int H, int W, float* __restrict__ crops) {
@@ -435,10 +714,12 @@ hipError_t net_backward(svr_posenet* net, const float* crops, const float* orien
     if (e != hipSuccess) return e;
     // fc1 (ReLU on h)
     LMat feat{net->act[6], B, kFeat + kOrient, orient, kFeat, kOrient};
-    e = lin_wgrad(net->dh, net->h, feat, g + net->off[12], g + net->off[13], B, kFeat + kOrient, kHidden, st,
+    e = relu_mask(net->dh, net->h, (int64_t)B * kHidden, st);
+    if (e != hipSuccess) return e;
+    e = lin_wgrad(net->dh, nullptr, feat, g + net->off[12], g + net->off[13], B, kFeat + kOrient, kHidden, st,
                   net->ws, kSplitWs);
     if (e != hipSuccess) return e;
-    e = lin_dgrad(net->dh, net->h, net->params + net->off[12], net->dfeat, B, kFeat + kOrient, kHidden, st);
+    e = lin_dgrad(net->dh, nullptr, net->params + net->off[12], net->dfeat, B, kFeat + kOrient, kHidden, st);
     if (e != hipSuccess) return e;
     // the first 512 feature gradients (row stride 524) are d a6 ([B,128,2,2] flattened)
     e = hipMemcpy2DAsync(net->dact[6], sizeof(float) * kFeat, net->dfeat, sizeof(float) * (kFeat + kOrient),
@@ -447,11 +728,13 @@ hipError_t net_backward(svr_posenet* net, const float* crops, const float* orien
     for (int l = 5; l >= 0; --l) {
         ConvShape s = conv_shape(B, kCh[l], kSide[l], kSide[l], kCh[l + 1]);
         const float* in = l == 0 ? crops : net->act[l];
-        e = conv_wgrad(net->dact[l + 1], net->act[l + 1], in, g + net->off[2 * l], g + net->off[2 * l + 1], s, st,
-                       net->ws, kSplitWs);
+        e = relu_mask(net->dact[l + 1], net->act[l + 1], (int64_t)B * s.Co * s.OH * s.OW, st);
+        if (e != hipSuccess) return e;
+        e = conv_wgrad(net->dact[l + 1], nullptr, in, g + net->off[2 * l], g + net->off[2 * l + 1], s, st, net->ws,
+                       kSplitWs);
         if (e != hipSuccess) return e;
         if (l > 0) {
-            e = conv_dgrad(net->dact[l + 1], net->act[l + 1], net->params + net->off[2 * l], net->dact[l], s, st);
+            e = conv_dgrad(net->dact[l + 1], nullptr, net->params + net->off[2 * l], net->dact[l], s, st);
             if (e != hipSuccess) return e;
         }
     }
