@@ -114,7 +114,7 @@ def make_workload(name, seed=0):
     elif name == "batched":
         prob = synth.config4(seed)
         desc = ("16 cube subjects, Gaussians log-uniform 1.5e5-1.5e6 (8.2M total), 3-9 stacks of 20-48 slices, "
-                "192-320 px, thickness 2.5-4.5 mm, one persistent launch")
+                "192-320 px, thickness 2.5-4.5 mm, all subjects in one launch per stage")
     elif name == "cube":
         prob = synth.config1(seed)
         desc = "cube phantom, 2,000 Gaussians, 3 stacks x 16 slices of 32x32 px at 1x1x3 mm"
