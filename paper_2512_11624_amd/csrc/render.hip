@@ -362,28 +362,38 @@ __device__ inline LaneBox lane_box(const Record& R, int tx0, int ty0, int xmax, 
 // Forward walk of one instance's box inside its tile, rows outer and columns
 // inner: adds round(amq max(e - e_T, 0)) to acc[y * T + x] (tile-local pixel)
 // with an integer LDS atomic; pixels outside the cut add an integer zero
-// (branch-free).  Returns the number of in-cut pixels when kCount.
+// (branch-free).  The term is amq e - amq e_T clamped (v_med3) to zero on the
+// side opposite to amq's sign, rounded half up to an integer
+// (v_cvt_rpi_i32_f32); the LDS address is the loop variable.  Returns the
+// number of in-cut pixels when kCount.
+__device__ inline int round_half_up(float v) {
+    int q;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(q) : "v"(v));
+    return q;
+}
+
 template <int T, bool kCount>
 __device__ inline unsigned int forward_walk(const LaneBox& b, float amq, int* acc, float etau) {
     const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
     const int hh = w > 0 ? h : 0;
     const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
+    const float c = -amq * etau;
+    const float lo = amq >= 0.f ? 0.f : -__builtin_inff(), hi = amq >= 0.f ? __builtin_inff() : 0.f;
     float dy = (float)b.y0 - b.pyl;
-    int gr = b.y0 * T + b.x0;
+    int* row = acc + b.y0 * T + b.x0;
     unsigned int cnt = 0;
     for (int r = 0; r < hh; ++r) {
         const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
         float dx = dx0;
-        int gi = gr;
-        for (int c = 0; c < w; ++c) {
-            const float v = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy)) - etau;
-            atomicAdd(&acc[gi], __float2int_rn(amq * fmaxf(v, 0.f)));
-            if (kCount) cnt += v > 0.f ? 1u : 0u;
+        int* const end = row + w;
+        for (int* p = row; p < end; ++p) {
+            const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy));
+            atomicAdd(p, round_half_up(__builtin_amdgcn_fmed3f(fmaf(amq, e, c), lo, hi)));
+            if (kCount) cnt += e > etau ? 1u : 0u;
             dx += 1.f;
-            ++gi;
         }
         dy += 1.f;
-        gr += T;
+        row += T;
     }
     return cnt;
 }
