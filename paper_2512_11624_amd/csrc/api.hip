@@ -91,6 +91,11 @@ struct svr_ctx {
     int32_t loss_kind = 0;        // SVR_LOSS_MSE / SVR_LOSS_L1
     DevBuf<float> d_regpart;      // scale-regulariser block partials
     DevBuf<float> d_bias_scratch; // bias-field adjoint partials
+    DevBuf<float> d_pose_part, d_pose_pp;  // projection adjoint: pose sums per workgroup, per 256 workgroups
+    DevBuf<int4> d_pose_w1;                // their first-level work items (subject, columns, parts)
+    DevBuf<int2> d_pose_w2;                // second-level work items (subject, columns)
+    int64_t pose_part_floats = 0, pose_pp_floats = 0;
+    int32_t n_pose_w1 = 0, n_pose_w2 = 0;
     DevBuf<int32_t> d_dens_n, d_dens_pos;   // densification: outputs per Gaussian and their scan
     DevBuf<int64_t> d_dens_off;             // densification: new per-subject offsets
     DevBuf<long long> d_dens_tot;
@@ -284,10 +289,10 @@ int build_tables(svr_ctx* c) {
     std::vector<SubjectInfo> subj(c->n_subjects);
     std::vector<GaussBlock> blocks;
     for (int s = 0; s < c->n_subjects; ++s) {
+        subj[s] = SubjectInfo{};
         subj[s].g_begin = c->gauss_off[s];
         subj[s].g_end = c->gauss_off[s + 1];
-        subj[s].s_begin = 0;
-        subj[s].s_end = 0;
+        subj[s].part0 = kProjParts * (int32_t)blocks.size();
         for (int64_t g0 = subj[s].g_begin; g0 < subj[s].g_end; g0 += kGaussBlock) {
             GaussBlock b;
             b.g_begin = g0;
@@ -306,6 +311,29 @@ int build_tables(svr_ctx* c) {
         }
     }
     c->n_blocks = (int32_t)blocks.size();
+    // the projection adjoint's two-level pose reduction: rows of 6 ns sums
+    // per workgroup, then per 256 workgroups (work items of 64 columns)
+    std::vector<int4> w1;
+    std::vector<int2> w2;
+    int64_t pose_rows = 0, pp_rows = 0;
+    for (int s = 0; s < c->n_subjects; ++s) {
+        const int32_t nb_s = (int32_t)((subj[s].g_end - subj[s].g_begin + kGaussBlock - 1) / kGaussBlock);
+        const int64_t C = 6 * (int64_t)(subj[s].s_end - subj[s].s_begin);
+        subj[s].nparts = kProjParts * nb_s;
+        subj[s].nrc = (subj[s].nparts + kPoseRowChunk - 1) / kPoseRowChunk;
+        subj[s].pose_base = pose_rows;
+        subj[s].pp_base = pp_rows;
+        pose_rows += (int64_t)subj[s].nparts * C;
+        pp_rows += (int64_t)subj[s].nrc * C;
+        for (int cg = 0; cg < (int)((C + 63) / 64); ++cg) {
+            for (int rc = 0; rc < subj[s].nrc; ++rc) w1.push_back(make_int4(s, cg, rc, 0));
+            w2.push_back(make_int2(s, cg));
+        }
+    }
+    c->pose_part_floats = pose_rows;
+    c->pose_pp_floats = pp_rows;
+    c->n_pose_w1 = (int32_t)w1.size();
+    c->n_pose_w2 = (int32_t)w2.size();
     if (c->host_only) return SVR_OK;
     hipStream_t st = c->stream;
     HIPCHK(c, hipStreamSynchronize(st));
@@ -319,6 +347,12 @@ int build_tables(svr_ctx* c) {
     HIPCHK(c, ensure(c->d_tile_sse, tile_slice.size()));
     HIPCHK(c, ensure(c->d_slice_sse, (size_t)c->M));
     HIPCHK(c, ensure(c->d_pose_acc, (size_t)c->M * 6));
+    HIPCHK(c, ensure(c->d_pose_w1, std::max<size_t>(w1.size(), 1)));
+    HIPCHK(c, ensure(c->d_pose_w2, std::max<size_t>(w2.size(), 1)));
+    if (!w1.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_pose_w1.p, w1.data(), w1.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    if (!w2.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d_pose_w2.p, w2.data(), w2.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     HIPCHK(c, ensure(c->d_counts, (size_t)c->N));
     HIPCHK(c, ensure(c->d_offsets, (size_t)c->N));
     if (!geo.empty())
@@ -688,6 +722,7 @@ int svr_ctx_destroy(svr_ctx* c) {
         release(c->d_tkeys); release(c->d_tvals); release(c->d_tkeys2); release(c->d_tvals2);
         release(c->d_tsort_tmp);
         release(c->d_dens_n); release(c->d_dens_pos); release(c->d_dens_off); release(c->d_dens_tot);
+        release(c->d_pose_part); release(c->d_pose_pp); release(c->d_pose_w1); release(c->d_pose_w2);
         release(c->d_regpart); release(c->d_bias_scratch); release(c->d_smask); release(c->d_fwd_part);
         release(c->d_init_tab); release(c->d_init_pose); release(c->d_init_subpix); release(c->d_init_cdf);
         release(c->d_init_bsum); release(c->d_init_base); release(c->d_init_total); release(c->d_init_g);
@@ -904,9 +939,16 @@ int svr_backward(svr_ctx* c, const float* grad_pred, const float* grad_scale, co
     ProjectArgs pa = project_args(c);
     {
         StageScope sc(c, ST_PROJECT_BACKWARD);
+        const bool two_level = c->max_subject_slices <= 512;
+        if (two_level) {
+            HIPCHK(c, ensure(c->d_pose_part, (size_t)std::max<int64_t>(c->pose_part_floats, 1)));
+            HIPCHK(c, ensure(c->d_pose_pp, (size_t)std::max<int64_t>(c->pose_pp_floats, 1)));
+        }
         HIPCHK(c, launch_project_backward(pa, c->d_offsets.p, c->d_counts.p, c->d_rec.p, c->d_rec_inst.p,
                                           c->d_inst_grad.p, c->n_inst, out->mean, out->log_scale, out->quat,
-                                          out->amp, c->d_pose_acc.p, c->max_subject_slices, st));
+                                          out->amp, c->d_pose_acc.p, c->max_subject_slices,
+                                          two_level ? c->d_pose_part.p : nullptr, two_level ? c->d_pose_pp.p : nullptr,
+                                          c->d_pose_w1.p, c->n_pose_w1, c->d_pose_w2.p, c->n_pose_w2, c->M, st));
     }
     {
         StageScope sc(c, ST_POSE_CHAIN);

@@ -535,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
     const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
     int64_t n_inst, float* __restrict__ g_mean, float* __restrict__ g_log_scale, float* __restrict__ g_quat,
-    float* __restrict__ g_amp, float* __restrict__ pose_acc, int use_lds) {
+    float* __restrict__ g_amp, float* __restrict__ pose_acc, int use_lds, float* __restrict__ pose_part) {
     // dynamic LDS: per-slice pose sums [6 * ns] floats, then this pass's
     // fixed-point pose sums [6 * ns] int64 (8-byte aligned: 6 * ns floats is
     // a multiple of 8 bytes)
@@ -546,12 +546,18 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
     __shared__ float s_act[kGAct][NGS];
     // workgroup = one NGS-Gaussian part of a Gaussian block
     constexpr int NS = kBlock / NGS;
+    static_assert(NS == kProjParts, "parts per Gaussian block");
     const GaussBlock blk = a.blocks[blockIdx.x / NS];
     const int64_t g0 = blk.g_begin + (int64_t)(blockIdx.x % NS) * NGS;
-    if (g0 >= blk.g_end) return;  // empty part (uniform)
-    const int64_t g1 = min(g0 + (int64_t)NGS, blk.g_end);
     const SubjectInfo si = a.subj[blk.subject];
     const int ns = si.s_end - si.s_begin;
+    float* const prow = pose_part + si.pose_base + (int64_t)((int)blockIdx.x - si.part0) * 6 * ns;
+    if (g0 >= blk.g_end) {  // empty part (uniform): a zero row of pose sums
+        if (use_lds)
+            for (int k = threadIdx.x; k < 6 * ns; k += kBlock) prow[k] = 0.f;
+        return;
+    }
+    const int64_t g1 = min(g0 + (int64_t)NGS, blk.g_end);
     unsigned long long* s_ipose = reinterpret_cast<unsigned long long*>(s_pose + 6 * ns);
     const int tid = threadIdx.x, lane = tid & 63;
     const int ng = (int)(g1 - g0);
@@ -773,13 +779,53 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         for (int k = 0; k < 3; ++k) g_mean[3 * j + k] = s_gacc[6 + k][tid];
         g_amp[j] = s_gacc[9][tid];
     }
-    if (use_lds) {
+    if (use_lds) {  // the part's row of pose sums, reduced over parts in a fixed order below
         __syncthreads();
-        for (int k = tid; k < 6 * ns; k += blockDim.x) {
-            const float v = s_pose[k];
-            if (v != 0.f) atomicAdd(&pose_acc[6 * (int64_t)si.s_begin + k], v);
-        }
+        for (int k = tid; k < 6 * ns; k += blockDim.x) prow[k] = s_pose[k];
     }
+}
+
+// Pose sums, first level: work item (subject, 64 columns, kPoseRowChunk
+// parts); wave q adds parts q, q + 4, ... of the item in order, the four wave
+// sums are added in wave order.
+__global__ __launch_bounds__(256) void k_pose_sum_parts(const float* __restrict__ part,
+                                                        const SubjectInfo* __restrict__ subj,
+                                                        const int4* __restrict__ w1, float* __restrict__ pp) {
+    __shared__ float s_sum[4][64];
+    const int4 w = w1[blockIdx.x];  // subject, column group, row chunk
+    const SubjectInfo si = subj[w.x];
+    const int C = 6 * (si.s_end - si.s_begin);
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = w.y * 64 + lane;
+    const int p0 = w.z * kPoseRowChunk, p1 = min(si.nparts, p0 + kPoseRowChunk);
+    float v = 0.f;
+    if (col < C)
+        for (int p = p0 + q; p < p1; p += 4) v += part[si.pose_base + (int64_t)p * C + col];
+    s_sum[q][lane] = v;
+    __syncthreads();
+    if (q == 0 && col < C)
+        pp[si.pp_base + (int64_t)w.z * C + col] = (s_sum[0][lane] + s_sum[1][lane]) + (s_sum[2][lane] + s_sum[3][lane]);
+}
+
+// Pose sums, second level: work item (subject, 64 columns); wave q adds the
+// first level's rows q, q + 4, ... in order, the four wave sums are added in
+// wave order -> pose_acc (overwritten).
+__global__ __launch_bounds__(256) void k_pose_sum_rows(const float* __restrict__ pp,
+                                                       const SubjectInfo* __restrict__ subj,
+                                                       const int2* __restrict__ w2, float* __restrict__ pose_acc) {
+    __shared__ float s_sum[4][64];
+    const int2 w = w2[blockIdx.x];  // subject, column group
+    const SubjectInfo si = subj[w.x];
+    const int C = 6 * (si.s_end - si.s_begin);
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int col = w.y * 64 + lane;
+    float v = 0.f;
+    if (col < C)
+        for (int r = q; r < si.nrc; r += 4) v += pp[si.pp_base + (int64_t)r * C + col];
+    s_sum[q][lane] = v;
+    __syncthreads();
+    if (q == 0 && col < C)
+        pose_acc[6 * (int64_t)si.s_begin + col] = (s_sum[0][lane] + s_sum[1][lane]) + (s_sum[2][lane] + s_sum[3][lane]);
 }
 
 // K11: d omega = J_l(omega)^T d delta, d tau = d t.
@@ -839,15 +885,24 @@ hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* off
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
                                    const Record* rec, const int2* rec_inst, const float4* inst_grad,
                                    int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,
-                                   float* g_amp, float* pose_acc, int32_t max_subject_slices,
-                                   hipStream_t st) {
+                                   float* g_amp, float* pose_acc, int32_t max_subject_slices, float* pose_part,
+                                   float* pose_pp, const int4* w1, int32_t n_w1, const int2* w2, int32_t n_w2,
+                                   int32_t m, hipStream_t st) {
     if (a.n_blocks <= 0) return hipSuccess;
-    const int use_lds = (max_subject_slices <= 512) ? 1 : 0;  // dynamic LDS 72 B per slice
+    const int use_lds = (max_subject_slices <= 512 && pose_part && pose_pp && w1) ? 1 : 0;  // 72 B LDS per slice
     const size_t lds = use_lds ? (sizeof(float) + sizeof(unsigned long long)) * 6 * (size_t)max_subject_slices : 0;
     constexpr int NGS = kPartGauss;
     hipLaunchKernelGGL(k_project_backward<NGS>, dim3(a.n_blocks * (kBlock / NGS)), dim3(kBlock), lds, st, a, offsets,
                        counts, rec, rec_inst, inst_grad, n_inst, g_mean, g_log_scale, g_quat, g_amp, pose_acc,
-                       use_lds);
+                       use_lds, pose_part);
+    if (use_lds && m > 0) {
+        if (n_w1 > 0)
+            hipLaunchKernelGGL(k_pose_sum_parts, dim3((unsigned)n_w1), dim3(256), 0, st, (const float*)pose_part,
+                               a.subj, w1, pose_pp);
+        if (n_w2 > 0)
+            hipLaunchKernelGGL(k_pose_sum_rows, dim3((unsigned)n_w2), dim3(256), 0, st, (const float*)pose_pp,
+                               a.subj, w2, pose_acc);
+    }
     return hipGetLastError();
 }
 

@@ -38,7 +38,16 @@ struct SlicePose {
 struct SubjectInfo {
     int64_t g_begin, g_end;
     int32_t s_begin, s_end;
+    // projection adjoint's per-slice pose sums: the subject's workgroups
+    // (parts) are part0 .. part0 + nparts - 1; part k writes its 6 ns sums
+    // at pose_base + k 6 ns, and the first reduction level writes nrc rows
+    // of 6 ns (one per kPoseRowChunk parts) at pp_base
+    int32_t part0, nparts, nrc, pad;
+    int64_t pose_base, pp_base;
 };
+// workgroups of the projection adjoint per Gaussian block (256 Gaussians)
+constexpr int kProjParts = 2;
+constexpr int kPoseRowChunk = 64;  // parts per first-level row of the pose reduction
 
 // Block table of the per-Gaussian kernels: blocks never straddle subjects.
 struct GaussBlock {
@@ -152,11 +161,15 @@ hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st)
 hipError_t launch_emit(const ProjectArgs& a, const int2* counts, const int2* offsets, Record* rec,
                        int2* rec_inst, uint32_t* keys, uint32_t* vals, int* fallback, const int* overflow,
                        hipStream_t st);
+// pose_part / pose_pp / w1: the two-level pose reduction (SubjectInfo); when
+// max_subject_slices <= 512 the pose sums are reduced through them in a
+// fixed order, else they are added to pose_acc atomically per record
 hipError_t launch_project_backward(const ProjectArgs& a, const int2* offsets, const int2* counts,
                                    const Record* rec, const int2* rec_inst, const float4* inst_grad,
                                    int64_t n_inst, float* g_mean, float* g_log_scale, float* g_quat,
-                                   float* g_amp, float* pose_acc, int32_t max_subject_slices,
-                                   hipStream_t st);
+                                   float* g_amp, float* pose_acc, int32_t max_subject_slices, float* pose_part,
+                                   float* pose_pp, const int4* w1, int32_t n_w1, const int2* w2, int32_t n_w2,
+                                   int32_t m, hipStream_t st);
 hipError_t launch_pose_chain(const float* pose, const float* pose_acc, float* g_pose, int32_t m,
                              hipStream_t st);
 

@@ -175,6 +175,29 @@ def test_forward_is_deterministic(ctx, mode):
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
 
 
+def test_pose_gradient_is_deterministic(ctx):
+    """The slices' pose gradients are summed in a fixed order (per workgroup
+    in fixed point, then over workgroups in two ordered levels): repeating the
+    adjoint gives the same bits, on several subjects."""
+    subs = [synth.config1(s, n_gauss=1200 + 400 * s, n_per_stack=6 + 2 * s) for s in range(3)]
+    prob = synth.concat(subs)
+    params, pose, _ = _setup(prob, seed=17)
+    g = to_dev(np.random.default_rng(18).standard_normal(prob.n_pixels).astype(np.float32))
+    ctx.svr_set_config(tile=16, batch=128, persistent=0, cutoff=3.0, forward_mode=1)
+    ctx.svr_set_geometry(prob)
+    dev = gpu_params(params, pose)
+    outs = []
+    for _ in range(3):
+        ctx.svr_project_bin(*dev)
+        grads = [torch.empty_like(x) for x in dev]
+        ctx.svr_backward(g, *grads)
+        outs.append(grads[4])
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    core, bnd = oracle.backward_band(prob, g.cpu().numpy().astype(np.float64), 3.0, BAND, params=params, pose=pose)
+    print(check_band(outs[0].cpu().numpy(), core["pose"], bnd["pose"], "pose"))
+
+
 def test_backward_with_random_upstream(ctx):
     """Adjoint alone: an arbitrary seeded upstream gradient (not a loss gradient)."""
     prob = synth.config1(1, n_gauss=1000)
