@@ -409,13 +409,13 @@ struct AdjointSums {
 // (T x T in LDS), rows outer and columns inner, with the per-row sums folded
 // in with dy (three accumulations per pixel).
 template <int T>
-__device__ inline AdjointSums adjoint_walk(const LaneBox& b, const float* g, float etau) {
+__device__ inline AdjointSums adjoint_walk(const LaneBox& b, const float* g, float etau, int stride = T) {
     const int w = max(b.x1 - b.x0 + 1, 0), h = max(b.y1 - b.y0 + 1, 0);
     const int hh = w > 0 ? h : 0;
     AdjointSums S = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const float dx0 = (float)b.x0 - b.pxl, b2a01 = 2.f * b.a01;
     float dy = (float)b.y0 - b.pyl;
-    int gr = b.y0 * T + b.x0;
+    int gr = b.y0 * stride + b.x0;
     for (int r = 0; r < hh; ++r) {
         const float zy = fmaf(b.a11 * dy, dy, b.bz), bxl = b2a01 * dy;
         float R0 = 0.f, R1 = 0.f, R2 = 0.f, dx = dx0;
@@ -424,8 +424,9 @@ __device__ inline AdjointSums adjoint_walk(const LaneBox& b, const float* g, flo
             const float gv = g[gi];
             const float e = __builtin_amdgcn_exp2f(fmaf(dx, fmaf(b.a00, dx, bxl), zy));
             const float v = e - etau;
-            S.Sa = fmaf(gv, fmaxf(v, 0.f), S.Sa);
-            const float t = (v > 0.f) ? gv * e : 0.f;
+            const float gm = (v > 0.f) ? gv : 0.f;  // g inside the cut
+            S.Sa = fmaf(gm, v, S.Sa);
+            const float t = gm * e;
             const float tx = t * dx;
             R0 += t;
             R1 += tx;
@@ -440,7 +441,7 @@ __device__ inline AdjointSums adjoint_walk(const LaneBox& b, const float* g, flo
         S.Sxy = fmaf(dy, R1, S.Sxy);
         S.Syy = fmaf(dy * dy, R0, S.Syy);
         dy += 1.f;
-        gr += T;
+        gr += stride;
     }
     return S;
 }
@@ -795,39 +796,49 @@ __global__ __launch_bounds__(256) void k_forward_chunk(RenderArgs a, const float
     const float inv_msum = (kLoss && msum[0] > 0.f) ? 1.f / msum[0] : 0.f;
     float* s_facc = reinterpret_cast<float*>(s_iacc);
 
-    // the lane's instances: tile, run head, record and box (independent loads)
+    // the lane's instances: tile, run head, record and box.  The loads come
+    // in two dependent rounds, each issued at once and without branches
+    // (indices clamped, results selected): keys (the instance's and its
+    // predecessor's) and record ids; then records, tile origins and ranges.
     int tile[NI], fin[NI], rslot[NI];
     bool head[NI];
     int4 org[NI];
     uint64_t hm[NI];
     LaneBox b[NI];
+    uint32_t key[NI], kprev[NI], rid[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int64_t inst = c0 + k * NT + tid;
-        tile[k] = -1;
-        head[k] = false;
-        org[k] = make_int4(0, 0, 0, 0);
-        if (inst < a.n_inst) {
-            const uint32_t t = a.inst_key[inst] >> kClassBits;
-            if (t < (uint32_t)a.n_tiles) {
-                tile[k] = (int)t;
-                head[k] = inst == c0 || (a.inst_key[inst - 1] >> kClassBits) != t;
-                org[k] = a.tile_org[t];
-            }
-        }
+        const int64_t ic = min(inst, a.n_inst - 1);
+        key[k] = a.inst_key[ic];
+        kprev[k] = a.inst_key[ic > 0 ? ic - 1 : 0];
+        rid[k] = a.inst_rec[ic];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    Record R[NI];
+    int2 rg[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
+        const int64_t inst = c0 + k * NT + tid;
+        const uint32_t t = inst < a.n_inst ? key[k] >> kClassBits : ~0u;
+        const bool live = t < (uint32_t)a.n_tiles;
+        tile[k] = live ? (int)t : -1;
+        head[k] = live && (inst == c0 || (kprev[k] >> kClassBits) != t);
+        R[k] = a.rec[live ? rid[k] : 0u];
+        org[k] = a.tile_org[live ? t : 0u];
+        rg[k] = a.ranges[live ? t : 0u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int64_t inst = c0 + k * NT + tid;
         b[k] = LaneBox{};
         fin[k] = -1;
         if (tile[k] >= 0) {
-            const int64_t inst = c0 + k * NT + tid;
-            const Record R = a.rec[a.inst_rec[inst]];
             const TileOrg o = tile_org(org[k]);
-            b[k] = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+            b[k] = lane_box(R[k], o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
             if (head[k]) {
-                const int2 rg = a.ranges[tile[k]];
-                const bool inside = rg.x >= c0 && rg.y <= c0 + kChunk;
+                const bool inside = rg[k].x >= c0 && rg[k].y <= c0 + kChunk;
                 fin[k] = inside ? -1 : (inst == c0 ? 0 : 1);
             }
         }
@@ -1136,14 +1147,16 @@ __global__ __launch_bounds__(256) void k_backward_tiles(RenderArgs a, const floa
 // instance's gradient to its emission slot: no cross-lane reduction and no
 // atomics, so the result is deterministic and independent of the chunking.
 template <int T>
-__global__ __launch_bounds__(256) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
-                                                 const float* __restrict__ grad_scale,
-                                                 float4* __restrict__ inst_grad) {
-    constexpr int NT = 256, NW = 4, NI = kBwdPer, kChunk = NT * NI;
-    constexpr int KT = (2048 * NI / (T * T)) > 0 ? 2048 * NI / (T * T) : 1;  // tiles staged per pass (8 NI KB)
+__global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
+                                                    const float* __restrict__ grad_scale,
+                                                    float4* __restrict__ inst_grad) {
+    constexpr int NT = 256, NI = kBwdPer, kChunk = NT * NI;
+    constexpr int KT = 2048 / (T * T) > 0 ? 2048 / (T * T) : 1;  // tiles staged (8 KB)
+    constexpr int Q = T * T / 4;                                   // float4 per tile
+    constexpr int NS = (KT * Q + NT - 1) / NT;                     // staged float4 per thread
     __shared__ __align__(16) float s_g[KT * T * T];
-    __shared__ int s_wsum[NI][NW];
-    __shared__ int4 s_org[KT];  // the pass's tiles (TileOrg packing)
+    __shared__ int s_wsum[NI][4];
+    __shared__ int4 s_org[KT];  // a pass's tiles (TileOrg packing)
     const int tid = threadIdx.x;
     const int64_t n_chunks = (a.n_inst + kChunk - 1) / kChunk;
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
@@ -1151,74 +1164,120 @@ __global__ __launch_bounds__(256) void k_backward(RenderArgs a, const float* __r
     const int64_t c0 = chunk * kChunk;
     const float tau2k = SVR_KZ * a.tau2;
     const float scale = grad_scale ? grad_scale[0] : 1.f;
-    const uint32_t tf = a.inst_key[c0] >> kClassBits;
-    const uint32_t tl = a.inst_key[min(c0 + kChunk, a.n_inst) - 1] >> kClassBits;
-    const bool fast = tf < (uint32_t)a.n_tiles && tl < (uint32_t)a.n_tiles && tl - tf < (uint32_t)KT;
-    if (fast)
-        for (uint32_t t = tf; t <= tl; ++t)
-            stage_tile<T, NT>(grad_pred, tile_org(a.tile_org[t]), s_g + (t - tf) * T * T);
 
-    // the lane's instances: tile (-1 past the end or for emission padding),
-    // whether each heads a run of its tile in the chunk, record and box
-    int tile[NI], rslot[NI];
-    bool head[NI];
-    int4 org[NI];
-    uint64_t hm[NI];
-    uint32_t e_slot[NI];
-    LaneBox b[NI];
+    // Loads in three dependent rounds, each issued at once and without
+    // branches (indices clamped, results selected): (1) the chunk's first and
+    // last keys and the lane's keys, record ids and emission slots; (2) the
+    // lane's records and tile origins, and the origins of the tiles to stage;
+    // (3) the staged upstream gradients.
+    const uint32_t kf = a.inst_key[c0], kl = a.inst_key[min(c0 + kChunk, a.n_inst) - 1];
+    uint32_t key[NI], rid[NI], e_slot[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-        const int64_t inst = c0 + k * NT + tid;
-        tile[k] = -1;
-        head[k] = false;
-        org[k] = make_int4(0, 0, 0, 0);
-        if (inst < a.n_inst) {
-            const uint32_t t = a.inst_key[inst] >> kClassBits;
-            if (t < (uint32_t)a.n_tiles) {
-                tile[k] = (int)t;
-                head[k] = inst == c0 || (a.inst_key[inst - 1] >> kClassBits) != t;
-                org[k] = a.tile_org[t];
-            }
-        }
+        const int64_t ic = min(c0 + k * NT + tid, a.n_inst - 1);
+        key[k] = a.inst_key[ic];
+        rid[k] = a.inst_rec[ic];
+        e_slot[k] = a.inst_idx[ic];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t tf = kf >> kClassBits, tl = kl >> kClassBits;
+    const bool fast = tf < (uint32_t)a.n_tiles && tl < (uint32_t)a.n_tiles && tl - tf < (uint32_t)KT;
+    // staged float4 q: tile q / Q, row and column of q % Q (at T = 32 a
+    // thread's s-th float4 lies in the chunk's s-th tile, whose origin is
+    // then uniform).  Outside the fast case tf and tl may be padding keys
+    // (above every tile id): stage loads then read tile 0, a real tile, and
+    // are unused.
+    int4 ov[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int sl = Q >= NT ? s : (tid + s * NT) / Q;
+        ov[s] = a.tile_org[fast ? min(tf + (uint32_t)sl, tl) : 0u];
+    }
+    uint32_t t[NI];
+    Record R[NI];
+    int4 org[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-        b[k] = LaneBox{};
-        e_slot[k] = 0;
-        if (tile[k] >= 0) {
-            const int64_t inst = c0 + k * NT + tid;
-            const Record R = a.rec[a.inst_rec[inst]];
-            e_slot[k] = a.inst_idx[inst];
-            const TileOrg o = tile_org(org[k]);
-            b[k] = lane_box(R, o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+        t[k] = c0 + k * NT + tid < a.n_inst ? key[k] >> kClassBits : ~0u;
+        const bool live = t[k] < (uint32_t)a.n_tiles;
+        R[k] = a.rec[live ? rid[k] : 0u];
+        org[k] = a.tile_org[live ? t[k] : 0u];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // a tile whole inside its slice and 16-byte aligned (the usual case)
+    // takes one 16-byte load per float4, others four clamped loads
+    float4 sv[NS];
+    const int nq = fast ? (int)(tl - tf + 1) * Q : 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int q = tid + s * NT;
+        const int64_t base = (int64_t)(((uint64_t)(uint32_t)ov[s].y << 32) | (uint64_t)(uint32_t)ov[s].x);
+        const int stride = ov[s].w & 0xffff, vw = (ov[s].w >> 16) & 0xff, vh = (int)((uint32_t)ov[s].w >> 24);
+        const int qq = q % Q, px = (qq % (T / 4)) * 4, py = qq / (T / 4);
+        const float* row = grad_pred + base + (int64_t)min(py, vh - 1) * stride;
+        const bool use = q < nq;
+        if (vw == T && vh == T && ((base | stride) & 3) == 0) {
+            const float4 v = *reinterpret_cast<const float4*>(row + px);
+            sv[s] = use ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            const float x = row[min(px, vw - 1)], y = row[min(px + 1, vw - 1)];
+            const float z = row[min(px + 2, vw - 1)], w = row[min(px + 3, vw - 1)];
+            const bool in = use && py < vh;
+            sv[s] = make_float4(in && px < vw ? x : 0.f, in && px + 1 < vw ? y : 0.f, in && px + 2 < vw ? z : 0.f,
+                                in && px + 3 < vw ? w : 0.f);
         }
     }
     if (fast) {
-        __syncthreads();  // the staged gradients are visible
+        // float4 q of the staged tiles sits at s_g[4 q] (tile q / Q, row and
+        // column of q % Q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int q = tid + s * NT;
+            if (q < nq) *reinterpret_cast<float4*>(s_g + 4 * q) = sv[s];
+        }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < NI; ++k)
-            if (tile[k] >= 0)
-                store_adjoint(adjoint_walk<T>(b[k], s_g + (tile[k] - (int)tf) * T * T, a.etau), b[k], scale,
-                              inst_grad, e_slot[k]);
+            if (t[k] < (uint32_t)a.n_tiles) {
+                const TileOrg o = tile_org(org[k]);
+                const LaneBox b = lane_box(R[k], o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+                store_adjoint(adjoint_walk<T>(b, s_g + (t[k] - tf) * T * T, a.etau), b, scale, inst_grad,
+                              e_slot[k]);
+            }
         return;
     }
+    // the chunk spans more than KT tiles (rare): its runs of tiles are staged
+    // in passes of KT; each lane's record and tile origin are reloaded
+    // (cached) when its pass comes rather than held in registers
+    int tile[NI], rslot[NI];
+    bool head[NI];
+    uint64_t hm[NI];
 #pragma unroll
-    for (int k = 0; k < NI; ++k) hm[k] = __ballot(head[k]);
+    for (int k = 0; k < NI; ++k) {
+        const int64_t inst = c0 + k * NT + tid;
+        const bool live = t[k] < (uint32_t)a.n_tiles;
+        tile[k] = live ? (int)t[k] : -1;
+        head[k] = live && (inst == c0 || (a.inst_key[inst - 1] >> kClassBits) != t[k]);
+        hm[k] = __ballot(head[k]);
+    }
     const int nd = chunk_runs<NI>(hm, tile, head, s_wsum, rslot);
     for (int p0 = 0; p0 < nd; p0 += KT) {
         const int np = min(KT, nd - p0);
         if (p0 > 0) __syncthreads();  // the previous pass is done with LDS
 #pragma unroll
         for (int k = 0; k < NI; ++k)
-            if (head[k] && rslot[k] >= p0 && rslot[k] < p0 + np) s_org[rslot[k] - p0] = org[k];
+            if (head[k] && rslot[k] >= p0 && rslot[k] < p0 + np) s_org[rslot[k] - p0] = a.tile_org[t[k]];
         __syncthreads();
         for (int sl = 0; sl < np; ++sl) stage_tile<T, NT>(grad_pred, tile_org(s_org[sl]), s_g + sl * T * T);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NI; ++k)
-            if (rslot[k] >= p0 && rslot[k] < p0 + np)
-                store_adjoint(adjoint_walk<T>(b[k], s_g + (rslot[k] - p0) * T * T, a.etau), b[k], scale, inst_grad,
+            if (rslot[k] >= p0 && rslot[k] < p0 + np) {
+                const TileOrg o = tile_org(a.tile_org[t[k]]);
+                const LaneBox b = lane_box(a.rec[rid[k]], o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+                store_adjoint(adjoint_walk<T>(b, s_g + (rslot[k] - p0) * T * T, a.etau), b, scale, inst_grad,
                               e_slot[k]);
+            }
     }
 }
 
