@@ -44,6 +44,11 @@ FLOP_CULL_CAND = 25.0     # plane test per (slice, Gaussian) candidate
 FLOP_CULL_REC = 150.0     # projection per kept record
 FLOP_PROJ_BWD_REC = 400.0
 BYTES_SORT_INST_PASS = 20.0   # upsweep key read 4 + downsweep key/value read 8 + write 8
+# adjoint tile kernel, per instance: key, record id and emission slot read (12),
+# record payload read (28: centre, beta', amplitude, conic), seven sums
+# written (28); per slice pixel: its upstream gradient read once (4)
+BYTES_BWD_INST = 68.0
+BYTES_BWD_PIXEL = 4.0
 BYTES_EMIT = (32.0, 8.0)      # per record, per instance
 # Normalised Top-K model (Eqs. 2 and 5), per (pixel, neighbour) pair: forward
 # 57 FLOP + 1 exp (Sigma_obs, cofactor inverse, quadratic form, sums); adjoint
@@ -130,8 +135,11 @@ def stage_roofline(stage, ms, st, n_incut):
         w = FLOP_FWD_PAIR * n_incut
         return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
     if stage == "backward_tile":
-        w = FLOP_BWD_PAIR * n_incut
-        return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
+        # bound by its memory accesses, not by its arithmetic: with the pixel
+        # walk (all of its FP32 work) removed the kernel keeps 91 % of its
+        # time on the head workload; the FP32 figure is stage_alu's
+        w = BYTES_BWD_INST * st["n_instances"] + BYTES_BWD_PIXEL * st["n_pixels"]
+        return "hbm", w / sec / 1e9, PEAK_HBM / 1e9, "GB/s", w
     if stage == "cull_count":
         w = FLOP_CULL_CAND * st["n_candidates"] + FLOP_CULL_REC * st["n_records"]
         return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
@@ -151,6 +159,17 @@ def stage_roofline(stage, ms, st, n_incut):
         w = FLOP_TOPK_BWD_PAIR * n_incut
         return "alu", w / sec / 1e12, PEAK_FP32 / 1e12, "TFLOP/s", w
     return None
+
+
+def stage_alu(stage, ms, n_incut):
+    """FP32 rate of a tile kernel's algorithmic arithmetic (TFLOP/s, fraction
+    of the FP32 vector peak), whatever bounds it; None for other stages."""
+    per = {"forward_tile": FLOP_FWD_PAIR, "backward_tile": FLOP_BWD_PAIR}.get(stage)
+    if per is None:
+        return None
+    achieved = per * n_incut / (ms / 1e3) / 1e12
+    return dict(achieved=round(achieved, 4), peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                frac=round(achieved / (PEAK_FP32 / 1e12), 6), work_per_launch=per * n_incut)
 
 
 def cpu_baseline(prob, params, pose, target, budget_s=15.0):
@@ -414,6 +433,9 @@ def main():
         roofline = dict(bound=bound, achieved=round(achieved, 4), peak=peak, unit=unit,
                         frac=round(achieved / peak, 6), traffic=traffic, kernel=dominant,
                         avg_ms=round(dom_ms, 5), work_per_launch=work)
+        alu = stage_alu(dominant, dom_ms, n_incut)
+        if alu and bound != "alu":
+            roofline["alu"] = alu
 
     sequential = None
     if args.workload == "batched":

@@ -1157,6 +1157,7 @@ __global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* 
     __shared__ __align__(16) float s_g[KT * T * T];
     __shared__ int s_wsum[NI][4];
     __shared__ int4 s_org[KT];  // a pass's tiles (TileOrg packing)
+    __shared__ int s_other[4];  // per wave: a lane's tile is neither tf nor tl
     const int tid = threadIdx.x;
     const int64_t n_chunks = (a.n_inst + kChunk - 1) / kChunk;
     const int64_t chunk = xcd_tile(blockIdx.x, (int)n_chunks);
@@ -1180,18 +1181,25 @@ __global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* 
         e_slot[k] = a.inst_idx[ic];
     }
     __builtin_amdgcn_sched_barrier(0);
+    // Staged slots: the chunk's tiles tf..tl when they are at most KT
+    // consecutive ids ("range"), else tf and tl in slots 0 and 1 ("pair"),
+    // which serves when every instance's tile is one of the two (checked
+    // after the staging barrier); otherwise the runs of tiles go in passes.
     const uint32_t tf = kf >> kClassBits, tl = kl >> kClassBits;
-    const bool fast = tf < (uint32_t)a.n_tiles && tl < (uint32_t)a.n_tiles && tl - tf < (uint32_t)KT;
-    // staged float4 q: tile q / Q, row and column of q % Q (at T = 32 a
-    // thread's s-th float4 lies in the chunk's s-th tile, whose origin is
-    // then uniform).  Outside the fast case tf and tl may be padding keys
-    // (above every tile id): stage loads then read tile 0, a real tile, and
-    // are unused.
+    const bool valid_ends = tf < (uint32_t)a.n_tiles && tl < (uint32_t)a.n_tiles;
+    const bool range = valid_ends && tl - tf < (uint32_t)KT;
+    const bool pair = valid_ends && !range;
+    const int nslot = range ? (int)(tl - tf) + 1 : (pair ? 2 : 0);
+    // staged float4 q: slot q / Q, row and column of q % Q (at T = 32 a
+    // thread's s-th float4 lies in slot s, whose origin is then uniform).
+    // Without slots tf and tl may be padding keys (above every tile id):
+    // stage loads then read tile 0, a real tile, and are unused.
     int4 ov[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int sl = Q >= NT ? s : (tid + s * NT) / Q;
-        ov[s] = a.tile_org[fast ? min(tf + (uint32_t)sl, tl) : 0u];
+        const uint32_t ts = range ? min(tf + (uint32_t)sl, tl) : (sl == 0 ? tf : tl);
+        ov[s] = a.tile_org[nslot > 0 ? ts : 0u];
     }
     uint32_t t[NI];
     Record R[NI];
@@ -1207,7 +1215,7 @@ __global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* 
     // a tile whole inside its slice and 16-byte aligned (the usual case)
     // takes one 16-byte load per float4, others four clamped loads
     float4 sv[NS];
-    const int nq = fast ? (int)(tl - tf + 1) * Q : 0;
+    const int nq = nslot * Q;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int q = tid + s * NT;
@@ -1227,28 +1235,37 @@ __global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* 
                                 in && px + 3 < vw ? w : 0.f);
         }
     }
-    if (fast) {
-        // float4 q of the staged tiles sits at s_g[4 q] (tile q / Q, row and
+    if (nslot > 0) {
+        // float4 q of the staged slots sits at s_g[4 q] (slot q / Q, row and
         // column of q % Q)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int q = tid + s * NT;
             if (q < nq) *reinterpret_cast<float4*>(s_g + 4 * q) = sv[s];
         }
-        __syncthreads();
+        bool other = false;
 #pragma unroll
-        for (int k = 0; k < NI; ++k)
-            if (t[k] < (uint32_t)a.n_tiles) {
-                const TileOrg o = tile_org(org[k]);
-                const LaneBox b = lane_box(R[k], o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
-                store_adjoint(adjoint_walk<T>(b, s_g + (t[k] - tf) * T * T, a.etau), b, scale, inst_grad,
-                              e_slot[k]);
-            }
-        return;
+        for (int k = 0; k < NI; ++k) other |= t[k] < (uint32_t)a.n_tiles && t[k] != tf && t[k] != tl;
+        const bool wave_other = __any(other);
+        if ((tid & 63) == 0) s_other[tid >> 6] = wave_other ? 1 : 0;
+        __syncthreads();
+        if (range || !(s_other[0] | s_other[1] | s_other[2] | s_other[3])) {  // uniform
+#pragma unroll
+            for (int k = 0; k < NI; ++k)
+                if (t[k] < (uint32_t)a.n_tiles) {
+                    const TileOrg o = tile_org(org[k]);
+                    const LaneBox b = lane_box(R[k], o.x0, o.y0, o.vw - 1, o.vh - 1, tau2k);
+                    const int slot = range ? (int)(t[k] - tf) : (t[k] == tf ? 0 : 1);
+                    store_adjoint(adjoint_walk<T>(b, s_g + slot * T * T, a.etau), b, scale, inst_grad, e_slot[k]);
+                }
+            return;
+        }
     }
-    // the chunk spans more than KT tiles (rare): its runs of tiles are staged
-    // in passes of KT; each lane's record and tile origin are reloaded
-    // (cached) when its pass comes rather than held in registers
+    // the chunk holds more than two tiles that are not KT consecutive ids
+    // (rare): its runs of tiles are staged in passes of KT (the barrier in
+    // chunk_runs orders them after the staging above); each lane's record
+    // and tile origin are reloaded (cached) when its pass comes rather than
+    // held in registers
     int tile[NI], rslot[NI];
     bool head[NI];
     uint64_t hm[NI];

@@ -19,12 +19,27 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout.strip() == ""  # no JSON line
 
 
-@pytest.mark.parametrize("stage,per_pair", [("backward_tile", bench.FLOP_BWD_PAIR), ("forward_tile", bench.FLOP_FWD_PAIR)])
-def test_stage_roofline_is_work_over_time(stage, per_pair):
-    bound, achieved, peak, unit, work = bench.stage_roofline(stage, 0.5, {}, 1e8)
+def test_forward_roofline_is_flops_over_time():
+    bound, achieved, peak, unit, work = bench.stage_roofline("forward_tile", 0.5, {}, 1e8)
     assert bound == "alu" and unit == "TFLOP/s" and peak == pytest.approx(157.3)
-    assert work == pytest.approx(per_pair * 1e8)
-    assert achieved == pytest.approx(per_pair * 1e8 / 0.5e-3 / 1e12)
+    assert work == pytest.approx(bench.FLOP_FWD_PAIR * 1e8)
+    assert achieved == pytest.approx(bench.FLOP_FWD_PAIR * 1e8 / 0.5e-3 / 1e12)
+
+
+def test_adjoint_roofline_is_algorithmic_bytes_over_time():
+    st = {"n_instances": 7.5e6, "n_pixels": 8388608}
+    bound, achieved, peak, unit, work = bench.stage_roofline("backward_tile", 0.25, st, 1e8)
+    assert bound == "hbm" and unit == "GB/s" and peak == pytest.approx(8000.0)
+    assert work == pytest.approx(68.0 * 7.5e6 + 4.0 * 8388608)
+    assert achieved == pytest.approx(work / 0.25e-3 / 1e9)
+
+
+@pytest.mark.parametrize("stage,per_pair", [("backward_tile", bench.FLOP_BWD_PAIR), ("forward_tile", bench.FLOP_FWD_PAIR)])
+def test_tile_kernels_also_report_their_fp32_rate(stage, per_pair):
+    alu = bench.stage_alu(stage, 0.5, 1e8)
+    assert alu["peak"] == pytest.approx(157.3) and alu["work_per_launch"] == pytest.approx(per_pair * 1e8)
+    assert alu["achieved"] == pytest.approx(per_pair * 1e8 / 0.5e-3 / 1e12, rel=1e-4)
+    assert bench.stage_alu("sort", 0.5, 1e8) is None
 
 
 def test_traffic_record_needs_matching_stage_tile_and_workload():
