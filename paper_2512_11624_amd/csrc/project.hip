@@ -603,32 +603,62 @@ __global__ __launch_bounds__(kBlock) void k_project_backward(
         }
         float acc[kGAcc];
         for (int q = 0; q < kGAcc; ++q) acc[q] = 0.f;
-        const Record R = valid ? rec[R0 + lr] : Record{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
-        const int i = __float_as_int(R.r1.w);
-        if (valid && i >= si.s_begin && i < si.s_end) {
+        // Loads in two rounds, each issued at once without branches (indices
+        // clamped, results selected): the record and its instance range, then
+        // the first two instance gradients (most records have one or two) and
+        // the slice's geometry and pose.
+        const int64_t rl = R0 + min(lr, nrec_blk - 1);
+        const Record Rl = rec[rl];
+        const int2 ri = rec_inst[rl];
+        __builtin_amdgcn_sched_barrier(0);
+        const int i = valid ? __float_as_int(Rl.r1.w) : -1;
+        const bool live = valid && i >= si.s_begin && i < si.s_end;
+        const int is_ = live ? i : si.s_begin;
+        const int64_t e0 = ri.x, ecnt = live ? ri.y : 0;
+        const int64_t ea = n_inst > 0 ? min(max(e0, (int64_t)0), n_inst - 1) : 0;
+        const int64_t eb = n_inst > 0 ? min(max(e0 + 1, (int64_t)0), n_inst - 1) : 0;
+        float4 u0 = make_float4(0.f, 0.f, 0.f, 0.f), w0 = u0, u1 = u0, w1 = u0;
+        if (n_inst > 0) {  // uniform
+            u0 = inst_grad[2 * ea];
+            w0 = inst_grad[2 * ea + 1];
+            u1 = inst_grad[2 * eb];
+            w1 = inst_grad[2 * eb + 1];
+        }
+        const SlicePose sp = a.pose[is_];
+        const float3 sig2 = make_float3(a.geo[is_].sig2[0], a.geo[is_].sig2[1], a.geo[is_].sig2[2]);
+        const float sdx = a.geo[is_].dx, sdy = a.geo[is_].dy;
+        __builtin_amdgcn_sched_barrier(0);
+        if (live) {
             GAct ga;  // only the fields the projection and its adjoint read
             for (int k = 0; k < 3; ++k) ga.mu[k] = s_act[k][g];
             for (int k = 0; k < 6; ++k) ga.S[k] = s_act[3 + k][g];
             ga.lsum = s_act[9][g];
             ga.c = s_act[10][g];
-            const int2 ri = rec_inst[R0 + lr];
+            // instance sums in slot order (the first two from the loads above)
             float G[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int64_t e = ri.x; e < (int64_t)ri.x + ri.y && e < n_inst; ++e) {
+            if (ecnt >= 1 && e0 >= 0 && e0 < n_inst) {
+                G[0] += u0.x; G[1] += u0.y; G[2] += u0.z; G[3] += u0.w;
+                G[4] += w0.x; G[5] += w0.y; G[6] += w0.z;
+            }
+            if (ecnt >= 2 && e0 + 1 < n_inst) {
+                G[0] += u1.x; G[1] += u1.y; G[2] += u1.z; G[3] += u1.w;
+                G[4] += w1.x; G[5] += w1.y; G[6] += w1.z;
+            }
+            for (int64_t e = e0 + 2; e < e0 + ecnt && e < n_inst; ++e) {
                 const float4 u = inst_grad[2 * e], w = inst_grad[2 * e + 1];
                 G[0] += u.x; G[1] += u.y; G[2] += u.z; G[3] += u.w;
                 G[4] += w.x; G[5] += w.y; G[6] += w.z;
             }
-            const SliceGeo& sg = a.geo[i];
-            const SlicePose& sp = a.pose[i];
             Proj p;
-            project(ga, sp, sg.sig2, tau2, p);
+            const float sg2[3] = {sig2.x, sig2.y, sig2.z};
+            project(ga, sp, sg2, tau2, p);
             const float is = 1.f / p.s22;
             // stored units -> natural units
             const float dbeta = SVR_KZ * G[1];
-            const float du0 = G[2] / sg.dx, du1 = G[3] / sg.dy;
-            const float ga00 = SVR_KZ * sg.dx * sg.dx * G[4];
-            const float ga01 = 0.5f * SVR_KZ * sg.dx * sg.dy * G[5];
-            const float ga11 = SVR_KZ * sg.dy * sg.dy * G[6];
+            const float du0 = G[2] / sdx, du1 = G[3] / sdy;
+            const float ga00 = SVR_KZ * sdx * sdx * G[4];
+            const float ga01 = 0.5f * SVR_KZ * sdx * sdy * G[5];
+            const float ga11 = SVR_KZ * sdy * sdy * G[6];
             // A = C^-1  ->  G_C = -A G_A A
             const float t00 = p.A00 * ga00 + p.A01 * ga01, t01 = p.A00 * ga01 + p.A01 * ga11;
             const float t10 = p.A01 * ga00 + p.A11 * ga01, t11 = p.A01 * ga01 + p.A11 * ga11;
