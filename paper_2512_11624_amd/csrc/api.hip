@@ -72,6 +72,7 @@ struct svr_ctx {
     // device tables
     DevBuf<SliceGeo> d_geo;
     DevBuf<SlicePose> d_pose;
+    DevBuf<SlicePlane> d_plane;
     DevBuf<SubjectInfo> d_subj;
     DevBuf<GaussBlock> d_blocks;
     DevBuf<int32_t> d_tile_slice;
@@ -339,6 +340,7 @@ int build_tables(svr_ctx* c) {
     HIPCHK(c, hipStreamSynchronize(st));
     HIPCHK(c, ensure(c->d_geo, geo.size()));
     HIPCHK(c, ensure(c->d_pose, geo.size()));
+    HIPCHK(c, ensure(c->d_plane, geo.size()));
     HIPCHK(c, ensure(c->d_subj, subj.size()));
     HIPCHK(c, ensure(c->d_blocks, blocks.size()));
     HIPCHK(c, ensure(c->d_tile_slice, tile_slice.size()));
@@ -424,6 +426,7 @@ ProjectArgs project_args(svr_ctx* c) {
     a.amp = c->params.amp;
     a.geo = c->d_geo.p;
     a.pose = c->d_pose.p;
+    a.plane = c->d_plane.p;
     a.subj = c->d_subj.p;
     a.blocks = c->d_blocks.p;
     a.n_blocks = c->n_blocks;
@@ -518,7 +521,7 @@ int project_bin_impl(svr_ctx* c, const svr_params* p) {
     }
     {
         StageScope sc(c, ST_SLICE_POSE);
-        HIPCHK(c, launch_slice_pose(c->d_geo.p, p->pose, c->d_pose.p, c->M, st));
+        HIPCHK(c, launch_slice_pose(c->d_geo.p, p->pose, c->d_pose.p, c->M, st, c->d_plane.p));
     }
     HIPCHK(c, ensure(c->d_smask, (size_t)std::max<int64_t>(c->N, 1) * (size_t)std::max((c->max_subject_slices + 31) / 32, 1)));
     ProjectArgs pa = project_args(c);
@@ -711,7 +714,7 @@ int svr_ctx_destroy(svr_ctx* c) {
     if (!c->host_only) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
-        release(c->d_geo); release(c->d_pose); release(c->d_subj); release(c->d_blocks);
+        release(c->d_geo); release(c->d_pose); release(c->d_plane); release(c->d_subj); release(c->d_blocks);
         release(c->d_tile_slice); release(c->d_tile_org); release(c->d_counts); release(c->d_offsets); release(c->d_scan_tmp);
         release(c->d_totals); release(c->d_rec); release(c->d_rec_inst); release(c->d_inst_grad);
         release(c->d_idx); release(c->d_idx2); release(c->d_keys);

@@ -71,14 +71,16 @@ __device__ inline void activate_dummy(GAct& g) {
 }
 
 // Cheap plane test: beta = m_z^2 / s_zz <= T^2.
-__device__ inline bool plane_pass(const GAct& g, const SlicePose& sp, float sig2z, float tau2) {
-    const float w0 = g.mu[0] - sp.t[0], w1 = g.mu[1] - sp.t[1], w2 = g.mu[2] - sp.t[2];
-    const float n0 = sp.R[2], n1 = sp.R[5], n2 = sp.R[8];
-    const float mz = n0 * w0 + n1 * w1 + n2 * w2;
-    const float sn0 = g.S[0] * n0 + g.S[1] * n1 + g.S[2] * n2;
-    const float sn1 = g.S[1] * n0 + g.S[3] * n1 + g.S[4] * n2;
-    const float sn2 = g.S[2] * n0 + g.S[4] * n1 + g.S[5] * n2;
-    const float szz = n0 * sn0 + n1 * sn1 + n2 * sn2 + sig2z;
+// S = (S00, S01, S02, S11, S12, S22); the plane's coefficients turn m_z and
+// S'_zz into three and six multiply-adds.
+__device__ inline bool plane_pass(const GAct& g, const SlicePlane& pl, float tau2) {
+    const float mz = fmaf(pl.n[2], g.mu[2], fmaf(pl.n[1], g.mu[1], pl.n[0] * g.mu[0])) - pl.d;
+    float szz = fmaf(g.S[4], pl.q[5], pl.sig2z);
+    szz = fmaf(g.S[2], pl.q[4], szz);
+    szz = fmaf(g.S[1], pl.q[3], szz);
+    szz = fmaf(g.S[5], pl.q[2], szz);
+    szz = fmaf(g.S[3], pl.q[1], szz);
+    szz = fmaf(g.S[0], pl.q[0], szz);
     return mz * mz <= tau2 * szz;
 }
 
@@ -187,7 +189,7 @@ __device__ inline Record make_record(const Proj& p, const SliceGeo& sg, float c,
 // K2: slice pose.  R = Exp(omega) R0 (Rodrigues), t = t0 + tau.
 // ---------------------------------------------------------------------------
 __global__ void k_slice_pose(const SliceGeo* __restrict__ geo, const float* __restrict__ pose,
-                             SlicePose* __restrict__ out, int32_t m) {
+                             SlicePose* __restrict__ out, SlicePlane* __restrict__ plane, int32_t m) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
     const float wx = pose[6 * i], wy = pose[6 * i + 1], wz = pose[6 * i + 2];
@@ -218,6 +220,23 @@ __global__ void k_slice_pose(const SliceGeo* __restrict__ geo, const float* __re
     sp.w[2] = wz;
     sp.pad = 0.f;
     out[i] = sp;
+    if (plane) {
+        SlicePlane pl;
+        const float n0 = sp.R[2], n1 = sp.R[5], n2 = sp.R[8];
+        pl.n[0] = n0;
+        pl.n[1] = n1;
+        pl.n[2] = n2;
+        pl.d = fmaf(n2, sp.t[2], fmaf(n1, sp.t[1], n0 * sp.t[0]));
+        pl.q[0] = n0 * n0;
+        pl.q[1] = n1 * n1;
+        pl.q[2] = n2 * n2;
+        pl.q[3] = 2.f * n0 * n1;
+        pl.q[4] = 2.f * n0 * n2;
+        pl.q[5] = 2.f * n1 * n2;
+        pl.sig2z = g.sig2[2];
+        pl.pad = 0.f;
+        plane[i] = pl;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -304,10 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_cull(ProjectArgs a, int2* __restrict
 
     uint32_t word = 0;
     for (int i = si.s_begin; i < si.s_end; ++i) {
-        const SlicePose& sp = a.pose[i];
-        const float sig2z = a.geo[i].sig2[2];
         const int li = i - si.s_begin;
-        if (valid && plane_pass(g, sp, sig2z, tau2)) {
+        if (valid && plane_pass(g, a.plane[i], tau2)) {
             s_list[cnt][threadIdx.x] = (uint16_t)li;
             ++cnt;
             word |= 1u << (li & 31);
@@ -887,9 +904,9 @@ __global__ void k_pose_chain(const float* __restrict__ pose, const float* __rest
 }  // namespace
 
 hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,
-                             hipStream_t st) {
+                             hipStream_t st, SlicePlane* plane) {
     if (m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_slice_pose, dim3((m + 127) / 128), dim3(128), 0, st, geo, pose, out, m);
+    hipLaunchKernelGGL(k_slice_pose, dim3((m + 127) / 128), dim3(128), 0, st, geo, pose, out, plane, m);
     return hipGetLastError();
 }
 

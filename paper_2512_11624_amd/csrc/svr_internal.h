@@ -35,6 +35,19 @@ struct SlicePose {
     float pad;
 };
 
+// Per-iteration plane-test coefficients of a slice (built with its pose):
+// unit normal n = R e_z, offset d = n . t, the products of n's components
+// (n0^2, n1^2, n2^2, 2 n0 n1, 2 n0 n2, 2 n1 n2) and the through-plane PSF
+// variance, so that m_z = n . mu - d and S'_zz = n^T Sigma n + sig2z cost
+// three and six multiply-adds per (slice, Gaussian) candidate.
+struct SlicePlane {
+    float n[3];
+    float d;
+    float q[6];
+    float sig2z;
+    float pad;
+};
+
 struct SubjectInfo {
     int64_t g_begin, g_end;
     int32_t s_begin, s_end;
@@ -142,6 +155,7 @@ struct ProjectArgs {
     const float* amp;
     const SliceGeo* geo;
     const SlicePose* pose;
+    const SlicePlane* plane;  // per slice, with pose
     const SubjectInfo* subj;
     const GaussBlock* blocks;
     int32_t n_blocks;
@@ -153,8 +167,9 @@ struct ProjectArgs {
     int32_t smask_words;
 };
 
+// plane (may be NULL): the slices' plane-test coefficients
 hipError_t launch_slice_pose(const SliceGeo* geo, const float* pose, SlicePose* out, int32_t m,
-                             hipStream_t st);
+                             hipStream_t st, SlicePlane* plane = nullptr);
 hipError_t launch_cull_count(const ProjectArgs& a, int2* counts, hipStream_t st);
 // fallback: int per Gaussian block (scratch, written by the first kernel)
 // overflow (may be NULL): when *overflow != 0 the emission writes nothing.
