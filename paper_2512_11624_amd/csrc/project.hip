@@ -432,6 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
         Box bx;
         bx.nonempty = false;
         int nt = 0, sl = -1;
+        int tbase = 0, ntx = 0;  // the slice's first tile and tiles per row, in registers: a load between
+                                 // the instance stores below would wait for the stores too
         const SliceGeo* sgp = nullptr;
         if (e != 0xffffffffu) {
             const int jl = (int)(e >> 16);
@@ -445,6 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
             Proj p;
             project(gj, a.pose[sl], sgp->sig2, tau2, p);
             bx = pixel_box(p, *sgp, tau2);
+            tbase = sgp->tile_base;
+            ntx = sgp->ntx;
             if (bx.nonempty) {
                 R = make_record(p, *sgp, gj.c, sl);
                 nt = (bx.kx1 / T - bx.kx0 / T + 1) * (bx.ky1 / T - bx.ky0 / T + 1);
@@ -479,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(ProjectArgs a, const int2* __re
                 const int ch = min(bx.ky1, ty * T + T - 1) - max(bx.ky0, ty * T) + 1;
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const int cw = min(bx.kx1, tx * T + T - 1) - max(bx.kx0, tx * T) + 1;
-                    keys[o] = ((uint32_t)(sgp->tile_base + ty * sgp->ntx + tx) << kClassBits) | shape_class(cw, ch);
+                    keys[o] = ((uint32_t)(tbase + ty * ntx + tx) << kClassBits) | shape_class(cw, ch);
                     vals[o] = (uint32_t)(R0 + t);
                     ++o;
                 }
