@@ -701,15 +701,27 @@ __device__ inline void finish_tile(const RenderArgs& a, int tile, const float* a
                                    float* __restrict__ tile_sse, float* s_red) {
     const int tid = threadIdx.x;
     float sq = 0.f;
-    for (int p = tid; p < T * T; p += NT) {
-        const int px = p % T, py = p / T;
-        if (px < o.vw && py < o.vh) {
-            const int64_t pi = o.base + (int64_t)py * o.stride + px;
-            const float y = acc[p];
-            pred[pi] = y;
-            if (kLoss) loss_term(a.loss_kind, mask[pi], y - target[pi], inv_msum, sq, grad ? grad + pi : nullptr);
-        }
+    // every target and mask load of the thread is issued before its first
+    // store: a load issued after a store waits for the store as well
+    constexpr int PPT = (T * T + NT - 1) / NT;
+    float tv[PPT], mv[PPT];
+    int64_t pix[PPT];
+    bool in[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int p = tid + k * NT, px = p % T, py = p / T;
+        in[k] = p < T * T && px < o.vw && py < o.vh;
+        pix[k] = in[k] ? o.base + (int64_t)py * o.stride + px : o.base;  // the tile's first pixel is inside
+        tv[k] = kLoss ? target[pix[k]] : 0.f;
+        mv[k] = kLoss ? mask[pix[k]] : 0.f;
     }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+        if (in[k]) {
+            const float y = acc[tid + k * NT];
+            pred[pix[k]] = y;
+            if (kLoss) loss_term(a.loss_kind, mv[k], y - tv[k], inv_msum, sq, grad ? grad + pix[k] : nullptr);
+        }
     if (kLoss) {
         for (int o2 = 32; o2 > 0; o2 >>= 1) sq += __shfl_xor(sq, o2, 64);
         if ((tid & 63) == 0) s_red[tid >> 6] = sq;
