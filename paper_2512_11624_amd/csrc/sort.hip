@@ -45,10 +45,14 @@ __global__ __launch_bounds__(kThreads) void k_upsweep(const uint32_t* __restrict
         for (int j = 0; j < D; ++j) s_h[q][threadIdx.x * D + j] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kItems;
-    for (int k = 0; k < kIters; ++k) {
-        const int64_t i = base + (int64_t)k * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[w][(keys[i] >> shift) & dmask], 1);
-    }
+    // all of the thread's key loads in flight at once (index clamped, result
+    // unused past the end), then the counts
+    uint32_t kk[kIters];
+#pragma unroll
+    for (int k = 0; k < kIters; ++k) kk[k] = keys[min(base + (int64_t)k * kThreads + threadIdx.x, n - 1)];
+#pragma unroll
+    for (int k = 0; k < kIters; ++k)
+        if (base + (int64_t)k * kThreads + threadIdx.x < n) atomicAdd(&s_h[w][(kk[k] >> shift) & dmask], 1);
     __syncthreads();
     for (int j = 0; j < D; ++j) {
         const int d = j * kThreads + threadIdx.x;  // coalesced over the block index for fixed j
@@ -91,13 +95,23 @@ __global__ __launch_bounds__(kThreads) void k_downsweep(const uint32_t* __restri
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t kk[kIters], vv[kIters], xx[kIdx ? kIters : 1];
     int rk[kIters];
+    // all of the thread's loads in flight at once (index clamped, results
+    // selected), then the ranking
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        const int64_t i = base + (int64_t)w * (kIters * 64) + (int64_t)it * 64 + lane;
+        const int64_t ic = min(i, n - 1);
+        kk[it] = keys_in[ic];
+        vv[it] = vals_in[ic];
+        if (kIdx == 1) xx[it] = idx_in[ic];
+        if (kIdx == 2) xx[it] = (uint32_t)i;
+    }
+    __builtin_amdgcn_sched_barrier(0);
     for (int it = 0; it < kIters; ++it) {
         const int64_t i = base + (int64_t)w * (kIters * 64) + (int64_t)it * 64 + lane;
         const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const uint32_t val = valid ? vals_in[i] : 0u;
-        if (kIdx == 1) xx[it] = valid ? idx_in[i] : 0u;
-        if (kIdx == 2) xx[it] = (uint32_t)i;
+        const uint32_t key = valid ? kk[it] : 0u;
+        const uint32_t val = valid ? vv[it] : 0u;
         const int d = (int)((key >> shift) & dmask);
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < nbits; ++b) {
