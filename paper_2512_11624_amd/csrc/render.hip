@@ -43,10 +43,14 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, int2
     if (s0 >= n) return;
     uint32_t key[4];
     uint32_t k[6];  // tile ids of keys s0 - 1 .. s0 + 4 (n_tiles outside the list)
-    k[0] = s0 > 0 ? keys[s0 - 1] >> kClassBits : n_tiles;
+    // the six loads in flight at once (indices clamped, results selected)
+    uint32_t raw[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) raw[j] = keys[min(max(s0 - 1 + j, (int64_t)0), n - 1)];
+    k[0] = s0 > 0 ? raw[0] >> kClassBits : n_tiles;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        const uint32_t v = s0 + j < n ? keys[s0 + j] : 0xffffffffu;
+        const uint32_t v = s0 + j < n ? raw[j + 1] : 0xffffffffu;
         if (j < 4) key[j] = v;
         k[j + 1] = s0 + j < n ? min(v >> kClassBits, n_tiles) : n_tiles;
     }

@@ -67,9 +67,14 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_reduce(const T* __restrict__ in, int64_t n,
                                                      L2* __restrict__ partial) {
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kPer;
+    // the thread's loads in flight at once (index clamped, past the end unused)
+    L2 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = load2(in, min(base + k, n - 1));
     L2 s{0, 0};
+#pragma unroll
     for (int k = 0; k < kPer; ++k)
-        if (base + k < n) s = l2add(s, load2(in, base + k));
+        if (base + k < n) s = l2add(s, v[k]);
     L2 tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -97,9 +102,12 @@ __global__ __launch_bounds__(kThreads) void k_down(const T* __restrict__ in, T* 
                                                    int64_t n, const L2* __restrict__ partial) {
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kPer;
     L2 v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) v[k] = load2(in, min(base + k, n - 1));  // in flight at once
     L2 s{0, 0};
+#pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        v[k] = (base + k < n) ? load2(in, base + k) : L2{0, 0};
+        if (base + k >= n) v[k] = L2{0, 0};
         s = l2add(s, v[k]);
     }
     L2 tot;
