@@ -527,6 +527,9 @@ __global__ __launch_bounds__(256) void k_class_order(const uint32_t* __restrict_
         __syncthreads();
         uint32_t kk[PER], vv[PER], xx[PER];
         int rk[PER];
+        // a wave stops at its first iteration without entries (wave-uniform):
+        // small tiles rank only the iterations they fill
+        const int nit = min(PER, max(0, (sn - wv * PER * 64 + 63) >> 6));
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
             const int j = wv * PER * 64 + it * 64 + lane;
@@ -534,9 +537,11 @@ __global__ __launch_bounds__(256) void k_class_order(const uint32_t* __restrict_
             kk[it] = valid ? keys[base + j] : 0u;
             vv[it] = valid ? vals[base + j] : 0u;
             xx[it] = valid ? idx[base + j] : 0u;
+            rk[it] = -1;
         }
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
+            if (it >= nit) continue;  // wave-uniform
             const int j = wv * PER * 64 + it * 64 + lane;
             const bool valid = j < sn;
             const int c = (int)(kk[it] & (uint32_t)(kClasses - 1));
