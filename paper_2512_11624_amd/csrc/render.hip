@@ -703,34 +703,46 @@ __global__ __launch_bounds__(256) void k_forward_tiles(RenderArgs a, const float
 // term's gradient and the tile's loss partial tile_sse[tile].  acc holds the
 // tile's T x T sums (tile-local row major).  Called by all threads of the
 // workgroup; s_red holds a float per wave.
-template <int T, int NT, bool kLoss>
+template <int T, int NT, bool kLoss, bool kPrefetch = false>
 __device__ inline void finish_tile(const RenderArgs& a, int tile, const float* acc, const TileOrg& o,
                                    const float* __restrict__ target, const float* __restrict__ mask,
                                    float inv_msum, float* __restrict__ pred, float* __restrict__ grad,
                                    float* __restrict__ tile_sse, float* s_red) {
     const int tid = threadIdx.x;
     float sq = 0.f;
-    // every target and mask load of the thread is issued before its first
-    // store: a load issued after a store waits for the store as well
-    constexpr int PPT = (T * T + NT - 1) / NT;
-    float tv[PPT], mv[PPT];
-    int64_t pix[PPT];
-    bool in[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int p = tid + k * NT, px = p % T, py = p / T;
-        in[k] = p < T * T && px < o.vw && py < o.vh;
-        pix[k] = in[k] ? o.base + (int64_t)py * o.stride + px : o.base;  // the tile's first pixel is inside
-        tv[k] = kLoss ? target[pix[k]] : 0.f;
-        mv[k] = kLoss ? mask[pix[k]] : 0.f;
-    }
-#pragma unroll
-    for (int k = 0; k < PPT; ++k)
-        if (in[k]) {
-            const float y = acc[tid + k * NT];
-            pred[pix[k]] = y;
-            if (kLoss) loss_term(a.loss_kind, mv[k], y - tv[k], inv_msum, sq, grad ? grad + pix[k] : nullptr);
+    if (kPrefetch) {
+        // every target and mask load of the thread is issued before its first
+        // store: a load issued after a store waits for the store as well
+        constexpr int PPT = (T * T + NT - 1) / NT;
+        float tv[PPT], mv[PPT];
+        int64_t pix[PPT];
+        bool in[PPT];
+    #pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int p = tid + k * NT, px = p % T, py = p / T;
+            in[k] = p < T * T && px < o.vw && py < o.vh;
+            pix[k] = in[k] ? o.base + (int64_t)py * o.stride + px : o.base;  // the tile's first pixel is inside
+            tv[k] = kLoss ? target[pix[k]] : 0.f;
+            mv[k] = kLoss ? mask[pix[k]] : 0.f;
         }
+    #pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            if (in[k]) {
+                const float y = acc[tid + k * NT];
+                pred[pix[k]] = y;
+                if (kLoss) loss_term(a.loss_kind, mv[k], y - tv[k], inv_msum, sq, grad ? grad + pix[k] : nullptr);
+            }
+    } else {  // fewer registers where the caller holds many
+        for (int p = tid; p < T * T; p += NT) {
+            const int px = p % T, py = p / T;
+            if (px < o.vw && py < o.vh) {
+                const int64_t pi = o.base + (int64_t)py * o.stride + px;
+                const float y = acc[p];
+                pred[pi] = y;
+                if (kLoss) loss_term(a.loss_kind, mask[pi], y - target[pi], inv_msum, sq, grad ? grad + pi : nullptr);
+            }
+        }
+    }
     if (kLoss) {
         for (int o2 = 32; o2 > 0; o2 >>= 1) sq += __shfl_xor(sq, o2, 64);
         if ((tid & 63) == 0) s_red[tid >> 6] = sq;
@@ -972,7 +984,7 @@ __global__ __launch_bounds__(256) void k_forward_finish(RenderArgs a, const floa
         const int p = threadIdx.x + k * NT;
         if (p < T * T) s_acc[p] = acc[k];
     }
-    finish_tile<T, NT, kLoss>(a, tile, s_acc, tile_org(a.tile_org[tile]), target, mask, inv_msum, pred, grad,
+    finish_tile<T, NT, kLoss, true>(a, tile, s_acc, tile_org(a.tile_org[tile]), target, mask, inv_msum, pred, grad,
                               tile_sse, s_red);
 }
 
