@@ -1173,12 +1173,13 @@ __global__ __launch_bounds__(256) void k_backward_tiles(RenderArgs a, const floa
 // list (256 kBwdPer instances, kBwdPer per lane, which may span a few tiles).
 // The binning orders each tile's instances by footprint box shape, so the 64
 // consecutive instances a wave takes walk boxes of (nearly) one shape.  When
-// the chunk's instances lie in at most KT consecutive tiles (the usual case)
-// their upstream gradients are staged in LDS at once, while the lanes'
-// record loads are in flight; otherwise in passes of up to KT of the chunk's
-// tiles.  Each lane walks its records' boxes (adjoint_walk) and writes each
-// instance's gradient to its emission slot: no cross-lane reduction and no
-// atomics, so the result is deterministic and independent of the chunking.
+// the chunk's instances lie in at most KT consecutive tiles, or in just its
+// first and last tile (the usual cases), their upstream gradients are staged
+// in LDS at once, while the lanes' record loads are in flight; otherwise in
+// passes of up to KT of the chunk's tiles.  Each lane walks its records'
+// boxes (adjoint_walk) and writes each instance's gradient to its emission
+// slot: no cross-lane reduction and no atomics, so the result is
+// deterministic and independent of the chunking.
 template <int T>
 __global__ __launch_bounds__(256, 8) void k_backward(RenderArgs a, const float* __restrict__ grad_pred,
                                                     const float* __restrict__ grad_scale,
