@@ -552,7 +552,7 @@ __device__ inline void seg_scan(float (&v)[kN], int key) {
 }
 
 template <int NGS>
-__global__ __launch_bounds__(kBlock) void k_project_backward(
+__global__ __launch_bounds__(kBlock, 7) void k_project_backward(
     ProjectArgs a, const int2* __restrict__ offsets, const int2* __restrict__ counts,
     const Record* __restrict__ rec, const int2* __restrict__ rec_inst, const float4* __restrict__ inst_grad,
     int64_t n_inst, float* __restrict__ g_mean, float* __restrict__ g_log_scale, float* __restrict__ g_quat,
